@@ -1,0 +1,110 @@
+"""Test-only tiled Cholesky reference on the CPU (numpy, FP64).
+
+Each tile operation applies its updates one rank-1 term at a time in
+ascending order, with every product rounded before it is subtracted, so
+every element of the matrix sees exactly the same rounded operations in the
+same order as the unblocked right-looking oracle.  Any topological order of
+the tile DAG therefore produces the oracle's factor bit for bit.  The tile
+tasks are those of the right-looking tile Cholesky (Buttari et al., the
+PLASMA algorithm the paper schedules, section 4.1 "Benchmarks"):
+
+    POTRF(k):      A_kk <- chol(A_kk)
+    TRSM(i, k):    A_ik <- A_ik L_kk^{-T}                  (i > k)
+    SYRK(i, k):    A_ii <- A_ii - L_ik L_ik^T  (lower)     (i > k)
+    GEMM(i, j, k): A_ij <- A_ij - L_ik L_jk^T              (i > j > k)
+
+This module is independent of both the oracle and the GPU library.
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+POTRF, TRSM, SYRK, GEMM = 0, 1, 2, 3
+
+
+def tile_bounds(n: int, nb: int, t: int):
+    return t * nb, min(n, (t + 1) * nb)
+
+
+class NotPositiveDefinite(Exception):
+    def __init__(self, col):
+        super().__init__("pivot %d not positive" % col)
+        self.col = col
+
+
+def tile_potrf(T: np.ndarray, col0: int = 0):
+    m = T.shape[0]
+    for c in range(m):
+        d = T[c, c]
+        if not (d > 0.0):
+            raise NotPositiveDefinite(col0 + c + 1)
+        T[c, c] = math.sqrt(d)
+        T[c + 1:, c] = T[c + 1:, c] / T[c, c]
+        for j in range(c + 1, m):
+            T[j:, j] = T[j:, j] - T[j:, c] * T[j, c]
+
+
+def tile_trsm(X: np.ndarray, Lkk: np.ndarray):
+    m = Lkk.shape[0]
+    for c in range(m):
+        X[:, c] = X[:, c] / Lkk[c, c]
+        for c2 in range(c + 1, m):
+            X[:, c2] = X[:, c2] - X[:, c] * Lkk[c2, c]
+
+
+def tile_syrk(C: np.ndarray, X: np.ndarray):
+    mi, mk = X.shape
+    for q in range(mk):
+        for j in range(mi):
+            C[j:, j] = C[j:, j] - X[j:, q] * X[j, q]
+
+
+def tile_gemm(C: np.ndarray, X: np.ndarray, Y: np.ndarray):
+    for q in range(X.shape[1]):
+        C[:, :] = C - np.multiply.outer(X[:, q], Y[:, q])
+
+
+def run_task(A: np.ndarray, n: int, nb: int, kind: int, i: int, j: int, k: int):
+    """Apply one tile task in place to the (row-major numpy) matrix A."""
+    ri0, ri1 = tile_bounds(n, nb, i)
+    rj0, rj1 = tile_bounds(n, nb, j)
+    rk0, rk1 = tile_bounds(n, nb, k)
+    if kind == POTRF:
+        tile_potrf(A[rk0:rk1, rk0:rk1], rk0)
+    elif kind == TRSM:
+        tile_trsm(A[ri0:ri1, rk0:rk1], A[rk0:rk1, rk0:rk1])
+    elif kind == SYRK:
+        tile_syrk(A[ri0:ri1, ri0:ri1], A[ri0:ri1, rk0:rk1])
+    elif kind == GEMM:
+        tile_gemm(A[ri0:ri1, rj0:rj1], A[ri0:ri1, rk0:rk1], A[rj0:rj1, rk0:rk1])
+    else:
+        raise ValueError(kind)
+
+
+def tasks_k_major(n: int, nb: int):
+    """Tile tasks in the textbook loop order (k outer)."""
+    T = (n + nb - 1) // nb
+    out = []
+    for k in range(T):
+        out.append((POTRF, k, k, k))
+        for i in range(k + 1, T):
+            out.append((TRSM, i, k, k))
+        for i in range(k + 1, T):
+            out.append((SYRK, i, i, k))
+            for j in range(k + 1, i):
+                out.append((GEMM, i, j, k))
+    return out
+
+
+def tiled_cholesky(A: np.ndarray, nb: int, order=None):
+    """Factor a copy of A with the tile algorithm; returns (L_lower_full_array, info)."""
+    A = np.array(A, dtype=np.float64, copy=True)
+    n = A.shape[0]
+    order = tasks_k_major(n, nb) if order is None else order
+    try:
+        for kind, i, j, k in order:
+            run_task(A, n, nb, kind, i, j, k)
+    except NotPositiveDefinite as e:
+        return A, e.col
+    return A, 0
