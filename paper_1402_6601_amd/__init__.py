@@ -1,0 +1,220 @@
+"""Python binding of libtchol (tiled FP64 Cholesky on one MI355X).
+
+Argument marshalling only: every step of the factorization and of the solve
+runs in the library's HIP kernels; torch provides device memory and the
+stream.  There is no CPU fallback: if libtchol.so has not been built, or no
+GPU is visible, the calls raise.
+
+Layout.  torch tensors are row-major.  The library works on column-major
+storage and reads only the lower triangle.  A symmetric row-major A has the
+same bytes as its column-major self, so it is passed unchanged; after the
+factorization its column-major lower triangle holds L, i.e. the row-major
+view holds L^T in its upper triangle and ``A.mT`` is L (lower part).
+Right-hand sides are passed as a column-major copy (``B.mT.contiguous()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtchol.so")
+
+OP_FACTOR, OP_SOLVE = 0, 1
+POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2
+E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL = -100, -101, -102, -103
+KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV"]
+
+_lib = None
+
+
+class TcholError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s failed: %d (%s)" % (where, code, strerror(code) if _lib else "?"))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("seed", ctypes.c_uint32), ("wait_limit_us", ctypes.c_int64),
+                ("kernel_ms", ctypes.POINTER(ctypes.c_float)), ("trace", ctypes.c_void_p)]
+
+
+def load() -> ctypes.CDLL:
+    """Load libtchol.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtchol.so is not built; run `python -m paper_1402_6601_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, u32, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    lib.tchol_workspace_bytes.restype = i64
+    lib.tchol_workspace_bytes.argtypes = [i32, i64, i64, i64]
+    lib.tchol_factor.restype = i32
+    lib.tchol_factor.argtypes = [vp, i64, i64, vp, i64, vp]
+    lib.tchol_factor_ex.restype = i32
+    lib.tchol_factor_ex.argtypes = [vp, i64, i64, vp, i64, vp, ctypes.POINTER(Opts)]
+    lib.tchol_solve.restype = i32
+    lib.tchol_solve.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp]
+    lib.tchol_solve_ex.restype = i32
+    lib.tchol_solve_ex.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, ctypes.POINTER(Opts)]
+    lib.tchol_strerror.restype = ctypes.c_char_p
+    lib.tchol_strerror.argtypes = [i32]
+    lib.tchol_version.restype = ctypes.c_char_p
+    lib.tchol_version.argtypes = []
+    lib.tchol_plan_query.restype = i32
+    lib.tchol_plan_query.argtypes = [i32, i64, i64, i32, u32, P64, P32, P32, P32, P32, P32, P32, P64, P32, P32,
+                                     P32, P32]
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().tchol_strerror(int(code)).decode()
+
+
+def version() -> str:
+    return load().tchol_version().decode()
+
+
+def workspace_bytes(op: int, n: int, nb: int, nrhs: int = 0) -> int:
+    r = load().tchol_workspace_bytes(op, n, nb, nrhs)
+    if r < 0:
+        raise TcholError(int(r), "tchol_workspace_bytes")
+    return int(r)
+
+
+# ---------------------------------------------------------------- plan introspection (host only)
+
+def plan_query(op: int, n: int, nb: int, policy: int = POLICY_RANK, seed: int = 0) -> dict:
+    """The task DAG, ranks and claim order the library would execute (no GPU needed)."""
+    lib = load()
+    counts = np.zeros(4, dtype=np.int64)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    null32, null64 = ctypes.cast(None, P32), ctypes.cast(None, P64)
+    rc = lib.tchol_plan_query(op, n, nb, policy, seed, counts.ctypes.data_as(P64), null32, null32, null32, null32,
+                              null32, null32, null64, null32, null32, null32, null32)
+    if rc != 0:
+        raise TcholError(rc, "tchol_plan_query")
+    nt, ne, ni = int(counts[0]), int(counts[1]), int(counts[2])
+    a = {k: np.zeros(nt, dtype=np.int32) for k in ("kind", "i", "j", "k", "parts", "dep0")}
+    a["rank"] = np.zeros(nt, dtype=np.int64)
+    a["succ_off"] = np.zeros(nt + 1, dtype=np.int32)
+    a["succ"] = np.zeros(max(ne, 1), dtype=np.int32)
+    a["item_task"] = np.zeros(max(ni, 1), dtype=np.int32)
+    a["item_part"] = np.zeros(max(ni, 1), dtype=np.int32)
+    p = lambda x: x.ctypes.data_as(P32)
+    rc = lib.tchol_plan_query(op, n, nb, policy, seed, counts.ctypes.data_as(P64), p(a["kind"]), p(a["i"]),
+                              p(a["j"]), p(a["k"]), p(a["parts"]), p(a["dep0"]), a["rank"].ctypes.data_as(P64),
+                              p(a["succ_off"]), p(a["succ"]), p(a["item_task"]), p(a["item_part"]))
+    if rc != 0:
+        raise TcholError(rc, "tchol_plan_query")
+    a["succ"] = a["succ"][:ne]
+    a["item_task"] = a["item_task"][:ni]
+    a["item_part"] = a["item_part"][:ni]
+    a["ntask"], a["nedge"], a["nitem"], a["critical_path"] = nt, ne, ni, int(counts[3])
+    return a
+
+
+# ---------------------------------------------------------------- device entry points
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("tchol needs a ROCm GPU; none is visible")
+    return torch
+
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(torch, nbytes: int, device):
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace is not 256-byte aligned")
+    return ws
+
+
+def _opts(policy, seed, wait_limit_us, want_ms, trace):
+    o = Opts()
+    o.policy = policy
+    o.seed = seed
+    o.wait_limit_us = wait_limit_us
+    ms = ctypes.c_float(0.0)
+    o.kernel_ms = ctypes.pointer(ms) if want_ms else ctypes.cast(None, ctypes.POINTER(ctypes.c_float))
+    o.trace = ctypes.c_void_p(trace.data_ptr()) if trace is not None else None
+    return o, ms
+
+
+def factor_(A, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+            want_kernel_ms: bool = False, trace=None, check: bool = True):
+    """Factor in place.  A: CUDA float64 (n, n) contiguous, symmetric (only the
+    lower triangle of its column-major reading, i.e. the row-major upper
+    triangle, is read).  Returns info (0 = success), or (info, kernel_ms)."""
+    torch = _torch()
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+        raise ValueError("A must be a contiguous square float64 tensor")
+    if not A.is_cuda:
+        raise ValueError("A must be on the GPU")
+    n = A.shape[0]
+    lib = load()
+    with torch.cuda.device(A.device):
+        need = workspace_bytes(OP_FACTOR, n, nb) if n else 256
+        if ws is None or ws.numel() < need:
+            ws = _workspace(torch, need, A.device)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        rc = lib.tchol_factor_ex(ctypes.c_void_p(A.data_ptr()), n, nb, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 _stream_ptr(torch, A.device), ctypes.byref(o))
+    if rc < 0 and check:
+        raise TcholError(rc, "tchol_factor")
+    return (rc, ms.value) if want_kernel_ms else rc
+
+
+def factor(A, nb: int, **kw):
+    """Return (L, info): L is the lower Cholesky factor of the symmetric A (a new tensor)."""
+    torch = _torch()
+    W = A.detach().to(dtype=torch.float64).contiguous().clone()
+    info = factor_(W, nb, **kw)
+    if isinstance(info, tuple):
+        info = info[0]
+    return torch.tril(W.mT), info
+
+
+def solve_(L, Bc, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+           want_kernel_ms: bool = False, check: bool = True):
+    """Solve in place.  L: the (n, n) buffer factored by factor_ (column-major
+    lower = L).  Bc: CUDA float64 (nrhs, n) contiguous, i.e. B column-major."""
+    torch = _torch()
+    n = L.shape[0]
+    if Bc.dtype != torch.float64 or not Bc.is_contiguous() or Bc.dim() != 2 or Bc.shape[1] != n:
+        raise ValueError("Bc must be a contiguous float64 (nrhs, n) tensor (B in column-major order)")
+    nrhs = Bc.shape[0]
+    lib = load()
+    with torch.cuda.device(L.device):
+        need = workspace_bytes(OP_SOLVE, n, nb, nrhs) if n else 256
+        if ws is None or ws.numel() < need:
+            ws = _workspace(torch, need, L.device)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, None)
+        rc = lib.tchol_solve_ex(ctypes.c_void_p(L.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()), nrhs,
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(torch, L.device),
+                                ctypes.byref(o))
+    if rc != 0 and check:
+        raise TcholError(rc, "tchol_solve")
+    return (rc, ms.value) if want_kernel_ms else rc
+
+
+def solve(Lbuf, B, nb: int, **kw):
+    """X = A^{-1} B given the factored buffer of factor_; B is (n,) or (n, nrhs)."""
+    vec = B.dim() == 1
+    B2 = B.reshape(B.shape[0], -1)
+    Bc = B2.mT.contiguous()
+    solve_(Lbuf, Bc, nb, **kw)
+    X = Bc.mT
+    return X.reshape(-1) if vec else X

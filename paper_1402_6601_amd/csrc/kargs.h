@@ -1,0 +1,33 @@
+/* Arguments of the persistent kernel, shared by the host launcher and the
+   device code.  Plain C types only. */
+#ifndef TCHOL_KARGS_H
+#define TCHOL_KARGS_H
+#include <stdint.h>
+
+/* header words of the device workspace */
+#define HDR_TICKET 0   /* next ticket to hand out                          */
+#define HDR_ABORT 1    /* non-zero: every worker stops                      */
+#define HDR_INFO 2     /* first failing pivot column (1-based), 0 if none   */
+#define HDR_ERROR 3    /* runtime error code (TCHOL_E_TIMEOUT)              */
+#define HDR_DONE 4     /* work items completed                              */
+#define HDR_WORDS 64   /* 256 bytes                                         */
+
+typedef struct KArgs {
+  double *A;            /* factor: in/out matrix; solve: the factor L (read only) */
+  double *B;            /* solve: right-hand sides, overwritten by the solution   */
+  int64_t n, nb, ld, ldb, nrhs;
+  int32_t T, nitem;
+  int32_t gemm_m, gemm_n, trsm_rows, gemv_rows;
+  int32_t *hdr;         /* HDR_WORDS header words                                 */
+  int32_t *dep;         /* per task: predecessors not yet completed               */
+  int32_t *done;        /* per task: work items completed                         */
+  const int32_t *desc;  /* per task: kind, i, j, k, parts, succ_begin, succ_end, 0 */
+  const int32_t *succ;  /* successor lists                                        */
+  const int32_t *items; /* per ticket: task, part                                 */
+  int64_t wait_limit;   /* bound on one dependency wait, in 100 MHz clock ticks   */
+  uint64_t *trace;      /* optional: 4 words per work item                        */
+} KArgs;
+
+#define DESC_WORDS 8
+
+#endif

@@ -1,0 +1,265 @@
+// Host planner for the tile DAGs run by the persistent kernel.
+//
+// Factorization (right-looking tile Cholesky of Buttari et al., the PLASMA
+// DPOTRF the paper schedules, section 4.1 "Benchmarks"), T = ceil(n / nb):
+//   POTRF(k)        preds: SYRK(k, k-1)                  succs: TRSM(i, k), i > k
+//   TRSM(i, k)      preds: POTRF(k), GEMM(i, k, k-1)     succs: SYRK(i, k), GEMM(i, j, k) k<j<i,
+//                                                               GEMM(m, i, k) m > i
+//   SYRK(i, k)      preds: TRSM(i, k), SYRK(i, k-1)      succs: SYRK(i, k+1) or POTRF(i)
+//   GEMM(i, j, k)   preds: TRSM(i,k), TRSM(j,k), GEMM(i,j,k-1)
+//                                                        succs: GEMM(i, j, k+1) or TRSM(i, j)
+// These edges are exactly the read-after-write and write-after-write
+// conflicts on tiles that a data-flow runtime detects (section 2); the
+// k-ascending chain of updates into each tile is kept, so every tile sees its
+// updates in a fixed order and the result does not depend on the schedule.
+//
+// Solve L L^T X = B (B split into row blocks like the tiles of L):
+//   FTRSV(k)        Y_k = L_kk^{-1} B_k       after FGEMV(k, k-1)
+//   FGEMV(i, k)     B_i -= L_ik Y_k, i > k    after FTRSV(k), FGEMV(i, k-1)
+//   BTRSV(k)        X_k = L_kk^{-T} Y_k       after FTRSV(T-1) (k = T-1) or BGEMV(k, k+1)
+//   BGEMV(i, k)     Y_i -= L_ki^T X_k, i < k  after BTRSV(k), BGEMV(i, k+1)
+//
+// Priority: the upward rank of HEFT (section 3.1): rank(t) = w(t) + max over
+// successors s of rank(s), with w the task's flop count in units of nb^3/3
+// (POTRF 1, TRSM 3, SYRK 3, GEMM 6; TRSV 1, GEMV 2) and no communication
+// term (one device).  Every weight is positive, so a task's rank exceeds each
+// successor's and the decreasing-rank order is topological.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <stdexcept>
+#include <tuple>
+
+#include "../../include/tchol.h"
+
+namespace tchol {
+
+namespace {
+
+struct Builder {
+  Plan& p;
+  const Split& s;
+  explicit Builder(Plan& plan, const Split& split) : p(plan), s(split) {}
+
+  int64_t tile_size(int32_t t) const { return std::min<int64_t>(p.nb, p.n - (int64_t)t * p.nb); }
+
+  int32_t add(int32_t kind, int32_t i, int32_t j, int32_t k, int32_t parts) {
+    p.kind.push_back(kind);
+    p.ti.push_back(i);
+    p.tj.push_back(j);
+    p.tk.push_back(k);
+    p.parts.push_back(parts);
+    return (int32_t)p.kind.size() - 1;
+  }
+
+  static int32_t cdiv(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
+};
+
+int64_t weight(int32_t kind) {
+  switch (kind) {
+    case TK_POTRF: return 1;
+    case TK_TRSM: return 3;
+    case TK_SYRK: return 3;
+    case TK_GEMM: return 6;
+    case TK_FTRSV: case TK_BTRSV: return 1;
+    default: return 2;
+  }
+}
+
+// successor lists as vectors, turned into CSR afterwards
+void build_factor(Builder& b, std::vector<std::vector<int32_t>>& succ) {
+  Plan& p = b.p;
+  const int32_t T = p.T;
+  std::vector<int32_t> id_potrf(T, -1), id_trsm((size_t)T * T, -1), id_syrk((size_t)T * T, -1);
+  std::vector<int32_t> id_gemm((size_t)T * T * T, -1);
+  auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
+  auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
+  for (int32_t k = 0; k < T; ++k) {
+    id_potrf[k] = b.add(TK_POTRF, k, k, k, 1);
+    for (int32_t i = k + 1; i < T; ++i)
+      id_trsm[ix2(i, k)] = b.add(TK_TRSM, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
+    for (int32_t i = k + 1; i < T; ++i) {
+      int32_t sb = Builder::cdiv(b.tile_size(i), b.s.gemm_m);
+      id_syrk[ix2(i, k)] = b.add(TK_SYRK, i, i, k, sb * (sb + 1) / 2);
+      for (int32_t j = k + 1; j < i; ++j)
+        id_gemm[ix3(i, j, k)] = b.add(TK_GEMM, i, j, k,
+                                      Builder::cdiv(b.tile_size(i), b.s.gemm_m) *
+                                          Builder::cdiv(b.tile_size(j), b.s.gemm_n));
+    }
+  }
+  succ.assign(p.kind.size(), {});
+  for (int32_t k = 0; k < T; ++k) {
+    for (int32_t i = k + 1; i < T; ++i) succ[id_potrf[k]].push_back(id_trsm[ix2(i, k)]);
+    for (int32_t i = k + 1; i < T; ++i) {
+      auto& st = succ[id_trsm[ix2(i, k)]];
+      st.push_back(id_syrk[ix2(i, k)]);
+      for (int32_t j = k + 1; j < i; ++j) st.push_back(id_gemm[ix3(i, j, k)]);
+      for (int32_t m = i + 1; m < T; ++m) st.push_back(id_gemm[ix3(m, i, k)]);
+      succ[id_syrk[ix2(i, k)]].push_back(k + 1 < i ? id_syrk[ix2(i, k + 1)] : id_potrf[i]);
+      for (int32_t j = k + 1; j < i; ++j)
+        succ[id_gemm[ix3(i, j, k)]].push_back(k + 1 < j ? id_gemm[ix3(i, j, k + 1)] : id_trsm[ix2(i, j)]);
+    }
+  }
+}
+
+void build_solve(Builder& b, std::vector<std::vector<int32_t>>& succ) {
+  Plan& p = b.p;
+  const int32_t T = p.T;
+  std::vector<int32_t> id_ft(T), id_bt(T), id_fg((size_t)T * T, -1), id_bg((size_t)T * T, -1);
+  auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
+  for (int32_t k = 0; k < T; ++k) {
+    id_ft[k] = b.add(TK_FTRSV, k, k, k, 1);
+    for (int32_t i = k + 1; i < T; ++i)
+      id_fg[ix2(i, k)] = b.add(TK_FGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
+  }
+  for (int32_t k = T - 1; k >= 0; --k) {
+    id_bt[k] = b.add(TK_BTRSV, k, k, k, 1);
+    for (int32_t i = 0; i < k; ++i)
+      id_bg[ix2(i, k)] = b.add(TK_BGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
+  }
+  succ.assign(p.kind.size(), {});
+  for (int32_t k = 0; k < T; ++k) {
+    for (int32_t i = k + 1; i < T; ++i) {
+      succ[id_ft[k]].push_back(id_fg[ix2(i, k)]);
+      succ[id_fg[ix2(i, k)]].push_back(k + 1 < i ? id_fg[ix2(i, k + 1)] : id_ft[i]);
+    }
+  }
+  succ[id_ft[T - 1]].push_back(id_bt[T - 1]);
+  for (int32_t k = T - 1; k >= 0; --k) {
+    for (int32_t i = 0; i < k; ++i) {
+      succ[id_bt[k]].push_back(id_bg[ix2(i, k)]);
+      succ[id_bg[ix2(i, k)]].push_back(k - 1 > i ? id_bg[ix2(i, k - 1)] : id_bt[i]);
+    }
+  }
+}
+
+// tie-break key: (step, kind, i, j); the backward sweep of the solve comes
+// after the forward one and runs k downwards.
+std::tuple<int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, int32_t t) {
+  int32_t kind = p.kind[t], step = p.tk[t];
+  if (kind == TK_BTRSV || kind == TK_BGEMV) step = p.T + (p.T - 1 - p.tk[t]);
+  int32_t kord = kind;
+  if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV
+  if (kind == TK_BGEMV) kord = 1;
+  if (kind == TK_FTRSV) kord = 0;
+  if (kind == TK_FGEMV) kord = 1;
+  return std::make_tuple(step, kord, p.ti[t], p.tj[t]);
+}
+
+uint32_t xorshift32(uint32_t& x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
+}  // namespace
+
+const Split& default_split() {
+  static const Split s;
+  return s;
+}
+
+std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed,
+                                 const Split& split) {
+  auto plan = std::make_shared<Plan>();
+  Plan& p = *plan;
+  p.op = op;
+  p.n = n;
+  p.nb = nb;
+  p.policy = policy;
+  p.seed = seed;
+  int64_t T64 = n == 0 ? 0 : (n + nb - 1) / nb;
+  // the largest DAG is the factorization's, about T^3/6 tasks and T^3/2 edges
+  if (T64 > 1200) return nullptr;
+  p.T = (int32_t)T64;
+  if (p.T == 0) {
+    p.succ_off.assign(1, 0);
+    return plan;
+  }
+  Builder b(p, split);
+  std::vector<std::vector<int32_t>> succ;
+  if (op == TCHOL_OP_FACTOR)
+    build_factor(b, succ);
+  else if (op == TCHOL_OP_SOLVE)
+    build_solve(b, succ);
+  else
+    return nullptr;
+  const int64_t nt = p.ntask();
+  p.dep0.assign(nt, 0);
+  p.succ_off.assign(nt + 1, 0);
+  for (int64_t t = 0; t < nt; ++t) {
+    p.succ_off[t + 1] = p.succ_off[t] + (int32_t)succ[t].size();
+    for (int32_t s : succ[t]) p.dep0[s]++;
+  }
+  p.succ.reserve(p.succ_off[nt]);
+  for (int64_t t = 0; t < nt; ++t) p.succ.insert(p.succ.end(), succ[t].begin(), succ[t].end());
+  // upward ranks: tasks were created in a topological order, so a reverse sweep suffices
+  p.rank.assign(nt, 0);
+  for (int64_t t = nt - 1; t >= 0; --t) {
+    int64_t best = 0;
+    for (int32_t e = p.succ_off[t]; e < p.succ_off[t + 1]; ++e) best = std::max(best, p.rank[p.succ[e]]);
+    p.rank[t] = weight(p.kind[t]) + best;
+  }
+  // claim order
+  p.order.resize(nt);
+  std::iota(p.order.begin(), p.order.end(), 0);
+  if (policy == TCHOL_POLICY_RANK) {
+    std::stable_sort(p.order.begin(), p.order.end(), [&](int32_t a, int32_t c) {
+      if (p.rank[a] != p.rank[c]) return p.rank[a] > p.rank[c];
+      return tie_key(p, a) < tie_key(p, c);
+    });
+  } else if (policy == TCHOL_POLICY_FIFO) {
+    std::stable_sort(p.order.begin(), p.order.end(),
+                     [&](int32_t a, int32_t c) { return tie_key(p, a) < tie_key(p, c); });
+  } else {
+    // Kahn's algorithm, choosing uniformly among the ready tasks
+    std::vector<int32_t> indeg = p.dep0, ready;
+    for (int64_t t = 0; t < nt; ++t)
+      if (indeg[t] == 0) ready.push_back((int32_t)t);
+    uint32_t x = seed ? seed : 0x9e3779b9u;
+    p.order.clear();
+    while (!ready.empty()) {
+      size_t pick = xorshift32(x) % ready.size();
+      int32_t t = ready[pick];
+      ready[pick] = ready.back();
+      ready.pop_back();
+      p.order.push_back(t);
+      for (int32_t e = p.succ_off[t]; e < p.succ_off[t + 1]; ++e)
+        if (--indeg[p.succ[e]] == 0) ready.push_back(p.succ[e]);
+    }
+  }
+  int64_t ni = 0;
+  for (int64_t t = 0; t < nt; ++t) ni += p.parts[t];
+  if (ni > (int64_t)INT32_MAX / 2) return nullptr;
+  p.item_task.reserve(ni);
+  p.item_part.reserve(ni);
+  for (int32_t t : p.order)
+    for (int32_t q = 0; q < p.parts[t]; ++q) {
+      p.item_task.push_back(t);
+      p.item_part.push_back(q);
+    }
+  return plan;
+}
+
+std::shared_ptr<const Plan> get_plan(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed) {
+  static std::mutex mu;
+  static std::map<std::tuple<int32_t, int64_t, int64_t, int32_t, uint32_t>, std::shared_ptr<const Plan>> cache;
+  auto key = std::make_tuple(op, n, nb, policy, policy == TCHOL_POLICY_RANDOM ? seed : 0u);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  std::shared_ptr<const Plan> p = build_plan(op, n, nb, policy, seed, default_split());
+  if (!p) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if (cache.size() > 64) cache.clear();
+  cache[key] = p;
+  return p;
+}
+
+}  // namespace tchol

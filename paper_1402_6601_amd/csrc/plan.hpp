@@ -1,0 +1,59 @@
+// Host planner: builds the tile task DAG of the right-looking tile Cholesky
+// (and of the tiled triangular solves), its dependency counters, successor
+// lists, upward ranks and the ticket order in which the persistent kernel's
+// workers claim work items.
+//
+// The paper's runtime discovers the same DAG implicitly from the data each
+// task reads and writes (section 2, data-flow model), makes a task ready
+// when its last predecessor completes (section 2.2, "activate") and, in its
+// HEFT strategy, recalls the original priority rule: decreasing upward rank,
+// the length of the longest path to the exit (section 3.1).  On one GPU all
+// workers are identical, so the placement phase disappears and only the
+// priority order remains; it is computed here once per (operation, n, nb).
+#pragma once
+#include <cstdint>
+#include <memory>
+#include <vector>
+
+#include "tchol_kinds.h"   // task kinds, numbered alike on host and device
+
+namespace tchol {
+
+struct Plan {
+  int32_t op = 0;          // TCHOL_OP_FACTOR / TCHOL_OP_SOLVE
+  int64_t n = 0, nb = 0;   // matrix order, tile size
+  int32_t T = 0;           // tiles per side
+  int32_t policy = 0;      // TCHOL_POLICY_*
+  uint32_t seed = 0;       // for TCHOL_POLICY_RANDOM
+  // per task
+  std::vector<int32_t> kind, ti, tj, tk;   // kind and tile coordinates (i, j, k)
+  std::vector<int32_t> parts;              // work items the task is split into
+  std::vector<int32_t> dep0;               // initial dependency counter (in-degree)
+  std::vector<int32_t> succ_off;           // CSR successor lists, size ntask + 1
+  std::vector<int32_t> succ;
+  std::vector<int64_t> rank;               // upward rank, in units of nb^3/3 flops
+  std::vector<int32_t> order;              // tasks in claim order
+  std::vector<int32_t> item_task, item_part;  // work items in ticket order
+  int64_t ntask() const { return (int64_t)kind.size(); }
+  int64_t nitem() const { return (int64_t)item_task.size(); }
+  int64_t nedge() const { return (int64_t)succ.size(); }
+};
+
+// Work-item granularity (rows x cols of one work item of each task kind).
+struct Split {
+  int32_t gemm_m = 128, gemm_n = 128;   // GEMM/SYRK output sub-tile
+  int32_t trsm_rows = 32;               // TRSM row strip
+  int32_t gemv_rows = 128;              // solve update row strip
+};
+
+// Builds (or fetches from a process-wide cache) the plan.  Returns nullptr
+// for arguments the planner cannot represent (task counts beyond int32).
+std::shared_ptr<const Plan> get_plan(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed);
+
+// Uncached build, used by get_plan and by the plan-introspection entry point.
+std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed,
+                                 const Split& split);
+
+const Split& default_split();
+
+}  // namespace tchol

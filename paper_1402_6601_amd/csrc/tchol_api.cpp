@@ -1,0 +1,316 @@
+// C ABI of libtchol: argument checks, workspace layout, plan upload and the
+// launch of the persistent kernel.  See include/tchol.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/tchol.h"
+#include "kargs.h"
+#include "plan.hpp"
+
+extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid,
+                                       hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+extern "C" hipError_t tchol_dev_max_grid(int device, int* grid);
+
+namespace {
+
+using tchol::Plan;
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Byte offsets of the workspace regions.  [dep0, end) is a copy of the
+// plan's constant image, uploaded in one transfer; hdr, dep and done are
+// (re)initialised by a small kernel on every call.
+struct Layout {
+  int64_t hdr = 0, dep = 0, done = 0, dep0 = 0, desc = 0, succ = 0, items = 0, end = 0;
+};
+
+Layout layout_of(const Plan& p) {
+  Layout L;
+  const int64_t nt = p.ntask();
+  L.hdr = 0;
+  L.dep = align_up(HDR_WORDS * 4);
+  L.done = align_up(L.dep + 4 * nt);
+  L.dep0 = align_up(L.done + 4 * nt);
+  L.desc = align_up(L.dep0 + 4 * nt);
+  L.succ = align_up(L.desc + 4 * DESC_WORDS * nt);
+  L.items = align_up(L.succ + 4 * p.nedge());
+  L.end = align_up(L.items + 8 * p.nitem());
+  return L;
+}
+
+// The constant part of the workspace for one plan, built once, in pinned
+// host memory when the runtime can provide it.
+struct Image {
+  Layout lay;
+  std::vector<char> pageable;
+  char* pinned = nullptr;
+  int64_t bytes = 0;
+  const char* data() const { return pinned ? pinned : pageable.data(); }
+  ~Image() {
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+std::shared_ptr<const Image> image_of(const std::shared_ptr<const Plan>& p) {
+  static std::mutex mu;
+  static std::map<const Plan*, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(p.get());
+    if (it != cache.end() && !it->second.first.expired()) return it->second.second;
+  }
+  auto img = std::make_shared<Image>();
+  img->lay = layout_of(*p);
+  const Layout& L = img->lay;
+  img->bytes = L.end - L.dep0;
+  char* buf = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&buf), (size_t)img->bytes, hipHostMallocDefault) == hipSuccess && buf) {
+    img->pinned = buf;
+  } else {
+    (void)hipGetLastError();
+    img->pageable.resize((size_t)img->bytes);
+    buf = img->pageable.data();
+  }
+  std::memset(buf, 0, (size_t)img->bytes);
+  const int64_t nt = p->ntask();
+  int32_t* dep0 = reinterpret_cast<int32_t*>(buf + (L.dep0 - L.dep0));
+  int32_t* desc = reinterpret_cast<int32_t*>(buf + (L.desc - L.dep0));
+  int32_t* succ = reinterpret_cast<int32_t*>(buf + (L.succ - L.dep0));
+  int32_t* items = reinterpret_cast<int32_t*>(buf + (L.items - L.dep0));
+  for (int64_t t = 0; t < nt; ++t) {
+    dep0[t] = p->dep0[t];
+    int32_t* d = desc + DESC_WORDS * t;
+    d[0] = p->kind[t];
+    d[1] = p->ti[t];
+    d[2] = p->tj[t];
+    d[3] = p->tk[t];
+    d[4] = p->parts[t];
+    d[5] = p->succ_off[t];
+    d[6] = p->succ_off[t + 1];
+    d[7] = 0;
+  }
+  if (p->nedge()) std::memcpy(succ, p->succ.data(), 4 * (size_t)p->nedge());
+  for (int64_t i = 0; i < p->nitem(); ++i) {
+    items[2 * i] = p->item_task[i];
+    items[2 * i + 1] = p->item_part[i];
+  }
+  std::lock_guard<std::mutex> g(mu);
+  if (cache.size() > 64) cache.clear();
+  cache[p.get()] = std::make_pair(std::weak_ptr<const Plan>(p), std::shared_ptr<const Image>(img));
+  return img;
+}
+
+struct DeviceInfo {
+  int grid = 0;
+  int64_t clock_khz = 0;
+};
+
+hipError_t device_info(DeviceInfo* out) {
+  static std::mutex mu;
+  static std::map<int, DeviceInfo> cache;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  DeviceInfo di;
+  e = tchol_dev_max_grid(dev, &di.grid);
+  if (e != hipSuccess) return e;
+  int khz = 0;
+  e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return e;
+  di.clock_khz = khz > 0 ? khz : 100000;
+  cache[dev] = di;
+  *out = di;
+  return hipSuccess;
+}
+
+bool nb_ok(int64_t nb) { return nb >= TCHOL_NB_MIN && nb <= TCHOL_NB_MAX && nb % 16 == 0; }
+
+const tchol_opts kDefaultOpts = {TCHOL_POLICY_RANK, 0u, 0, nullptr, nullptr};
+
+int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrhs, void* ws, int64_t ws_bytes,
+            void* stream_v, const tchol_opts* opts, int32_t ws_arg) {
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
+  auto plan = tchol::get_plan(op, n, nb, o.policy, o.seed);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  const Layout L = layout_of(*plan);
+  if (ws_bytes < L.end) return -(ws_arg + 1);
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
+  auto img = image_of(plan);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+  DeviceInfo di;
+  if (device_info(&di) != hipSuccess) return TCHOL_E_HIP;
+  char* w = static_cast<char*>(ws);
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.A = A;
+  a.B = B;
+  a.n = n;
+  a.nb = nb;
+  a.ld = n;
+  a.ldb = n;
+  a.nrhs = nrhs;
+  a.T = plan->T;
+  a.nitem = (int32_t)plan->nitem();
+  const tchol::Split& sp = tchol::default_split();
+  a.gemm_m = sp.gemm_m;
+  a.gemm_n = sp.gemm_n;
+  a.trsm_rows = sp.trsm_rows;
+  a.gemv_rows = sp.gemv_rows;
+  a.hdr = reinterpret_cast<int32_t*>(w + L.hdr);
+  a.dep = reinterpret_cast<int32_t*>(w + L.dep);
+  a.done = reinterpret_cast<int32_t*>(w + L.done);
+  a.desc = reinterpret_cast<const int32_t*>(w + L.desc);
+  a.succ = reinterpret_cast<const int32_t*>(w + L.succ);
+  a.items = reinterpret_cast<const int32_t*>(w + L.items);
+  const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
+  a.wait_limit = limit_us * di.clock_khz / 1000;
+  a.trace = o.trace;
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int32_t rc = 0;
+  int32_t hdr[HDR_WORDS];
+  hipError_t e = hipMemcpyAsync(w + L.dep0, img->data(), (size_t)img->bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && o.kernel_ms) {
+    e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+  }
+  const int grid = (int)std::min<int64_t>(di.grid, std::max<int64_t>(1, plan->nitem()));
+  if (e == hipSuccess)
+    e = tchol_dev_launch(&a, (int32_t)plan->ntask(), reinterpret_cast<const int32_t*>(w + L.dep0), grid, stream,
+                         ev0, ev1);
+  if (e == hipSuccess) e = hipMemcpyAsync(hdr, a.hdr, sizeof(hdr), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess && o.kernel_ms) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev0, ev1);
+    *o.kernel_ms = ms;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (e != hipSuccess) return TCHOL_E_HIP;
+  if (hdr[HDR_ERROR] != 0)
+    rc = TCHOL_E_TIMEOUT;
+  else if (hdr[HDR_INFO] > 0)
+    rc = hdr[HDR_INFO];
+  else if (hdr[HDR_DONE] != a.nitem)
+    rc = TCHOL_E_INTERNAL;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs) {
+  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE) return -1;
+  if (n < 0) return -2;
+  if (!nb_ok(nb)) return -3;
+  if (op == TCHOL_OP_SOLVE && nrhs < 0) return -4;
+  auto plan = tchol::get_plan(op, n, nb, TCHOL_POLICY_RANK, 0);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  // every policy yields the same task, edge and item counts, hence the same layout
+  return layout_of(*plan).end;
+}
+
+int32_t tchol_factor_ex(double* A, int64_t n, int64_t nb, void* ws, int64_t ws_bytes, void* stream,
+                        const tchol_opts* opts) {
+  if (n < 0) return -2;
+  if (!nb_ok(nb)) return -3;
+  if (n == 0) return 0;
+  if (!A) return -1;
+  if (!ws) return -4;
+  if (ws_bytes <= 0) return -5;
+  return run(TCHOL_OP_FACTOR, A, nullptr, n, nb, 0, ws, ws_bytes, stream, opts, 4);
+}
+
+int32_t tchol_factor(double* A, int64_t n, int64_t nb, void* ws, int64_t ws_bytes, void* stream) {
+  return tchol_factor_ex(A, n, nb, ws, ws_bytes, stream, nullptr);
+}
+
+int32_t tchol_solve_ex(const double* L, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
+                       void* stream, const tchol_opts* opts) {
+  if (n < 0) return -2;
+  if (!nb_ok(nb)) return -3;
+  if (nrhs < 0) return -5;
+  if (n == 0 || nrhs == 0) return 0;
+  if (!L) return -1;
+  if (!B) return -4;
+  if (!ws) return -6;
+  if (ws_bytes <= 0) return -7;
+  return run(TCHOL_OP_SOLVE, const_cast<double*>(L), B, n, nb, nrhs, ws, ws_bytes, stream, opts, 6);
+}
+
+int32_t tchol_solve(const double* L, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
+                    void* stream) {
+  return tchol_solve_ex(L, n, nb, B, nrhs, ws, ws_bytes, stream, nullptr);
+}
+
+const char* tchol_strerror(int32_t code) {
+  if (code == 0) return "success";
+  if (code > 0) return "matrix is not positive definite (leading minor of order `code`)";
+  if (code == TCHOL_E_HIP) return "a HIP runtime call failed";
+  if (code == TCHOL_E_TIMEOUT) return "a dependency wait inside the kernel exceeded its bound";
+  if (code == TCHOL_E_UNSUPPORTED) return "unsupported size or option";
+  if (code == TCHOL_E_INTERNAL) return "work items left unfinished at kernel exit";
+  if (code < 0 && code > -100) return "invalid argument (number -code)";
+  return "unknown error";
+}
+
+const char* tchol_version(void) { return "tchol 0.1 (gfx950)"; }
+
+int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed, int64_t* counts,
+                         int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* parts, int32_t* dep0,
+                         int64_t* rank, int32_t* succ_off, int32_t* succ, int32_t* item_task, int32_t* item_part) {
+  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE) return -1;
+  if (n < 0) return -2;
+  if (!nb_ok(nb)) return -3;
+  if (policy < TCHOL_POLICY_RANK || policy > TCHOL_POLICY_RANDOM) return -4;
+  auto p = tchol::get_plan(op, n, nb, policy, seed);
+  if (!p) return TCHOL_E_UNSUPPORTED;
+  const int64_t nt = p->ntask();
+  if (counts) {
+    // longest path counted in tasks; creation order is topological
+    std::vector<int32_t> depth(nt, 1);
+    int32_t cp = 0;
+    for (int64_t t = nt - 1; t >= 0; --t) {
+      int32_t best = 0;
+      for (int32_t e = p->succ_off[t]; e < p->succ_off[t + 1]; ++e) best = std::max(best, depth[p->succ[e]]);
+      depth[t] = 1 + best;
+      cp = std::max(cp, depth[t]);
+    }
+    counts[0] = nt;
+    counts[1] = p->nedge();
+    counts[2] = p->nitem();
+    counts[3] = cp;
+  }
+  for (int64_t t = 0; t < nt; ++t) {
+    if (kind) kind[t] = p->kind[t];
+    if (ti) ti[t] = p->ti[t];
+    if (tj) tj[t] = p->tj[t];
+    if (tk) tk[t] = p->tk[t];
+    if (parts) parts[t] = p->parts[t];
+    if (dep0) dep0[t] = p->dep0[t];
+    if (rank) rank[t] = p->rank[t];
+  }
+  if (succ_off) std::copy(p->succ_off.begin(), p->succ_off.end(), succ_off);
+  if (succ) std::copy(p->succ.begin(), p->succ.end(), succ);
+  if (item_task) std::copy(p->item_task.begin(), p->item_task.end(), item_task);
+  if (item_part) std::copy(p->item_part.begin(), p->item_part.end(), item_part);
+  return 0;
+}
+
+}  // extern "C"

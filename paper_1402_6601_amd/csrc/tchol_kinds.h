@@ -1,0 +1,16 @@
+/* Task kinds of the tile DAGs executed by the persistent kernel.  Included by
+   the host planner and by the device code so both number them alike. */
+#ifndef TCHOL_KINDS_H
+#define TCHOL_KINDS_H
+/* factorization (right-looking tile Cholesky) */
+#define TK_POTRF 0   /* L_kk = chol(A_kk)                      */
+#define TK_TRSM  1   /* A_ik <- A_ik L_kk^{-T},  i > k         */
+#define TK_SYRK  2   /* A_ii <- A_ii - L_ik L_ik^T (lower)      */
+#define TK_GEMM  3   /* A_ij <- A_ij - L_ik L_jk^T,  i > j > k  */
+/* solve L L^T X = B by tiles of rows of B */
+#define TK_FTRSV 4   /* Y_k <- L_kk^{-1} B_k                    */
+#define TK_FGEMV 5   /* B_i <- B_i - L_ik Y_k,   i > k          */
+#define TK_BTRSV 6   /* X_k <- L_kk^{-T} Y_k                    */
+#define TK_BGEMV 7   /* Y_i <- Y_i - L_ki^T X_k, i < k          */
+#define TK_NKINDS 8
+#endif
