@@ -41,6 +41,12 @@
 extern "C" {
 #endif
 
+#if defined(__GNUC__)
+#define TCHOL_API __attribute__((visibility("default")))
+#else
+#define TCHOL_API
+#endif
+
 #define TCHOL_OP_FACTOR 0
 #define TCHOL_OP_SOLVE 1
 
@@ -72,40 +78,40 @@ typedef struct tchol_opts {
 /* Bytes of device workspace needed by `op` (TCHOL_OP_*) for order n and tile
    size nb (nrhs is ignored by TCHOL_OP_FACTOR).  Returns -i for an invalid
    argument i, TCHOL_E_UNSUPPORTED beyond the supported sizes. */
-int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs);
+TCHOL_API int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs);
 
 /* Factor A = L L^T in place: on success the lower triangle of A holds L.
    Paper: the Cholesky tile DAG (section 4.1, "Benchmarks").
    Arguments: 1 A, 2 n >= 0, 3 nb in [16, 512] and a multiple of 16,
    4 ws, 5 ws_bytes, 6 stream.  n need not be a multiple of nb (edge tiles). */
-int32_t tchol_factor(double *A, int64_t n, int64_t nb, void *ws, int64_t ws_bytes, void *stream);
-int32_t tchol_factor_ex(double *A, int64_t n, int64_t nb, void *ws, int64_t ws_bytes, void *stream,
+TCHOL_API int32_t tchol_factor(double *A, int64_t n, int64_t nb, void *ws, int64_t ws_bytes, void *stream);
+TCHOL_API int32_t tchol_factor_ex(double *A, int64_t n, int64_t nb, void *ws, int64_t ws_bytes, void *stream,
                         const tchol_opts *opts);
 
 /* Solve (L L^T) X = B in place (B := X) given the factor from tchol_factor,
    by a forward then a backward tiled substitution on the same scheduler.
    Arguments: 1 L, 2 n, 3 nb, 4 B (n x nrhs, column-major, ld n), 5 nrhs >= 0,
    6 ws, 7 ws_bytes, 8 stream. */
-int32_t tchol_solve(const double *L, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
+TCHOL_API int32_t tchol_solve(const double *L, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
                     int64_t ws_bytes, void *stream);
-int32_t tchol_solve_ex(const double *L, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
+TCHOL_API int32_t tchol_solve_ex(const double *L, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
                        int64_t ws_bytes, void *stream, const tchol_opts *opts);
 
 /* Human-readable text for a return code (static storage). */
-const char *tchol_strerror(int32_t code);
+TCHOL_API const char *tchol_strerror(int32_t code);
 
 /* Host-only plan introspection (no HIP call).  Fills, when the pointers are
    non-NULL: counts[0..3] = {ntask, nedge, nitem, critical-path task count};
    per task (ntask entries): kind, i, j, k, parts, initial dependency count,
    upward rank; succ_off (ntask + 1) and succ (nedge); and the claim order as
    work items item_task / item_part (nitem).  Returns 0 or a negative code. */
-int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed, int64_t *counts,
+TCHOL_API int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed, int64_t *counts,
                          int32_t *kind, int32_t *ti, int32_t *tj, int32_t *tk, int32_t *parts,
                          int32_t *dep0, int64_t *rank, int32_t *succ_off, int32_t *succ,
                          int32_t *item_task, int32_t *item_part);
 
 /* Library version string. */
-const char *tchol_version(void);
+TCHOL_API const char *tchol_version(void);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@
 #include "tchol_kinds.h"
 
 #define NT 256                 // threads per workgroup: 4 wavefronts of 64
-#define LDS_DOUBLES 18176      // 145408 bytes of LDS per workgroup
+#define LDS_DOUBLES 20352      // 162816 bytes of LDS per workgroup (gfx950 allows 163840)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -36,32 +36,80 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 }
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+
+// Value of v in lane l (l wave-uniform), as a scalar broadcast.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// ---------------------------------------------------------------------------
+// Direct global -> LDS loads.  One instruction moves 16 (or 4) bytes per lane
+// into LDS at a wave-uniform base + lane * size, without passing through
+// registers, so the K panels stream in while the matrix cores run.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ void dma16(const void* g, double* l) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void_t*)l, 16, 0, 0);
+}
+__device__ __forceinline__ void dma4(const void* g, double* l) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void_t*)l, 4, 0, 0);
+}
+
+constexpr int imin_c(int a, int b) { return a < b ? a : b; }
+
+// Store with device (agent) scope: it is written through to the device's
+// point of coherence instead of staying dirty in this XCD's L2.  All results
+// a work item publishes to other workgroups are written this way.
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// s_waitcnt vmcnt(N) with the other counters left alone (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
 
 // ---------------------------------------------------------------------------
 // Matrix-core tile product used by every update:
-//     C[M x N] -= Ap[M x K] * Bp[N x K]^T,   M <= BM, N <= BN.
+//     C[M x N] -= Ap[M x K] * Bp[N x K]^T,   M <= BM, N <= BN, K % KC == 0.
 // The four wavefronts form a WGM x (4/WGM) grid; each owns a (BM/WGM) x
-// (BN*WGM/4) piece of C as 16x16 MFMA blocks held in registers from the
-// first load of C to the final store.  K is streamed in chunks of KC columns
-// through LDS, double buffered: the global loads of the next chunk are in
-// flight while the matrix cores consume the current one.  With lower_only,
-// entries of C above its diagonal are left untouched (diagonal blocks of
-// SYRK and of the POTRF panels).
-template <int BM, int BN, int KC, int WGM>
+// (BN*WGM/4) piece of C as 16x16 MFMA blocks held in accumulator registers
+// from the load of C to the final store.  K is streamed in chunks of KC
+// columns through NST LDS stages filled by direct-to-LDS loads, NST-1 chunks
+// ahead of the matrix cores.  Full, 16-byte aligned panels use 16-byte
+// transfers; ragged ones use 4-byte transfers with row indices clamped into
+// the panel (rows past M hold copies and only feed outputs that are never
+// stored).  With lower_only, entries of C above its diagonal are untouched.
+// With Cl set, the result goes to LDS at Cl (column-major, leading dimension
+// ldl; it must not overlap the NST stages) instead of back to C.
+template <int BM, int BN, int KC, int WGM, int NST>
 __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* __restrict__ Ap,
                                           const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
-                                          bool lower_only, double* lds) {
+                                          bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0) {
   constexpr int WGN = 4 / WGM;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int RB = WTM / 16, CB = WTN / 16;
-  constexpr int ALD = BM + 8, BLD = BN + 8;
-  constexpr int NA = BM * KC / NT, NB = BN * KC / NT;
-  static_assert(NA * NT == BM * KC && NB * NT == BN * KC, "staging must divide evenly");
-  double* As = lds;                  // [2][KC][ALD]
-  double* Bs = lds + 2 * KC * ALD;   // [2][KC][BLD]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int STAGE = KC * (BM + BN);                       // doubles per stage
+  constexpr int QA16 = KC * BM / 128, QB16 = KC * BN / 128;   // 1 KB transfers per stage
+  constexpr int QA4 = KC * BM / 32, QB4 = KC * BN / 32;       // 256 B transfers per stage
+  constexpr int J16 = (QA16 + QB16 + 3) / 4, J4 = (QA4 + QB4 + 3) / 4;  // transfer slots per wavefront
+  constexpr int W16 = (QA16 + QB16) / 4, W4 = (QA4 + QB4) / 4;            // fewest transfers per wavefront
+  static_assert(QA16 * 128 == KC * BM && QB16 * 128 == KC * BN, "stage must be whole 1 KB segments");
+  static_assert(W16 >= 1 && W4 >= 1, "every wavefront must issue transfers for every chunk");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
   const int l16 = lane & 15, lg = lane >> 4;
+  // 16-byte transfers need even row counts (a transfer covers rows r, r + 1)
+  // and 16-byte aligned columns; otherwise 4-byte transfers are used.
+  const bool fast = ((M & 1) == 0) && ((N & 1) == 0) && (ld % 2 == 0) &&
+                    ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) % 16 == 0);
 
   d4 acc[RB][CB];
 #pragma unroll
@@ -71,64 +119,82 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = wm * WTM + rb * 16 + l16, col = wn * WTN + cb * 16 + 4 * i + lg;
-        // out-of-range lanes read a clamped in-range address and discard it,
-        // so that every load is unconditional
-        const double v = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
-        acc[rb][cb][i] = ((row < M) & (col < N)) ? v : 0.0;
+        acc[rb][cb][i] = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
       }
 
-  double ra[NA], rbv[NB];
-  const int nch = (K + KC - 1) / KC;
-  // Byte offsets from the (wave-uniform) panel bases fit in 32 bits: a tile
-  // column block spans at most 512 columns of a matrix of order <= 614400.
-  const char* Ab = reinterpret_cast<const char*>(Ap);
-  const char* Bb = reinterpret_cast<const char*>(Bp);
-  const uint32_t ld8 = (uint32_t)ld * 8u;
-#define GEMM_GLOAD(k0)                                                                 \
-  _Pragma("unroll") for (int s = 0; s < NA; ++s) {                                     \
-    const int idx = tid + NT * s, r = idx % BM, k = (k0) + idx / BM;                   \
-    const double v = *reinterpret_cast<const double*>(Ab + ((uint32_t)imin(k, K - 1) * ld8 + (uint32_t)imin(r, M - 1) * 8u)); \
-    ra[s] = ((r < M) & (k < K)) ? v : 0.0;                                               \
-  }                                                                                    \
-  _Pragma("unroll") for (int s = 0; s < NB; ++s) {                                     \
-    const int idx = tid + NT * s, r = idx % BN, k = (k0) + idx / BN;                   \
-    const double v = *reinterpret_cast<const double*>(Bb + ((uint32_t)imin(k, K - 1) * ld8 + (uint32_t)imin(r, N - 1) * 8u)); \
-    rbv[s] = ((r < N) & (k < K)) ? v : 0.0;                                               \
-  }
-#define GEMM_LSTORE(st)                                                  \
-  _Pragma("unroll") for (int s = 0; s < NA; ++s) {                       \
-    const int idx = tid + NT * s;                                        \
-    As[((st) * KC + idx / BM) * ALD + idx % BM] = ra[s];                 \
-  }                                                                      \
-  _Pragma("unroll") for (int s = 0; s < NB; ++s) {                       \
-    const int idx = tid + NT * s;                                        \
-    Bs[((st) * KC + idx / BN) * BLD + idx % BN] = rbv[s];                \
-  }
-  GEMM_GLOAD(0)
-  GEMM_LSTORE(0)
-  __syncthreads();
+  // Every wavefront issues the same number of transfers for every chunk
+  // (rows past M or N are clamped to the last valid ones, whose copies only
+  // feed outputs that are never stored), so the number of transfers still in
+  // flight behind a chunk is known and the wait below can be exact.
+  auto issue = [&](int ch) {
+    double* As = lds + (ch % NST) * STAGE;
+    double* Bs = As + KC * BM;
+    const int k0 = ch * KC;
+    if (fast) {
+#pragma unroll
+      for (int j = 0; j < J16; ++j) {
+        const int q = wave + 4 * j;
+        if (q < QA16) {
+          const int e = q * 128 + 2 * lane, c = e / BM, r = imin(e % BM, M - 2);
+          dma16(Ap + (int64_t)(k0 + c) * ld + r, As + q * 128);
+        } else if (q < QA16 + QB16) {
+          const int e = (q - QA16) * 128 + 2 * lane, c = e / BN, r = imin(e % BN, N - 2);
+          dma16(Bp + (int64_t)(k0 + c) * ld + r, Bs + (q - QA16) * 128);
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int j = 0; j < J4; ++j) {
+        const int q = wave + 4 * j;
+        if (q < QA4) {
+          const int e = q * 32 + (lane >> 1), c = e / BM, r = imin(e % BM, M - 1);
+          dma4(reinterpret_cast<const float*>(Ap + (int64_t)(k0 + c) * ld + r) + (lane & 1), As + q * 32);
+        } else if (q < QA4 + QB4) {
+          const int e = (q - QA4) * 32 + (lane >> 1), c = e / BN, r = imin(e % BN, N - 1);
+          dma4(reinterpret_cast<const float*>(Bp + (int64_t)(k0 + c) * ld + r) + (lane & 1), Bs + (q - QA4) * 32);
+        }
+      }
+    }
+  };
+
+  const int nch = K / KC;
+#pragma unroll
+  for (int p = 0; p < NST - 1; ++p)
+    if (p < nch) issue(p);
   for (int ch = 0; ch < nch; ++ch) {
-    const int st = ch & 1;
-    if (ch + 1 < nch) { GEMM_GLOAD((ch + 1) * KC) }
-    const double* as = As + st * KC * ALD;
-    const double* bs = Bs + st * KC * BLD;
-#pragma unroll 2
+    // Chunk ch has landed once no more than the later chunks' transfers are
+    // outstanding.  A wavefront issues W or W + 1 transfers per chunk; waiting
+    // for "at most W per later chunk" (capped at the counter's range) is
+    // exact or stricter, never short.
+    const int later = imin(nch - 1 - ch, NST - 2);
+    if (fast) {
+      if (later >= 2) wait_vmcnt<imin_c(2 * W16, 63)>();
+      else if (later == 1) wait_vmcnt<imin_c(W16, 63)>();
+      else wait_vmcnt<0>();
+    } else {
+      if (later >= 2) wait_vmcnt<imin_c(2 * W4, 63)>();
+      else if (later == 1) wait_vmcnt<imin_c(W4, 63)>();
+      else wait_vmcnt<0>();
+    }
+    __syncthreads();
+    if (ch + NST - 1 < nch) issue(ch + NST - 1);
+    const double* as = lds + (ch % NST) * STAGE;
+    const double* bs = as + KC * BM;
+#pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       double fa[RB], fb[CB];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) fa[rb] = -as[(ks * 4 + lg) * ALD + wm * WTM + rb * 16 + l16];
+      for (int rb = 0; rb < RB; ++rb) fa[rb] = as[(ks * 4 + lg) * BM + wm * WTM + rb * 16 + l16];
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) fb[cb] = bs[(ks * 4 + lg) * BLD + wn * WTN + cb * 16 + l16];
+      for (int cb = 0; cb < CB; ++cb) fb[cb] = bs[(ks * 4 + lg) * BN + wn * WTN + cb * 16 + l16];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma_f64(fb[cb], fa[rb], acc[rb][cb]);
+        for (int cb = 0; cb < CB; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[cb], fa[rb], acc[rb][cb], 0, 0, 2 /* neg B */);
     }
-    if (ch + 1 < nch) { GEMM_LSTORE(st ^ 1) }
-    __syncthreads();
   }
-#undef GEMM_GLOAD
-#undef GEMM_LSTORE
+  __syncthreads();  // every wavefront is done with the stages before LDS is reused
 
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
@@ -137,7 +203,12 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = wm * WTM + rb * 16 + l16, col = wn * WTN + cb * 16 + 4 * i + lg;
-        if (row < M && col < N && (!lower_only || row >= col)) C[(int64_t)col * ld + row] = acc[rb][cb][i];
+        if (row < M && col < N && (!lower_only || row >= col)) {
+          if (Cl)
+            Cl[col * ldl + row] = acc[rb][cb][i];  // result kept in LDS (column-major, ld ldl)
+          else
+            st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
+        }
       }
 }
 
@@ -145,50 +216,115 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
 #define GB 128
 __device__ __forceinline__ void gemm_nt(double* C, const double* Ap, const double* Bp, int64_t ld, int M, int N,
                                         int K, bool lower_only, double* lds) {
-  gemm_core<GB, GB, 16, 2>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+  gemm_core<GB, GB, 16, 2, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
 }
 
 // ---------------------------------------------------------------------------
 // POTRF work item: Akk (m x m, m <= 512) := chol(Akk), lower, in place.
-// Left-looking by panels of PW columns.  For each panel: the matrix cores
-// apply all earlier columns to it (a 512 x 32 product with K = the panel's
-// offset), the panel is loaded into LDS, its columns are factored one by one
-// (sqrt, division, rank-1 update of the panel's later columns) and it is
-// written back.  Returns 0, or the 1-based column (within the tile) whose
-// pivot is not positive.
-#define PW 32
-#define PLD 512
+// Left-looking by panels of PW = 16 columns; a panel stays in LDS from its
+// update to its store:
+//  1. the matrix cores apply every earlier column to the panel (gemm_core in
+//     slabs of 256 rows, result written to LDS);
+//  2. one wavefront factors the panel's 16 x 16 diagonal block in registers:
+//     lane r holds row r, the pivot and the column entries it needs are
+//     broadcast across lanes (readlane), so no barrier is needed;
+//  3. every thread solves one row below the block against it (forward
+//     substitution, the block and its reciprocal pivots in LDS);
+//  4. the finished panel is written to the tile once.
+// Returns 0, or the 1-based column (within the tile) whose pivot is not
+// positive (zero, negative or NaN).
+#define PW 16
+#define PPLD 516                              // LDS leading dimension of the panel
+#define P_STAGE_DOUBLES (272 * 8 * 4)         // gemm_core<256, 16, 8, 4, 4> stages
 
 __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds) {
-  double* Ps = lds;  // [PW][PLD]
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* Ps = lds + P_STAGE_DOUBLES;              // [PW][PPLD] the panel
+  double* Ldd = Ps + PW * PPLD;                     // [PW][PW + 1] its diagonal block
+  double* Linv = Ldd + PW * (PW + 1);               // [PW] reciprocal pivots
+  __shared__ int s_info;
   for (int c0 = 0; c0 < m; c0 += PW) {
     const int w = imin(PW, m - c0);
     const int R = m - c0;
     double* P = Akk + (int64_t)c0 * ld + c0;
     if (c0 > 0) {
-      gemm_core<PLD, PW, 8, 4>(P, Akk + c0, Akk + c0, ld, R, w, c0, true, lds);
-      __syncthreads();
-    }
-    for (int c = 0; c < w; ++c)
-      for (int r = c + tid; r < R; r += NT) Ps[c * PLD + r] = P[(int64_t)c * ld + r];
-    __syncthreads();
-    for (int cc = 0; cc < w; ++cc) {
-      const double d = Ps[cc * PLD + cc];
-      if (!(d > 0.0)) return c0 + cc + 1;
-      const double lkk = sqrt(d);
-      __syncthreads();
-      for (int r = cc + 1 + tid; r < R; r += NT) Ps[cc * PLD + r] = Ps[cc * PLD + r] / lkk;
-      if (tid == 0) Ps[cc * PLD + cc] = lkk;
-      __syncthreads();
-      for (int c2 = cc + 1; c2 < w; ++c2) {
-        const double l2 = Ps[cc * PLD + c2];
-        for (int r = c2 + tid; r < R; r += NT) Ps[c2 * PLD + r] -= Ps[cc * PLD + r] * l2;
+      // P - L[c0:, 0:c0] L[c0:c0+w, 0:c0]^T into LDS, in (at most two) slabs of 256 rows
+      for (int s0 = 0; s0 < R; s0 += 256) {
+        gemm_core<256, PW, 8, 4, 4>(P + s0, Akk + c0 + s0, Akk + c0, ld, imin(256, R - s0), w, c0, false, lds,
+                                    Ps + s0, PPLD);
+        __syncthreads();
       }
+    } else {
+      for (int c = 0; c < w; ++c)
+        for (int r = tid; r < R; r += NT) Ps[c * PPLD + r] = P[(int64_t)c * ld + r];
       __syncthreads();
     }
+    if (wave == 0) {
+      // Lane r holds row r of the block.  Rows and columns past w are padded
+      // with the identity, so every loop below has a fixed trip count (the
+      // code is fully unrolled and x stays in registers).
+      double x[PW];
+      const int r = imin(lane, w - 1);
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        const double v = Ps[imin(c, w - 1) * PPLD + r];
+        x[c] = (lane < w) ? (((c <= lane) & (c < w)) ? v : 0.0) : (c == lane ? 1.0 : 0.0);
+      }
+      int info = 0;
+#pragma unroll
+      for (int cc = 0; cc < PW; ++cc) {
+        const double d = readlane_f64(x[cc], cc);
+        // the first column whose pivot is not positive; the arithmetic goes on
+        // (its results are discarded when info != 0)
+        info = (info == 0 && !(d > 0.0)) ? c0 + cc + 1 : info;
+        const double l = sqrt(d);
+        const double inv = 1.0 / l;
+        x[cc] = (lane == cc) ? l : ((lane > cc) ? x[cc] * inv : x[cc]);
+#pragma unroll
+        for (int c2 = cc + 1; c2 < PW; ++c2) {
+          const double v = readlane_f64(x[cc], c2);
+          x[c2] = (lane >= c2) ? x[c2] - x[cc] * v : x[c2];
+        }
+      }
+      if (lane == 0) s_info = info;
+      if (lane < w) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c)
+          if (c <= lane) Ps[c * PPLD + lane] = x[c];
+      }
+      if (lane < PW) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c) Ldd[lane * (PW + 1) + c] = (c <= lane) ? x[c] : 0.0;
+        Linv[lane] = 1.0 / x[lane];
+      }
+    }
+    __syncthreads();
+    const int info = __builtin_amdgcn_readfirstlane(s_info);
+    if (info != 0) return info;
+    // rows below the diagonal block: y := y L_dd^{-T}, one row per thread
+    // and pass, column by column (right-looking); columns past w see the
+    // identity padding of Ldd
+#pragma unroll 1
+    for (int r = w + tid; r < R; r += NT) {
+      double y[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) y[c] = Ps[c * PPLD + r];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        y[c] *= Linv[c];
+#pragma unroll
+        for (int c2 = c + 1; c2 < PW; ++c2) y[c2] -= y[c] * Ldd[c2 * (PW + 1) + c];
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) Ps[c * PPLD + r] = y[c];
+    }
+    __syncthreads();
+    // the finished panel (lower part) to the tile, then make it visible to
+    // every wavefront before the next panel's update reads it
     for (int c = 0; c < w; ++c)
-      for (int r = c + tid; r < R; r += NT) P[(int64_t)c * ld + r] = Ps[c * PLD + r];
+      for (int r = c + tid; r < R; r += NT) st_dev(P + (int64_t)c * ld + r, Ps[c * PPLD + r]);
+    wait_vmcnt<0>();
     __syncthreads();
   }
   return 0;
@@ -200,118 +336,169 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 // block of 16 columns: one wavefront solves the 16x16 triangle by forward
 // substitution (each lane one row, in registers), then the matrix cores
 // subtract the block's contribution from every later column of the strip.
+// The L fragments of a step are requested before its triangular solve so
+// that their latency hides behind it; the reciprocal pivots are formed once.
 #define TS 32
 
-__device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double* __restrict__ Lkk, int64_t ld, int S, int mk,
-                           double* lds) {
-  double* Xs = lds;               // [mk][TS]
-  double* Ld = lds + 512 * TS;    // [16][17] diagonal block of L_kk
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double* __restrict__ Lkk, int64_t ld, int S,
+                                           int mk, double* lds) {
+  double* Xs = lds;                 // [mk][TS]
+  double* Ld = lds + 512 * TS;      // [2][16][17] diagonal blocks of L_kk, double buffered
+  double* Linv = Ld + 2 * 16 * 17;  // [mk] reciprocal pivots
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
   {
     const int r = tid & (TS - 1);
     for (int c = tid / TS; c < mk; c += NT / TS) Xs[c * TS + r] = (r < S) ? X[(int64_t)c * ld + r] : 0.0;
+    for (int c = tid; c < mk; c += NT) Linv[c] = 1.0 / Lkk[(int64_t)c * ld + c];
+    const int a = tid >> 4, b = tid & 15;
+    Ld[a * 17 + b] = (a >= b) ? Lkk[(int64_t)b * ld + a] : 0.0;
   }
   __syncthreads();
-  for (int q0 = 0; q0 < mk; q0 += 16) {
-    {
-      const int a = tid >> 4, b = tid & 15;
-      Ld[a * 17 + b] = (a >= b) ? Lkk[(int64_t)(q0 + b) * ld + q0 + a] : 0.0;
+  int it = 0;
+  for (int q0 = 0; q0 < mk; q0 += 16, ++it) {
+    const int ncb = (mk - q0 - 16) >> 4;
+    // requests for this step: the next diagonal block and this wave's L fragments
+    const int a = tid >> 4, b = tid & 15;
+    // unconditional loads from clamped addresses (selects afterwards keep
+    // them independent of each other)
+    const int qn = imin(q0 + 16, mk - 16);
+    const double ldn = Lkk[(int64_t)(qn + b) * ld + qn + a];
+    const double ldnext = (a >= b) ? ldn : 0.0;
+    double fl[8][4];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int cb = wave + 4 * t;
+      const int crow = imin(q0 + 16 + cb * 16 + l16, mk - 1);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) fl[t][kk] = Lkk[(int64_t)(q0 + kk * 4 + lg) * ld + crow];
     }
-    __syncthreads();
+    const double* Lb = Ld + (it & 1) * 272;
     if (tid < TS) {
       double x[16];
 #pragma unroll
-      for (int b = 0; b < 16; ++b) x[b] = Xs[(q0 + b) * TS + tid];
+      for (int bb = 0; bb < 16; ++bb) x[bb] = Xs[(q0 + bb) * TS + tid];
 #pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        x[b] = x[b] / Ld[b * 17 + b];
+      for (int bb = 0; bb < 16; ++bb) {
+        x[bb] = x[bb] * Linv[q0 + bb];
 #pragma unroll
-        for (int a = b + 1; a < 16; ++a) x[a] -= x[b] * Ld[a * 17 + b];
+        for (int aa = bb + 1; aa < 16; ++aa) x[aa] -= x[bb] * Lb[aa * 17 + bb];
       }
 #pragma unroll
-      for (int b = 0; b < 16; ++b) Xs[(q0 + b) * TS + tid] = x[b];
+      for (int bb = 0; bb < 16; ++bb) Xs[(q0 + bb) * TS + tid] = x[bb];
     }
     __syncthreads();
-    // X[:, c2] -= X[:, q0:q0+16] L[c2, q0:q0+16]^T for the later column blocks
-    const int ncb = (mk - q0 - 16) >> 4;
-    for (int u = wave; u < 2 * ncb; u += 4) {
-      const int rbk = u & 1, cbase = q0 + 16 + (u >> 1) * 16;
-      d4 acc;
+    // X[:, c2] -= X[:, q0:q0+16] L[c2, q0:q0+16]^T for this wave's later column blocks
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = Xs[(cbase + 4 * i + lg) * TS + rbk * 16 + l16];
+    for (int t = 0; t < 8; ++t) {
+      const int cb = wave + 4 * t;
+      if (cb < ncb) {
+        const int cbase = q0 + 16 + cb * 16;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int q = q0 + kk * 4 + lg;
-        const double fa = -Xs[q * TS + rbk * 16 + l16];
-        const double fb = Lkk[(int64_t)q * ld + cbase + l16];
-        acc = mfma_f64(fb, fa, acc);
+        for (int rbk = 0; rbk < 2; ++rbk) {
+          d4 acc;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i] = Xs[(cbase + 4 * i + lg) * TS + rbk * 16 + l16];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double fx = Xs[(q0 + kk * 4 + lg) * TS + rbk * 16 + l16];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], fx, acc, 0, 0, 2 /* neg B */);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Xs[(cbase + 4 * i + lg) * TS + rbk * 16 + l16] = acc[i];
+        }
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Xs[(cbase + 4 * i + lg) * TS + rbk * 16 + l16] = acc[i];
     }
+    if (q0 + 16 < mk) Ld[((it + 1) & 1) * 272 + a * 17 + b] = ldnext;
     __syncthreads();
   }
   {
     const int r = tid & (TS - 1);
     if (r < S)
-      for (int c = tid / TS; c < mk; c += NT / TS) X[(int64_t)c * ld + r] = Xs[c * TS + r];
+      for (int c = tid / TS; c < mk; c += NT / TS) st_dev(X + (int64_t)c * ld + r, Xs[c * TS + r]);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Solve work items.  Right-hand sides are processed 16 columns at a time,
-// staged in LDS as Ys[j][r] (16 x 512).
-#define YLD 512
+// Solve work items.  Right-hand sides are processed 16 columns at a time
+// (the N of an MFMA block), staged in LDS as Ys[j][r] (16 x YLD).
+// MFMA layout used here: A operand = L fragment (rows of L on lanes % 16),
+// B operand = Y fragment (right-hand sides on lanes % 16); a lane then holds
+// rows 4i + lane/16 of one right-hand side (lane % 16) of the 16x16 result.
+#define YLD 520
 
 __device__ __forceinline__ void stage_rhs(double* Ys, const double* Bk, int64_t ldb, int m, int j0, int jn) {
-  for (int idx = threadIdx.x; idx < 16 * YLD; idx += NT) {
-    const int j = idx / YLD, r = idx % YLD;
-    Ys[idx] = (j < jn && r < m) ? Bk[(int64_t)(j0 + j) * ldb + r] : 0.0;
+  for (int idx = threadIdx.x; idx < 16 * 512; idx += NT) {
+    const int j = idx >> 9, r = idx & 511;
+    Ys[j * YLD + r] = (j < jn && r < m) ? Bk[(int64_t)(j0 + imin(j, jn - 1)) * ldb + imin(r, m - 1)] : 0.0;
   }
 }
 
 __device__ __forceinline__ void unstage_rhs(const double* Ys, double* Bk, int64_t ldb, int m, int j0, int jn) {
-  for (int idx = threadIdx.x; idx < 16 * YLD; idx += NT) {
-    const int j = idx / YLD, r = idx % YLD;
-    if (j < jn && r < m) Bk[(int64_t)(j0 + j) * ldb + r] = Ys[idx];
+  for (int idx = threadIdx.x; idx < 16 * 512; idx += NT) {
+    const int j = idx >> 9, r = idx & 511;
+    if (j < jn && r < m) st_dev(Bk + (int64_t)(j0 + j) * ldb + r, Ys[j * YLD + r]);
   }
 }
 
-// Y_k := L_kk^{-1} B_k, forward substitution by blocks of 16 rows.
-__device__ __forceinline__ void ftrsv(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb, int m, int nrhs,
-                      double* lds) {
-  double* Ys = lds;
-  const int tid = threadIdx.x;
+// Y_k := L_kk^{-1} B_k (m <= 512 rows), forward substitution by blocks of 16
+// rows: a 16-lane triangular solve (one right-hand side per lane, the
+// diagonal block and its reciprocal pivots in LDS), then the matrix cores
+// subtract the block's contribution from every later row block.
+__device__ __forceinline__ void ftrsv(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb, int m,
+                                      int nrhs, double* lds) {
+  double* Ys = lds;                   // [16][YLD]
+  double* Ld = lds + 16 * YLD;        // [16][17] diagonal block
+  double* Linv = Ld + 16 * 17;        // [512] reciprocal pivots
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int nblk = (m + 15) >> 4;
+  for (int c = tid; c < m; c += NT) Linv[c] = 1.0 / Lkk[(int64_t)c * ld + c];
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
     stage_rhs(Ys, Bk, ldb, m, j0, jn);
-    __syncthreads();
-    for (int r0 = 0; r0 < m; r0 += 16) {
-      const int bw = imin(16, m - r0);
-      if (tid < 16) {
-        double* y = Ys + tid * YLD + r0;
-        for (int a = 0; a < bw; ++a) {
-          double s = y[a];
-          for (int b = 0; b < a; ++b) s -= Lkk[(int64_t)(r0 + b) * ld + r0 + a] * y[b];
-          y[a] = s / Lkk[(int64_t)(r0 + a) * ld + r0 + a];
-        }
+    for (int rb = 0; rb < nblk; ++rb) {
+      const int r0 = rb * 16, bw = imin(16, m - r0);
+      {
+        const int a = tid >> 4, b = tid & 15;
+        const double v = Lkk[(int64_t)(r0 + imin(b, bw - 1)) * ld + r0 + imin(a, bw - 1)];
+        Ld[a * 17 + b] = ((a >= b) & (a < bw) & (b < bw)) ? v : 0.0;
       }
       __syncthreads();
-      const int rl = tid & 63, jg = tid >> 6;
-      for (int r = r0 + bw + rl; r < m; r += 64) {
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int b = 0; b < bw; ++b) {
-          const double l = Lkk[(int64_t)(r0 + b) * ld + r];
-          s0 += l * Ys[(jg * 4 + 0) * YLD + r0 + b];
-          s1 += l * Ys[(jg * 4 + 1) * YLD + r0 + b];
-          s2 += l * Ys[(jg * 4 + 2) * YLD + r0 + b];
-          s3 += l * Ys[(jg * 4 + 3) * YLD + r0 + b];
+      if (tid < 16) {
+        double y[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) y[a] = Ys[tid * YLD + r0 + a];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+          if (a < bw) {
+            double t = y[a];
+#pragma unroll
+            for (int b = 0; b < a; ++b) t -= Ld[a * 17 + b] * y[b];
+            y[a] = t * Linv[r0 + a];
+          }
         }
-        Ys[(jg * 4 + 0) * YLD + r] -= s0;
-        Ys[(jg * 4 + 1) * YLD + r] -= s1;
-        Ys[(jg * 4 + 2) * YLD + r] -= s2;
-        Ys[(jg * 4 + 3) * YLD + r] -= s3;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) Ys[tid * YLD + r0 + a] = y[a];
+      }
+      __syncthreads();
+      // later row blocks: Y[rows] -= L[rows, r0:r0+16] Y[r0:r0+16]
+      for (int ub = rb + 1 + wave; ub < nblk; ub += 4) {
+        const int rr = ub * 16;
+        d4 acc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int q = r0 + kk * 4 + lg;
+          const double fl = (q < m) ? Lkk[(int64_t)imin(q, m - 1) * ld + imin(rr + l16, m - 1)] : 0.0;
+          const double fy = Ys[l16 * YLD + q];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl, fy, acc, 0, 0, 2 /* neg B */);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
       }
       __syncthreads();
     }
@@ -320,42 +507,61 @@ __device__ __forceinline__ void ftrsv(const double* __restrict__ Lkk, int64_t ld
   }
 }
 
-// X_k := L_kk^{-T} Y_k, backward substitution by blocks of 16 rows.
-__device__ __forceinline__ void btrsv(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb, int m, int nrhs,
-                      double* lds) {
+// X_k := L_kk^{-T} Y_k, backward substitution by blocks of 16 rows (last
+// block first); the update of the rows above uses L's transposed blocks.
+__device__ __forceinline__ void btrsv(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb, int m,
+                                      int nrhs, double* lds) {
   double* Ys = lds;
-  const int tid = threadIdx.x;
+  double* Ld = lds + 16 * YLD;
+  double* Linv = Ld + 16 * 17;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, lg = lane >> 4;
   const int nblk = (m + 15) >> 4;
+  for (int c = tid; c < m; c += NT) Linv[c] = 1.0 / Lkk[(int64_t)c * ld + c];
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
     stage_rhs(Ys, Bk, ldb, m, j0, jn);
-    __syncthreads();
     for (int rb = nblk - 1; rb >= 0; --rb) {
       const int r0 = rb * 16, bw = imin(16, m - r0);
-      if (tid < 16) {
-        double* y = Ys + tid * YLD + r0;
-        for (int a = bw - 1; a >= 0; --a) {
-          double s = y[a];
-          for (int b = a + 1; b < bw; ++b) s -= Lkk[(int64_t)(r0 + a) * ld + r0 + b] * y[b];
-          y[a] = s / Lkk[(int64_t)(r0 + a) * ld + r0 + a];
-        }
+      {
+        const int a = tid >> 4, b = tid & 15;
+        const double v = Lkk[(int64_t)(r0 + imin(b, bw - 1)) * ld + r0 + imin(a, bw - 1)];
+        Ld[a * 17 + b] = ((a >= b) & (a < bw) & (b < bw)) ? v : 0.0;
       }
       __syncthreads();
-      const int rl = tid & 63, jg = tid >> 6;
-      for (int r = rl; r < r0; r += 64) {
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        const double* colr = Lkk + (int64_t)r * ld + r0;  // L[r0 + b][r], contiguous in b
-        for (int b = 0; b < bw; ++b) {
-          const double l = colr[b];
-          s0 += l * Ys[(jg * 4 + 0) * YLD + r0 + b];
-          s1 += l * Ys[(jg * 4 + 1) * YLD + r0 + b];
-          s2 += l * Ys[(jg * 4 + 2) * YLD + r0 + b];
-          s3 += l * Ys[(jg * 4 + 3) * YLD + r0 + b];
+      if (tid < 16) {
+        double y[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) y[a] = Ys[tid * YLD + r0 + a];
+#pragma unroll
+        for (int a = 15; a >= 0; --a) {
+          if (a < bw) {
+            double t = y[a];
+#pragma unroll
+            for (int b = a + 1; b < 16; ++b) t -= Ld[b * 17 + a] * y[b];
+            y[a] = t * Linv[r0 + a];
+          }
         }
-        Ys[(jg * 4 + 0) * YLD + r] -= s0;
-        Ys[(jg * 4 + 1) * YLD + r] -= s1;
-        Ys[(jg * 4 + 2) * YLD + r] -= s2;
-        Ys[(jg * 4 + 3) * YLD + r] -= s3;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) Ys[tid * YLD + r0 + a] = y[a];
+      }
+      __syncthreads();
+      // earlier row blocks: Y[rows] -= L[r0:r0+16, rows]^T X[r0:r0+16]
+      for (int ub = wave; ub < rb; ub += 4) {
+        const int rr = ub * 16;
+        d4 acc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int q = r0 + kk * 4 + lg;
+          const double fl = (q < m) ? Lkk[(int64_t)(rr + l16) * ld + imin(q, m - 1)] : 0.0;
+          const double fy = Ys[l16 * YLD + q];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl, fy, acc, 0, 0, 2 /* neg B */);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
       }
       __syncthreads();
     }
@@ -365,49 +571,89 @@ __device__ __forceinline__ void btrsv(const double* __restrict__ Lkk, int64_t ld
 }
 
 // B_i[rows] -= L_ik[rows, :] Y_k  (forward update), rows = a strip of <= 128.
-__device__ __forceinline__ void fgemv(const double* __restrict__ Lik, int64_t ld, double* Bi, const double* Yk, int64_t ldb,
-                      int rows, int mk, int nrhs, double* lds) {
+// Each wavefront owns two 16-row blocks of the strip; the L fragments are
+// read straight from HBM (16 consecutive rows of a column per lane group).
+__device__ __forceinline__ void fgemv(const double* __restrict__ Lik, int64_t ld, double* Bi, const double* Yk,
+                                      int64_t ldb, int rows, int mk, int nrhs, double* lds) {
   double* Ys = lds;
-  const int tid = threadIdx.x, r = tid & 127, jh = tid >> 7;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, lg = lane >> 4;
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
     stage_rhs(Ys, Yk, ldb, mk, j0, jn);
     __syncthreads();
-    if (r < rows) {
-      double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int c = 0; c < mk; ++c) {
-        const double l = Lik[(int64_t)c * ld + r];
+    d4 acc[2];
+    const int jc = imin(l16, jn - 1);
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) s[jj] += l * Ys[(jh * 8 + jj) * YLD + c];
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = (wave * 2 + t) * 16 + 4 * i + lg;
+        acc[t][i] = Bi[(int64_t)(j0 + jc) * ldb + imin(r, rows - 1)];
       }
+    const int ra = imin((wave * 2) * 16 + l16, rows - 1), rbb = imin((wave * 2 + 1) * 16 + l16, rows - 1);
+#pragma unroll 4
+    for (int k0 = 0; k0 < mk; k0 += 4) {
+      const int q = imin(k0 + lg, mk - 1);
+      const double f0 = Lik[(int64_t)q * ld + ra];
+      const double f1 = Lik[(int64_t)q * ld + rbb];
+      const double fy = (k0 + lg < mk) ? Ys[l16 * YLD + k0 + lg] : 0.0;
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0, fy, acc[0], 0, 0, 2 /* neg B */);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1, fy, acc[1], 0, 0, 2);
+    }
+    if (l16 < jn) {
 #pragma unroll
-      for (int jj = 0; jj < 8; ++jj)
-        if (jh * 8 + jj < jn) Bi[(int64_t)(j0 + jh * 8 + jj) * ldb + r] -= s[jj];
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = (wave * 2 + t) * 16 + 4 * i + lg;
+          if (r < rows) st_dev(Bi + (int64_t)(j0 + l16) * ldb + r, acc[t][i]);
+        }
     }
     __syncthreads();
   }
 }
 
 // Y_i[cols] -= L_ki[:, cols]^T X_k  (backward update), cols = a strip of <= 128.
-__device__ __forceinline__ void bgemv(const double* __restrict__ Lki, int64_t ld, double* Yi, const double* Xk, int64_t ldb,
-                      int cols, int mk, int nrhs, double* lds) {
+__device__ __forceinline__ void bgemv(const double* __restrict__ Lki, int64_t ld, double* Yi, const double* Xk,
+                                      int64_t ldb, int cols, int mk, int nrhs, double* lds) {
   double* Xs = lds;
-  const int tid = threadIdx.x, c = tid & 127, jh = tid >> 7;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, lg = lane >> 4;
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
     stage_rhs(Xs, Xk, ldb, mk, j0, jn);
     __syncthreads();
-    if (c < cols) {
-      double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      const double* colc = Lki + (int64_t)c * ld;
-      for (int r = 0; r < mk; ++r) {
-        const double l = colc[r];
+    d4 acc[2];
+    const int jc = imin(l16, jn - 1);
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) s[jj] += l * Xs[(jh * 8 + jj) * YLD + r];
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = (wave * 2 + t) * 16 + 4 * i + lg;
+        acc[t][i] = Yi[(int64_t)(j0 + jc) * ldb + imin(c, cols - 1)];
       }
+    const double* c0p = Lki + (int64_t)imin((wave * 2) * 16 + l16, cols - 1) * ld;
+    const double* c1p = Lki + (int64_t)imin((wave * 2 + 1) * 16 + l16, cols - 1) * ld;
+#pragma unroll 4
+    for (int k0 = 0; k0 < mk; k0 += 4) {
+      const int q = imin(k0 + lg, mk - 1);
+      const double f0 = c0p[q];
+      const double f1 = c1p[q];
+      const double fx = (k0 + lg < mk) ? Xs[l16 * YLD + k0 + lg] : 0.0;
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0, fx, acc[0], 0, 0, 2 /* neg B */);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1, fx, acc[1], 0, 0, 2);
+    }
+    if (l16 < jn) {
 #pragma unroll
-      for (int jj = 0; jj < 8; ++jj)
-        if (jh * 8 + jj < jn) Yi[(int64_t)(j0 + jh * 8 + jj) * ldb + c] -= s[jj];
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = (wave * 2 + t) * 16 + 4 * i + lg;
+          if (c < cols) st_dev(Yi + (int64_t)(j0 + l16) * ldb + c, acc[t][i]);
+        }
     }
     __syncthreads();
   }
@@ -550,12 +796,18 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         ok = 0;
         break;
     }
-    // make this work item's stores visible device-wide, then activate
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Publish, then activate.  Every global store of a work item is a
+    // device-scope store (st_dev), written through to the device's point of
+    // coherence; once each wavefront has seen its stores complete (vmcnt 0)
+    // the item's results are visible to any CU that invalidates its caches
+    // before reading them (the acquire after each wait).  This replaces an
+    // agent-scope release fence, whose L2 write-back costs tens of
+    // microseconds per work item on this part.
+    wait_vmcnt<0>();
     __syncthreads();
     if (wave == 0 && ok) {
       int prev = 0;
-      if (lane == 0) prev = __hip_atomic_fetch_add(&a.done[task], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) prev = __hip_atomic_fetch_add(&a.done[task], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       prev = uniform_i(prev);
       if (prev == uniform_i(d[4]) - 1) {
         const int e0 = uniform_i(d[5]), e1 = uniform_i(d[6]);

@@ -1,0 +1,103 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, and rejects invalid arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+tc = pytest.importorskip("paper_1402_6601_amd")
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tchol.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return tc.load()
+    except ImportError as e:
+        pytest.skip(str(e))
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:TCHOL_API\s+)?(?:const\s+)?\w+\s*\*?\s*(tchol_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ["tchol_factor", "tchol_solve", "tchol_workspace_bytes", "tchol_strerror", "tchol_factor_ex",
+                     "tchol_solve_ex", "tchol_plan_query", "tchol_version"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_internal_symbols_are_not_exported(lib):
+    for name in ["tchol_dev_launch", "tchol_dev_max_grid"]:
+        with pytest.raises(AttributeError):
+            getattr(lib, name)
+
+
+def test_workspace_bytes_validation(lib):
+    assert lib.tchol_workspace_bytes(7, 10, 16, 0) == -1
+    assert lib.tchol_workspace_bytes(0, -1, 16, 0) == -2
+    for nb in (0, 8, 24, 100, 528, 1024):
+        assert lib.tchol_workspace_bytes(0, 10, nb, 0) == -3
+    assert lib.tchol_workspace_bytes(1, 10, 16, -1) == -4
+    assert lib.tchol_workspace_bytes(0, 0, 16, 0) > 0
+    a = lib.tchol_workspace_bytes(0, 1024, 128, 0)
+    b = lib.tchol_workspace_bytes(0, 2048, 128, 0)
+    assert 0 < a < b and a % 256 == 0
+
+
+FAKE = ctypes.c_void_p(0x10000)       # never dereferenced: every call below fails validation first
+FAKE_MISALIGNED = ctypes.c_void_p(0x10008)
+
+
+def test_factor_validation_before_any_hip_call(lib):
+    need = lib.tchol_workspace_bytes(0, 256, 64, 0)
+    assert lib.tchol_factor(FAKE, -1, 64, FAKE, need, None) == -2
+    assert lib.tchol_factor(FAKE, 256, 40, FAKE, need, None) == -3
+    assert lib.tchol_factor(FAKE, 256, 8, FAKE, need, None) == -3
+    assert lib.tchol_factor(None, 0, 64, None, 0, None) == 0          # nothing to do
+    assert lib.tchol_factor(None, 256, 64, FAKE, need, None) == -1
+    assert lib.tchol_factor(FAKE, 256, 64, None, need, None) == -4
+    assert lib.tchol_factor(FAKE, 256, 64, FAKE, 0, None) == -5
+    assert lib.tchol_factor(FAKE, 256, 64, FAKE, need - 256, None) == -5   # too small
+    assert lib.tchol_factor(FAKE, 256, 64, FAKE_MISALIGNED, need, None) == -4
+
+
+def test_solve_validation_before_any_hip_call(lib):
+    need = lib.tchol_workspace_bytes(1, 256, 64, 4)
+    assert lib.tchol_solve(FAKE, -1, 64, FAKE, 4, FAKE, need, None) == -2
+    assert lib.tchol_solve(FAKE, 256, 12, FAKE, 4, FAKE, need, None) == -3
+    assert lib.tchol_solve(FAKE, 256, 64, FAKE, -1, FAKE, need, None) == -5
+    assert lib.tchol_solve(FAKE, 256, 64, FAKE, 0, FAKE, need, None) == 0
+    assert lib.tchol_solve(None, 256, 64, FAKE, 4, FAKE, need, None) == -1
+    assert lib.tchol_solve(FAKE, 256, 64, None, 4, FAKE, need, None) == -4
+    assert lib.tchol_solve(FAKE, 256, 64, FAKE, 4, None, need, None) == -6
+    assert lib.tchol_solve(FAKE, 256, 64, FAKE, 4, FAKE, 16, None) == -7
+    assert lib.tchol_solve(FAKE, 256, 64, FAKE, 4, FAKE_MISALIGNED, need, None) == -6
+
+
+def test_strerror_and_version(lib):
+    for code in (0, 5, -3, tc.E_HIP, tc.E_TIMEOUT, tc.E_UNSUPPORTED, tc.E_INTERNAL, -999):
+        assert isinstance(tc.strerror(code), str) and tc.strerror(code)
+    assert "gfx950" in tc.version()
+
+
+def test_plan_query_validation(lib):
+    with pytest.raises(tc.TcholError):
+        tc.plan_query(5, 100, 16)
+    with pytest.raises(tc.TcholError):
+        tc.plan_query(0, 100, 20)
+    with pytest.raises(tc.TcholError):
+        tc.plan_query(0, 100, 16, policy=9)
+
+
+def test_unsupported_size(lib):
+    assert lib.tchol_workspace_bytes(0, 16 * 2000, 16, 0) == tc.E_UNSUPPORTED

@@ -1,0 +1,248 @@
+"""Host planner: the tile DAG, its counters, ranks and claim order (no GPU).
+
+The DAG is checked against an independent derivation: the paper's runtime
+discovers dependencies from the data each task reads and writes (section 2,
+data-flow model).  Replaying the tile tasks in program order and linking
+each access to the last writer of that tile must give exactly the planner's
+edges.  The claim order must be topological for every policy, the upward
+ranks must satisfy their recurrence (section 3.1, HEFT's priority rule), and
+a host simulation of the workers' claim / wait / release protocol must
+finish and reproduce the oracle's factor bit for bit.
+"""
+import collections
+
+import numpy as np
+import pytest
+
+import spd_inputs
+from tests import tiled_ref
+
+tc = pytest.importorskip("paper_1402_6601_amd")
+
+POTRF, TRSM, SYRK, GEMM, FTRSV, FGEMV, BTRSV, BGEMV = range(8)
+WEIGHT = {POTRF: 1, TRSM: 3, SYRK: 3, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2}
+
+
+def plan(op, n, nb, policy=0, seed=0):
+    try:
+        return tc.plan_query(op, n, nb, policy, seed)
+    except ImportError as e:  # library not built
+        pytest.skip(str(e))
+
+
+def task_key(p, t):
+    return (int(p["kind"][t]), int(p["i"][t]), int(p["j"][t]), int(p["k"][t]))
+
+
+def edges(p):
+    out = set()
+    for t in range(p["ntask"]):
+        for e in range(p["succ_off"][t], p["succ_off"][t + 1]):
+            out.add((task_key(p, t), task_key(p, int(p["succ"][e]))))
+    return out
+
+
+def dataflow_edges_factor(T):
+    """Replay the right-looking tile algorithm in program order; an edge joins
+    each access to a tile with the last task that wrote that tile."""
+    last_writer = {}
+    out = set()
+
+    def access(task, reads, writes):
+        for tile in list(reads) + list(writes):
+            if tile in last_writer and last_writer[tile] != task:
+                out.add((last_writer[tile], task))
+        for tile in writes:
+            last_writer[tile] = task
+
+    for k in range(T):
+        access((POTRF, k, k, k), [(k, k)], [(k, k)])
+        for i in range(k + 1, T):
+            access((TRSM, i, k, k), [(k, k), (i, k)], [(i, k)])
+        for i in range(k + 1, T):
+            access((SYRK, i, i, k), [(i, k), (i, i)], [(i, i)])
+            for j in range(k + 1, i):
+                access((GEMM, i, j, k), [(i, k), (j, k), (i, j)], [(i, j)])
+    return out
+
+
+def dataflow_edges_solve(T):
+    """Same replay for the forward then backward block substitution; the
+    blocks of B and the final tiles of L are the data."""
+    last_writer = {}
+    out = set()
+
+    def access(task, reads, writes):
+        for blk in list(reads) + list(writes):
+            if blk in last_writer and last_writer[blk] != task:
+                out.add((last_writer[blk], task))
+        for blk in writes:
+            last_writer[blk] = task
+
+    for k in range(T):
+        access((FTRSV, k, k, k), [k], [k])
+        for i in range(k + 1, T):
+            access((FGEMV, i, k, k), [k, i], [i])
+    for k in range(T - 1, -1, -1):
+        access((BTRSV, k, k, k), [k], [k])
+        for i in range(k):
+            access((BGEMV, i, k, k), [k, i], [i])
+    # keep only edges that are not implied by a path (the planner lists
+    # direct dependencies; the replay can also link a block to an older reader)
+    succ = collections.defaultdict(set)
+    for a, b in out:
+        succ[a].add(b)
+
+    def reachable(a, b, skip_direct):
+        stack = [x for x in succ[a] if not (skip_direct and x == b)]
+        seen = set()
+        while stack:
+            x = stack.pop()
+            if x == b:
+                return True
+            if x in seen:
+                continue
+            seen.add(x)
+            stack.extend(succ[x])
+        return False
+
+    return {(a, b) for (a, b) in out if not reachable(a, b, True)}
+
+
+@pytest.mark.parametrize("n,nb", [(16, 16), (32, 16), (48, 16), (1024, 128), (1000, 128), (32768, 512)])
+def test_factor_counts_closed_forms(n, nb):
+    p = plan(0, n, nb)
+    T = -(-n // nb)
+    ngemm = T * (T - 1) * (T - 2) // 6
+    assert p["ntask"] == T + 2 * (T * (T - 1) // 2) + ngemm
+    assert p["nedge"] == 3 * T * (T - 1) // 2 + 3 * ngemm
+    assert int(np.sum(p["dep0"])) == p["nedge"]
+    assert p["critical_path"] == 3 * T - 2
+    kinds = collections.Counter(p["kind"].tolist())
+    assert kinds[POTRF] == T and kinds[TRSM] == T * (T - 1) // 2 == kinds[SYRK] and kinds[GEMM] == ngemm
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 5, 8])
+def test_factor_edges_equal_dataflow(T):
+    p = plan(0, 16 * T, 16)
+    assert edges(p) == dataflow_edges_factor(T)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 6])
+def test_solve_edges_equal_dataflow(T):
+    p = plan(1, 16 * T, 16)
+    assert edges(p) == dataflow_edges_solve(T)
+
+
+@pytest.mark.parametrize("op,n,nb", [(0, 1024, 128), (0, 1000, 128), (1, 1000, 128), (0, 4096, 512)])
+def test_ranks_follow_recurrence(op, n, nb):
+    p = plan(op, n, nb)
+    for t in range(p["ntask"]):
+        succ_ranks = [p["rank"][p["succ"][e]] for e in range(p["succ_off"][t], p["succ_off"][t + 1])]
+        assert p["rank"][t] == WEIGHT[int(p["kind"][t])] + (max(succ_ranks) if succ_ranks else 0)
+
+
+def check_topological(p):
+    nt = p["ntask"]
+    preds = [[] for _ in range(nt)]
+    for t in range(nt):
+        for e in range(p["succ_off"][t], p["succ_off"][t + 1]):
+            preds[p["succ"][e]].append(t)
+    first = {}
+    seen_parts = collections.defaultdict(list)
+    for idx, (t, q) in enumerate(zip(p["item_task"], p["item_part"])):
+        first.setdefault(int(t), idx)
+        seen_parts[int(t)].append(int(q))
+    assert len(first) == nt
+    for t in range(nt):
+        assert seen_parts[t] == list(range(p["parts"][t]))  # parts consecutive, in order
+        for s in preds[t]:
+            assert first[s] < first[t]
+
+
+@pytest.mark.parametrize("policy,seed", [(0, 0), (1, 0), (2, 1), (2, 7)])
+@pytest.mark.parametrize("op,n,nb", [(0, 1024, 128), (0, 1000, 96), (1, 1000, 128)])
+def test_claim_order_is_topological(policy, seed, op, n, nb):
+    check_topological(plan(op, n, nb, policy, seed))
+
+
+def test_rank_order_ties_are_deterministic():
+    a = plan(0, 2048, 128)
+    b = plan(0, 2048, 128)
+    assert np.array_equal(a["item_task"], b["item_task"])
+    # decreasing rank along the claim order
+    r = a["rank"][a["item_task"]]
+    assert np.all(np.diff(r) <= 0)
+
+
+def test_random_policy_depends_on_seed():
+    a = plan(0, 1024, 128, 2, 1)
+    b = plan(0, 1024, 128, 2, 2)
+    assert not np.array_equal(a["item_task"], b["item_task"])
+
+
+def simulate(p, A, n, nb, workers=8, spin_limit=10_000, corrupt=None):
+    """Host model of the device protocol: workers claim tickets in order, wait
+    until the task's counter is zero, run the item, and the last item of a
+    task decrements its successors' counters.  Each tile task is applied once,
+    when its last item completes.  Returns (A, status)."""
+    dep = p["dep0"].astype(np.int64).copy()
+    if corrupt is not None:
+        dep[corrupt] += 1
+    done = np.zeros(p["ntask"], dtype=np.int64)
+    ticket = 0
+    held = [None] * workers
+    spins = [0] * workers
+    nitem = p["nitem"]
+    finished = 0
+    rng = np.random.default_rng(0)
+    while finished < nitem:
+        progressed = False
+        for w in rng.permutation(workers):
+            if held[w] is None:
+                if ticket >= nitem:
+                    continue
+                held[w] = ticket
+                ticket += 1
+                spins[w] = 0
+            t = int(p["item_task"][held[w]])
+            if dep[t] != 0:
+                spins[w] += 1
+                if spins[w] > spin_limit:
+                    return A, "timeout"
+                continue
+            done[t] += 1
+            if done[t] == p["parts"][t]:
+                kind, i, j, k = task_key(p, t)
+                tiled_ref.run_task(A, n, nb, kind, i, j, k)
+                for e in range(p["succ_off"][t], p["succ_off"][t + 1]):
+                    dep[p["succ"][e]] -= 1
+            held[w] = None
+            finished += 1
+            progressed = True
+        if not progressed and all(h is None for h in held) and ticket >= nitem:
+            break
+    return A, "ok"
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2])
+@pytest.mark.parametrize("n,nb", [(64, 16), (80, 16)])
+def test_simulated_protocol_matches_oracle_bitwise(oracle_lib, policy, n, nb):
+    A, _ = spd_inputs.spd_matrix(n, seed=n + policy)
+    p = plan(0, n, nb, policy, 3)
+    L, status = simulate(p, np.array(A), n, nb)
+    assert status == "ok"
+    F, info = oracle_lib.potrf(A)
+    assert info == 0
+    assert np.array_equal(np.tril(L), np.tril(F))
+
+
+def test_simulated_protocol_times_out_on_a_corrupted_counter():
+    n, nb = 64, 16
+    A, _ = spd_inputs.spd_matrix(n, seed=1)
+    p = plan(0, n, nb)
+    # one extra count on the last POTRF: it can never become ready, the
+    # bounded wait must turn that into a timeout instead of spinning forever
+    victim = int(np.where((p["kind"] == POTRF) & (p["k"] == 3))[0][0])
+    _, status = simulate(p, np.array(A), n, nb, corrupt=victim, spin_limit=2000)
+    assert status == "timeout"
