@@ -88,20 +88,27 @@ __device__ __forceinline__ void wait_vmcnt() {
 // stored).  With lower_only, entries of C above its diagonal are untouched.
 // With Cl set, the result goes to LDS at Cl (column-major, leading dimension
 // ldl; it must not overlap the NST stages) instead of back to C.
-template <int BM, int BN, int KC, int WGM, int NST>
+template <int BM, int BN, int KC, int WGM, int NST, int PAD = 8>
 __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* __restrict__ Ap,
                                           const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
                                           bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0) {
   constexpr int WGN = 4 / WGM;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int RB = WTM / 16, CB = WTN / 16;
-  constexpr int STAGE = KC * (BM + BN);                       // doubles per stage
+  // LDS rows of the staged panels (one k index each) are padded so that the
+  // four lane groups of a fragment read hit different banks
+  constexpr int ALD = BM + PAD, BLD = BN + PAD;
+  constexpr int STAGE = KC * (ALD + BLD);                     // doubles per stage
   constexpr int QA16 = KC * BM / 128, QB16 = KC * BN / 128;   // 1 KB transfers per stage
   constexpr int QA4 = KC * BM / 32, QB4 = KC * BN / 32;       // 256 B transfers per stage
   constexpr int J16 = (QA16 + QB16 + 3) / 4, J4 = (QA4 + QB4 + 3) / 4;  // transfer slots per wavefront
   constexpr int W16 = (QA16 + QB16) / 4, W4 = (QA4 + QB4) / 4;            // fewest transfers per wavefront
   static_assert(QA16 * 128 == KC * BM && QB16 * 128 == KC * BN, "stage must be whole 1 KB segments");
+  static_assert(BM % 128 == 0 || 128 % BM == 0, "a 1 KB segment must cover whole rows or a row part");
+  static_assert(BN % 128 == 0 || 128 % BN == 0, "a 1 KB segment must cover whole rows or a row part");
+  static_assert(PAD == 0 || (BM % 128 == 0 && BN % 128 == 0), "padded rows need segments that stay within a row");
   static_assert(W16 >= 1 && W4 >= 1, "every wavefront must issue transfers for every chunk");
+  static_assert(NST * STAGE <= LDS_DOUBLES, "stages must fit the workgroup LDS");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WGN, wn = wave % WGN;
@@ -126,20 +133,23 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
   // (rows past M or N are clamped to the last valid ones, whose copies only
   // feed outputs that are never stored), so the number of transfers still in
   // flight behind a chunk is known and the wait below can be exact.
+  // A segment (one transfer of a wavefront) covers consecutive doubles of the
+  // column-major panel: part of one k row, or whole k rows when the row is
+  // shorter than the segment (then the rows are unpadded and contiguous).
   auto issue = [&](int ch) {
     double* As = lds + (ch % NST) * STAGE;
-    double* Bs = As + KC * BM;
+    double* Bs = As + KC * ALD;
     const int k0 = ch * KC;
     if (fast) {
 #pragma unroll
       for (int j = 0; j < J16; ++j) {
         const int q = wave + 4 * j;
         if (q < QA16) {
-          const int e = q * 128 + 2 * lane, c = e / BM, r = imin(e % BM, M - 2);
-          dma16(Ap + (int64_t)(k0 + c) * ld + r, As + q * 128);
+          const int e0 = q * 128, e = e0 + 2 * lane, c = e / BM, r = imin(e % BM, M - 2);
+          dma16(Ap + (int64_t)(k0 + c) * ld + r, As + (e0 / BM) * ALD + e0 % BM);
         } else if (q < QA16 + QB16) {
-          const int e = (q - QA16) * 128 + 2 * lane, c = e / BN, r = imin(e % BN, N - 2);
-          dma16(Bp + (int64_t)(k0 + c) * ld + r, Bs + (q - QA16) * 128);
+          const int e0 = (q - QA16) * 128, e = e0 + 2 * lane, c = e / BN, r = imin(e % BN, N - 2);
+          dma16(Bp + (int64_t)(k0 + c) * ld + r, Bs + (e0 / BN) * BLD + e0 % BN);
         }
       }
     } else {
@@ -147,11 +157,13 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
       for (int j = 0; j < J4; ++j) {
         const int q = wave + 4 * j;
         if (q < QA4) {
-          const int e = q * 32 + (lane >> 1), c = e / BM, r = imin(e % BM, M - 1);
-          dma4(reinterpret_cast<const float*>(Ap + (int64_t)(k0 + c) * ld + r) + (lane & 1), As + q * 32);
+          const int e0 = q * 32, e = e0 + (lane >> 1), c = e / BM, r = imin(e % BM, M - 1);
+          dma4(reinterpret_cast<const float*>(Ap + (int64_t)(k0 + c) * ld + r) + (lane & 1),
+               As + (e0 / BM) * ALD + e0 % BM);
         } else if (q < QA4 + QB4) {
-          const int e = (q - QA4) * 32 + (lane >> 1), c = e / BN, r = imin(e % BN, N - 1);
-          dma4(reinterpret_cast<const float*>(Bp + (int64_t)(k0 + c) * ld + r) + (lane & 1), Bs + (q - QA4) * 32);
+          const int e0 = (q - QA4) * 32, e = e0 + (lane >> 1), c = e / BN, r = imin(e % BN, N - 1);
+          dma4(reinterpret_cast<const float*>(Bp + (int64_t)(k0 + c) * ld + r) + (lane & 1),
+               Bs + (e0 / BN) * BLD + e0 % BN);
         }
       }
     }
@@ -179,19 +191,28 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
     __syncthreads();
     if (ch + NST - 1 < nch) issue(ch + NST - 1);
     const double* as = lds + (ch % NST) * STAGE;
-    const double* bs = as + KC * BM;
+    const double* bs = as + KC * ALD;
+    // fragments of k-step ks + 1 are read while the MFMAs of ks run
+    double fa[2][RB], fb[2][CB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) fa[0][rb] = as[lg * ALD + wm * WTM + rb * 16 + l16];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) fb[0][cb] = bs[lg * BLD + wn * WTN + cb * 16 + l16];
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
-      double fa[RB], fb[CB];
+      const int cur = ks & 1, nxt = cur ^ 1;
+      if (ks + 1 < KC / 4) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) fa[rb] = as[(ks * 4 + lg) * BM + wm * WTM + rb * 16 + l16];
+        for (int rb = 0; rb < RB; ++rb) fa[nxt][rb] = as[((ks + 1) * 4 + lg) * ALD + wm * WTM + rb * 16 + l16];
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) fb[cb] = bs[(ks * 4 + lg) * BN + wn * WTN + cb * 16 + l16];
+        for (int cb = 0; cb < CB; ++cb) fb[nxt][cb] = bs[((ks + 1) * 4 + lg) * BLD + wn * WTN + cb * 16 + l16];
+      }
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[cb], fa[rb], acc[rb][cb], 0, 0, 2 /* neg B */);
+          acc[rb][cb] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(fb[cur][cb], fa[cur][rb], acc[rb][cb], 0, 0, 2 /* neg B */);
     }
   }
   __syncthreads();  // every wavefront is done with the stages before LDS is reused
@@ -251,7 +272,7 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
     if (c0 > 0) {
       // P - L[c0:, 0:c0] L[c0:c0+w, 0:c0]^T into LDS, in (at most two) slabs of 256 rows
       for (int s0 = 0; s0 < R; s0 += 256) {
-        gemm_core<256, PW, 8, 4, 4>(P + s0, Akk + c0 + s0, Akk + c0, ld, imin(256, R - s0), w, c0, false, lds,
+        gemm_core<256, PW, 8, 4, 4, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, imin(256, R - s0), w, c0, false, lds,
                                     Ps + s0, PPLD);
         __syncthreads();
       }
@@ -484,21 +505,38 @@ __device__ __forceinline__ void ftrsv(const double* __restrict__ Lkk, int64_t ld
         for (int a = 0; a < 16; ++a) Ys[tid * YLD + r0 + a] = y[a];
       }
       __syncthreads();
-      // later row blocks: Y[rows] -= L[rows, r0:r0+16] Y[r0:r0+16]
-      for (int ub = rb + 1 + wave; ub < nblk; ub += 4) {
-        const int rr = ub * 16;
-        d4 acc;
+      // later row blocks: Y[rows] -= L[rows, r0:r0+16] Y[r0:r0+16].  A wave
+      // owns row blocks rb + 1 + wave + 4t; all its L fragments are requested
+      // at once so that their latency is paid once per block row.
+      {
+        double fl[8][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
+        for (int t = 0; t < 8; ++t) {
+          const int rr = imin((rb + 1 + wave + 4 * t) * 16 + l16, m - 1);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int q = r0 + kk * 4 + lg;
-          const double fl = (q < m) ? Lkk[(int64_t)imin(q, m - 1) * ld + imin(rr + l16, m - 1)] : 0.0;
-          const double fy = Ys[l16 * YLD + q];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl, fy, acc, 0, 0, 2 /* neg B */);
+          for (int kk = 0; kk < 4; ++kk) {
+            const int q = r0 + kk * 4 + lg;
+            const double v = Lkk[(int64_t)imin(q, m - 1) * ld + rr];
+            fl[t][kk] = (q < m) ? v : 0.0;
+          }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
+        for (int t = 0; t < 8; ++t) {
+          const int ub = rb + 1 + wave + 4 * t;
+          if (ub < nblk) {
+            const int rr = ub * 16;
+            d4 acc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              const double fy = Ys[l16 * YLD + r0 + kk * 4 + lg];
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], fy, acc, 0, 0, 2 /* neg B */);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
+          }
+        }
       }
       __syncthreads();
     }
@@ -547,21 +585,37 @@ __device__ __forceinline__ void btrsv(const double* __restrict__ Lkk, int64_t ld
         for (int a = 0; a < 16; ++a) Ys[tid * YLD + r0 + a] = y[a];
       }
       __syncthreads();
-      // earlier row blocks: Y[rows] -= L[r0:r0+16, rows]^T X[r0:r0+16]
-      for (int ub = wave; ub < rb; ub += 4) {
-        const int rr = ub * 16;
-        d4 acc;
+      // earlier row blocks: Y[rows] -= L[r0:r0+16, rows]^T X[r0:r0+16], the
+      // wave's L fragments requested at once as above
+      {
+        double fl[8][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
+        for (int t = 0; t < 8; ++t) {
+          const int cc = imin((wave + 4 * t) * 16 + l16, m - 1);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int q = r0 + kk * 4 + lg;
-          const double fl = (q < m) ? Lkk[(int64_t)(rr + l16) * ld + imin(q, m - 1)] : 0.0;
-          const double fy = Ys[l16 * YLD + q];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl, fy, acc, 0, 0, 2 /* neg B */);
+          for (int kk = 0; kk < 4; ++kk) {
+            const int q = r0 + kk * 4 + lg;
+            const double v = Lkk[(int64_t)cc * ld + imin(q, m - 1)];
+            fl[t][kk] = (q < m) ? v : 0.0;
+          }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
+        for (int t = 0; t < 8; ++t) {
+          const int ub = wave + 4 * t;
+          if (ub < rb) {
+            const int rr = ub * 16;
+            d4 acc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              const double fy = Ys[l16 * YLD + r0 + kk * 4 + lg];
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], fy, acc, 0, 0, 2 /* neg B */);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
+          }
+        }
       }
       __syncthreads();
     }
@@ -593,14 +647,23 @@ __device__ __forceinline__ void fgemv(const double* __restrict__ Lik, int64_t ld
         acc[t][i] = Bi[(int64_t)(j0 + jc) * ldb + imin(r, rows - 1)];
       }
     const int ra = imin((wave * 2) * 16 + l16, rows - 1), rbb = imin((wave * 2 + 1) * 16 + l16, rows - 1);
-#pragma unroll 4
-    for (int k0 = 0; k0 < mk; k0 += 4) {
-      const int q = imin(k0 + lg, mk - 1);
-      const double f0 = Lik[(int64_t)q * ld + ra];
-      const double f1 = Lik[(int64_t)q * ld + rbb];
-      const double fy = (k0 + lg < mk) ? Ys[l16 * YLD + k0 + lg] : 0.0;
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0, fy, acc[0], 0, 0, 2 /* neg B */);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1, fy, acc[1], 0, 0, 2);
+    // K in batches of 32: the batch's 16 L fragments are requested together
+    // (this update streams L from HBM; it needs many loads in flight)
+    for (int kb = 0; kb < mk; kb += 32) {
+      double f0[8], f1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = imin(kb + 4 * u + lg, mk - 1);
+        f0[u] = Lik[(int64_t)q * ld + ra];
+        f1[u] = Lik[(int64_t)q * ld + rbb];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = kb + 4 * u + lg;
+        const double fy = (k < mk) ? Ys[l16 * YLD + imin(k, 511)] : 0.0;
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[u], fy, acc[0], 0, 0, 2 /* neg B */);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[u], fy, acc[1], 0, 0, 2);
+      }
     }
     if (l16 < jn) {
 #pragma unroll
@@ -637,14 +700,21 @@ __device__ __forceinline__ void bgemv(const double* __restrict__ Lki, int64_t ld
       }
     const double* c0p = Lki + (int64_t)imin((wave * 2) * 16 + l16, cols - 1) * ld;
     const double* c1p = Lki + (int64_t)imin((wave * 2 + 1) * 16 + l16, cols - 1) * ld;
-#pragma unroll 4
-    for (int k0 = 0; k0 < mk; k0 += 4) {
-      const int q = imin(k0 + lg, mk - 1);
-      const double f0 = c0p[q];
-      const double f1 = c1p[q];
-      const double fx = (k0 + lg < mk) ? Xs[l16 * YLD + k0 + lg] : 0.0;
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0, fx, acc[0], 0, 0, 2 /* neg B */);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1, fx, acc[1], 0, 0, 2);
+    for (int kb = 0; kb < mk; kb += 32) {
+      double f0[8], f1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = imin(kb + 4 * u + lg, mk - 1);
+        f0[u] = c0p[q];
+        f1[u] = c1p[q];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = kb + 4 * u + lg;
+        const double fx = (k < mk) ? Xs[l16 * YLD + imin(k, 511)] : 0.0;
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[u], fx, acc[0], 0, 0, 2 /* neg B */);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[u], fx, acc[1], 0, 0, 2);
+      }
     }
     if (l16 < jn) {
 #pragma unroll
