@@ -233,11 +233,16 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
       }
 }
 
-// GEMM / SYRK work item: a 128 x 128 sub-tile of C, K = nb.
+// GEMM / SYRK work item: a 128 x 128 sub-tile of C, K = nb.  Chunks of 32
+// columns through two stages need half the workgroup barriers of chunks of
+// 16 through four; a K that is only a multiple of 16 takes the latter.
 #define GB 128
 __device__ __forceinline__ void gemm_nt(double* C, const double* Ap, const double* Bp, int64_t ld, int M, int N,
                                         int K, bool lower_only, double* lds) {
-  gemm_core<GB, GB, 16, 2, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+  if (K % 32 == 0)
+    gemm_core<GB, GB, 32, 2, 2>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+  else
+    gemm_core<GB, GB, 16, 2, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
 }
 
 // ---------------------------------------------------------------------------
