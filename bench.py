@@ -81,13 +81,15 @@ def sampled_reconstruction(torch, W, A0, n, count=64, seed=123):
 
 
 def run_calib_copy(nbytes: int, reps: int):
-    """A plain device copy of known size, to scale the PMC byte counters."""
+    """A plain elementwise copy kernel (b = a * 1) that reads and writes
+    nbytes each, to scale the PMC byte counters (a same-dtype copy_ may be
+    served by a DMA engine that the counters do not see)."""
     import torch
     n = nbytes // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(reps):
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(json.dumps({"calib_copy_bytes": n * 8, "reps": reps}), flush=True)
 

@@ -18,8 +18,12 @@ ARCH = os.environ.get("TCHOL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["tchol_device.hip", "tchol_api.cpp", "plan.cpp"]
 
-# Packed FP32 instructions are disabled for all device code.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions are disabled for all device code.  Matrix-core
+# accumulators are allocated in ordinary vector registers: with the default
+# (accumulation registers) the compiler copies every loop-carried
+# accumulator between the two register files on each K chunk.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def hipcc() -> str:

@@ -8,9 +8,13 @@
 #define HDR_TICKET 0   /* next ticket to hand out                          */
 #define HDR_ABORT 1    /* non-zero: every worker stops                      */
 #define HDR_INFO 2     /* first failing pivot column (1-based), 0 if none   */
-#define HDR_ERROR 3    /* runtime error code (TCHOL_E_TIMEOUT)              */
+#define HDR_ERROR 3    /* DEV_ERR_* code of the first runtime error, 0 if none */
 #define HDR_DONE 4     /* work items completed                              */
 #define HDR_WORDS 64   /* 256 bytes                                         */
+
+/* runtime error codes in HDR_ERROR */
+#define DEV_ERR_TIMEOUT 1 /* a dependency wait exceeded its bound                  */
+#define DEV_ERR_LAYOUT 2  /* a work item violated the launch's alignment contract  */
 
 typedef struct KArgs {
   double *A;            /* factor: in/out matrix; solve: the factor L (read only) */

@@ -202,8 +202,10 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   if (e != hipSuccess) return TCHOL_E_HIP;
-  if (hdr[HDR_ERROR] != 0)
+  if (hdr[HDR_ERROR] == DEV_ERR_TIMEOUT)
     rc = TCHOL_E_TIMEOUT;
+  else if (hdr[HDR_ERROR] != 0)
+    rc = TCHOL_E_INTERNAL;
   else if (hdr[HDR_INFO] > 0)
     rc = hdr[HDR_INFO];
   else if (hdr[HDR_DONE] != a.nitem)

@@ -79,133 +79,113 @@ __device__ __forceinline__ void wait_vmcnt() {
 // Matrix-core tile product used by every update:
 //     C[M x N] -= Ap[M x K] * Bp[N x K]^T,   M <= BM, N <= BN, K % KC == 0.
 // The four wavefronts form a WGM x (4/WGM) grid; each owns a (BM/WGM) x
-// (BN*WGM/4) piece of C as 16x16 MFMA blocks held in accumulator registers
-// from the load of C to the final store.  K is streamed in chunks of KC
+// (BN*WGM/4) piece of C as 16x16 MFMA blocks held in registers from the load
+// of C to the final store.  K is streamed in chunks of KC
 // columns through NST LDS stages filled by direct-to-LDS loads, NST-1 chunks
-// ahead of the matrix cores.  Full, 16-byte aligned panels use 16-byte
-// transfers; ragged ones use 4-byte transfers with row indices clamped into
-// the panel (rows past M hold copies and only feed outputs that are never
-// stored).  With lower_only, entries of C above its diagonal are untouched.
+// ahead of the matrix cores.  SEG = 128 moves 16 bytes per lane and needs
+// even M and N, even ld and 16-byte aligned panels; SEG = 32 moves 4 bytes
+// per lane and has no such needs.  Row indices are clamped into the panel
+// (rows past M hold copies and only feed outputs that are never stored).  With lower_only, entries of C above its diagonal are untouched.
 // With Cl set, the result goes to LDS at Cl (column-major, leading dimension
 // ldl; it must not overlap the NST stages) instead of back to C.
-template <int BM, int BN, int KC, int WGM, int NST, int PAD = 8>
-__device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* __restrict__ Ap,
-                                          const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
-                                          bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0) {
-  constexpr int WGN = 4 / WGM;
-  constexpr int WTM = BM / WGM, WTN = BN / WGN;
-  constexpr int RB = WTM / 16, CB = WTN / 16;
-  // LDS rows of the staged panels (one k index each) are padded so that the
-  // four lane groups of a fragment read hit different banks
-  constexpr int ALD = BM + PAD, BLD = BN + PAD;
-  constexpr int STAGE = KC * (ALD + BLD);                     // doubles per stage
-  constexpr int QA16 = KC * BM / 128, QB16 = KC * BN / 128;   // 1 KB transfers per stage
-  constexpr int QA4 = KC * BM / 32, QB4 = KC * BN / 32;       // 256 B transfers per stage
-  constexpr int J16 = (QA16 + QB16 + 3) / 4, J4 = (QA4 + QB4 + 3) / 4;  // transfer slots per wavefront
-  constexpr int W16 = (QA16 + QB16) / 4, W4 = (QA4 + QB4) / 4;            // fewest transfers per wavefront
-  static_assert(QA16 * 128 == KC * BM && QB16 * 128 == KC * BN, "stage must be whole 1 KB segments");
+//
+// The chunk loop is kept free of branches in its steady state (the transfer
+// width is fixed per kernel instance, a transfer slot's panel is known at
+// compile time, and the last NST-1 chunks are peeled off), so that the
+// accumulators stay in the matrix-core registers across chunks.
+template <int BM, int BN, int KC, int WGM, int NST, int PAD>
+struct GemmShape {
+  static constexpr int WGN = 4 / WGM;
+  static constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  static constexpr int RB = WTM / 16, CB = WTN / 16;
+  // LDS rows of the staged panels (one k index each) may be padded
+  static constexpr int ALD = BM + PAD, BLD = BN + PAD;
+  static constexpr int STAGE = KC * (ALD + BLD);  // doubles per stage
+  static_assert(NST * STAGE <= LDS_DOUBLES, "stages must fit the workgroup LDS");
   static_assert(BM % 128 == 0 || 128 % BM == 0, "a 1 KB segment must cover whole rows or a row part");
   static_assert(BN % 128 == 0 || 128 % BN == 0, "a 1 KB segment must cover whole rows or a row part");
   static_assert(PAD == 0 || (BM % 128 == 0 && BN % 128 == 0), "padded rows need segments that stay within a row");
-  static_assert(W16 >= 1 && W4 >= 1, "every wavefront must issue transfers for every chunk");
-  static_assert(NST * STAGE <= LDS_DOUBLES, "stages must fit the workgroup LDS");
+};
+
+// K loop with SEG-double transfers per wavefront instruction (128: 16-byte
+// lanes, 32: 4-byte lanes).
+template <int BM, int BN, int KC, int WGM, int NST, int PAD, int SEG, int RB, int CB>
+__device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __restrict__ Ap,
+                                           const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
+                                           double* lds) {
+  using S = GemmShape<BM, BN, KC, WGM, NST, PAD>;
+  static_assert(RB == S::RB && CB == S::CB, "accumulator shape");
+  constexpr int ALD = S::ALD, BLD = S::BLD, STAGE = S::STAGE;
+  constexpr int QA = KC * BM / SEG, QB = KC * BN / SEG;  // transfers per stage
+  static_assert(QA * SEG == KC * BM && QB * SEG == KC * BN, "stage must be whole segments");
+  // When both counts divide by four, transfer slot j of every wavefront
+  // serves the same panel and every wavefront issues the same number.
+  constexpr bool UNIFORM = (QA % 4 == 0) && (QB % 4 == 0);
+  constexpr int J = (QA + QB + 3) / 4;  // transfer slots per wavefront
+  constexpr int W = (QA + QB) / 4;      // fewest transfers per wavefront and chunk
+  static_assert(W >= 1, "every wavefront must issue transfers for every chunk");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave / WGN, wn = wave % WGN;
+  const int wm = wave / S::WGN, wn = wave % S::WGN;
   const int l16 = lane & 15, lg = lane >> 4;
-  // 16-byte transfers need even row counts (a transfer covers rows r, r + 1)
-  // and 16-byte aligned columns; otherwise 4-byte transfers are used.
-  const bool fast = ((M & 1) == 0) && ((N & 1) == 0) && (ld % 2 == 0) &&
-                    ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) % 16 == 0);
 
-  d4 acc[RB][CB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = wm * WTM + rb * 16 + l16, col = wn * WTN + cb * 16 + 4 * i + lg;
-        acc[rb][cb][i] = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
-      }
-
-  // Every wavefront issues the same number of transfers for every chunk
-  // (rows past M or N are clamped to the last valid ones, whose copies only
-  // feed outputs that are never stored), so the number of transfers still in
-  // flight behind a chunk is known and the wait below can be exact.
-  // A segment (one transfer of a wavefront) covers consecutive doubles of the
-  // column-major panel: part of one k row, or whole k rows when the row is
-  // shorter than the segment (then the rows are unpadded and contiguous).
-  auto issue = [&](int ch) {
+  // One transfer: segment q of panel X (rows R = BM or BN, valid rows V) of
+  // chunk ch.  A segment covers consecutive doubles of the column-major
+  // panel: part of one k row, or whole k rows when the row is shorter than
+  // the segment (then the rows are unpadded and contiguous).  Each 16-byte
+  // lane moves rows (r, r + 1); each 4-byte lane half of one double.
+  auto xfer = [&](const double* X, int R, int XLD, int V, int q, int k0, double* dst) __attribute__((always_inline)) {
+    const int e0 = q * SEG;
+    const int e = e0 + (SEG == 128 ? 2 * lane : (lane >> 1));
+    const int c = e / R;
+    const double* src;
+    if (SEG == 128) {
+      src = X + (int64_t)(k0 + c) * ld + imin(e % R, V - 2);
+      dma16(src, dst + (e0 / R) * XLD + e0 % R);
+    } else {
+      src = X + (int64_t)(k0 + c) * ld + imin(e % R, V - 1);
+      dma4(reinterpret_cast<const float*>(src) + (lane & 1), dst + (e0 / R) * XLD + e0 % R);
+    }
+  };
+  auto slot = [&](int j, int k0, double* As, double* Bs) __attribute__((always_inline)) {
+    const int q = wave + 4 * j;
+    if (UNIFORM) {
+      if (j < QA / 4) xfer(Ap, BM, ALD, M, q, k0, As);
+      else xfer(Bp, BN, BLD, N, q - QA, k0, Bs);
+    } else {
+      if (q < QA) xfer(Ap, BM, ALD, M, q, k0, As);
+      else if (q < QA + QB) xfer(Bp, BN, BLD, N, q - QA, k0, Bs);
+    }
+  };
+  auto issue = [&](int ch) __attribute__((always_inline)) {
     double* As = lds + (ch % NST) * STAGE;
     double* Bs = As + KC * ALD;
     const int k0 = ch * KC;
-    if (fast) {
+    if constexpr (SEG == 128) {
 #pragma unroll
-      for (int j = 0; j < J16; ++j) {
-        const int q = wave + 4 * j;
-        if (q < QA16) {
-          const int e0 = q * 128, e = e0 + 2 * lane, c = e / BM, r = imin(e % BM, M - 2);
-          dma16(Ap + (int64_t)(k0 + c) * ld + r, As + (e0 / BM) * ALD + e0 % BM);
-        } else if (q < QA16 + QB16) {
-          const int e0 = (q - QA16) * 128, e = e0 + 2 * lane, c = e / BN, r = imin(e % BN, N - 2);
-          dma16(Bp + (int64_t)(k0 + c) * ld + r, Bs + (e0 / BN) * BLD + e0 % BN);
-        }
-      }
-    } else {
-#pragma unroll 4
-      for (int j = 0; j < J4; ++j) {
-        const int q = wave + 4 * j;
-        if (q < QA4) {
-          const int e0 = q * 32, e = e0 + (lane >> 1), c = e / BM, r = imin(e % BM, M - 1);
-          dma4(reinterpret_cast<const float*>(Ap + (int64_t)(k0 + c) * ld + r) + (lane & 1),
-               As + (e0 / BM) * ALD + e0 % BM);
-        } else if (q < QA4 + QB4) {
-          const int e0 = (q - QA4) * 32, e = e0 + (lane >> 1), c = e / BN, r = imin(e % BN, N - 1);
-          dma4(reinterpret_cast<const float*>(Bp + (int64_t)(k0 + c) * ld + r) + (lane & 1),
-               Bs + (e0 / BN) * BLD + e0 % BN);
-        }
-      }
+      for (int j = 0; j < J; ++j) slot(j, k0, As, Bs);
+    } else {  // many narrow transfers: a rolled loop keeps their addresses out of registers
+#pragma unroll 2
+      for (int j = 0; j < J; ++j) slot(j, k0, As, Bs);
     }
   };
-
-  const int nch = K / KC;
-#pragma unroll
-  for (int p = 0; p < NST - 1; ++p)
-    if (p < nch) issue(p);
-  for (int ch = 0; ch < nch; ++ch) {
-    // Chunk ch has landed once no more than the later chunks' transfers are
-    // outstanding.  A wavefront issues W or W + 1 transfers per chunk; waiting
-    // for "at most W per later chunk" (capped at the counter's range) is
-    // exact or stricter, never short.
-    const int later = imin(nch - 1 - ch, NST - 2);
-    if (fast) {
-      if (later >= 2) wait_vmcnt<imin_c(2 * W16, 63)>();
-      else if (later == 1) wait_vmcnt<imin_c(W16, 63)>();
-      else wait_vmcnt<0>();
-    } else {
-      if (later >= 2) wait_vmcnt<imin_c(2 * W4, 63)>();
-      else if (later == 1) wait_vmcnt<imin_c(W4, 63)>();
-      else wait_vmcnt<0>();
-    }
-    __syncthreads();
-    if (ch + NST - 1 < nch) issue(ch + NST - 1);
+  auto compute = [&](int ch) __attribute__((always_inline)) {
     const double* as = lds + (ch % NST) * STAGE;
     const double* bs = as + KC * ALD;
     // fragments of k-step ks + 1 are read while the MFMAs of ks run
     double fa[2][RB], fb[2][CB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) fa[0][rb] = as[lg * ALD + wm * WTM + rb * 16 + l16];
+    for (int rb = 0; rb < RB; ++rb) fa[0][rb] = as[lg * ALD + wm * S::WTM + rb * 16 + l16];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) fb[0][cb] = bs[lg * BLD + wn * WTN + cb * 16 + l16];
+    for (int cb = 0; cb < CB; ++cb) fb[0][cb] = bs[lg * BLD + wn * S::WTN + cb * 16 + l16];
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int cur = ks & 1, nxt = cur ^ 1;
       if (ks + 1 < KC / 4) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) fa[nxt][rb] = as[((ks + 1) * 4 + lg) * ALD + wm * WTM + rb * 16 + l16];
+        for (int rb = 0; rb < RB; ++rb) fa[nxt][rb] = as[((ks + 1) * 4 + lg) * ALD + wm * S::WTM + rb * 16 + l16];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) fb[nxt][cb] = bs[((ks + 1) * 4 + lg) * BLD + wn * WTN + cb * 16 + l16];
+        for (int cb = 0; cb < CB; ++cb) fb[nxt][cb] = bs[((ks + 1) * 4 + lg) * BLD + wn * S::WTN + cb * 16 + l16];
       }
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -214,7 +194,56 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
           acc[rb][cb] =
               __builtin_amdgcn_mfma_f64_16x16x4f64(fb[cur][cb], fa[cur][rb], acc[rb][cb], 0, 0, 2 /* neg B */);
     }
+  };
+
+  // Chunk ch has landed once no more than the later chunks' transfers are
+  // outstanding.  A wavefront issues W (or, when not UNIFORM, W + 1)
+  // transfers per chunk; waiting for "at most W per later chunk" (capped at
+  // the counter's range) is exact or stricter, never short.
+  const int nch = K / KC;
+#pragma unroll
+  for (int p = 0; p < NST - 1; ++p)
+    if (p < nch) issue(p);
+  int ch = 0;
+  for (; ch + NST - 1 < nch; ++ch) {  // steady state: NST - 2 later chunks in flight
+    wait_vmcnt<imin_c((NST - 2) * W, 63)>();
+    __syncthreads();
+    issue(ch + NST - 1);
+    compute(ch);
   }
+  for (; ch < nch; ++ch) {  // the last NST - 1 chunks: nothing more to issue
+    const int later = nch - 1 - ch;
+    if (later >= 2) wait_vmcnt<imin_c(2 * W, 63)>();
+    else if (later == 1) wait_vmcnt<imin_c(W, 63)>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    compute(ch);
+  }
+}
+
+template <int SEG, int BM, int BN, int KC, int WGM, int NST, int PAD = 8>
+__device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* __restrict__ Ap,
+                                          const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
+                                          bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0) {
+  using S = GemmShape<BM, BN, KC, WGM, NST, PAD>;
+  constexpr int RB = S::RB, CB = S::CB;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / S::WGN, wn = wave % S::WGN;
+  const int l16 = lane & 15, lg = lane >> 4;
+
+  d4 acc[RB][CB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
+        acc[rb][cb][i] = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
+      }
+
+  gemm_kloop<BM, BN, KC, WGM, NST, PAD, SEG>(acc, Ap, Bp, ld, M, N, K, lds);
   __syncthreads();  // every wavefront is done with the stages before LDS is reused
 
 #pragma unroll
@@ -223,7 +252,7 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = wm * WTM + rb * 16 + l16, col = wn * WTN + cb * 16 + 4 * i + lg;
+        const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
         if (row < M && col < N && (!lower_only || row >= col)) {
           if (Cl)
             Cl[col * ldl + row] = acc[rb][cb][i];  // result kept in LDS (column-major, ld ldl)
@@ -237,12 +266,13 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
 // columns through two stages need half the workgroup barriers of chunks of
 // 16 through four; a K that is only a multiple of 16 takes the latter.
 #define GB 128
+template <int SEG>
 __device__ __forceinline__ void gemm_nt(double* C, const double* Ap, const double* Bp, int64_t ld, int M, int N,
                                         int K, bool lower_only, double* lds) {
   if (K % 32 == 0)
-    gemm_core<GB, GB, 32, 2, 2>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+    gemm_core<SEG, GB, GB, 32, 2, 2>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
   else
-    gemm_core<GB, GB, 16, 2, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+    gemm_core<SEG, GB, GB, 16, 2, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,8 +291,9 @@ __device__ __forceinline__ void gemm_nt(double* C, const double* Ap, const doubl
 // positive (zero, negative or NaN).
 #define PW 16
 #define PPLD 516                              // LDS leading dimension of the panel
-#define P_STAGE_DOUBLES (272 * 8 * 4)         // gemm_core<256, 16, 8, 4, 4> stages
+#define P_STAGE_DOUBLES (272 * 8 * 4)         // stages of gemm_core<SEG, 256, 16, 8, 4, 4, 0>
 
+template <int SEG>
 __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -277,7 +308,7 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
     if (c0 > 0) {
       // P - L[c0:, 0:c0] L[c0:c0+w, 0:c0]^T into LDS, in (at most two) slabs of 256 rows
       for (int s0 = 0; s0 < R; s0 += 256) {
-        gemm_core<256, PW, 8, 4, 4, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, imin(256, R - s0), w, c0, false, lds,
+        gemm_core<SEG, 256, PW, 8, 4, 4, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, imin(256, R - s0), w, c0, false, lds,
                                     Ps + s0, PPLD);
         __syncthreads();
       }
@@ -761,7 +792,7 @@ __device__ __forceinline__ bool wait_ready(const KArgs& a, int task, int lane) {
     if (uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) != 0) return false;
     if ((int64_t)(wall_clock64() - t0) > a.wait_limit) {
       if (lane == 0) {
-        __hip_atomic_store(&a.hdr[HDR_ERROR], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.hdr[HDR_ERROR], DEV_ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&a.hdr[HDR_ABORT], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
       return false;
@@ -770,6 +801,21 @@ __device__ __forceinline__ bool wait_ready(const KArgs& a, int task, int lane) {
   return uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) == 0;
 }
 
+// Stops every worker with a runtime error code (the first one is kept).
+__device__ __forceinline__ void raise_error(const KArgs& a, int code) {
+  if (threadIdx.x == 0) {
+    int expected = 0;
+    __hip_atomic_compare_exchange_strong(&a.hdr[HDR_ERROR], &expected, code, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.hdr[HDR_ABORT], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// SEG = 128: the launch guarantees even n and a 16-byte aligned matrix, so
+// every panel the updates stream is 16-byte transferable; SEG = 32 serves
+// every other case.  One transfer width per kernel instance keeps the
+// update loops free of per-item branches.
+template <int SEG>
 __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
   __shared__ double lds[LDS_DOUBLES];
   __shared__ int s_claim[3];
@@ -810,7 +856,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     switch (kind) {
       case TK_POTRF: {
         double* Akk = a.A + (tk * nb) * ld + tk * nb;
-        const int info = uniform_i(potrf_tile(Akk, ld, (int)tile_size(a, tk), lds));
+        const int info = uniform_i(potrf_tile<SEG>(Akk, ld, (int)tile_size(a, tk), lds));
         if (info != 0) {
           ok = 0;
           if (tid == 0) {
@@ -844,7 +890,13 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         double* C = a.A + (tj * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m;
         const double* Ap = a.A + (tk * nb) * ld + ti * nb + si * a.gemm_m;
         const double* Bp = a.A + (tk * nb) * ld + tj * nb + sj * a.gemm_n;
-        gemm_nt(C, Ap, Bp, ld, M, N, (int)tile_size(a, tk), kind == TK_SYRK && si == sj, lds);
+        if (SEG == 128 && (((M | N | (int)ld) & 1) != 0 ||
+                           ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) != 0)) {
+          raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
+          ok = 0;
+          break;
+        }
+        gemm_nt<SEG>(C, Ap, Bp, ld, M, N, (int)tile_size(a, tk), kind == TK_SYRK && si == sj, lds);
         break;
       }
       case TK_FTRSV:
@@ -923,7 +975,11 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
     e = hipEventRecord(ev0, stream);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(tchol_persistent, dim3(grid), dim3(NT), 0, stream, *a);
+  const bool wide = (a->ld % 2 == 0) && (reinterpret_cast<uintptr_t>(a->A) % 16 == 0);
+  if (wide)
+    hipLaunchKernelGGL(tchol_persistent<128>, dim3(grid), dim3(NT), 0, stream, *a);
+  else
+    hipLaunchKernelGGL(tchol_persistent<32>, dim3(grid), dim3(NT), 0, stream, *a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev1) e = hipEventRecord(ev1, stream);
@@ -934,8 +990,13 @@ extern "C" hipError_t tchol_dev_max_grid(int device, int* grid) {
   int cus = 0, occ = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tchol_persistent, NT, 0);
+  // both instances share the LDS size and launch bounds; take the smaller occupancy
+  int occ32 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tchol_persistent<128>, NT, 0);
   if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ32, tchol_persistent<32>, NT, 0);
+  if (e != hipSuccess) return e;
+  occ = occ < occ32 ? occ : occ32;
   *grid = cus * (occ > 0 ? occ : 1);
   return hipSuccess;
 }
