@@ -188,9 +188,10 @@ def factor(A, nb: int, **kw):
 
 
 def solve_(L, Bc, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
-           want_kernel_ms: bool = False, check: bool = True):
+           want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Solve in place.  L: the (n, n) buffer factored by factor_ (column-major
-    lower = L).  Bc: CUDA float64 (nrhs, n) contiguous, i.e. B column-major."""
+    lower = L).  Bc: CUDA float64 (nrhs, n) contiguous, i.e. B column-major.
+    trace: optional CUDA int64 tensor of 4 words per work item (see factor_)."""
     torch = _torch()
     n = L.shape[0]
     if Bc.dtype != torch.float64 or not Bc.is_contiguous() or Bc.dim() != 2 or Bc.shape[1] != n:
@@ -201,7 +202,7 @@ def solve_(L, Bc, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_lim
         need = workspace_bytes(OP_SOLVE, n, nb, nrhs) if n else 256
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, L.device)
-        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, None)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
         rc = lib.tchol_solve_ex(ctypes.c_void_p(L.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()), nrhs,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(torch, L.device),
                                 ctypes.byref(o))

@@ -499,164 +499,185 @@ __device__ __forceinline__ void unstage_rhs(const double* Ys, double* Bk, int64_
   }
 }
 
-// Y_k := L_kk^{-1} B_k (m <= 512 rows), forward substitution by blocks of 16
-// rows: a 16-lane triangular solve (one right-hand side per lane, the
-// diagonal block and its reciprocal pivots in LDS), then the matrix cores
-// subtract the block's contribution from every later row block.
-__device__ __forceinline__ void ftrsv(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb, int m,
-                                      int nrhs, double* lds) {
-  double* Ys = lds;                   // [16][YLD]
-  double* Ld = lds + 16 * YLD;        // [16][17] diagonal block
-  double* Linv = Ld + 16 * 17;        // [512] reciprocal pivots
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int l16 = lane & 15, lg = lane >> 4;
+// Tile solves, register resident.  The tile's rows form blocks of 16
+// (nblk <= 32); wavefront w owns blocks w, w + 4, ..., and keeps their
+// right-hand sides in registers in the layout of an MFMA result: element v
+// of lane l holds row 4v + l/16 of right-hand side l%16.  That is also the
+// layout of the B operand of an MFMA's k-step v, so a solved block feeds the
+// updates of the other blocks without leaving registers.
+//
+// Block rb is solved by its owner in four dependent 4-row sub-steps:
+// y_s := W_s r_s with W_s the inverse of the s-th 4x4 diagonal block of L
+// (one MFMA whose A operand is W_s in rows 4s..4s+3 and zero elsewhere),
+// then the rows below lose L[rows, 4s..4s+3] y_s (one MFMA).  The 4x4
+// inverses are formed once per task by substitution; a 4x4 inverse of an
+// integer factor with power-of-two pivots is exact, so such systems are
+// still solved exactly.  The solved block is published through LDS (two
+// buffers, one barrier per block) and every wavefront subtracts its
+// contribution from the blocks it owns; the owner of the next block
+// updates and solves that block first.  The L fragments of block rb's
+// updates are requested one block ahead.
+//
+// LDS: Fr[blk][s][f][64] the A-operand fragments of the sub-steps (f = 0:
+// inverse, f = 1: update), then two 16 x 16 exchange buffers.
+#define FR_SLOT(blk, s, f) ((((blk) * 4 + (s)) * 2 + (f)) * 64)
+
+// Builds Fr for the forward (trans = false) or backward (trans = true)
+// solve of the nblk diagonal 16-blocks of L_kk (m rows).  Rows and columns
+// past m behave as the identity.
+__device__ __forceinline__ void build_block_fragments(const double* __restrict__ Lkk, int64_t ld, int m,
+                                                      bool trans, double* Fr) {
+  const int tid = threadIdx.x;
   const int nblk = (m + 15) >> 4;
-  for (int c = tid; c < m; c += NT) Linv[c] = 1.0 / Lkk[(int64_t)c * ld + c];
-  for (int j0 = 0; j0 < nrhs; j0 += 16) {
-    const int jn = imin(16, nrhs - j0);
-    stage_rhs(Ys, Bk, ldb, m, j0, jn);
-    for (int rb = 0; rb < nblk; ++rb) {
-      const int r0 = rb * 16, bw = imin(16, m - r0);
-      {
-        const int a = tid >> 4, b = tid & 15;
-        const double v = Lkk[(int64_t)(r0 + imin(b, bw - 1)) * ld + r0 + imin(a, bw - 1)];
-        Ld[a * 17 + b] = ((a >= b) & (a < bw) & (b < bw)) ? v : 0.0;
+  // update fragments, and zeros in the inverse slots
+  for (int idx = tid; idx < nblk * 4 * 64; idx += NT) {
+    const int lane = idx & 63, s = (idx >> 6) & 3, blk = idx >> 8;
+    const int l16 = lane & 15, lg = lane >> 4;
+    const int r0 = blk * 16, bw = imin(16, m - r0);
+    // forward: A[i][k] = L[r0+i][r0+4s+k] for i >= 4s+4; backward:
+    // A[i][k] = L[r0+4s+k][r0+i] for i < 4s
+    const int row = trans ? 4 * s + lg : l16, col = trans ? l16 : 4 * s + lg;
+    const bool live = trans ? (l16 < 4 * s) : (l16 >= 4 * s + 4);
+    const double v = Lkk[(int64_t)(r0 + imin(col, bw - 1)) * ld + r0 + imin(row, bw - 1)];
+    Fr[FR_SLOT(blk, s, 1) + lane] = (live & (row < bw) & (col < bw)) ? v : 0.0;
+    Fr[FR_SLOT(blk, s, 0) + lane] = 0.0;
+  }
+  __syncthreads();
+  // column c of the inverse of the 4x4 block (blk, s), by substitution
+  for (int idx = tid; idx < nblk * 16; idx += NT) {
+    const int c = idx & 3, s = (idx >> 2) & 3, blk = idx >> 4;
+    const int r0 = blk * 16 + 4 * s, bw = imin(4, m - r0);  // bw may be <= 0: identity
+    double d[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool in = (j <= i) & (i < bw) & (j < bw);
+        const double v = Lkk[(int64_t)(imin(m - 1, r0 + imin(j, 3))) * ld + imin(m - 1, r0 + imin(i, 3))];
+        d[i][j] = in ? v : (i == j ? 1.0 : 0.0);
       }
-      __syncthreads();
-      if (tid < 16) {
-        double y[16];
+    double w[4];
 #pragma unroll
-        for (int a = 0; a < 16; ++a) y[a] = Ys[tid * YLD + r0 + a];
+    for (int i = 0; i < 4; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-        for (int a = 0; a < 16; ++a) {
-          if (a < bw) {
-            double t = y[a];
-#pragma unroll
-            for (int b = 0; b < a; ++b) t -= Ld[a * 17 + b] * y[b];
-            y[a] = t * Linv[r0 + a];
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 16; ++a) Ys[tid * YLD + r0 + a] = y[a];
-      }
-      __syncthreads();
-      // later row blocks: Y[rows] -= L[rows, r0:r0+16] Y[r0:r0+16].  A wave
-      // owns row blocks rb + 1 + wave + 4t; all its L fragments are requested
-      // at once so that their latency is paid once per block row.
-      {
-        double fl[8][4];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int rr = imin((rb + 1 + wave + 4 * t) * 16 + l16, m - 1);
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int q = r0 + kk * 4 + lg;
-            const double v = Lkk[(int64_t)imin(q, m - 1) * ld + rr];
-            fl[t][kk] = (q < m) ? v : 0.0;
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int ub = rb + 1 + wave + 4 * t;
-          if (ub < nblk) {
-            const int rr = ub * 16;
-            d4 acc;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-              const double fy = Ys[l16 * YLD + r0 + kk * 4 + lg];
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], fy, acc, 0, 0, 2 /* neg B */);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
-          }
-        }
-      }
-      __syncthreads();
+      for (int j = 0; j < i; ++j) t -= d[i][j] * w[j];
+      w[i] = (i < c) ? 0.0 : t * (1.0 / d[i][i]);
     }
-    unstage_rhs(Ys, Bk, ldb, m, j0, jn);
-    __syncthreads();
+    // forward A[i'][k'] = W[i'-4s][k'] (i' in 4s..4s+3) -> lane k'*16 + i';
+    // backward A[i'][k'] = W[k'][i'-4s] -> lane i*16 + 4s + c
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i >= c) Fr[FR_SLOT(blk, s, 0) + (trans ? i * 16 + 4 * s + c : c * 16 + 4 * s + i)] = w[i];
+  }
+  __syncthreads();
+}
+
+// Solves the owner's block in place (acc: the block's right-hand sides).
+__device__ __forceinline__ void solve_block(d4& acc, const double* Fr, int blk, bool trans, int lane) {
+#pragma unroll
+  for (int ss = 0; ss < 4; ++ss) {
+    const int s = trans ? 3 - ss : ss;
+    const d4 z = __builtin_amdgcn_mfma_f64_16x16x4f64(Fr[FR_SLOT(blk, s, 0) + lane], acc[s], d4{0.0, 0.0, 0.0, 0.0},
+                                                     0, 0, 0);
+    acc[s] = z[s];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Fr[FR_SLOT(blk, s, 1) + lane], z[s], acc, 0, 0, 2 /* neg B */);
   }
 }
 
-// X_k := L_kk^{-T} Y_k, backward substitution by blocks of 16 rows (last
-// block first); the update of the rows above uses L's transposed blocks.
-__device__ __forceinline__ void btrsv(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb, int m,
-                                      int nrhs, double* lds) {
-  double* Ys = lds;
-  double* Ld = lds + 16 * YLD;
-  double* Linv = Ld + 16 * 17;
+// trans = false: Y_k := L_kk^{-1} B_k; trans = true: X_k := L_kk^{-T} Y_k.
+__device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb,
+                                           int m, int nrhs, bool trans, double* lds) {
+  double* Fr = lds;                  // [nblk][4][2][64]
+  double* Ex = lds + 32 * 4 * 2 * 64;  // [2][4][64]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
   const int nblk = (m + 15) >> 4;
-  for (int c = tid; c < m; c += NT) Linv[c] = 1.0 / Lkk[(int64_t)c * ld + c];
+  build_block_fragments(Lkk, ld, m, trans, Fr);
+  // fragments of the updates by solved block rb of the owned blocks ub = wave + 4t:
+  // forward L[ub rows][rb cols], backward L[rb rows][ub cols]^T
+  auto fetch = [&](int rb, double (&fl)[8][4]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int ur = imin((wave + 4 * t) * 16 + l16, m - 1);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int q = imin(rb * 16 + 4 * kk + lg, m - 1);
+        fl[t][kk] = trans ? Lkk[(int64_t)ur * ld + q] : Lkk[(int64_t)q * ld + ur];
+      }
+    }
+  };
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
-    stage_rhs(Ys, Bk, ldb, m, j0, jn);
-    for (int rb = nblk - 1; rb >= 0; --rb) {
-      const int r0 = rb * 16, bw = imin(16, m - r0);
-      {
-        const int a = tid >> 4, b = tid & 15;
-        const double v = Lkk[(int64_t)(r0 + imin(b, bw - 1)) * ld + r0 + imin(a, bw - 1)];
-        Ld[a * 17 + b] = ((a >= b) & (a < bw) & (b < bw)) ? v : 0.0;
+    const int jc = imin(l16, jn - 1);
+    d4 acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = (wave + 4 * t) * 16 + 4 * v + lg;
+        const double x = Bk[(int64_t)(j0 + jc) * ldb + imin(row, m - 1)];
+        acc[t][v] = (row < m) ? x : 0.0;
       }
-      __syncthreads();
-      if (tid < 16) {
-        double y[16];
+    const int first = trans ? nblk - 1 : 0;
+    double fla[8][4], flb[8][4];
+    fetch(first, fla);
+    // the first block: solved by its owner, published in buffer 0
 #pragma unroll
-        for (int a = 0; a < 16; ++a) y[a] = Ys[tid * YLD + r0 + a];
+    for (int t = 0; t < 8; ++t)
+      if (wave + 4 * t == first) {
+        solve_block(acc[t], Fr, first, trans, lane);
 #pragma unroll
-        for (int a = 15; a >= 0; --a) {
-          if (a < bw) {
-            double t = y[a];
-#pragma unroll
-            for (int b = a + 1; b < 16; ++b) t -= Ld[b * 17 + a] * y[b];
-            y[a] = t * Linv[r0 + a];
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 16; ++a) Ys[tid * YLD + r0 + a] = y[a];
+        for (int v = 0; v < 4; ++v) Ex[v * 64 + lane] = acc[t][v];
       }
-      __syncthreads();
-      // earlier row blocks: Y[rows] -= L[r0:r0+16, rows]^T X[r0:r0+16], the
-      // wave's L fragments requested at once as above
-      {
-        double fl[8][4];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int cc = imin((wave + 4 * t) * 16 + l16, m - 1);
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int q = r0 + kk * 4 + lg;
-            const double v = Lkk[(int64_t)cc * ld + imin(q, m - 1)];
-            fl[t][kk] = (q < m) ? v : 0.0;
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int ub = wave + 4 * t;
-          if (ub < rb) {
-            const int rr = ub * 16;
-            d4 acc;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] = Ys[l16 * YLD + rr + 4 * i + lg];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-              const double fy = Ys[l16 * YLD + r0 + kk * 4 + lg];
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], fy, acc, 0, 0, 2 /* neg B */);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) Ys[l16 * YLD + rr + 4 * i + lg] = acc[i];
-          }
-        }
-      }
-      __syncthreads();
-    }
-    unstage_rhs(Ys, Bk, ldb, m, j0, jn);
     __syncthreads();
+    // one step: block rb is solved and published in buffer (step & 1); its
+    // contribution goes to every block still to be solved, the next block first
+    auto step = [&](int step_i, const double (&fl)[8][4], double (&fln)[8][4]) __attribute__((always_inline)) {
+      const int rb = trans ? nblk - 1 - step_i : step_i;
+      const int nx = trans ? rb - 1 : rb + 1;
+      const bool has_next = trans ? (rb > 0) : (rb + 1 < nblk);
+      const double* ex = Ex + (step_i & 1) * 256;
+      double* exn = Ex + ((step_i + 1) & 1) * 256;
+      d4 yb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) yb[v] = ex[v * 64 + lane];
+      if (has_next) fetch(nx, fln);
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (has_next && wave + 4 * t == nx) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], yb[kk], acc[t], 0, 0, 2 /* neg B */);
+          solve_block(acc[t], Fr, nx, trans, lane);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) exn[v * 64 + lane] = acc[t][v];
+        }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int ub = wave + 4 * t;
+        if ((trans ? ub < nx : (ub > nx && ub < nblk))) {
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], yb[kk], acc[t], 0, 0, 2 /* neg B */);
+        }
+      }
+      __syncthreads();
+    };
+    for (int si = 0; si < nblk; si += 2) {
+      step(si, fla, flb);
+      if (si + 1 < nblk) step(si + 1, flb, fla);
+    }
+    if (l16 < jn) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = (wave + 4 * t) * 16 + 4 * v + lg;
+          if (row < m) st_dev(Bk + (int64_t)(j0 + l16) * ldb + row, acc[t][v]);
+        }
+    }
   }
 }
 
@@ -900,10 +921,9 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         break;
       }
       case TK_FTRSV:
-        ftrsv(a.A + (tk * nb) * ld + tk * nb, ld, a.B + tk * nb, a.ldb, (int)tile_size(a, tk), (int)a.nrhs, lds);
-        break;
       case TK_BTRSV:
-        btrsv(a.A + (tk * nb) * ld + tk * nb, ld, a.B + tk * nb, a.ldb, (int)tile_size(a, tk), (int)a.nrhs, lds);
+        tile_solve(a.A + (tk * nb) * ld + tk * nb, ld, a.B + tk * nb, a.ldb, (int)tile_size(a, tk), (int)a.nrhs,
+                   kind == TK_BTRSV, lds);
         break;
       case TK_FGEMV: {
         const int r0 = part * a.gemv_rows;

@@ -67,7 +67,8 @@ def test_config1_factor_and_solve(tc):
     assert oracle.solve_backward_error(A, x, b[:, 0])[0] <= 1e-15
 
 
-@pytest.mark.parametrize("n,nb,nrhs", [(1000, 128, 16), (512, 64, 3), (700, 512, 20), (33, 16, 1)])
+@pytest.mark.parametrize("n,nb,nrhs", [(1000, 128, 16), (512, 64, 3), (700, 512, 20), (33, 16, 1), (1000, 256, 17),
+                                         (600, 384, 5), (500, 144, 7), (2048, 512, 16)])
 def test_solve_matches_oracle(tc, n, nb, nrhs):
     A, B = spd_inputs.spd_matrix_and_rhs(n, n + nrhs, nrhs=nrhs)
     W = _dev(A)
