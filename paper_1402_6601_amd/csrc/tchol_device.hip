@@ -485,10 +485,20 @@ __device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double*
 // rows 4i + lane/16 of one right-hand side (lane % 16) of the 16x16 result.
 #define YLD 520
 
+// All 32 loads of a thread are requested before any is stored, so staging
+// costs one memory latency rather than one per element.
 __device__ __forceinline__ void stage_rhs(double* Ys, const double* Bk, int64_t ldb, int m, int j0, int jn) {
-  for (int idx = threadIdx.x; idx < 16 * 512; idx += NT) {
-    const int j = idx >> 9, r = idx & 511;
-    Ys[j * YLD + r] = (j < jn && r < m) ? Bk[(int64_t)(j0 + imin(j, jn - 1)) * ldb + imin(r, m - 1)] : 0.0;
+  constexpr int PER = 16 * 512 / NT;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int idx = threadIdx.x + u * NT, j = idx >> 9, r = idx & 511;
+    v[u] = Bk[(int64_t)(j0 + imin(j, jn - 1)) * ldb + imin(r, m - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int idx = threadIdx.x + u * NT, j = idx >> 9, r = idx & 511;
+    Ys[j * YLD + r] = (j < jn && r < m) ? v[u] : 0.0;
   }
 }
 
@@ -527,48 +537,68 @@ __device__ __forceinline__ void unstage_rhs(const double* Ys, double* Bk, int64_
 // past m behave as the identity.
 __device__ __forceinline__ void build_block_fragments(const double* __restrict__ Lkk, int64_t ld, int m,
                                                       bool trans, double* Fr) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int s = tid >> 6;  // wavefront w builds sub-step w of every block
+  const int l16 = lane & 15, lg = lane >> 4;
   const int nblk = (m + 15) >> 4;
-  // update fragments, and zeros in the inverse slots
-  for (int idx = tid; idx < nblk * 4 * 64; idx += NT) {
-    const int lane = idx & 63, s = (idx >> 6) & 3, blk = idx >> 8;
-    const int l16 = lane & 15, lg = lane >> 4;
-    const int r0 = blk * 16, bw = imin(16, m - r0);
-    // forward: A[i][k] = L[r0+i][r0+4s+k] for i >= 4s+4; backward:
-    // A[i][k] = L[r0+4s+k][r0+i] for i < 4s
+  // update fragments (and zeros in the inverse slots): all 32 loads are
+  // requested before any is used.  Forward: A[i][k] = L[r0+i][r0+4s+k] for
+  // i >= 4s+4; backward: A[i][k] = L[r0+4s+k][r0+i] for i < 4s.
+  {
     const int row = trans ? 4 * s + lg : l16, col = trans ? l16 : 4 * s + lg;
     const bool live = trans ? (l16 < 4 * s) : (l16 >= 4 * s + 4);
-    const double v = Lkk[(int64_t)(r0 + imin(col, bw - 1)) * ld + r0 + imin(row, bw - 1)];
-    Fr[FR_SLOT(blk, s, 1) + lane] = (live & (row < bw) & (col < bw)) ? v : 0.0;
-    Fr[FR_SLOT(blk, s, 0) + lane] = 0.0;
+    double v[32];
+#pragma unroll
+    for (int blk = 0; blk < 32; ++blk) {
+      const int r0 = imin(blk, nblk - 1) * 16, bw = imin(16, m - r0);
+      v[blk] = Lkk[(int64_t)(r0 + imin(col, bw - 1)) * ld + r0 + imin(row, bw - 1)];
+    }
+#pragma unroll
+    for (int blk = 0; blk < 32; ++blk) {
+      if (blk < nblk) {
+        const int bw = imin(16, m - blk * 16);
+        Fr[FR_SLOT(blk, s, 1) + lane] = (live & (row < bw) & (col < bw)) ? v[blk] : 0.0;
+        Fr[FR_SLOT(blk, s, 0) + lane] = 0.0;
+      }
+    }
   }
   __syncthreads();
-  // column c of the inverse of the 4x4 block (blk, s), by substitution
-  for (int idx = tid; idx < nblk * 16; idx += NT) {
-    const int c = idx & 3, s = (idx >> 2) & 3, blk = idx >> 4;
-    const int r0 = blk * 16 + 4 * s, bw = imin(4, m - r0);  // bw may be <= 0: identity
-    double d[4][4];
+  // column c of the inverse of the 4x4 block (blk, s), by substitution; a
+  // thread takes blocks tid/16 and tid/16 + 16
+  {
+    const int c = tid & 3, s4 = (tid >> 2) & 3;
+    double d[2][4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int h = 0; h < 2; ++h) {
+      const int blk = imin((tid >> 4) + 16 * h, nblk - 1);
+      const int r0 = blk * 16 + 4 * s4, bw = imin(4, m - r0);  // bw may be <= 0: identity
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bool in = (j <= i) & (i < bw) & (j < bw);
-        const double v = Lkk[(int64_t)(imin(m - 1, r0 + imin(j, 3))) * ld + imin(m - 1, r0 + imin(i, 3))];
-        d[i][j] = in ? v : (i == j ? 1.0 : 0.0);
-      }
-    double w[4];
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double t = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int j = 0; j < i; ++j) t -= d[i][j] * w[j];
-      w[i] = (i < c) ? 0.0 : t * (1.0 / d[i][i]);
+        for (int j = 0; j < 4; ++j) {
+          const double x = Lkk[(int64_t)(imin(m - 1, r0 + j)) * ld + imin(m - 1, r0 + i)];
+          d[h][i][j] = ((j <= i) & (i < bw) & (j < bw)) ? x : (i == j ? 1.0 : 0.0);
+        }
     }
-    // forward A[i'][k'] = W[i'-4s][k'] (i' in 4s..4s+3) -> lane k'*16 + i';
-    // backward A[i'][k'] = W[k'][i'-4s] -> lane i*16 + 4s + c
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (i >= c) Fr[FR_SLOT(blk, s, 0) + (trans ? i * 16 + 4 * s + c : c * 16 + 4 * s + i)] = w[i];
+    for (int h = 0; h < 2; ++h) {
+      const int blk = (tid >> 4) + 16 * h;
+      if (blk < nblk) {
+        double w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double t = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+          for (int j = 0; j < i; ++j) t -= d[h][i][j] * w[j];
+          w[i] = (i < c) ? 0.0 : t * (1.0 / d[h][i][i]);
+        }
+        // forward A[i'][k'] = W[i'-4s][k'] (i' in 4s..4s+3) -> lane k'*16 + i';
+        // backward A[i'][k'] = W[k'][i'-4s] -> lane i*16 + 4s + c
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i >= c) Fr[FR_SLOT(blk, s4, 0) + (trans ? i * 16 + 4 * s4 + c : c * 16 + 4 * s4 + i)] = w[i];
+      }
+    }
   }
   __syncthreads();
 }
