@@ -389,91 +389,140 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 
 // ---------------------------------------------------------------------------
 // TRSM work item: a strip of S <= 32 rows of A_ik, X := X L_kk^{-T}
-// (mk = order of L_kk, a multiple of 16).  The strip lives in LDS.  For each
-// block of 16 columns: one wavefront solves the 16x16 triangle by forward
-// substitution (each lane one row, in registers), then the matrix cores
-// subtract the block's contribution from every later column of the strip.
-// The L fragments of a step are requested before its triangular solve so
-// that their latency hides behind it; the reciprocal pivots are formed once.
+// (mk = order of L_kk, a multiple of 16).  Transposed, X^T := L_kk^{-1} X^T
+// is a forward solve with the strip's rows as 32 right-hand sides (two
+// groups of 16).  The strip lives in LDS as Xs[g][c][16] (row 16g + j,
+// column c), which the MFMA fragments read without bank conflicts.  For
+// each block of 16 columns, wavefronts 0 and 1 solve the block for their
+// row group in four 4-column sub-steps on the matrix cores (the exact 4x4
+// inverse of the diagonal block's sub-block applied by one MFMA, then one
+// MFMA for the columns after it), then every wavefront subtracts the block's
+// contribution from its later column blocks.  The solver's L data for the
+// next step is requested one step ahead; the update fragments at the start
+// of the step, to land during the solve.
 #define TS 32
 
 __device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double* __restrict__ Lkk, int64_t ld, int S,
                                            int mk, double* lds) {
-  double* Xs = lds;                 // [mk][TS]
-  double* Ld = lds + 512 * TS;      // [2][16][17] diagonal blocks of L_kk, double buffered
-  double* Linv = Ld + 2 * 16 * 17;  // [mk] reciprocal pivots
+  double* Xs = lds;  // [2][512][16]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
+  const int nblk = mk >> 4;
+  // the strip: thread (r, c0) moves rows r of columns c0 + 8u, 16 loads in flight
   {
-    const int r = tid & (TS - 1);
-    for (int c = tid / TS; c < mk; c += NT / TS) Xs[c * TS + r] = (r < S) ? X[(int64_t)c * ld + r] : 0.0;
-    for (int c = tid; c < mk; c += NT) Linv[c] = 1.0 / Lkk[(int64_t)c * ld + c];
-    const int a = tid >> 4, b = tid & 15;
-    Ld[a * 17 + b] = (a >= b) ? Lkk[(int64_t)b * ld + a] : 0.0;
+    const int r = tid & 31, c0 = tid >> 5, rr = imin(r, S - 1);
+#pragma unroll 1
+    for (int part = 0; part < 4; ++part) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = X[(int64_t)imin(c0 + 8 * (u + 16 * part), mk - 1) * ld + rr];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 8 * (u + 16 * part);
+        if (c < mk) Xs[(r >> 4) * 8192 + c * 16 + (r & 15)] = (r < S) ? v[u] : 0.0;
+      }
+    }
   }
-  __syncthreads();
-  int it = 0;
-  for (int q0 = 0; q0 < mk; q0 += 16, ++it) {
-    const int ncb = (mk - q0 - 16) >> 4;
-    // requests for this step: the next diagonal block and this wave's L fragments
-    const int a = tid >> 4, b = tid & 15;
-    // unconditional loads from clamped addresses (selects afterwards keep
-    // them independent of each other)
-    const int qn = imin(q0 + 16, mk - 16);
-    const double ldn = Lkk[(int64_t)(qn + b) * ld + qn + a];
-    const double ldnext = (a >= b) ? ldn : 0.0;
+  // Step data.  Solver lanes (wavefronts 0, 1): the 4x4 sub-block entries
+  // d[a][b] (a >= b) of sub-block s* = l16 / 4 and the update entries
+  // L[q0 + l16][q0 + 4s + lg], requested one step ahead; every wavefront:
+  // the fragments L[later column block rows, q0 + 4kk + lg], requested at
+  // the start of the step and used after the block's solve.
+  struct SolveData {
+    double d[10];
+    double fd[4];
+  };
+  auto fetch_solve = [&](int rb, SolveData& sd) __attribute__((always_inline)) {
+    const int q0 = rb * 16;
+    const int sb = q0 + 4 * (l16 >> 2);
+    int n = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int bq = 0; bq <= a; ++bq) sd.d[n++] = Lkk[(int64_t)(sb + bq) * ld + sb + a];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) sd.fd[s4] = Lkk[(int64_t)(q0 + 4 * s4 + lg) * ld + q0 + l16];
+  };
+  auto step = [&](int rb, const SolveData& sd, SolveData& sdn) __attribute__((always_inline)) {
+    const int q0 = rb * 16;
+    __syncthreads();  // the block's columns are final (and, first time, the strip is staged)
     double fl[8][4];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int cb = wave + 4 * t;
-      const int crow = imin(q0 + 16 + cb * 16 + l16, mk - 1);
+      const int crow = imin(q0 + 16 + (wave + 4 * t) * 16 + l16, mk - 1);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) fl[t][kk] = Lkk[(int64_t)(q0 + kk * 4 + lg) * ld + crow];
     }
-    const double* Lb = Ld + (it & 1) * 272;
-    if (tid < TS) {
-      double x[16];
+    if (wave < 2) {
+      if (rb + 1 < nblk) fetch_solve(rb + 1, sdn);
+      const int g = wave;
+      // column lg of the inverse of sub-block s* = l16 / 4; this lane's A entry is row l16 % 4
+      double dd[4][4];
+      {
+        int n = 0;
 #pragma unroll
-      for (int bb = 0; bb < 16; ++bb) x[bb] = Xs[(q0 + bb) * TS + tid];
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int bb = 0; bb < 16; ++bb) {
-        x[bb] = x[bb] * Linv[q0 + bb];
+          for (int bq = 0; bq < 4; ++bq) dd[a][bq] = (bq <= a) ? sd.d[n++] : 0.0;
+      }
+      double w[4];
 #pragma unroll
-        for (int aa = bb + 1; aa < 16; ++aa) x[aa] -= x[bb] * Lb[aa * 17 + bb];
+      for (int a = 0; a < 4; ++a) {
+        double t = (a == lg) ? 1.0 : 0.0;
+#pragma unroll
+        for (int bq = 0; bq < a; ++bq) t -= dd[a][bq] * w[bq];
+        w[a] = (a < lg) ? 0.0 : t * (1.0 / dd[a][a]);
+      }
+      const int i4 = l16 & 3;
+      const double wmine = (i4 == 0) ? w[0] : (i4 == 1) ? w[1] : (i4 == 2) ? w[2] : w[3];
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = Xs[g * 8192 + (q0 + 4 * v + lg) * 16 + l16];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const double fw = ((l16 >> 2) == s4) ? wmine : 0.0;
+        const d4 z = __builtin_amdgcn_mfma_f64_16x16x4f64(fw, acc[s4], d4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+        acc[s4] = z[s4];
+        const double fdv = (l16 >= 4 * s4 + 4) ? sd.fd[s4] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fdv, z[s4], acc, 0, 0, 2 /* neg B */);
       }
 #pragma unroll
-      for (int bb = 0; bb < 16; ++bb) Xs[(q0 + bb) * TS + tid] = x[bb];
+      for (int v = 0; v < 4; ++v) Xs[g * 8192 + (q0 + 4 * v + lg) * 16 + l16] = acc[v];
     }
     __syncthreads();
-    // X[:, c2] -= X[:, q0:q0+16] L[c2, q0:q0+16]^T for this wave's later column blocks
+    // X^T[later column blocks] -= L[those rows, q0:q0+16] X^T[q0:q0+16] for both row groups
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int cb = wave + 4 * t;
-      if (cb < ncb) {
-        const int cbase = q0 + 16 + cb * 16;
+      const int cb = rb + 1 + wave + 4 * t;
+      if (cb < nblk) {
 #pragma unroll
-        for (int rbk = 0; rbk < 2; ++rbk) {
+        for (int g = 0; g < 2; ++g) {
           d4 acc;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[i] = Xs[(cbase + 4 * i + lg) * TS + rbk * 16 + l16];
+          for (int v = 0; v < 4; ++v) acc[v] = Xs[g * 8192 + (cb * 16 + 4 * v + lg) * 16 + l16];
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) {
-            const double fx = Xs[(q0 + kk * 4 + lg) * TS + rbk * 16 + l16];
+            const double fx = Xs[g * 8192 + (q0 + kk * 4 + lg) * 16 + l16];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], fx, acc, 0, 0, 2 /* neg B */);
           }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) Xs[(cbase + 4 * i + lg) * TS + rbk * 16 + l16] = acc[i];
+          for (int v = 0; v < 4; ++v) Xs[g * 8192 + (cb * 16 + 4 * v + lg) * 16 + l16] = acc[v];
         }
       }
     }
-    if (q0 + 16 < mk) Ld[((it + 1) & 1) * 272 + a * 17 + b] = ldnext;
-    __syncthreads();
+  };
+  SolveData sa, sb;
+  if (wave < 2) fetch_solve(0, sa);
+  for (int rb = 0; rb < nblk; rb += 2) {
+    step(rb, sa, sb);
+    if (rb + 1 < nblk) step(rb + 1, sb, sa);
   }
+  __syncthreads();
   {
-    const int r = tid & (TS - 1);
+    const int r = tid & 31, c0 = tid >> 5;
     if (r < S)
-      for (int c = tid / TS; c < mk; c += NT / TS) st_dev(X + (int64_t)c * ld + r, Xs[c * TS + r]);
+      for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ld + r, Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
   }
 }
 
@@ -485,20 +534,23 @@ __device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double*
 // rows 4i + lane/16 of one right-hand side (lane % 16) of the 16x16 result.
 #define YLD 520
 
-// All 32 loads of a thread are requested before any is stored, so staging
-// costs one memory latency rather than one per element.
+// The loads of a thread are requested 16 at a time before any is stored,
+// so staging costs two memory latencies rather than one per element.
 __device__ __forceinline__ void stage_rhs(double* Ys, const double* Bk, int64_t ldb, int m, int j0, int jn) {
-  constexpr int PER = 16 * 512 / NT;
-  double v[PER];
+  constexpr int PER = 16 * 512 / NT, BATCH = 16;
+#pragma unroll 1
+  for (int u0 = 0; u0 < PER; u0 += BATCH) {
+    double v[BATCH];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int idx = threadIdx.x + u * NT, j = idx >> 9, r = idx & 511;
-    v[u] = Bk[(int64_t)(j0 + imin(j, jn - 1)) * ldb + imin(r, m - 1)];
-  }
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = threadIdx.x + (u0 + u) * NT, j = idx >> 9, r = idx & 511;
+      v[u] = Bk[(int64_t)(j0 + imin(j, jn - 1)) * ldb + imin(r, m - 1)];
+    }
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int idx = threadIdx.x + u * NT, j = idx >> 9, r = idx & 511;
-    Ys[j * YLD + r] = (j < jn && r < m) ? v[u] : 0.0;
+    for (int u = 0; u < BATCH; ++u) {
+      const int idx = threadIdx.x + (u0 + u) * NT, j = idx >> 9, r = idx & 511;
+      Ys[j * YLD + r] = (j < jn && r < m) ? v[u] : 0.0;
+    }
   }
 }
 
