@@ -49,6 +49,7 @@ extern "C" {
 
 #define TCHOL_OP_FACTOR 0
 #define TCHOL_OP_SOLVE 1
+#define TCHOL_OP_BATCHED 2 /* factor + solve of many systems (plan introspection only) */
 
 #define TCHOL_POLICY_RANK 0   /* decreasing upward rank (default)          */
 #define TCHOL_POLICY_FIFO 1   /* step-major: (k, kind, i, j) ascending      */
@@ -97,6 +98,36 @@ TCHOL_API int32_t tchol_solve(const double *L, int64_t n, int64_t nb, double *B,
 TCHOL_API int32_t tchol_solve_ex(const double *L, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
                        int64_t ws_bytes, void *stream, const tchol_opts *opts);
 
+/* Batched factor + solve of `batch` independent SPD systems in ONE launch
+   of the persistent kernel.  Paper: the same tile DAG (section 4.1) per
+   system; the systems' DAGs are merged into one, each system's solve
+   joined to its factorization by data flow (POTRF(k) before FTRSV(k),
+   TRSM(i, k) before FGEMV(i, k)), and claimed in decreasing upward rank
+   (section 3.1) measured in flops, so long critical paths start first.
+   Host arrays, one entry per system s:
+     a_off[s]  element offset of A_s from A; A_s is n[s] x n[s], column-major,
+               leading dimension lda[s] >= max(1, n[s]); lower triangle used;
+     b_off[s]  element offset of B_s from B; B_s is n[s] x nrhs, column-major,
+               leading dimension n[s]; overwritten by the solution;
+     n[s] >= 0 its order; nb[s] its tile size (as for tchol_factor), chosen
+               per system (e.g. by a tuned table: one tile, or several tiles
+               that spread one system over many workgroups).
+   info (host, batch entries, out): 0, or the LAPACK-style failing column of
+   that system; a failing system stops only its own remaining work (its A
+   and B are then partly overwritten), the others complete.
+   Systems must not overlap in memory.  The faster 16-byte transfer path is
+   used when every lda[s] is even, every A_s is 16-byte aligned, and every
+   odd n[s] has lda[s] > n[s] (e.g. lda[s] = n[s] rounded up to even).
+   Arguments: 1 A, 2 a_off, 3 lda, 4 B, 5 b_off, 6 n, 7 nb, 8 nrhs >= 0,
+   9 batch >= 0, 10 info, 11 ws, 12 ws_bytes, 13 stream, 14 opts (NULL or as
+   for tchol_factor_ex).  Returns 0 when the launch ran (per-system failures
+   are reported in info only), or a negative code. */
+TCHOL_API int64_t tchol_batched_workspace_bytes(const int32_t *n, const int32_t *nb, int32_t batch);
+TCHOL_API int32_t tchol_factor_solve_batched(double *A, const int64_t *a_off, const int32_t *lda, double *B,
+                                             const int64_t *b_off, const int32_t *n, const int32_t *nb,
+                                             int32_t nrhs, int32_t batch, int32_t *info, void *ws,
+                                             int64_t ws_bytes, void *stream, const tchol_opts *opts);
+
 /* Human-readable text for a return code (static storage). */
 TCHOL_API const char *tchol_strerror(int32_t code);
 
@@ -109,6 +140,15 @@ TCHOL_API int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t po
                          int32_t *kind, int32_t *ti, int32_t *tj, int32_t *tk, int32_t *parts,
                          int32_t *dep0, int64_t *rank, int32_t *succ_off, int32_t *succ,
                          int32_t *item_task, int32_t *item_part);
+
+/* The same introspection for the merged DAG of tchol_factor_solve_batched
+   (systems given by n and nb, batch entries); sys (ntask) receives each
+   task's system.  Returns 0 or a negative code. */
+TCHOL_API int32_t tchol_batched_plan_query(const int32_t *n, const int32_t *nb, int32_t batch, int32_t policy,
+                                           uint32_t seed, int64_t *counts, int32_t *kind, int32_t *ti, int32_t *tj,
+                                           int32_t *tk, int32_t *sys, int32_t *parts, int32_t *dep0, int64_t *rank,
+                                           int32_t *succ_off, int32_t *succ, int32_t *item_task,
+                                           int32_t *item_part);
 
 /* Library version string. */
 TCHOL_API const char *tchol_version(void);

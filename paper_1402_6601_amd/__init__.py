@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
-OP_FACTOR, OP_SOLVE = 0, 1
+OP_FACTOR, OP_SOLVE, OP_BATCHED = 0, 1, 2
 POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL = -100, -101, -102, -103
 KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV"]
@@ -70,6 +70,14 @@ def load() -> ctypes.CDLL:
     lib.tchol_plan_query.restype = i32
     lib.tchol_plan_query.argtypes = [i32, i64, i64, i32, u32, P64, P32, P32, P32, P32, P32, P32, P64, P32, P32,
                                      P32, P32]
+    lib.tchol_batched_plan_query.restype = i32
+    lib.tchol_batched_plan_query.argtypes = [P32, P32, i32, i32, u32, P64, P32, P32, P32, P32, P32, P32, P32, P64,
+                                             P32, P32, P32, P32]
+    lib.tchol_batched_workspace_bytes.restype = i64
+    lib.tchol_batched_workspace_bytes.argtypes = [P32, P32, i32]
+    lib.tchol_factor_solve_batched.restype = i32
+    lib.tchol_factor_solve_batched.argtypes = [vp, P64, P32, vp, P64, P32, P32, i32, i32, P32, vp, i64, vp,
+                                               ctypes.POINTER(Opts)]
     _lib = lib
     return lib
 
@@ -120,6 +128,60 @@ def plan_query(op: int, n: int, nb: int, policy: int = POLICY_RANK, seed: int = 
     a["item_part"] = a["item_part"][:ni]
     a["ntask"], a["nedge"], a["nitem"], a["critical_path"] = nt, ne, ni, int(counts[3])
     return a
+
+
+def _i32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+
+
+def _i64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+
+
+def batched_plan_query(n, nb, policy: int = POLICY_RANK, seed: int = 0) -> dict:
+    """The merged factor + solve DAG of a batched launch (no GPU needed); as
+    plan_query, plus "sys", the system of every task."""
+    lib = load()
+    n32, nb32 = _i32(n), _i32(nb)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    null32, null64 = ctypes.cast(None, P32), ctypes.cast(None, P64)
+    counts = np.zeros(4, dtype=np.int64)
+    p = lambda x: x.ctypes.data_as(P32)
+    rc = lib.tchol_batched_plan_query(p(n32), p(nb32), len(n32), policy, seed, counts.ctypes.data_as(P64), null32,
+                                      null32, null32, null32, null32, null32, null32, null64, null32, null32,
+                                      null32, null32)
+    if rc != 0:
+        raise TcholError(rc, "tchol_batched_plan_query")
+    nt, ne, ni = int(counts[0]), int(counts[1]), int(counts[2])
+    a = {k: np.zeros(max(nt, 1), dtype=np.int32) for k in ("kind", "i", "j", "k", "sys", "parts", "dep0")}
+    a["rank"] = np.zeros(max(nt, 1), dtype=np.int64)
+    a["succ_off"] = np.zeros(nt + 1, dtype=np.int32)
+    a["succ"] = np.zeros(max(ne, 1), dtype=np.int32)
+    a["item_task"] = np.zeros(max(ni, 1), dtype=np.int32)
+    a["item_part"] = np.zeros(max(ni, 1), dtype=np.int32)
+    rc = lib.tchol_batched_plan_query(p(n32), p(nb32), len(n32), policy, seed, counts.ctypes.data_as(P64),
+                                      p(a["kind"]), p(a["i"]), p(a["j"]), p(a["k"]), p(a["sys"]), p(a["parts"]),
+                                      p(a["dep0"]), a["rank"].ctypes.data_as(P64), p(a["succ_off"]), p(a["succ"]),
+                                      p(a["item_task"]), p(a["item_part"]))
+    if rc != 0:
+        raise TcholError(rc, "tchol_batched_plan_query")
+    for k in ("kind", "i", "j", "k", "sys", "parts", "dep0", "rank"):
+        a[k] = a[k][:nt]
+    a["succ"] = a["succ"][:ne]
+    a["item_task"] = a["item_task"][:ni]
+    a["item_part"] = a["item_part"][:ni]
+    a["ntask"], a["nedge"], a["nitem"], a["critical_path"] = nt, ne, ni, int(counts[3])
+    return a
+
+
+def batched_workspace_bytes(n, nb) -> int:
+    n32, nb32 = _i32(n), _i32(nb)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    r = load().tchol_batched_workspace_bytes(n32.ctypes.data_as(P32), nb32.ctypes.data_as(P32), len(n32))
+    if r < 0:
+        raise TcholError(int(r), "tchol_batched_workspace_bytes")
+    return int(r)
 
 
 # ---------------------------------------------------------------- device entry points
@@ -219,3 +281,43 @@ def solve(Lbuf, B, nb: int, **kw):
     solve_(Lbuf, Bc, nb, **kw)
     X = Bc.mT
     return X.reshape(-1) if vec else X
+
+
+def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: int = POLICY_RANK, seed: int = 0,
+                          wait_limit_us: int = 0, ws=None, want_kernel_ms: bool = False, trace=None,
+                          check: bool = True):
+    """Factor and solve many systems in one launch, in place.
+
+    A, B: CUDA float64 1-D tensors holding every system (see
+    tchol_factor_solve_batched for the per-system layout given by the host
+    arrays a_off, lda, b_off, n and nb).  Returns the per-system info array
+    (numpy int32), or (info, kernel_ms)."""
+    torch = _torch()
+    if A.dtype != torch.float64 or B.dtype != torch.float64 or not A.is_contiguous() or not B.is_contiguous():
+        raise ValueError("A and B must be contiguous float64 tensors")
+    a_off, b_off, lda, n, nb = _i64(a_off), _i64(b_off), _i32(lda), _i32(n), _i32(nb)
+    batch = len(n)
+    if not (len(a_off) == len(b_off) == len(lda) == len(nb) == batch):
+        raise ValueError("per-system arrays must have the same length")
+    if batch and (int(np.max(a_off + lda.astype(np.int64) * n)) > A.numel() or
+                  (nrhs and int(np.max(b_off + n.astype(np.int64) * nrhs)) > B.numel())):
+        raise ValueError("a system extends past the end of A or B")
+    info = np.zeros(max(batch, 1), dtype=np.int32)
+    lib = load()
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    with torch.cuda.device(A.device):
+        need = batched_workspace_bytes(n, nb) if batch else 256
+        if ws is None or ws.numel() < need:
+            ws = _workspace(torch, need, A.device)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        rc = lib.tchol_factor_solve_batched(ctypes.c_void_p(A.data_ptr()), a_off.ctypes.data_as(P64),
+                                            lda.ctypes.data_as(P32), ctypes.c_void_p(B.data_ptr()),
+                                            b_off.ctypes.data_as(P64), n.ctypes.data_as(P32),
+                                            nb.ctypes.data_as(P32), int(nrhs), batch, info.ctypes.data_as(P32),
+                                            ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                            _stream_ptr(torch, A.device), ctypes.byref(o))
+    if rc != 0 and check:
+        raise TcholError(rc, "tchol_factor_solve_batched")
+    info = info[:batch]
+    return (info, ms.value) if want_kernel_ms else info

@@ -28,10 +28,15 @@ typedef struct KArgs {
   const int32_t *desc;  /* per task: kind, i, j, k, parts, succ_begin, succ_end, 0 */
   const int32_t *succ;  /* successor lists                                        */
   const int32_t *items; /* per ticket: task, part                                 */
+  const int64_t *sys;   /* per system, SYS_WORDS words: a_off, b_off, n, nb, ld   */
+  int32_t *sinfo;       /* per system: failing column (batched launches)          */
+  int32_t batched;      /* 1: a failing system stops only its own work             */
+  int32_t nsys;
   int64_t wait_limit;   /* bound on one dependency wait, in 100 MHz clock ticks   */
   uint64_t *trace;      /* optional: 4 words per work item                        */
 } KArgs;
 
-#define DESC_WORDS 8
+#define DESC_WORDS 8   /* kind, i, j, k, parts, succ_begin, succ_end, system */
+#define SYS_WORDS 8    /* a_off, b_off, n, nb, ld, 0, 0, 0                    */
 
 #endif

@@ -19,6 +19,10 @@
 //   BTRSV(k)        X_k = L_kk^{-T} Y_k       after FTRSV(T-1) (k = T-1) or BGEMV(k, k+1)
 //   BGEMV(i, k)     Y_i -= L_ki^T X_k, i < k  after BTRSV(k), BGEMV(i, k+1)
 //
+// Batched plans hold several systems (each with its own order and tile
+// size); each system's solve follows its factorization through the edges
+// POTRF(k) -> FTRSV(k) and TRSM(i, k) -> FGEMV(i, k).
+//
 // Priority: the upward rank of HEFT (section 3.1): rank(t) = w(t) + max over
 // successors s of rank(s), with w the task's flop count in units of nb^3/3
 // (POTRF 1, TRSM 3, SYRK 3, GEMM 6; TRSV 1, GEMV 2) and no communication
@@ -39,23 +43,38 @@ namespace tchol {
 
 namespace {
 
+// Adds the tasks of one system to the plan (successor lists kept as
+// vectors, indexed by global task id, turned into CSR afterwards).
 struct Builder {
   Plan& p;
   const Split& s;
-  explicit Builder(Plan& plan, const Split& split) : p(plan), s(split) {}
+  std::vector<std::vector<int32_t>>& succ;
+  int32_t sys;
+  int64_t n, nb;
+  int32_t T;
+  Builder(Plan& plan, const Split& split, std::vector<std::vector<int32_t>>& succ_lists, int32_t system)
+      : p(plan), s(split), succ(succ_lists), sys(system), n(plan.systems[system].n), nb(plan.systems[system].nb),
+        T(plan.systems[system].T) {}
 
-  int64_t tile_size(int32_t t) const { return std::min<int64_t>(p.nb, p.n - (int64_t)t * p.nb); }
+  int64_t tile_size(int32_t t) const { return std::min<int64_t>(nb, n - (int64_t)t * nb); }
 
   int32_t add(int32_t kind, int32_t i, int32_t j, int32_t k, int32_t parts) {
     p.kind.push_back(kind);
     p.ti.push_back(i);
     p.tj.push_back(j);
     p.tk.push_back(k);
+    p.sys.push_back(sys);
     p.parts.push_back(parts);
+    succ.emplace_back();
     return (int32_t)p.kind.size() - 1;
   }
 
   static int32_t cdiv(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
+};
+
+// ids of one system's tasks, for the edges between its factor and solve DAGs
+struct FactorIds {
+  std::vector<int32_t> potrf, trsm;  // trsm[i * T + k]
 };
 
 int64_t weight(int32_t kind) {
@@ -69,10 +88,9 @@ int64_t weight(int32_t kind) {
   }
 }
 
-// successor lists as vectors, turned into CSR afterwards
-void build_factor(Builder& b, std::vector<std::vector<int32_t>>& succ) {
-  Plan& p = b.p;
-  const int32_t T = p.T;
+void build_factor(Builder& b, FactorIds* ids = nullptr) {
+  auto& succ = b.succ;
+  const int32_t T = b.T;
   std::vector<int32_t> id_potrf(T, -1), id_trsm((size_t)T * T, -1), id_syrk((size_t)T * T, -1);
   std::vector<int32_t> id_gemm((size_t)T * T * T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
@@ -90,7 +108,6 @@ void build_factor(Builder& b, std::vector<std::vector<int32_t>>& succ) {
                                           Builder::cdiv(b.tile_size(j), b.s.gemm_n));
     }
   }
-  succ.assign(p.kind.size(), {});
   for (int32_t k = 0; k < T; ++k) {
     for (int32_t i = k + 1; i < T; ++i) succ[id_potrf[k]].push_back(id_trsm[ix2(i, k)]);
     for (int32_t i = k + 1; i < T; ++i) {
@@ -103,11 +120,15 @@ void build_factor(Builder& b, std::vector<std::vector<int32_t>>& succ) {
         succ[id_gemm[ix3(i, j, k)]].push_back(k + 1 < j ? id_gemm[ix3(i, j, k + 1)] : id_trsm[ix2(i, j)]);
     }
   }
+  if (ids) {
+    ids->potrf = id_potrf;
+    ids->trsm = id_trsm;
+  }
 }
 
-void build_solve(Builder& b, std::vector<std::vector<int32_t>>& succ) {
-  Plan& p = b.p;
-  const int32_t T = p.T;
+void build_solve(Builder& b, const FactorIds* after = nullptr) {
+  auto& succ = b.succ;
+  const int32_t T = b.T;
   std::vector<int32_t> id_ft(T), id_bt(T), id_fg((size_t)T * T, -1), id_bg((size_t)T * T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   for (int32_t k = 0; k < T; ++k) {
@@ -120,7 +141,13 @@ void build_solve(Builder& b, std::vector<std::vector<int32_t>>& succ) {
     for (int32_t i = 0; i < k; ++i)
       id_bg[ix2(i, k)] = b.add(TK_BGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
   }
-  succ.assign(p.kind.size(), {});
+  if (after) {
+    // the solve of a system reads the final tiles of its factor
+    for (int32_t k = 0; k < T; ++k) {
+      succ[after->potrf[k]].push_back(id_ft[k]);
+      for (int32_t i = k + 1; i < T; ++i) succ[after->trsm[ix2(i, k)]].push_back(id_fg[ix2(i, k)]);
+    }
+  }
   for (int32_t k = 0; k < T; ++k) {
     for (int32_t i = k + 1; i < T; ++i) {
       succ[id_ft[k]].push_back(id_fg[ix2(i, k)]);
@@ -138,15 +165,17 @@ void build_solve(Builder& b, std::vector<std::vector<int32_t>>& succ) {
 
 // tie-break key: (step, kind, i, j); the backward sweep of the solve comes
 // after the forward one and runs k downwards.
-std::tuple<int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, int32_t t) {
+std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, int32_t t) {
+  const int32_t T = p.systems[p.sys[t]].T;
   int32_t kind = p.kind[t], step = p.tk[t];
-  if (kind == TK_BTRSV || kind == TK_BGEMV) step = p.T + (p.T - 1 - p.tk[t]);
+  if (kind == TK_BTRSV || kind == TK_BGEMV) step = T + (T - 1 - p.tk[t]);
+  if (p.op == TCHOL_OP_BATCHED && kind >= TK_FTRSV) step += T;  // a system's solve after its factor
   int32_t kord = kind;
   if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV
   if (kind == TK_BGEMV) kord = 1;
   if (kind == TK_FTRSV) kord = 0;
   if (kind == TK_FGEMV) kord = 1;
-  return std::make_tuple(step, kord, p.ti[t], p.tj[t]);
+  return std::make_tuple(p.sys[t], step, kord, p.ti[t], p.tj[t]);
 }
 
 uint32_t xorshift32(uint32_t& x) {
@@ -163,46 +192,33 @@ const Split& default_split() {
   return s;
 }
 
-std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed,
-                                 const Split& split) {
-  auto plan = std::make_shared<Plan>();
-  Plan& p = *plan;
-  p.op = op;
-  p.n = n;
-  p.nb = nb;
-  p.policy = policy;
-  p.seed = seed;
-  int64_t T64 = n == 0 ? 0 : (n + nb - 1) / nb;
-  // the largest DAG is the factorization's, about T^3/6 tasks and T^3/2 edges
-  if (T64 > 1200) return nullptr;
-  p.T = (int32_t)T64;
-  if (p.T == 0) {
-    p.succ_off.assign(1, 0);
-    return plan;
-  }
-  Builder b(p, split);
-  std::vector<std::vector<int32_t>> succ;
-  if (op == TCHOL_OP_FACTOR)
-    build_factor(b, succ);
-  else if (op == TCHOL_OP_SOLVE)
-    build_solve(b, succ);
-  else
-    return nullptr;
+namespace {
+
+// dependency counters, CSR successors, upward ranks, claim order and work items
+bool finalize(Plan& p, std::vector<std::vector<int32_t>>& succ, int32_t policy, uint32_t seed) {
   const int64_t nt = p.ntask();
   p.dep0.assign(nt, 0);
   p.succ_off.assign(nt + 1, 0);
   for (int64_t t = 0; t < nt; ++t) {
+    if ((int64_t)p.succ_off[t] + (int64_t)succ[t].size() > (int64_t)INT32_MAX) return false;
     p.succ_off[t + 1] = p.succ_off[t] + (int32_t)succ[t].size();
     for (int32_t s : succ[t]) p.dep0[s]++;
   }
   p.succ.reserve(p.succ_off[nt]);
   for (int64_t t = 0; t < nt; ++t) p.succ.insert(p.succ.end(), succ[t].begin(), succ[t].end());
-  // upward ranks: tasks were created in a topological order, so a reverse sweep suffices
+  // upward ranks: tasks were created in a topological order, so a reverse
+  // sweep suffices.  Systems of different tile sizes are weighed in a common
+  // unit, (16)^3/3 flops, so that their ranks compare.
   p.rank.assign(nt, 0);
   for (int64_t t = nt - 1; t >= 0; --t) {
     int64_t best = 0;
     for (int32_t e = p.succ_off[t]; e < p.succ_off[t + 1]; ++e) best = std::max(best, p.rank[p.succ[e]]);
-    p.rank[t] = weight(p.kind[t]) + best;
+    int64_t w = weight(p.kind[t]);
+    if (p.op == TCHOL_OP_BATCHED) {
+      const int64_t u = p.systems[p.sys[t]].nb / 16;
+      w *= u * u * u;
+    }
+    p.rank[t] = w + best;
   }
   // claim order
   p.order.resize(nt);
@@ -234,7 +250,7 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
   }
   int64_t ni = 0;
   for (int64_t t = 0; t < nt; ++t) ni += p.parts[t];
-  if (ni > (int64_t)INT32_MAX / 2) return nullptr;
+  if (ni > (int64_t)INT32_MAX / 2) return false;
   p.item_task.reserve(ni);
   p.item_part.reserve(ni);
   for (int32_t t : p.order)
@@ -242,6 +258,75 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
       p.item_task.push_back(t);
       p.item_part.push_back(q);
     }
+  return true;
+}
+
+}  // namespace
+
+std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed,
+                                 const Split& split) {
+  auto plan = std::make_shared<Plan>();
+  Plan& p = *plan;
+  p.op = op;
+  p.n = n;
+  p.nb = nb;
+  p.policy = policy;
+  p.seed = seed;
+  int64_t T64 = n == 0 ? 0 : (n + nb - 1) / nb;
+  // the largest DAG is the factorization's, about T^3/6 tasks and T^3/2 edges
+  if (T64 > 1200) return nullptr;
+  p.T = (int32_t)T64;
+  System sy;
+  sy.n = n;
+  sy.nb = nb;
+  sy.ld = n;
+  sy.T = p.T;
+  p.systems.push_back(sy);
+  if (p.T == 0) {
+    p.succ_off.assign(1, 0);
+    return plan;
+  }
+  std::vector<std::vector<int32_t>> succ;
+  Builder b(p, split, succ, 0);
+  if (op == TCHOL_OP_FACTOR)
+    build_factor(b);
+  else if (op == TCHOL_OP_SOLVE)
+    build_solve(b);
+  else
+    return nullptr;
+  if (!finalize(p, succ, policy, seed)) return nullptr;
+  return plan;
+}
+
+std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
+                                         const Split& split) {
+  auto plan = std::make_shared<Plan>();
+  Plan& p = *plan;
+  p.op = TCHOL_OP_BATCHED;
+  p.policy = policy;
+  p.seed = seed;
+  p.systems = systems;
+  int64_t est = 0;
+  for (auto& sy : p.systems) {
+    const int64_t T64 = sy.n == 0 ? 0 : (sy.n + sy.nb - 1) / sy.nb;
+    if (T64 > 1200) return nullptr;
+    sy.T = (int32_t)T64;
+    est += T64 * T64 * T64 / 6 + 3 * T64 * T64 + 4;
+  }
+  if (est > (int64_t)INT32_MAX / 4) return nullptr;
+  std::vector<std::vector<int32_t>> succ;
+  for (int32_t s = 0; s < (int32_t)p.systems.size(); ++s) {
+    if (p.systems[s].T == 0) continue;
+    Builder b(p, split, succ, s);
+    FactorIds ids;
+    build_factor(b, &ids);
+    build_solve(b, &ids);
+  }
+  if (p.ntask() == 0) {
+    p.succ_off.assign(1, 0);
+    return plan;
+  }
+  if (!finalize(p, succ, policy, seed)) return nullptr;
   return plan;
 }
 

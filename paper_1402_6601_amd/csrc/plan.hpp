@@ -19,19 +19,30 @@
 
 namespace tchol {
 
+// One system of a plan: its matrix and right-hand sides, as offsets (in
+// elements) from the launch's base pointers, and its order and tile size.
+struct System {
+  int64_t a_off = 0, b_off = 0;  // A_s at A + a_off (column-major, ld), B_s at B + b_off (ld n)
+  int64_t n = 0, nb = 0, ld = 0;
+  int32_t T = 0;                 // tiles per side
+};
+
 struct Plan {
-  int32_t op = 0;          // TCHOL_OP_FACTOR / TCHOL_OP_SOLVE
-  int64_t n = 0, nb = 0;   // matrix order, tile size
-  int32_t T = 0;           // tiles per side
+  int32_t op = 0;          // TCHOL_OP_FACTOR / TCHOL_OP_SOLVE / TCHOL_OP_BATCHED
+  int64_t n = 0, nb = 0;   // matrix order, tile size (single-system plans)
+  int32_t T = 0;           // tiles per side (single-system plans)
   int32_t policy = 0;      // TCHOL_POLICY_*
   uint32_t seed = 0;       // for TCHOL_POLICY_RANDOM
+  std::vector<System> systems;             // one for factor and solve plans
   // per task
   std::vector<int32_t> kind, ti, tj, tk;   // kind and tile coordinates (i, j, k)
+  std::vector<int32_t> sys;                // the system the task belongs to
   std::vector<int32_t> parts;              // work items the task is split into
   std::vector<int32_t> dep0;               // initial dependency counter (in-degree)
   std::vector<int32_t> succ_off;           // CSR successor lists, size ntask + 1
   std::vector<int32_t> succ;
-  std::vector<int64_t> rank;               // upward rank, in units of nb^3/3 flops
+  std::vector<int64_t> rank;               // upward rank, in units of nb^3/3 flops (of (nb/16)^3
+                                           // 16^3/3 flops in batched plans, whose systems differ in nb)
   std::vector<int32_t> order;              // tasks in claim order
   std::vector<int32_t> item_task, item_part;  // work items in ticket order
   int64_t ntask() const { return (int64_t)kind.size(); }
@@ -53,6 +64,13 @@ std::shared_ptr<const Plan> get_plan(int32_t op, int64_t n, int64_t nb, int32_t 
 // Uncached build, used by get_plan and by the plan-introspection entry point.
 std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed,
                                  const Split& split);
+
+// Factorization followed by the solve, for every system, as one DAG: each
+// system's factor tasks, then its solve tasks, joined by the data-flow
+// edges POTRF(k) -> FTRSV(k) and TRSM(i, k) -> FGEMV(i, k).  Uncached.
+// Returns nullptr if the task count exceeds what the kernel indexes.
+std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
+                                         const Split& split);
 
 const Split& default_split();
 

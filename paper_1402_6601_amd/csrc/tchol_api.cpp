@@ -13,7 +13,7 @@
 #include "kargs.h"
 #include "plan.hpp"
 
-extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid,
+extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid, int wide,
                                        hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 extern "C" hipError_t tchol_dev_max_grid(int device, int* grid);
 
@@ -25,28 +25,31 @@ constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Byte offsets of the workspace regions.  [dep0, end) is a copy of the
-// plan's constant image, uploaded in one transfer; hdr, dep and done are
+// plan's constant image (counters, descriptors, successors, ticket list and
+// the system table), uploaded in one transfer; hdr, dep, done and sinfo are
 // (re)initialised by a small kernel on every call.
 struct Layout {
-  int64_t hdr = 0, dep = 0, done = 0, dep0 = 0, desc = 0, succ = 0, items = 0, end = 0;
+  int64_t hdr = 0, dep = 0, done = 0, sinfo = 0, dep0 = 0, desc = 0, succ = 0, items = 0, sys = 0, end = 0;
 };
 
 Layout layout_of(const Plan& p) {
   Layout L;
-  const int64_t nt = p.ntask();
+  const int64_t nt = p.ntask(), ns = (int64_t)p.systems.size();
   L.hdr = 0;
   L.dep = align_up(HDR_WORDS * 4);
   L.done = align_up(L.dep + 4 * nt);
-  L.dep0 = align_up(L.done + 4 * nt);
+  L.sinfo = align_up(L.done + 4 * nt);
+  L.dep0 = align_up(L.sinfo + 4 * ns);
   L.desc = align_up(L.dep0 + 4 * nt);
   L.succ = align_up(L.desc + 4 * DESC_WORDS * nt);
   L.items = align_up(L.succ + 4 * p.nedge());
-  L.end = align_up(L.items + 8 * p.nitem());
+  L.sys = align_up(L.items + 8 * p.nitem());
+  L.end = align_up(L.sys + 8 * SYS_WORDS * ns);
   return L;
 }
 
-// The constant part of the workspace for one plan, built once, in pinned
-// host memory when the runtime can provide it.
+// The constant part of the workspace for one plan, in pinned host memory
+// when the runtime can provide it.
 struct Image {
   Layout lay;
   std::vector<char> pageable;
@@ -58,6 +61,57 @@ struct Image {
   }
 };
 
+std::shared_ptr<Image> make_image(const Plan& p, bool pin) {
+  auto img = std::make_shared<Image>();
+  img->lay = layout_of(p);
+  const Layout& L = img->lay;
+  img->bytes = L.end - L.dep0;
+  char* buf = nullptr;
+  if (pin && hipHostMalloc(reinterpret_cast<void**>(&buf), (size_t)img->bytes, hipHostMallocDefault) == hipSuccess &&
+      buf) {
+    img->pinned = buf;
+  } else {
+    if (pin) (void)hipGetLastError();
+    img->pageable.resize((size_t)img->bytes);
+    buf = img->pageable.data();
+  }
+  std::memset(buf, 0, (size_t)img->bytes);
+  const int64_t nt = p.ntask();
+  int32_t* dep0 = reinterpret_cast<int32_t*>(buf + (L.dep0 - L.dep0));
+  int32_t* desc = reinterpret_cast<int32_t*>(buf + (L.desc - L.dep0));
+  int32_t* succ = reinterpret_cast<int32_t*>(buf + (L.succ - L.dep0));
+  int32_t* items = reinterpret_cast<int32_t*>(buf + (L.items - L.dep0));
+  int64_t* sys = reinterpret_cast<int64_t*>(buf + (L.sys - L.dep0));
+  for (int64_t t = 0; t < nt; ++t) {
+    dep0[t] = p.dep0[t];
+    int32_t* d = desc + DESC_WORDS * t;
+    d[0] = p.kind[t];
+    d[1] = p.ti[t];
+    d[2] = p.tj[t];
+    d[3] = p.tk[t];
+    d[4] = p.parts[t];
+    d[5] = p.succ_off[t];
+    d[6] = p.succ_off[t + 1];
+    d[7] = p.sys[t];
+  }
+  if (p.nedge()) std::memcpy(succ, p.succ.data(), 4 * (size_t)p.nedge());
+  for (int64_t i = 0; i < p.nitem(); ++i) {
+    items[2 * i] = p.item_task[i];
+    items[2 * i + 1] = p.item_part[i];
+  }
+  for (size_t s = 0; s < p.systems.size(); ++s) {
+    const tchol::System& sy = p.systems[s];
+    int64_t* r = sys + SYS_WORDS * s;
+    r[0] = sy.a_off;
+    r[1] = sy.b_off;
+    r[2] = sy.n;
+    r[3] = sy.nb;
+    r[4] = sy.ld;
+  }
+  return img;
+}
+
+// Cached per plan (single-system plans are themselves cached).
 std::shared_ptr<const Image> image_of(const std::shared_ptr<const Plan>& p) {
   static std::mutex mu;
   static std::map<const Plan*, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
@@ -66,44 +120,10 @@ std::shared_ptr<const Image> image_of(const std::shared_ptr<const Plan>& p) {
     auto it = cache.find(p.get());
     if (it != cache.end() && !it->second.first.expired()) return it->second.second;
   }
-  auto img = std::make_shared<Image>();
-  img->lay = layout_of(*p);
-  const Layout& L = img->lay;
-  img->bytes = L.end - L.dep0;
-  char* buf = nullptr;
-  if (hipHostMalloc(reinterpret_cast<void**>(&buf), (size_t)img->bytes, hipHostMallocDefault) == hipSuccess && buf) {
-    img->pinned = buf;
-  } else {
-    (void)hipGetLastError();
-    img->pageable.resize((size_t)img->bytes);
-    buf = img->pageable.data();
-  }
-  std::memset(buf, 0, (size_t)img->bytes);
-  const int64_t nt = p->ntask();
-  int32_t* dep0 = reinterpret_cast<int32_t*>(buf + (L.dep0 - L.dep0));
-  int32_t* desc = reinterpret_cast<int32_t*>(buf + (L.desc - L.dep0));
-  int32_t* succ = reinterpret_cast<int32_t*>(buf + (L.succ - L.dep0));
-  int32_t* items = reinterpret_cast<int32_t*>(buf + (L.items - L.dep0));
-  for (int64_t t = 0; t < nt; ++t) {
-    dep0[t] = p->dep0[t];
-    int32_t* d = desc + DESC_WORDS * t;
-    d[0] = p->kind[t];
-    d[1] = p->ti[t];
-    d[2] = p->tj[t];
-    d[3] = p->tk[t];
-    d[4] = p->parts[t];
-    d[5] = p->succ_off[t];
-    d[6] = p->succ_off[t + 1];
-    d[7] = 0;
-  }
-  if (p->nedge()) std::memcpy(succ, p->succ.data(), 4 * (size_t)p->nedge());
-  for (int64_t i = 0; i < p->nitem(); ++i) {
-    items[2 * i] = p->item_task[i];
-    items[2 * i + 1] = p->item_part[i];
-  }
+  std::shared_ptr<const Image> img = make_image(*p, true);
   std::lock_guard<std::mutex> g(mu);
   if (cache.size() > 64) cache.clear();
-  cache[p.get()] = std::make_pair(std::weak_ptr<const Plan>(p), std::shared_ptr<const Image>(img));
+  cache[p.get()] = std::make_pair(std::weak_ptr<const Plan>(p), img);
   return img;
 }
 
@@ -140,16 +160,15 @@ bool nb_ok(int64_t nb) { return nb >= TCHOL_NB_MIN && nb <= TCHOL_NB_MAX && nb %
 
 const tchol_opts kDefaultOpts = {TCHOL_POLICY_RANK, 0u, 0, nullptr, nullptr};
 
-int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrhs, void* ws, int64_t ws_bytes,
-            void* stream_v, const tchol_opts* opts, int32_t ws_arg) {
-  const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
-  auto plan = tchol::get_plan(op, n, nb, o.policy, o.seed);
-  if (!plan) return TCHOL_E_UNSUPPORTED;
-  const Layout L = layout_of(*plan);
+// Uploads the plan image, launches reset + persistent kernel on the stream,
+// reads the header back and synchronises.  sinfo_out (batched): per-system
+// failing columns.  Returns the library code.
+int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_t nrhs, bool wide, bool batched,
+                void* ws, int64_t ws_bytes, void* stream_v, const tchol_opts& o, int32_t ws_arg,
+                int32_t* sinfo_out) {
+  const Layout& L = img.lay;
   if (ws_bytes < L.end) return -(ws_arg + 1);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
-  auto img = image_of(plan);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
   DeviceInfo di;
   if (device_info(&di) != hipSuccess) return TCHOL_E_HIP;
@@ -158,13 +177,13 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
   std::memset(&a, 0, sizeof(a));
   a.A = A;
   a.B = B;
-  a.n = n;
-  a.nb = nb;
-  a.ld = n;
-  a.ldb = n;
+  a.n = plan.n;
+  a.nb = plan.nb;
+  a.ld = plan.n;
+  a.ldb = plan.n;
   a.nrhs = nrhs;
-  a.T = plan->T;
-  a.nitem = (int32_t)plan->nitem();
+  a.T = plan.T;
+  a.nitem = (int32_t)plan.nitem();
   const tchol::Split& sp = tchol::default_split();
   a.gemm_m = sp.gemm_m;
   a.gemm_n = sp.gemm_n;
@@ -176,6 +195,10 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
   a.desc = reinterpret_cast<const int32_t*>(w + L.desc);
   a.succ = reinterpret_cast<const int32_t*>(w + L.succ);
   a.items = reinterpret_cast<const int32_t*>(w + L.items);
+  a.sys = reinterpret_cast<const int64_t*>(w + L.sys);
+  a.sinfo = reinterpret_cast<int32_t*>(w + L.sinfo);
+  a.batched = batched ? 1 : 0;
+  a.nsys = (int32_t)plan.systems.size();
   const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
   a.wait_limit = limit_us * di.clock_khz / 1000;
   a.trace = o.trace;
@@ -183,16 +206,18 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int32_t rc = 0;
   int32_t hdr[HDR_WORDS];
-  hipError_t e = hipMemcpyAsync(w + L.dep0, img->data(), (size_t)img->bytes, hipMemcpyHostToDevice, stream);
+  hipError_t e = hipMemcpyAsync(w + L.dep0, img.data(), (size_t)img.bytes, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess && o.kernel_ms) {
     e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
   }
-  const int grid = (int)std::min<int64_t>(di.grid, std::max<int64_t>(1, plan->nitem()));
+  const int grid = (int)std::min<int64_t>(di.grid, std::max<int64_t>(1, plan.nitem()));
   if (e == hipSuccess)
-    e = tchol_dev_launch(&a, (int32_t)plan->ntask(), reinterpret_cast<const int32_t*>(w + L.dep0), grid, stream,
-                         ev0, ev1);
+    e = tchol_dev_launch(&a, (int32_t)plan.ntask(), reinterpret_cast<const int32_t*>(w + L.dep0), grid,
+                         wide ? 1 : 0, stream, ev0, ev1);
   if (e == hipSuccess) e = hipMemcpyAsync(hdr, a.hdr, sizeof(hdr), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && sinfo_out && a.nsys > 0)
+    e = hipMemcpyAsync(sinfo_out, a.sinfo, 4 * (size_t)a.nsys, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e == hipSuccess && o.kernel_ms) {
     float ms = 0.f;
@@ -211,6 +236,81 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
   else if (hdr[HDR_DONE] != a.nitem)
     rc = TCHOL_E_INTERNAL;
   return rc;
+}
+
+int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrhs, void* ws, int64_t ws_bytes,
+            void* stream_v, const tchol_opts* opts, int32_t ws_arg) {
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
+  auto plan = tchol::get_plan(op, n, nb, o.policy, o.seed);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  auto img = image_of(plan);
+  // 16-byte panel transfers need an even leading dimension and an aligned matrix
+  const bool wide = (n % 2 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
+  return execute(*plan, *img, A, B, nrhs, wide, false, ws, ws_bytes, stream_v, o, ws_arg, nullptr);
+}
+
+void fill_query(const Plan& pl, int64_t* counts, int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* sys,
+                int32_t* parts, int32_t* dep0, int64_t* rank, int32_t* succ_off, int32_t* succ, int32_t* item_task,
+                int32_t* item_part) {
+  const Plan* p = &pl;
+  const int64_t nt = p->ntask();
+  if (counts) {
+    // longest path counted in tasks; creation order is topological
+    std::vector<int32_t> depth(nt, 1);
+    int32_t cp = 0;
+    for (int64_t t = nt - 1; t >= 0; --t) {
+      int32_t best = 0;
+      for (int32_t e = p->succ_off[t]; e < p->succ_off[t + 1]; ++e) best = std::max(best, depth[p->succ[e]]);
+      depth[t] = 1 + best;
+      cp = std::max(cp, depth[t]);
+    }
+    counts[0] = nt;
+    counts[1] = p->nedge();
+    counts[2] = p->nitem();
+    counts[3] = cp;
+  }
+  for (int64_t t = 0; t < nt; ++t) {
+    if (kind) kind[t] = p->kind[t];
+    if (ti) ti[t] = p->ti[t];
+    if (tj) tj[t] = p->tj[t];
+    if (tk) tk[t] = p->tk[t];
+    if (sys) sys[t] = p->sys[t];
+    if (parts) parts[t] = p->parts[t];
+    if (dep0) dep0[t] = p->dep0[t];
+    if (rank) rank[t] = p->rank[t];
+  }
+  if (succ_off) std::copy(p->succ_off.begin(), p->succ_off.end(), succ_off);
+  if (succ) std::copy(p->succ.begin(), p->succ.end(), succ);
+  if (item_task) std::copy(p->item_task.begin(), p->item_task.end(), item_task);
+  if (item_part) std::copy(p->item_part.begin(), p->item_part.end(), item_part);
+}
+
+// Validates the batched arguments and collects the systems; returns 0 or -i.
+int32_t batched_systems(const int64_t* a_off, const int32_t* lda, const int64_t* b_off, const int32_t* n,
+                        const int32_t* nb, int32_t batch, std::vector<tchol::System>* out) {
+  if (batch < 0) return -9;
+  if (batch > 0 && !n) return -6;
+  if (batch > 0 && !nb) return -7;
+  out->clear();
+  out->reserve(batch);
+  for (int32_t s = 0; s < batch; ++s) {
+    if (n[s] < 0) return -6;
+    if (!nb_ok(nb[s])) return -7;
+    tchol::System sy;
+    sy.n = n[s];
+    sy.nb = nb[s];
+    if (out && a_off && lda && b_off) {
+      if (a_off[s] < 0) return -2;
+      if (lda[s] < std::max<int32_t>(1, n[s])) return -3;
+      if (b_off[s] < 0) return -5;
+      sy.a_off = a_off[s];
+      sy.ld = lda[s];
+      sy.b_off = b_off[s];
+    }
+    out->push_back(sy);
+  }
+  return 0;
 }
 
 }  // namespace
@@ -261,6 +361,60 @@ int32_t tchol_solve(const double* L, int64_t n, int64_t nb, double* B, int64_t n
   return tchol_solve_ex(L, n, nb, B, nrhs, ws, ws_bytes, stream, nullptr);
 }
 
+int64_t tchol_batched_workspace_bytes(const int32_t* n, const int32_t* nb, int32_t batch) {
+  std::vector<tchol::System> systems;
+  if (batch < 0) return -3;
+  if (batch > 0 && !n) return -1;
+  if (batch > 0 && !nb) return -2;
+  const int32_t rc = batched_systems(nullptr, nullptr, nullptr, n, nb, batch, &systems);
+  if (rc == -6) return -1;
+  if (rc == -7) return -2;
+  if (rc != 0) return rc;
+  auto plan = tchol::build_batched_plan(systems, TCHOL_POLICY_RANK, 0, tchol::default_split());
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  return layout_of(*plan).end;
+}
+
+int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_t* lda, double* B,
+                                   const int64_t* b_off, const int32_t* n, const int32_t* nb, int32_t nrhs,
+                                   int32_t batch, int32_t* info, void* ws, int64_t ws_bytes, void* stream,
+                                   const tchol_opts* opts) {
+  if (nrhs < 0) return -8;
+  if (batch < 0) return -9;
+  if (batch == 0) return 0;
+  if (!a_off) return -2;
+  if (!lda) return -3;
+  if (!b_off) return -5;
+  if (!info) return -10;
+  std::vector<tchol::System> systems;
+  const int32_t rc = batched_systems(a_off, lda, b_off, n, nb, batch, &systems);
+  if (rc != 0) return rc;
+  bool any = false, wide = true;
+  for (auto& sy : systems) {
+    if (sy.n == 0) continue;
+    any = true;
+    // 16-byte transfers move rows in pairs: even ld, aligned columns, and a
+    // row after the last one when the order is odd
+    if (sy.ld % 2 != 0 || (reinterpret_cast<uintptr_t>(A + sy.a_off) % 16) != 0 || (sy.n % 2 != 0 && sy.ld <= sy.n))
+      wide = false;
+  }
+  for (int32_t s = 0; s < batch; ++s) info[s] = 0;
+  if (!any) return 0;
+  if (!A) return -1;
+  if (nrhs > 0 && !B) return -4;
+  if (!ws) return -11;
+  if (ws_bytes <= 0) return -12;
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
+  if (nrhs == 0) {
+    // nothing to solve: the plan still holds the solve tasks, which then have no columns
+  }
+  auto plan = tchol::build_batched_plan(systems, o.policy, o.seed, tchol::default_split());
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  auto img = make_image(*plan, false);
+  return execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 11, info);
+}
+
 const char* tchol_strerror(int32_t code) {
   if (code == 0) return "success";
   if (code > 0) return "matrix is not positive definite (leading minor of order `code`)";
@@ -283,35 +437,26 @@ int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint
   if (policy < TCHOL_POLICY_RANK || policy > TCHOL_POLICY_RANDOM) return -4;
   auto p = tchol::get_plan(op, n, nb, policy, seed);
   if (!p) return TCHOL_E_UNSUPPORTED;
-  const int64_t nt = p->ntask();
-  if (counts) {
-    // longest path counted in tasks; creation order is topological
-    std::vector<int32_t> depth(nt, 1);
-    int32_t cp = 0;
-    for (int64_t t = nt - 1; t >= 0; --t) {
-      int32_t best = 0;
-      for (int32_t e = p->succ_off[t]; e < p->succ_off[t + 1]; ++e) best = std::max(best, depth[p->succ[e]]);
-      depth[t] = 1 + best;
-      cp = std::max(cp, depth[t]);
-    }
-    counts[0] = nt;
-    counts[1] = p->nedge();
-    counts[2] = p->nitem();
-    counts[3] = cp;
-  }
-  for (int64_t t = 0; t < nt; ++t) {
-    if (kind) kind[t] = p->kind[t];
-    if (ti) ti[t] = p->ti[t];
-    if (tj) tj[t] = p->tj[t];
-    if (tk) tk[t] = p->tk[t];
-    if (parts) parts[t] = p->parts[t];
-    if (dep0) dep0[t] = p->dep0[t];
-    if (rank) rank[t] = p->rank[t];
-  }
-  if (succ_off) std::copy(p->succ_off.begin(), p->succ_off.end(), succ_off);
-  if (succ) std::copy(p->succ.begin(), p->succ.end(), succ);
-  if (item_task) std::copy(p->item_task.begin(), p->item_task.end(), item_task);
-  if (item_part) std::copy(p->item_part.begin(), p->item_part.end(), item_part);
+  fill_query(*p, counts, kind, ti, tj, tk, nullptr, parts, dep0, rank, succ_off, succ, item_task, item_part);
+  return 0;
+}
+
+int32_t tchol_batched_plan_query(const int32_t* n, const int32_t* nb, int32_t batch, int32_t policy, uint32_t seed,
+                                 int64_t* counts, int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* sys,
+                                 int32_t* parts, int32_t* dep0, int64_t* rank, int32_t* succ_off, int32_t* succ,
+                                 int32_t* item_task, int32_t* item_part) {
+  if (batch < 0) return -3;
+  if (batch > 0 && !n) return -1;
+  if (batch > 0 && !nb) return -2;
+  if (policy < TCHOL_POLICY_RANK || policy > TCHOL_POLICY_RANDOM) return -4;
+  std::vector<tchol::System> systems;
+  const int32_t rc = batched_systems(nullptr, nullptr, nullptr, n, nb, batch, &systems);
+  if (rc == -6) return -1;
+  if (rc == -7) return -2;
+  if (rc != 0) return rc;
+  auto p = tchol::build_batched_plan(systems, policy, seed, tchol::default_split());
+  if (!p) return TCHOL_E_UNSUPPORTED;
+  fill_query(*p, counts, kind, ti, tj, tk, sys, parts, dep0, rank, succ_off, succ, item_task, item_part);
   return 0;
 }
 

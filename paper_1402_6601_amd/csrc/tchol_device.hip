@@ -82,9 +82,10 @@ __device__ __forceinline__ void wait_vmcnt() {
 // (BN*WGM/4) piece of C as 16x16 MFMA blocks held in registers from the load
 // of C to the final store.  K is streamed in chunks of KC
 // columns through NST LDS stages filled by direct-to-LDS loads, NST-1 chunks
-// ahead of the matrix cores.  SEG = 128 moves 16 bytes per lane and needs
-// even M and N, even ld and 16-byte aligned panels; SEG = 32 moves 4 bytes
-// per lane and has no such needs.  Row indices are clamped into the panel
+// ahead of the matrix cores.  SEG = 128 moves 16 bytes per lane (rows in
+// pairs) and needs even ld, 16-byte aligned panels, and, when M or N is odd,
+// one readable row after the panel; SEG = 32 moves 4 bytes per lane and has
+// no such needs.  Row indices are clamped into the panel
 // (rows past M hold copies and only feed outputs that are never stored).  With lower_only, entries of C above its diagonal are untouched.
 // With Cl set, the result goes to LDS at Cl (column-major, leading dimension
 // ldl; it must not overlap the NST stages) instead of back to C.
@@ -140,7 +141,10 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
     const int c = e / R;
     const double* src;
     if (SEG == 128) {
-      src = X + (int64_t)(k0 + c) * ld + imin(e % R, V - 2);
+      // a pair starts at an even row no later than V - 1; for odd V the
+      // pair (V - 1, V) reads the row after the panel, which the launch
+      // contract guarantees to exist (leading dimension above the order)
+      src = X + (int64_t)(k0 + c) * ld + imin(e % R, (V - 1) & ~1);
       dma16(src, dst + (e0 / R) * XLD + e0 % R);
     } else {
       src = X + (int64_t)(k0 + c) * ld + imin(e % R, V - 1);
@@ -874,9 +878,9 @@ __device__ __forceinline__ int ld_relaxed(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int64_t tile_size(const KArgs& a, int t) {
-  const int64_t r = a.n - (int64_t)t * a.nb;
-  return r < a.nb ? r : a.nb;
+__device__ __forceinline__ int64_t tile_size(int64_t n, int64_t nb, int t) {
+  const int64_t r = n - (int64_t)t * nb;
+  return r < nb ? r : nb;
 }
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -914,7 +918,8 @@ __device__ __forceinline__ void raise_error(const KArgs& a, int code) {
   }
 }
 
-// SEG = 128: the launch guarantees even n and a 16-byte aligned matrix, so
+// SEG = 128: the launch guarantees even leading dimensions, 16-byte aligned
+// matrices and, for odd orders, a leading dimension above the order, so
 // every panel the updates stream is 16-byte transferable; SEG = 32 serves
 // every other case.  One transfer width per kernel instance keeps the
 // update loops free of per-item branches.
@@ -954,25 +959,38 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     if (task < 0) break;
     const int32_t* d = a.desc + DESC_WORDS * (int64_t)task;
     const int kind = uniform_i(d[0]), ti = uniform_i(d[1]), tj = uniform_i(d[2]), tk = uniform_i(d[3]);
-    const int64_t ld = a.ld, nb = a.nb;
+    // the task's system: base pointers, order, tile size, leading dimension
+    const int sid = uniform_i(d[7]);
+    const int64_t* sr = a.sys + SYS_WORDS * (int64_t)sid;
+    double* const Abase = a.A + sr[0];
+    double* const Bbase = a.B + sr[1];
+    const int64_t sn = sr[2], nb = sr[3], ld = sr[4], ldb = sn;
+    auto tsz = [&](int t) __attribute__((always_inline)) { return (int)tile_size(sn, nb, t); };
+    // in a batched launch a system whose factorization failed only passes
+    // its remaining tasks on, so that the DAG drains
+    const bool skip = a.batched && uniform_i(ld_relaxed(&a.sinfo[sid])) != 0;
     int ok = 1;
-    switch (kind) {
+    switch (skip ? -1 : kind) {
+      case -1:
+        break;
       case TK_POTRF: {
-        double* Akk = a.A + (tk * nb) * ld + tk * nb;
-        const int info = uniform_i(potrf_tile<SEG>(Akk, ld, (int)tile_size(a, tk), lds));
-        if (info != 0) {
-          ok = 0;
-          if (tid == 0) {
+        double* Akk = Abase + (tk * nb) * ld + tk * nb;
+        const int info = uniform_i(potrf_tile<SEG>(Akk, ld, tsz(tk), lds));
+        if (info != 0 && tid == 0) {
+          if (a.batched) {
+            __hip_atomic_store(&a.sinfo[sid], (int)(tk * nb) + info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
             __hip_atomic_store(&a.hdr[HDR_INFO], (int)(tk * nb) + info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.hdr[HDR_ABORT], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
+        if (info != 0 && !a.batched) ok = 0;
         break;
       }
       case TK_TRSM: {
         const int r0 = part * a.trsm_rows;
-        const int S = imin(a.trsm_rows, (int)tile_size(a, ti) - r0);
-        trsm_strip(a.A + (tk * nb) * ld + ti * nb + r0, a.A + (tk * nb) * ld + tk * nb, ld, S, (int)tile_size(a, tk),
+        const int S = imin(a.trsm_rows, tsz(ti) - r0);
+        trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, Abase + (tk * nb) * ld + tk * nb, ld, S, tsz(tk),
                    lds);
         break;
       }
@@ -984,41 +1002,41 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           while ((si + 1) * (si + 2) / 2 <= part) ++si;
           sj = part - si * (si + 1) / 2;
         } else {
-          const int ncj = (int)((tile_size(a, tj) + a.gemm_n - 1) / a.gemm_n);
+          const int ncj = (tsz(tj) + a.gemm_n - 1) / a.gemm_n;
           si = part / ncj;
           sj = part % ncj;
         }
-        const int M = imin(a.gemm_m, (int)tile_size(a, ti) - si * a.gemm_m);
-        const int N = imin(a.gemm_n, (int)tile_size(a, tj) - sj * a.gemm_n);
-        double* C = a.A + (tj * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m;
-        const double* Ap = a.A + (tk * nb) * ld + ti * nb + si * a.gemm_m;
-        const double* Bp = a.A + (tk * nb) * ld + tj * nb + sj * a.gemm_n;
-        if (SEG == 128 && (((M | N | (int)ld) & 1) != 0 ||
+        const int M = imin(a.gemm_m, tsz(ti) - si * a.gemm_m);
+        const int N = imin(a.gemm_n, tsz(tj) - sj * a.gemm_n);
+        double* C = Abase + (tj * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m;
+        const double* Ap = Abase + (tk * nb) * ld + ti * nb + si * a.gemm_m;
+        const double* Bp = Abase + (tk * nb) * ld + tj * nb + sj * a.gemm_n;
+        if (SEG == 128 && (((int)ld & 1) != 0 || (((M | N) & 1) != 0 && ld <= sn) ||
                            ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) != 0)) {
           raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
           ok = 0;
           break;
         }
-        gemm_nt<SEG>(C, Ap, Bp, ld, M, N, (int)tile_size(a, tk), kind == TK_SYRK && si == sj, lds);
+        gemm_nt<SEG>(C, Ap, Bp, ld, M, N, tsz(tk), kind == TK_SYRK && si == sj, lds);
         break;
       }
       case TK_FTRSV:
       case TK_BTRSV:
-        tile_solve(a.A + (tk * nb) * ld + tk * nb, ld, a.B + tk * nb, a.ldb, (int)tile_size(a, tk), (int)a.nrhs,
+        tile_solve(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
                    kind == TK_BTRSV, lds);
         break;
       case TK_FGEMV: {
         const int r0 = part * a.gemv_rows;
-        const int rows = imin(a.gemv_rows, (int)tile_size(a, ti) - r0);
-        fgemv(a.A + (tk * nb) * ld + ti * nb + r0, ld, a.B + ti * nb + r0, a.B + tk * nb, a.ldb, rows,
-              (int)tile_size(a, tk), (int)a.nrhs, lds);
+        const int rows = imin(a.gemv_rows, tsz(ti) - r0);
+        fgemv(Abase + (tk * nb) * ld + ti * nb + r0, ld, Bbase + ti * nb + r0, Bbase + tk * nb, ldb, rows, tsz(tk),
+              (int)a.nrhs, lds);
         break;
       }
       case TK_BGEMV: {
         const int c0 = part * a.gemv_rows;
-        const int cols = imin(a.gemv_rows, (int)tile_size(a, ti) - c0);
-        bgemv(a.A + (ti * nb + c0) * ld + tk * nb, ld, a.B + ti * nb + c0, a.B + tk * nb, a.ldb, cols,
-              (int)tile_size(a, tk), (int)a.nrhs, lds);
+        const int cols = imin(a.gemv_rows, tsz(ti) - c0);
+        bgemv(Abase + (ti * nb + c0) * ld + tk * nb, ld, Bbase + ti * nb + c0, Bbase + tk * nb, ldb, cols, tsz(tk),
+              (int)a.nrhs, lds);
         break;
       }
       default:
@@ -1056,28 +1074,32 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
 
 // Clears the header and the per-task completion counters and copies the
 // initial dependency counters; the plan's constant part is copied by the host.
-__global__ void tchol_reset(int32_t* hdr, int32_t* dep, int32_t* done, const int32_t* dep0, int32_t ntask) {
+__global__ void tchol_reset(int32_t* hdr, int32_t* dep, int32_t* done, const int32_t* dep0, int32_t ntask,
+                            int32_t* sinfo, int32_t nsys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < HDR_WORDS) hdr[i] = 0;
   if (i < ntask) {
     dep[i] = dep0[i];
     done[i] = 0;
   }
+  if (i < nsys) sinfo[i] = 0;
 }
 
-extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid,
+// wide: every panel the launch streams is 16-byte transferable (even
+// leading dimensions, 16-byte aligned matrices), decided by the host.
+extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid, int wide,
                                        hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
   const int rb = 256;
-  const int64_t cover = ntask > HDR_WORDS ? ntask : HDR_WORDS;
+  int64_t cover = ntask > HDR_WORDS ? ntask : HDR_WORDS;
+  if (a->nsys > cover) cover = a->nsys;
   hipLaunchKernelGGL(tchol_reset, dim3((unsigned)((cover + rb - 1) / rb)), dim3(rb), 0, stream, a->hdr, a->dep,
-                     a->done, dep0, ntask);
+                     a->done, dep0, ntask, a->sinfo, a->nsys);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev0) {
     e = hipEventRecord(ev0, stream);
     if (e != hipSuccess) return e;
   }
-  const bool wide = (a->ld % 2 == 0) && (reinterpret_cast<uintptr_t>(a->A) % 16 == 0);
   if (wide)
     hipLaunchKernelGGL(tchol_persistent<128>, dim3(grid), dim3(NT), 0, stream, *a);
   else

@@ -13,6 +13,11 @@ generated; the family used here stands in for them:
 
 ``shift`` is 1 for the plain FP64 workloads (condition number about 2.3) and
 1e-4 for the mixed-precision workload (condition number about 1.3e4).
+
+Batched workloads draw the orders first, ``ns = rng.integers(lo, hi + 1,
+count)``, then, system by system in index order, B_i (n_i x n_i) and the
+right-hand sides b_i (n_i x nrhs) from the same stream, with
+A_i = B_i B_i^T / n_i + shift I.
 """
 from __future__ import annotations
 
@@ -20,7 +25,8 @@ import numpy as np
 
 __all__ = [
     "spd_matrix", "spd_matrix_and_rhs", "draw_uniform_rows", "rhs", "integer_factor",
-    "integer_spd", "integer_rhs", "lower_upstream", "batched_sizes",
+    "integer_spd", "integer_rhs", "lower_upstream", "batched_sizes", "batched_systems", "pack_batched",
+    "batched_systems_device",
 ]
 
 
@@ -125,3 +131,76 @@ def spd_matrix_device(n: int, seed: int, shift: float = 1.0, device="cuda", chun
         blk.copy_(torch.tril(blk) + torch.tril(blk, -1).t())
     A.diagonal().add_(shift)
     return A, rng
+
+
+def _sym_from_lower(A: np.ndarray) -> np.ndarray:
+    return np.tril(A) + np.tril(A, -1).T
+
+
+def batched_systems(count: int, seed: int, nrhs: int, shift: float = 1.0, lo: int = 16, hi: int = 512,
+                    sizes=None):
+    """Host recipe of a batch: returns (ns, [A_i], [b_i]).  With ``sizes``
+    given, the orders are not drawn (the stream starts with B_0)."""
+    rng = np.random.default_rng(seed)
+    ns = np.asarray(sizes, dtype=np.int64) if sizes is not None else rng.integers(lo, hi + 1, size=count)
+    As, bs = [], []
+    for n in ns:
+        n = int(n)
+        B = rng.uniform(-1.0, 1.0, (n, n))
+        A = _sym_from_lower((B @ B.T) / float(max(n, 1)))
+        A[np.diag_indices(n)] += shift
+        As.append(A)
+        bs.append(rng.uniform(-1.0, 1.0, (n, nrhs)))
+    return ns, As, bs
+
+
+def _layout(ns, nrhs: int, align: int):
+    """Column-major packing: lda_i = n_i rounded up to ``align`` (>= 1), every
+    A_i starting at a multiple of ``align`` elements; B_i packed with ld n_i."""
+    ns = np.asarray(ns, dtype=np.int64)
+    lda = np.maximum(1, (ns + align - 1) // align * align)
+    sizes_a = lda * ns
+    a_off = np.concatenate([[0], np.cumsum(sizes_a)[:-1]]) if len(ns) else np.zeros(0, np.int64)
+    b_off = np.concatenate([[0], np.cumsum(ns * nrhs)[:-1]]) if len(ns) else np.zeros(0, np.int64)
+    return lda.astype(np.int64), a_off.astype(np.int64), b_off.astype(np.int64), int(sizes_a.sum()), \
+        int((ns * nrhs).sum())
+
+
+def pack_batched(As, bs, align: int = 2):
+    """Pack host systems into flat column-major arrays.  Returns
+    (A_flat, a_off, lda, B_flat, b_off) as numpy arrays."""
+    ns = [a.shape[0] for a in As]
+    nrhs = bs[0].shape[1] if bs else 0
+    lda, a_off, b_off, na, nbt = _layout(ns, nrhs, align)
+    Af = np.zeros(max(na, 1))
+    Bf = np.zeros(max(nbt, 1))
+    for A, b, o, l, ob in zip(As, bs, a_off, lda, b_off):
+        n = A.shape[0]
+        # column c of A (column-major) is row c of the symmetric A
+        Af[o:o + n * l].reshape(n, l)[:, :n] = A
+        Bf[ob:ob + n * nrhs].reshape(nrhs, n)[:] = b.T
+    return Af, a_off, lda, Bf, b_off
+
+
+def batched_systems_device(count: int, seed: int, nrhs: int, shift: float = 1.0, lo: int = 16, hi: int = 512,
+                           align: int = 2, device="cuda", sizes=None):
+    """The batched recipe with the products formed on the device (input
+    generation only), packed as :func:`pack_batched` does.  Returns
+    (ns, A_flat, a_off, lda, B_flat, b_off) with A_flat, B_flat device tensors."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    ns = np.asarray(sizes, dtype=np.int64) if sizes is not None else rng.integers(lo, hi + 1, size=count)
+    lda, a_off, b_off, na, nbt = _layout(ns, nrhs, align)
+    Af = torch.zeros(max(na, 1), dtype=torch.float64, device=device)
+    Bf = torch.zeros(max(nbt, 1), dtype=torch.float64, device=device)
+    for n, o, l, ob in zip(ns, a_off, lda, b_off):
+        n, o, l, ob = int(n), int(o), int(l), int(ob)
+        B = torch.from_numpy(rng.uniform(-1.0, 1.0, (n, n))).to(device)
+        A = torch.matmul(B, B.t().contiguous()) / float(max(n, 1))
+        A = torch.tril(A) + torch.tril(A, -1).t()
+        A.diagonal().add_(shift)
+        Af[o:o + n * l].view(n, l)[:, :n].copy_(A)
+        b = torch.from_numpy(rng.uniform(-1.0, 1.0, (n, nrhs))).to(device)
+        Bf[ob:ob + n * nrhs].view(nrhs, n).copy_(b.t())
+    return ns, Af, a_off, lda, Bf, b_off

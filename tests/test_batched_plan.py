@@ -1,0 +1,158 @@
+"""Host planner of the batched launch: many systems' factor + solve DAGs merged
+into one (no GPU).
+
+Each system's tasks are checked against the same independent derivation as
+the single-system plans: replaying its factorization and then its solve in
+program order, with the tiles of the factor and the blocks of the
+right-hand sides as the data (section 2, data-flow model), and keeping the
+edges no path implies, must give exactly the planner's edges for that system,
+and no edge may join two systems.  Claim orders must be topological and the
+ranks must follow HEFT's recurrence (section 3.1) with the weights scaled to
+a common flop unit, (nb / 16)^3 per system.
+"""
+import collections
+
+import numpy as np
+import pytest
+
+tc = pytest.importorskip("paper_1402_6601_amd")
+
+POTRF, TRSM, SYRK, GEMM, FTRSV, FGEMV, BTRSV, BGEMV = range(8)
+WEIGHT = {POTRF: 1, TRSM: 3, SYRK: 3, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2}
+
+
+def bplan(n, nb, policy=0, seed=0):
+    try:
+        return tc.batched_plan_query(n, nb, policy, seed)
+    except ImportError as e:  # library not built
+        pytest.skip(str(e))
+
+
+def reduce_transitively(out):
+    succ = collections.defaultdict(set)
+    for a, b in out:
+        succ[a].add(b)
+
+    def reachable(a, b):
+        stack = [x for x in succ[a] if x != b]
+        seen = set()
+        while stack:
+            x = stack.pop()
+            if x == b:
+                return True
+            if x in seen:
+                continue
+            seen.add(x)
+            stack.extend(succ[x])
+        return False
+
+    return {(a, b) for (a, b) in out if not reachable(a, b)}
+
+
+def dataflow_edges_factor_solve(T):
+    """Program-order replay of the tile factorization then the two tiled
+    substitutions; edges join each access to the last writer of the datum
+    (tiles ("L", i, j), right-hand-side blocks ("B", i))."""
+    last_writer = {}
+    out = set()
+
+    def access(task, reads, writes):
+        for d in list(reads) + list(writes):
+            if d in last_writer and last_writer[d] != task:
+                out.add((last_writer[d], task))
+        for d in writes:
+            last_writer[d] = task
+
+    for k in range(T):
+        access((POTRF, k, k, k), [("L", k, k)], [("L", k, k)])
+        for i in range(k + 1, T):
+            access((TRSM, i, k, k), [("L", k, k), ("L", i, k)], [("L", i, k)])
+        for i in range(k + 1, T):
+            access((SYRK, i, i, k), [("L", i, k), ("L", i, i)], [("L", i, i)])
+            for j in range(k + 1, i):
+                access((GEMM, i, j, k), [("L", i, k), ("L", j, k), ("L", i, j)], [("L", i, j)])
+    for k in range(T):
+        access((FTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)])
+        for i in range(k + 1, T):
+            access((FGEMV, i, k, k), [("L", i, k), ("B", k), ("B", i)], [("B", i)])
+    for k in range(T - 1, -1, -1):
+        access((BTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)])
+        for i in range(k):
+            access((BGEMV, i, k, k), [("L", k, i), ("B", k), ("B", i)], [("B", i)])
+    return reduce_transitively(out)
+
+
+def key(p, t):
+    return (int(p["kind"][t]), int(p["i"][t]), int(p["j"][t]), int(p["k"][t]))
+
+
+def system_edges(p):
+    per = collections.defaultdict(set)
+    for t in range(p["ntask"]):
+        for e in range(p["succ_off"][t], p["succ_off"][t + 1]):
+            s = int(p["succ"][e])
+            assert p["sys"][t] == p["sys"][s], "an edge joins two systems"
+            per[int(p["sys"][t])].add((key(p, t), key(p, s)))
+    return per
+
+
+SIZES = [
+    ([16], [16]),
+    ([100, 600, 0, 16], [512, 256, 16, 16]),
+    ([48, 33, 64], [16, 16, 32]),
+    ([1, 17, 200, 512, 513], [16, 16, 64, 128, 512]),
+]
+
+
+@pytest.mark.parametrize("n,nb", SIZES)
+def test_batched_edges_equal_dataflow(n, nb):
+    p = bplan(n, nb)
+    per = system_edges(p)
+    for s, (ns, nbs) in enumerate(zip(n, nb)):
+        T = -(-ns // nbs)
+        assert per.get(s, set()) == dataflow_edges_factor_solve(T), (s, ns, nbs)
+        # every task of the system is present
+        cnt = collections.Counter(int(k) for k, q in zip(p["kind"], p["sys"]) if q == s)
+        ng = T * (T - 1) * (T - 2) // 6
+        assert cnt.get(POTRF, 0) == T == cnt.get(FTRSV, 0) == cnt.get(BTRSV, 0)
+        assert cnt.get(TRSM, 0) == cnt.get(SYRK, 0) == T * (T - 1) // 2 == cnt.get(FGEMV, 0) == cnt.get(BGEMV, 0)
+        assert cnt.get(GEMM, 0) == ng
+
+
+@pytest.mark.parametrize("policy,seed", [(0, 0), (1, 0), (2, 3)])
+def test_batched_claim_order_is_topological(policy, seed):
+    n, nb = [1, 17, 200, 512, 513, 300], [16, 16, 64, 128, 512, 128]
+    p = bplan(n, nb, policy, seed)
+    nt = p["ntask"]
+    first = {}
+    for idx, t in enumerate(p["item_task"]):
+        first.setdefault(int(t), idx)
+    assert len(first) == nt
+    for t in range(nt):
+        for e in range(p["succ_off"][t], p["succ_off"][t + 1]):
+            assert first[t] < first[int(p["succ"][e])]
+
+
+def test_batched_ranks_follow_scaled_recurrence():
+    n, nb = [64, 600, 300, 1000], [16, 256, 128, 512]
+    p = bplan(n, nb)
+    for t in range(p["ntask"]):
+        u = nb[int(p["sys"][t])] // 16
+        succ = [p["rank"][p["succ"][e]] for e in range(p["succ_off"][t], p["succ_off"][t + 1])]
+        assert p["rank"][t] == WEIGHT[int(p["kind"][t])] * u ** 3 + (max(succ) if succ else 0)
+    # decreasing rank along the claim order
+    r = p["rank"][p["item_task"]]
+    assert np.all(np.diff(r) <= 0)
+
+
+def test_batched_plan_of_nothing():
+    p = bplan([0, 0], [16, 16])
+    assert p["ntask"] == 0 and p["nitem"] == 0
+
+
+def test_batched_argument_checks():
+    with pytest.raises(tc.TcholError):
+        bplan([10, 20], [16, 24])          # nb not a multiple of 16
+    with pytest.raises(tc.TcholError):
+        bplan([10, -1], [16, 16])          # negative order
+    assert tc.batched_workspace_bytes([100, 600], [512, 256]) > 0

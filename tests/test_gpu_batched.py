@@ -1,0 +1,136 @@
+"""GPU parity of the batched factor + solve launch (through the C ABI) against
+the CPU oracle, system by system.
+
+Bar, per system: the normwise-max entry error of L at most 1e-10 and of the
+solution at most 1e-10 (FP64), the oracle's info for a system that is not
+positive definite while every other system of the batch completes, exact
+results for integer systems, and bitwise-equal results under every claim
+order.  Systems mix single-tile orders (one workgroup each) with multi-tile
+ones (their tiles spread over workgroups), ragged edge tiles, and both the
+16-byte (even leading dimension) and 4-byte transfer paths.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import spd_inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import paper_1402_6601_amd as t
+    t.load()
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to the gpu-marked tests")
+    return t
+
+
+def _run(tc, As, bs, nb, align=2, **kw):
+    """Pack, run one batched launch, unpack: returns (info, [L_i], [X_i])."""
+    Af, ao, lda, Bf, bo = spd_inputs.pack_batched(As, bs, align)
+    A_d = torch.from_numpy(Af).cuda()
+    B_d = torch.from_numpy(Bf).cuda()
+    n = [a.shape[0] for a in As]
+    nrhs = bs[0].shape[1] if bs else 0
+    info = tc.factor_solve_batched_(A_d, ao, lda, B_d, bo, n, nb, nrhs, **kw)
+    torch.cuda.synchronize()
+    Ah, Bh = A_d.cpu().numpy(), B_d.cpu().numpy()
+    Ls, Xs = [], []
+    for i, m in enumerate(n):
+        raw = Ah[ao[i]:ao[i] + m * lda[i]].reshape(m, lda[i])[:, :m]   # row c = column c
+        Ls.append(np.tril(raw.T))
+        Xs.append(Bh[bo[i]:bo[i] + m * nrhs].reshape(nrhs, m).T)
+    return info, Ls, Xs
+
+
+def _nb_single(n):
+    return max(16, min(512, -(-n // 16) * 16))
+
+
+SIZES = [1, 16, 17, 100, 128, 255, 300, 511, 512, 513, 700, 33, 64, 250]
+
+
+def _systems(seed, sizes, nrhs=4):
+    _, As, bs = spd_inputs.batched_systems(len(sizes), seed, nrhs, sizes=sizes)
+    return As, bs
+
+
+@pytest.mark.parametrize("align", [2, 1])
+def test_batched_matches_oracle(tc, align):
+    As, bs = _systems(11, SIZES)
+    # single-tile systems up to 512; larger ones tiled by 128 / 256; two small
+    # systems tiled by 16 to exercise multi-tile DAGs of small orders
+    nb = [_nb_single(n) if n <= 512 else (128 if n < 600 else 256) for n in SIZES]
+    nb[SIZES.index(33)] = 16
+    nb[SIZES.index(250)] = 64
+    info, Ls, Xs = _run(tc, As, bs, nb, align=align)
+    assert np.all(info == 0)
+    for A, b, L, X in zip(As, bs, Ls, Xs):
+        Lo = oracle.cholesky(A)
+        assert oracle.factor_error(L, Lo) <= TOL
+        Xo = oracle.potrs(Lo, b)
+        assert np.max(np.abs(X - Xo)) / max(np.max(np.abs(Xo)), 1e-300) <= TOL
+        assert np.all(oracle.solve_backward_error(A, X, b) <= 1e-15)
+
+
+def test_batched_failure_stays_in_its_system(tc):
+    sizes = [200, 300, 64, 129]
+    As, bs = _systems(12, sizes)
+    A1, L0 = spd_inputs.integer_spd(300, seed=5)
+    j = 137
+    A1[j, j] -= L0[j, j] ** 2
+    _, info_o = oracle.potrf(A1)
+    assert info_o == j + 1
+    As[1] = A1
+    nb = [_nb_single(200), 128, 64, _nb_single(129)]
+    info, Ls, Xs = _run(tc, As, bs, nb)
+    assert list(info) == [0, j + 1, 0, 0]
+    for s in (0, 2, 3):
+        Lo = oracle.cholesky(As[s])
+        assert oracle.factor_error(Ls[s], Lo) <= TOL
+        Xo = oracle.potrs(Lo, bs[s])
+        assert np.max(np.abs(Xs[s] - Xo)) / np.max(np.abs(Xo)) <= TOL
+
+
+def test_batched_integer_systems_exact(tc):
+    sizes = [64, 300, 17, 512]
+    As, bs, L0s, X0s = [], [], [], []
+    for i, n in enumerate(sizes):
+        A, L0 = spd_inputs.integer_spd(n, seed=40 + i)
+        b, x0 = spd_inputs.integer_rhs(A, 3, seed=40 + i)
+        As.append(A), bs.append(b), L0s.append(L0), X0s.append(x0)
+    nb = [16, 128, 16, 512]
+    info, Ls, Xs = _run(tc, As, bs, nb)
+    assert np.all(info == 0)
+    for L, L0, X, X0 in zip(Ls, L0s, Xs, X0s):
+        assert np.array_equal(L, L0)
+        assert np.array_equal(X, X0)
+
+
+def test_batched_bitwise_across_policies(tc):
+    sizes = [400, 37, 600, 128, 250]
+    As, bs = _systems(13, sizes)
+    nb = [_nb_single(400), 16, 128, 128, 64]
+    ref = _run(tc, As, bs, nb)
+    for pol, seed in [(tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 5)]:
+        got = _run(tc, As, bs, nb, policy=pol, seed=seed)
+        assert np.array_equal(got[0], ref[0])
+        assert all(np.array_equal(a, b) for a, b in zip(got[1], ref[1]))
+        assert all(np.array_equal(a, b) for a, b in zip(got[2], ref[2]))
+
+
+def test_batched_factor_only_and_empty(tc):
+    As, bs = _systems(14, [100, 0, 50], nrhs=0)
+    nb = [112, 16, 64]
+    info, Ls, _ = _run(tc, As, bs, nb)
+    assert np.all(info == 0)
+    for A, L in zip(As, Ls):
+        if A.shape[0]:
+            assert oracle.factor_error(L, oracle.cholesky(A)) <= TOL
+    e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    assert len(tc.factor_solve_batched_(e, [], [], e, [], [], [], 4)) == 0
