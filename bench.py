@@ -94,6 +94,121 @@ def run_calib_copy(nbytes: int, reps: int):
     print(json.dumps({"calib_copy_bytes": n * 8, "reps": reps}), flush=True)
 
 
+def run_batched(args):
+    """4096 SPD systems, n_i uniform on [16, 512] (seed 4), A_i = B_i B_i^T / n_i + I,
+    factor + 4-RHS solve of all of them in one launch per step, tile sizes from
+    the autotuner's table (one tile per system where there is none)."""
+    import torch
+    import paper_1402_6601_amd as tc
+    from paper_1402_6601_amd import autotune
+    import spd_inputs
+
+    tc.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    seed = 4 if args.seed == 1 else args.seed
+    nrhs = 4
+    K, Wm = args.steps, args.warmup
+    t0 = time.time()
+    ns, A0, a_off, lda, B0, b_off = spd_inputs.batched_systems_device(args.count, seed, nrhs, device=dev)
+    table = autotune.load_table()
+    nb = autotune.tile_sizes(ns, table)
+    torch.cuda.synchronize()
+    log("batched inputs ready in %.1f s (%d systems, sum n = %d)" % (time.time() - t0, len(ns), int(ns.sum())))
+    ws = torch.empty(tc.batched_workspace_bytes(ns, nb), dtype=torch.uint8, device=dev)
+    As = [torch.empty_like(A0) for _ in range(K)]
+    Bs = [torch.empty_like(B0) for _ in range(K)]
+    Aw, Bw = torch.empty_like(A0), torch.empty_like(B0)
+    for w in range(Wm):
+        Aw.copy_(A0)
+        Bw.copy_(B0)
+        info = tc.factor_solve_batched_(Aw, a_off, lda, Bw, b_off, ns, nb, nrhs, ws=ws)
+        if np.any(info != 0):
+            raise RuntimeError("batched factorization failed")
+        log("warmup %d done" % (w + 1))
+    for s_ in range(K):
+        As[s_].copy_(A0)
+        Bs[s_].copy_(B0)
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t_start = time.perf_counter()
+    for s_ in range(K):
+        info, ms = tc.factor_solve_batched_(As[s_], a_off, lda, Bs[s_], b_off, ns, nb, nrhs, ws=ws,
+                                            want_kernel_ms=True)
+        kernel_ms.append(ms)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    if np.any(info != 0):
+        raise RuntimeError("batched factorization failed")
+    ms_per_step = (t_end - t_start) * 1e3 / K
+    kmean = float(np.mean(kernel_ms))
+    n64 = ns.astype(np.float64)
+    flops = float(np.sum(n64 ** 3) / 3.0)
+    # algorithmic bytes: read the lower triangle of A, write L, read L in each
+    # of the two substitutions, read and write the right-hand sides twice
+    tri = float(np.sum(n64 * (n64 + 1) / 2.0)) * 8.0
+    bytes_alg = 4.0 * tri + 4.0 * float(np.sum(n64)) * nrhs * 8.0
+    achieved = bytes_alg / (kmean * 1e-3) / 1e9
+
+    # checks on a sample of systems, and the oracle timed on the host on it
+    import oracle
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(len(ns), size=min(64, len(ns)), replace=False))
+    Ah0 = A0.cpu().numpy()
+    Bh0 = B0.cpu().numpy()
+    Ah = As[K - 1].cpu().numpy()
+    Bh = Bs[K - 1].cpu().numpy()
+    worst_l, worst_x = 0.0, 0.0
+    tcpu = 0.0
+    for i in sample:
+        n_, o, l, ob = int(ns[i]), int(a_off[i]), int(lda[i]), int(b_off[i])
+        Ai = np.ascontiguousarray(Ah0[o:o + n_ * l].reshape(n_, l)[:, :n_])
+        bi = np.ascontiguousarray(Bh0[ob:ob + n_ * nrhs].reshape(nrhs, n_).T)
+        Lg = np.tril(Ah[o:o + n_ * l].reshape(n_, l)[:, :n_].T)
+        Xg = Bh[ob:ob + n_ * nrhs].reshape(nrhs, n_).T
+        tc0 = time.perf_counter()
+        F, inf = oracle.potrf(Ai)
+        Xo = oracle.potrs(F, bi)
+        tcpu += time.perf_counter() - tc0
+        worst_l = max(worst_l, oracle.factor_error(Lg, F))
+        worst_x = max(worst_x, float(np.max(np.abs(Xg - Xo)) / np.max(np.abs(Xo))))
+    sample_flops = float(np.sum(n64[sample] ** 3) / 3.0)
+    out = {
+        "metric": "Cholesky TFLOP/s (sum of n_i^3/3), batched factor + 4-RHS solve in one launch",
+        "value": round(flops / (ms_per_step * 1e-3) / 1e12, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched fp64 factor + solve, %d systems, n_i ~ U{16..512} (seed %d), "
+                               "A_i = B_i B_i^T/n_i + I, 4 RHS, one persistent launch" % (len(ns), seed),
+                   "count": int(len(ns)), "seed": seed, "nrhs": nrhs,
+                   "tile_table": "tuned" if table else "one tile per system",
+                   "systems_split_into_tiles": int(np.sum(nb < ns))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "tchol_persistent (batched factor + solve DAG)", "kernel_ms_mean": round(kmean, 3),
+                     "bytes_per_launch": bytes_alg, "flops_per_launch": flops,
+                     "mfma_frac": round(flops / (kmean * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4)},
+        "kernel_ms": [round(x, 3) for x in kernel_ms],
+        "e_L_max_sampled": worst_l,
+        "e_x_max_sampled": worst_x,
+        "cpu_baseline": {"value": round(sample_flops / tcpu / 1e12, 6), "unit": "TFLOP/s",
+                         "cores": oracle.num_threads(), "kind": "oracle",
+                         "sample": "oracle FP64 factor + solve of %d sampled systems of the same batch "
+                                   "(factor flops only counted); %.3f s" % (len(sample), tcpu)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +222,9 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=8192,
                     help="order of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--workload", choices=["factor", "batched"], default="factor",
+                    help="factor: the n=32768 factor + solve (default); batched: 4096 systems in one launch")
+    ap.add_argument("--count", type=int, default=4096, help="batched: number of systems")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -116,6 +234,9 @@ def main():
         sys.exit(2)
     if args.calib_copy:
         run_calib_copy(args.calib_copy, max(1, args.steps))
+        return
+    if args.workload == "batched":
+        run_batched(args)
         return
 
     import torch

@@ -347,4 +347,28 @@ std::shared_ptr<const Plan> get_plan(int32_t op, int64_t n, int64_t nb, int32_t 
   return p;
 }
 
+std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed) {
+  static std::mutex mu;
+  static std::map<std::vector<int64_t>, std::shared_ptr<const Plan>> cache;
+  std::vector<int64_t> key;
+  key.reserve(2 * systems.size() + 2);
+  key.push_back(policy);
+  key.push_back(policy == TCHOL_POLICY_RANDOM ? seed : 0);
+  for (const System& sy : systems) {
+    key.push_back(sy.n);
+    key.push_back(sy.nb);
+  }
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  std::shared_ptr<const Plan> p = build_batched_plan(systems, policy, seed, default_split());
+  if (!p) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if (cache.size() >= 8) cache.clear();
+  cache[key] = p;
+  return p;
+}
+
 }  // namespace tchol

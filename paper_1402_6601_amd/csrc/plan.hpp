@@ -72,6 +72,11 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
 std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
                                          const Split& split);
 
+// The batched plan for these systems' orders and tile sizes, from a small
+// process-wide cache keyed by them (offsets and leading dimensions are not
+// part of the plan's task structure; the caller supplies them per launch).
+std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed);
+
 const Split& default_split();
 
 }  // namespace tchol

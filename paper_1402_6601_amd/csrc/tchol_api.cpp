@@ -61,7 +61,9 @@ struct Image {
   }
 };
 
-std::shared_ptr<Image> make_image(const Plan& p, bool pin) {
+// sys_override: the systems' offsets and leading dimensions for this launch
+// (a cached batched plan's own records are not used for them).
+std::shared_ptr<Image> make_image(const Plan& p, bool pin, const std::vector<tchol::System>* sys_override = nullptr) {
   auto img = std::make_shared<Image>();
   img->lay = layout_of(p);
   const Layout& L = img->lay;
@@ -100,7 +102,7 @@ std::shared_ptr<Image> make_image(const Plan& p, bool pin) {
     items[2 * i + 1] = p.item_part[i];
   }
   for (size_t s = 0; s < p.systems.size(); ++s) {
-    const tchol::System& sy = p.systems[s];
+    const tchol::System& sy = sys_override ? (*sys_override)[s] : p.systems[s];
     int64_t* r = sys + SYS_WORDS * s;
     r[0] = sy.a_off;
     r[1] = sy.b_off;
@@ -370,8 +372,9 @@ int64_t tchol_batched_workspace_bytes(const int32_t* n, const int32_t* nb, int32
   if (rc == -6) return -1;
   if (rc == -7) return -2;
   if (rc != 0) return rc;
-  auto plan = tchol::build_batched_plan(systems, TCHOL_POLICY_RANK, 0, tchol::default_split());
+  auto plan = tchol::get_batched_plan(systems, TCHOL_POLICY_RANK, 0);
   if (!plan) return TCHOL_E_UNSUPPORTED;
+  // every policy yields the same task, edge and item counts, hence the same layout
   return layout_of(*plan).end;
 }
 
@@ -409,9 +412,9 @@ int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_
   if (nrhs == 0) {
     // nothing to solve: the plan still holds the solve tasks, which then have no columns
   }
-  auto plan = tchol::build_batched_plan(systems, o.policy, o.seed, tchol::default_split());
+  auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
-  auto img = make_image(*plan, false);
+  auto img = make_image(*plan, false, &systems);
   return execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 11, info);
 }
 
