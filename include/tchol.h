@@ -59,6 +59,9 @@ extern "C" {
 #define TCHOL_E_TIMEOUT (-101)     /* the kernel's bounded wait expired      */
 #define TCHOL_E_UNSUPPORTED (-102) /* size beyond what the planner supports  */
 #define TCHOL_E_INTERNAL (-103)    /* inconsistent device state at exit      */
+#define TCHOL_E_NOCONV (-104)      /* refinement missed its target in maxit  */
+
+#define TCHOL_LOWP_FP32 1 /* mixed precision: FP32 working copy, FP32 matrix-core updates */
 
 #define TCHOL_NB_MIN 16
 #define TCHOL_NB_MAX 512
@@ -127,6 +130,37 @@ TCHOL_API int32_t tchol_factor_solve_batched(double *A, const int64_t *a_off, co
                                              const int64_t *b_off, const int32_t *n, const int32_t *nb,
                                              int32_t nrhs, int32_t batch, int32_t *info, void *ws,
                                              int64_t ws_bytes, void *stream, const tchol_opts *opts);
+
+/* Mixed-precision solve with iterative refinement: X = A^{-1} B to FP64
+   accuracy from a factorization whose trailing updates run in low precision.
+   A (n x n, column-major, ld n, lower triangle read, not modified) is first
+   copied to a low-precision working copy in the workspace; that copy is
+   factored on the same tile DAG and scheduler as tchol_factor (the paper's
+   Cholesky DAG, section 4.1): SYRK / GEMM / TRSM on the copy with FP32
+   matrix-core products, each diagonal tile promoted to FP64 for its POTRF
+   and kept in FP64.  Then x_0 = L~^{-T} L~^{-1} b, and while the normwise
+   backward error eta_j = ||r_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf)
+   of some column exceeds tol: r = b - A x in FP64 against the original A,
+   x += L~^{-T} L~^{-1} r (substitutions in FP64 arithmetic on the stored
+   factor).  Each iteration reads the stopping test back to the host once.
+   Arguments: 1 A, 2 n >= 0, 3 nb (as for tchol_factor), 4 B (n x nrhs, ld n,
+   in: right-hand sides, out: solutions), 5 nrhs >= 0, 6 lowp
+   (TCHOL_LOWP_FP32), 7 tol > 0 (target eta, e.g. 1e-12), 8 maxit >= 0
+   (corrections at most), 9 berr_out (host, nrhs entries or NULL: final eta
+   per column), 10 iters_out (host or NULL: corrections applied), 11 ws,
+   12 ws_bytes >= tchol_mixed_workspace_bytes(n, nb, nrhs), 13 stream,
+   14 opts (NULL or as for tchol_factor_ex; kernel_ms receives the
+   factorization kernel's time).
+   Returns 0 when every column met tol; k > 0 when the low-precision
+   factorization found the leading minor of order k not positive definite
+   (B unchanged); TCHOL_E_NOCONV when maxit corrections did not reach tol (B
+   holds the last iterate, berr_out its eta; LAPACK's mixed solvers then
+   fall back to the FP64 path, tchol_factor + tchol_solve); other negative
+   codes as for tchol_factor. */
+TCHOL_API int64_t tchol_mixed_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs);
+TCHOL_API int32_t tchol_solve_mixed(const double *A, int64_t n, int64_t nb, double *B, int64_t nrhs, int32_t lowp,
+                                    double tol, int32_t maxit, double *berr_out, int32_t *iters_out, void *ws,
+                                    int64_t ws_bytes, void *stream, const tchol_opts *opts);
 
 /* Human-readable text for a return code (static storage). */
 TCHOL_API const char *tchol_strerror(int32_t code);

@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
 OP_FACTOR, OP_SOLVE, OP_BATCHED = 0, 1, 2
 POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2
-E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL = -100, -101, -102, -103
+E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV = -100, -101, -102, -103, -104
+LOWP_FP32 = 1
 KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV"]
 
 _lib = None
@@ -63,6 +64,11 @@ def load() -> ctypes.CDLL:
     lib.tchol_solve.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp]
     lib.tchol_solve_ex.restype = i32
     lib.tchol_solve_ex.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, ctypes.POINTER(Opts)]
+    lib.tchol_mixed_workspace_bytes.restype = i64
+    lib.tchol_mixed_workspace_bytes.argtypes = [i64, i64, i64]
+    lib.tchol_solve_mixed.restype = i32
+    lib.tchol_solve_mixed.argtypes = [vp, i64, i64, vp, i64, i32, ctypes.c_double, i32,
+                                      ctypes.POINTER(ctypes.c_double), P32, vp, i64, vp, ctypes.POINTER(Opts)]
     lib.tchol_strerror.restype = ctypes.c_char_p
     lib.tchol_strerror.argtypes = [i32]
     lib.tchol_version.restype = ctypes.c_char_p
@@ -173,6 +179,13 @@ def batched_plan_query(n, nb, policy: int = POLICY_RANK, seed: int = 0) -> dict:
     a["item_part"] = a["item_part"][:ni]
     a["ntask"], a["nedge"], a["nitem"], a["critical_path"] = nt, ne, ni, int(counts[3])
     return a
+
+
+def mixed_workspace_bytes(n: int, nb: int, nrhs: int) -> int:
+    r = load().tchol_mixed_workspace_bytes(n, nb, nrhs)
+    if r < 0:
+        raise TcholError(int(r), "tchol_mixed_workspace_bytes")
+    return int(r)
 
 
 def batched_workspace_bytes(n, nb) -> int:
@@ -321,3 +334,67 @@ def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: 
         raise TcholError(rc, "tchol_factor_solve_batched")
     info = info[:batch]
     return (info, ms.value) if want_kernel_ms else info
+
+
+def solve_mixed_(A, Bc, nb: int, *, tol: float = 1e-12, maxit: int = 30, lowp: int = LOWP_FP32,
+                 policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+                 want_kernel_ms: bool = False, check: bool = True):
+    """Mixed-precision solve with iterative refinement, in place on Bc.
+
+    A: CUDA float64 (n, n) contiguous symmetric (read only).  Bc: CUDA float64
+    (nrhs, n) contiguous (B column-major), overwritten by the solution.
+    Returns (rc, iters, berr) with berr the final normwise backward error per
+    right-hand side (numpy); rc is 0, the failing leading minor of the
+    low-precision factorization, or E_NOCONV; with want_kernel_ms a fourth
+    entry gives the factorization kernel's time."""
+    torch = _torch()
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+        raise ValueError("A must be a contiguous square float64 tensor")
+    n = A.shape[0]
+    if Bc.dtype != torch.float64 or not Bc.is_contiguous() or Bc.dim() != 2 or Bc.shape[1] != n:
+        raise ValueError("Bc must be a contiguous float64 (nrhs, n) tensor (B in column-major order)")
+    nrhs = Bc.shape[0]
+    lib = load()
+    berr = np.zeros(max(nrhs, 1), dtype=np.float64)
+    iters = ctypes.c_int32(0)
+    with torch.cuda.device(A.device):
+        need = mixed_workspace_bytes(n, nb, nrhs) if n else 256
+        if ws is None or ws.numel() < need:
+            ws = _workspace(torch, need, A.device)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, None)
+        rc = lib.tchol_solve_mixed(ctypes.c_void_p(A.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()), nrhs,
+                                   lowp, float(tol), int(maxit), berr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(iters), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream_ptr(torch, A.device), ctypes.byref(o))
+    if check and rc < 0 and rc != E_NOCONV:
+        raise TcholError(rc, "tchol_solve_mixed")
+    out = (rc, int(iters.value), berr[:nrhs])
+    return out + (ms.value,) if want_kernel_ms else out
+
+
+def solve_mixed(A, B, nb: int, *, fallback: bool = True, **kw):
+    """X = A^{-1} B by the mixed-precision solve; B is (n,) or (n, nrhs).
+
+    When the low-precision factorization breaks down or the refinement does
+    not reach tol within maxit, and fallback is set, the system is solved by
+    the FP64 path (factor of a copy of A, then solve), as LAPACK's mixed
+    solvers do.  Returns (X, info) with info = {"rc", "iters", "berr",
+    "fallback"}."""
+    torch = _torch()
+    vec = B.dim() == 1
+    B2 = B.reshape(B.shape[0], -1)
+    Bc = B2.mT.contiguous().to(torch.float64)
+    rc, iters, berr = solve_mixed_(A, Bc, nb, **kw)[:3]
+    used = False
+    if rc != 0 and fallback:
+        Lbuf = A.detach().clone()
+        info = factor_(Lbuf, nb)
+        if info != 0:
+            raise TcholError(int(info), "tchol_factor (fallback)")
+        Bc = B2.mT.contiguous().to(torch.float64)
+        solve_(Lbuf, Bc, nb)
+        used = True
+    elif rc != 0:
+        raise TcholError(int(rc), "tchol_solve_mixed")
+    X = Bc.mT
+    return (X.reshape(-1) if vec else X), {"rc": int(rc), "iters": iters, "berr": berr, "fallback": used}

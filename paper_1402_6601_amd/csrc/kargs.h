@@ -17,7 +17,8 @@
 #define DEV_ERR_LAYOUT 2  /* a work item violated the launch's alignment contract  */
 
 typedef struct KArgs {
-  double *A;            /* factor: in/out matrix; solve: the factor L (read only) */
+  double *A;            /* factor: in/out matrix; solve: the factor L (read only);
+                           mixed precision: the FP32 working copy, cast             */
   double *B;            /* solve: right-hand sides, overwritten by the solution   */
   int64_t n, nb, ld, ldb, nrhs;
   int32_t T, nitem;
@@ -32,6 +33,10 @@ typedef struct KArgs {
   int32_t *sinfo;       /* per system: failing column (batched launches)          */
   int32_t batched;      /* 1: a failing system stops only its own work             */
   int32_t nsys;
+  double *D;            /* mixed precision: FP64 diagonal tiles, nb x nb each, T of them */
+  int32_t mixed;        /* 0: FP64; 1: mixed-precision factor, 2: its solves (A is the
+                           FP32 working copy)                                       */
+  int32_t pad1;
   int64_t wait_limit;   /* bound on one dependency wait, in 100 MHz clock ticks   */
   uint64_t *trace;      /* optional: 4 words per work item                        */
 } KArgs;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -16,6 +17,14 @@
 extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid, int wide,
                                        hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 extern "C" hipError_t tchol_dev_max_grid(int device, int* grid);
+extern "C" hipError_t tchol_refine_convert(const double* A, int64_t lda, float* W, int64_t ldw, int64_t n,
+                                           hipStream_t s);
+extern "C" hipError_t tchol_refine_residual(const double* A, int64_t lda, int64_t n, const double* X,
+                                            const double* Bin, double* Out, int64_t ldb, int nrhs, int absmode,
+                                            hipStream_t s);
+extern "C" hipError_t tchol_refine_colmax(const double* V, int64_t ldv, int64_t n, int ncols, double* out,
+                                          hipStream_t s);
+extern "C" hipError_t tchol_refine_axpy(double* X, const double* D, int64_t count, hipStream_t s);
 
 namespace {
 
@@ -113,19 +122,30 @@ std::shared_ptr<Image> make_image(const Plan& p, bool pin, const std::vector<tch
   return img;
 }
 
-// Cached per plan (single-system plans are themselves cached).
-std::shared_ptr<const Image> image_of(const std::shared_ptr<const Plan>& p) {
+// Cached per (plan, leading dimension); ld = 0 keeps the plan's own (the
+// mixed-precision working copy has a padded one).  Single-system plans are
+// themselves cached.
+std::shared_ptr<const Image> image_of(const std::shared_ptr<const Plan>& p, int64_t ld = 0) {
+  using Key = std::pair<const Plan*, int64_t>;
   static std::mutex mu;
-  static std::map<const Plan*, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
+  static std::map<Key, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
+  const Key key(p.get(), ld);
   {
     std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(p.get());
+    auto it = cache.find(key);
     if (it != cache.end() && !it->second.first.expired()) return it->second.second;
   }
-  std::shared_ptr<const Image> img = make_image(*p, true);
+  std::shared_ptr<const Image> img;
+  if (ld > 0) {
+    std::vector<tchol::System> sys = p->systems;
+    for (auto& sy : sys) sy.ld = ld;
+    img = make_image(*p, true, &sys);
+  } else {
+    img = make_image(*p, true);
+  }
   std::lock_guard<std::mutex> g(mu);
   if (cache.size() > 64) cache.clear();
-  cache[p.get()] = std::make_pair(std::weak_ptr<const Plan>(p), img);
+  cache[key] = std::make_pair(std::weak_ptr<const Plan>(p), img);
   return img;
 }
 
@@ -164,10 +184,12 @@ const tchol_opts kDefaultOpts = {TCHOL_POLICY_RANK, 0u, 0, nullptr, nullptr};
 
 // Uploads the plan image, launches reset + persistent kernel on the stream,
 // reads the header back and synchronises.  sinfo_out (batched): per-system
-// failing columns.  Returns the library code.
+// failing columns.  mixed: 0 FP64; 1 / 2 the mixed-precision factor / solve
+// (A is then the FP32 working copy and D its FP64 diagonal tiles).  Returns
+// the library code.
 int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_t nrhs, bool wide, bool batched,
                 void* ws, int64_t ws_bytes, void* stream_v, const tchol_opts& o, int32_t ws_arg,
-                int32_t* sinfo_out) {
+                int32_t* sinfo_out, double* D = nullptr, int mixed = 0) {
   const Layout& L = img.lay;
   if (ws_bytes < L.end) return -(ws_arg + 1);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
@@ -201,6 +223,8 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.sinfo = reinterpret_cast<int32_t*>(w + L.sinfo);
   a.batched = batched ? 1 : 0;
   a.nsys = (int32_t)plan.systems.size();
+  a.D = D;
+  a.mixed = mixed;
   const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
   a.wait_limit = limit_us * di.clock_khz / 1000;
   a.trace = o.trace;
@@ -315,6 +339,30 @@ int32_t batched_systems(const int64_t* a_off, const int32_t* lda, const int64_t*
   return 0;
 }
 
+
+// Mixed-precision solve: workspace regions (byte offsets).  The FP32 working
+// copy has ld = n + 3 rounded up to a multiple of 4 (its matrix-core loads
+// move four rows per 16-byte lane, so three rows past the order are read;
+// they hold zeros).
+struct MixedLayout {
+  int64_t ldw = 0, w = 0, d = 0, b0 = 0, r = 0, norms = 0, sched = 0, end = 0;
+};
+
+MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, const Plan& sp) {
+  MixedLayout M;
+  const int64_t T = (n + nb - 1) / nb;
+  M.ldw = (n + 3 + 3) / 4 * 4;
+  M.w = 0;
+  M.d = align_up(M.w + 4 * M.ldw * n);
+  M.b0 = align_up(M.d + 8 * T * nb * nb);
+  M.r = align_up(M.b0 + 8 * n * nrhs);
+  // the residual region first holds the row sums of |A| (n entries)
+  M.norms = align_up(M.r + 8 * n * std::max<int64_t>(nrhs, 1));
+  M.sched = align_up(M.norms + 8 * (1 + 3 * nrhs));
+  M.end = M.sched + std::max(layout_of(fp).end, layout_of(sp).end);
+  return M;
+}
+
 }  // namespace
 
 extern "C" {
@@ -418,6 +466,106 @@ int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_
   return execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 11, info);
 }
 
+int64_t tchol_mixed_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs) {
+  if (n < 0) return -1;
+  if (!nb_ok(nb)) return -2;
+  if (nrhs < 0) return -3;
+  auto fp = tchol::get_plan(TCHOL_OP_FACTOR, n, nb, TCHOL_POLICY_RANK, 0);
+  auto sp = tchol::get_plan(TCHOL_OP_SOLVE, n, nb, TCHOL_POLICY_RANK, 0);
+  if (!fp || !sp) return TCHOL_E_UNSUPPORTED;
+  return mixed_layout(n, nb, nrhs, *fp, *sp).end;
+}
+
+int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int64_t nrhs, int32_t lowp, double tol,
+                          int32_t maxit, double* berr_out, int32_t* iters_out, void* ws, int64_t ws_bytes,
+                          void* stream_v, const tchol_opts* opts) {
+  if (n < 0) return -2;
+  if (!nb_ok(nb)) return -3;
+  if (nrhs < 0) return -5;
+  if (lowp != TCHOL_LOWP_FP32) return -6;
+  if (!(tol > 0.0)) return -7;
+  if (maxit < 0) return -8;
+  if (iters_out) *iters_out = 0;
+  if (n == 0 || nrhs == 0) {
+    for (int64_t j = 0; j < nrhs; ++j)
+      if (berr_out) berr_out[j] = 0.0;
+    return 0;
+  }
+  if (!A) return -1;
+  if (!B) return -4;
+  if (!ws) return -11;
+  if (ws_bytes <= 0) return -12;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -11;
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
+  auto fplan = tchol::get_plan(TCHOL_OP_FACTOR, n, nb, o.policy, o.seed);
+  auto splan = tchol::get_plan(TCHOL_OP_SOLVE, n, nb, o.policy, o.seed);
+  if (!fplan || !splan) return TCHOL_E_UNSUPPORTED;
+  const MixedLayout M = mixed_layout(n, nb, nrhs, *fplan, *splan);
+  if (ws_bytes < M.end) return -12;
+  auto fimg = image_of(fplan, M.ldw);
+  auto simg = image_of(splan, M.ldw);
+  char* w = static_cast<char*>(ws);
+  float* W = reinterpret_cast<float*>(w + M.w);
+  double* D = reinterpret_cast<double*>(w + M.d);
+  double* B0 = reinterpret_cast<double*>(w + M.b0);
+  double* R = reinterpret_cast<double*>(w + M.r);
+  double* norms = reinterpret_cast<double*>(w + M.norms);  // {||A||, ||b_j||, ||x_j||, ||r_j||}
+  void* sched = w + M.sched;
+  const int64_t sched_bytes = ws_bytes - M.sched;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_v);
+  const int nr = (int)nrhs;
+
+  // the working copy, then its factorization (FP32 updates, FP64 diagonal tiles)
+  if (tchol_refine_convert(A, n, W, M.ldw, n, s) != hipSuccess) return TCHOL_E_HIP;
+  tchol_opts fo = o;
+  fo.trace = nullptr;
+  int32_t rc = execute(*fplan, *fimg, reinterpret_cast<double*>(W), nullptr, 0, true, false, sched, sched_bytes,
+                       stream_v, fo, 11, nullptr, D, 1);
+  if (rc != 0) return rc;
+  tchol_opts so = o;
+  so.trace = nullptr;
+  so.kernel_ms = nullptr;
+
+  // ||A||_inf (row sums of |A|, A symmetric) and ||b_j||_inf, kept with b
+  const size_t bbytes = 8 * (size_t)n * (size_t)nrhs;
+  if (hipMemcpyAsync(B0, B, bbytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return TCHOL_E_HIP;
+  if (tchol_refine_residual(A, n, n, B0, B0, R, n, 1, 1, s) != hipSuccess) return TCHOL_E_HIP;
+  if (tchol_refine_colmax(R, n, n, 1, norms, s) != hipSuccess) return TCHOL_E_HIP;
+  if (tchol_refine_colmax(B0, n, n, nr, norms + 1, s) != hipSuccess) return TCHOL_E_HIP;
+
+  // x_0
+  rc = execute(*splan, *simg, reinterpret_cast<double*>(W), B, nrhs, true, false, sched, sched_bytes, stream_v, so,
+               11, nullptr, D, 2);
+  if (rc != 0) return rc;
+  std::vector<double> hn(1 + 3 * (size_t)nrhs);
+  for (int32_t it = 0;; ++it) {
+    if (tchol_refine_residual(A, n, n, B, B0, R, n, nr, 0, s) != hipSuccess) return TCHOL_E_HIP;
+    if (tchol_refine_colmax(B, n, n, nr, norms + 1 + nrhs, s) != hipSuccess) return TCHOL_E_HIP;
+    if (tchol_refine_colmax(R, n, n, nr, norms + 1 + 2 * nrhs, s) != hipSuccess) return TCHOL_E_HIP;
+    if (hipMemcpyAsync(hn.data(), norms, 8 * hn.size(), hipMemcpyDeviceToHost, s) != hipSuccess) return TCHOL_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return TCHOL_E_HIP;
+    double worst = 0.0;
+    bool finite = true;
+    for (int64_t j = 0; j < nrhs; ++j) {
+      const double den = hn[0] * hn[1 + nrhs + j] + hn[1 + j];
+      const double rn = hn[1 + 2 * nrhs + j];
+      const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+      if (!(eta == eta) || eta == INFINITY) finite = false;
+      if (berr_out) berr_out[j] = eta;
+      worst = std::max(worst, eta);
+    }
+    if (iters_out) *iters_out = it;
+    if (finite && worst <= tol) return 0;
+    if (it >= maxit || !finite) return TCHOL_E_NOCONV;
+    // correction: R := L~^{-T} L~^{-1} R, then X += R
+    rc = execute(*splan, *simg, reinterpret_cast<double*>(W), R, nrhs, true, false, sched, sched_bytes, stream_v, so,
+                 11, nullptr, D, 2);
+    if (rc != 0) return rc;
+    if (tchol_refine_axpy(B, R, n * nrhs, s) != hipSuccess) return TCHOL_E_HIP;
+  }
+}
+
 const char* tchol_strerror(int32_t code) {
   if (code == 0) return "success";
   if (code > 0) return "matrix is not positive definite (leading minor of order `code`)";
@@ -425,6 +573,7 @@ const char* tchol_strerror(int32_t code) {
   if (code == TCHOL_E_TIMEOUT) return "a dependency wait inside the kernel exceeded its bound";
   if (code == TCHOL_E_UNSUPPORTED) return "unsupported size or option";
   if (code == TCHOL_E_INTERNAL) return "work items left unfinished at kernel exit";
+  if (code == TCHOL_E_NOCONV) return "iterative refinement did not reach its tolerance";
   if (code < 0 && code > -100) return "invalid argument (number -code)";
   return "unknown error";
 }

@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include "kargs.h"
+#include <type_traits>
 #include "tchol_kinds.h"
 
 #define NT 256                 // threads per workgroup: 4 wavefronts of 64
@@ -67,6 +68,12 @@ constexpr int imin_c(int a, int b) { return a < b ? a : b; }
 __device__ __forceinline__ void st_dev(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_dev(float* p, float v) {
+  __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // s_waitcnt vmcnt(N) with the other counters left alone (gfx9 encoding).
 template <int N>
@@ -280,6 +287,122 @@ __device__ __forceinline__ void gemm_nt(double* C, const double* Ap, const doubl
 }
 
 // ---------------------------------------------------------------------------
+// FP32 tile product for the mixed-precision factorization:
+//     C[M x N] -= Ap[M x K] * Bp[N x K]^T in FP32 storage, FP32 MFMA
+// (v_mfma_f32_16x16x4f32, the FP64 instruction's shape and operand layout)
+// with FP32 accumulation; 128 x 128 outputs, K % KC == 0.  A stage holds KC
+// k-rows laid out as [A row (128) | B row (128) | 16 pad] floats, so one
+// 16-byte-per-lane transfer moves one k-row of both panels (lanes 0..31: A,
+// lanes 32..63: B) and the padded rows keep the fragment reads free of bank
+// conflicts.  Rows are moved four at a time: the row group of the last valid
+// row may read up to three rows past the panel, which the mixed working copy
+// provides (its leading dimension exceeds the order by at least three).
+// The f32 MFMA has no operand negation, so the A fragment is negated.  Its
+// 16 x 16 result differs in layout from the f64 instruction's: element i of
+// lane l holds row 4 (l / 16) + i (not 4 i + l / 16) of column l % 16.
+#define F32_LD 272
+template <int KC, int NST>
+__device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float* __restrict__ Ap,
+                                              const float* __restrict__ Bp, int64_t ld, int M, int N, int K,
+                                              bool lower_only, double* lds_d) {
+  constexpr int STAGE = KC * F32_LD;  // floats per stage
+  constexpr int W = KC / 4;           // transfers per wavefront and chunk
+  static_assert(NST * STAGE <= 2 * LDS_DOUBLES, "stages must fit the workgroup LDS");
+  static_assert(KC % 4 == 0 && W >= 1, "every wavefront transfers whole k-rows");
+  float* lds = reinterpret_cast<float*>(lds_d);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 wavefronts, 64 x 64 each
+  const int l16 = lane & 15, lg = lane >> 4;
+  const bool arow = lane < 32;
+  const float* src0 = arow ? Ap + imin(4 * lane, (M - 1) & ~3) : Bp + imin(4 * (lane - 32), (N - 1) & ~3);
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 64 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+        acc[rb][cb][i] = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
+      }
+
+  static_assert(STAGE % 2 == 0 && F32_LD % 2 == 0, "destinations are addressed in doubles");
+  auto issue = [&](int ch) __attribute__((always_inline)) {
+    // destinations as double pointers into the shared array (stage and row offsets are even)
+    double* st = lds_d + (ch % NST) * (STAGE / 2);
+    const int k0 = ch * KC;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int q = wave + 4 * j;  // k-row of the chunk
+      dma16(src0 + (int64_t)(k0 + q) * ld, st + q * (F32_LD / 2));
+    }
+  };
+  auto compute = [&](int ch) __attribute__((always_inline)) {
+    const float* st = lds + (ch % NST) * STAGE;
+    float fa[2][4], fb[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) fa[0][rb] = -st[lg * F32_LD + wm * 64 + rb * 16 + l16];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) fb[0][cb] = st[lg * F32_LD + 128 + wn * 64 + cb * 16 + l16];
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int cur = ks & 1, nxt = cur ^ 1;
+      if (ks + 1 < KC / 4) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) fa[nxt][rb] = -st[((ks + 1) * 4 + lg) * F32_LD + wm * 64 + rb * 16 + l16];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          fb[nxt][cb] = st[((ks + 1) * 4 + lg) * F32_LD + 128 + wn * 64 + cb * 16 + l16];
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[cur][cb], fa[cur][rb], acc[rb][cb], 0, 0, 0);
+    }
+  };
+  const int nch = K / KC;
+#pragma unroll
+  for (int p = 0; p < NST - 1; ++p)
+    if (p < nch) issue(p);
+  int ch = 0;
+  for (; ch + NST - 1 < nch; ++ch) {
+    wait_vmcnt<imin_c((NST - 2) * W, 63)>();
+    __syncthreads();
+    issue(ch + NST - 1);
+    compute(ch);
+  }
+  for (; ch < nch; ++ch) {
+    const int later = nch - 1 - ch;
+    if (later >= 2) wait_vmcnt<imin_c(2 * W, 63)>();
+    else if (later == 1) wait_vmcnt<imin_c(W, 63)>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    compute(ch);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 64 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+        if (row < M && col < N && (!lower_only || row >= col)) st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
+      }
+}
+
+__device__ __forceinline__ void gemm_nt_f32(float* C, const float* Ap, const float* Bp, int64_t ld, int M, int N,
+                                            int K, bool lower_only, double* lds) {
+  if (K % 32 == 0)
+    gemm_f32_core<32, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+  else
+    gemm_f32_core<16, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+}
+
+// ---------------------------------------------------------------------------
 // POTRF work item: Akk (m x m, m <= 512) := chol(Akk), lower, in place.
 // Left-looking by panels of PW = 16 columns; a panel stays in LDS from its
 // update to its store:
@@ -393,7 +516,8 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 
 // ---------------------------------------------------------------------------
 // TRSM work item: a strip of S <= 32 rows of A_ik, X := X L_kk^{-T}
-// (mk = order of L_kk, a multiple of 16).  Transposed, X^T := L_kk^{-1} X^T
+// (mk = order of L_kk, a multiple of 16; X in FP64 or, in the mixed-precision
+// factorization, FP32 storage, computed in FP64 either way).  Transposed, X^T := L_kk^{-1} X^T
 // is a forward solve with the strip's rows as 32 right-hand sides (two
 // groups of 16).  The strip lives in LDS as Xs[g][c][16] (row 16g + j,
 // column c), which the MFMA fragments read without bank conflicts.  For
@@ -406,8 +530,9 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 // of the step, to land during the solve.
 #define TS 32
 
-__device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double* __restrict__ Lkk, int64_t ld, int S,
-                                           int mk, double* lds) {
+template <typename TX>
+__device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, const double* __restrict__ Lkk, int64_t ld,
+                                           int S, int mk, double* lds) {
   double* Xs = lds;  // [2][512][16]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -420,7 +545,7 @@ __device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double*
     for (int part = 0; part < 4; ++part) {
       double v[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = X[(int64_t)imin(c0 + 8 * (u + 16 * part), mk - 1) * ld + rr];
+      for (int u = 0; u < 16; ++u) v[u] = (double)X[(int64_t)imin(c0 + 8 * (u + 16 * part), mk - 1) * ldx + rr];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int c = c0 + 8 * (u + 16 * part);
@@ -526,7 +651,7 @@ __device__ __forceinline__ void trsm_strip(double* __restrict__ X, const double*
   {
     const int r = tid & 31, c0 = tid >> 5;
     if (r < S)
-      for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ld + r, Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
+      for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ldx + r, (TX)Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
   }
 }
 
@@ -770,7 +895,8 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
 // B_i[rows] -= L_ik[rows, :] Y_k  (forward update), rows = a strip of <= 128.
 // Each wavefront owns two 16-row blocks of the strip; the L fragments are
 // read straight from HBM (16 consecutive rows of a column per lane group).
-__device__ __forceinline__ void fgemv(const double* __restrict__ Lik, int64_t ld, double* Bi, const double* Yk,
+template <typename TL>
+__device__ __forceinline__ void fgemv(const TL* __restrict__ Lik, int64_t ld, double* Bi, const double* Yk,
                                       int64_t ldb, int rows, int mk, int nrhs, double* lds) {
   double* Ys = lds;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -797,8 +923,8 @@ __device__ __forceinline__ void fgemv(const double* __restrict__ Lik, int64_t ld
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = imin(kb + 4 * u + lg, mk - 1);
-        f0[u] = Lik[(int64_t)q * ld + ra];
-        f1[u] = Lik[(int64_t)q * ld + rbb];
+        f0[u] = (double)Lik[(int64_t)q * ld + ra];
+        f1[u] = (double)Lik[(int64_t)q * ld + rbb];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -822,7 +948,8 @@ __device__ __forceinline__ void fgemv(const double* __restrict__ Lik, int64_t ld
 }
 
 // Y_i[cols] -= L_ki[:, cols]^T X_k  (backward update), cols = a strip of <= 128.
-__device__ __forceinline__ void bgemv(const double* __restrict__ Lki, int64_t ld, double* Yi, const double* Xk,
+template <typename TL>
+__device__ __forceinline__ void bgemv(const TL* __restrict__ Lki, int64_t ld, double* Yi, const double* Xk,
                                       int64_t ldb, int cols, int mk, int nrhs, double* lds) {
   double* Xs = lds;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -841,15 +968,15 @@ __device__ __forceinline__ void bgemv(const double* __restrict__ Lki, int64_t ld
         const int c = (wave * 2 + t) * 16 + 4 * i + lg;
         acc[t][i] = Yi[(int64_t)(j0 + jc) * ldb + imin(c, cols - 1)];
       }
-    const double* c0p = Lki + (int64_t)imin((wave * 2) * 16 + l16, cols - 1) * ld;
-    const double* c1p = Lki + (int64_t)imin((wave * 2 + 1) * 16 + l16, cols - 1) * ld;
+    const TL* c0p = Lki + (int64_t)imin((wave * 2) * 16 + l16, cols - 1) * ld;
+    const TL* c1p = Lki + (int64_t)imin((wave * 2 + 1) * 16 + l16, cols - 1) * ld;
     for (int kb = 0; kb < mk; kb += 32) {
       double f0[8], f1[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = imin(kb + 4 * u + lg, mk - 1);
-        f0[u] = c0p[q];
-        f1[u] = c1p[q];
+        f0[u] = (double)c0p[q];
+        f1[u] = (double)c1p[q];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -870,6 +997,47 @@ __device__ __forceinline__ void bgemv(const double* __restrict__ Lki, int64_t ld
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// POTRF of the mixed-precision factorization: the FP32 diagonal tile Wkk is
+// promoted to an FP64 tile Dk (ld nb, in the workspace), factored there in
+// FP64 by the same tile kernel, and rounded back into Wkk.  Dk is kept: the
+// TRSM strips of step k and the tile solves read L_kk from it in FP64.
+__device__ __forceinline__ int potrf_tile_mixed(float* __restrict__ Wkk, int64_t ldw, int m,
+                                                double* __restrict__ Dk, int64_t ldd, double* lds) {
+  const int tid = threadIdx.x;
+  // lower triangle (and diagonal) to FP64; 16 loads of a thread in flight
+  for (int base = 0; base < m * m; base += 16 * NT) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = imin(base + u * NT + tid, m * m - 1), c = idx / m, r = idx % m;
+      v[u] = Wkk[(int64_t)c * ldw + r];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = base + u * NT + tid, c = idx / m, r = idx % m;
+      if (idx < m * m && r >= c) st_dev(Dk + (int64_t)c * ldd + r, (double)v[u]);
+    }
+  }
+  wait_vmcnt<0>();
+  __syncthreads();
+  const int info = __builtin_amdgcn_readfirstlane(potrf_tile<128>(Dk, ldd, m, lds));
+  for (int base = 0; base < m * m; base += 16 * NT) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = imin(base + u * NT + tid, m * m - 1), c = idx / m, r = idx % m;
+      v[u] = Dk[(int64_t)c * ldd + r];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = base + u * NT + tid, c = idx / m, r = idx % m;
+      if (idx < m * m && r >= c) st_dev(Wkk + (int64_t)c * ldw + r, (float)v[u]);
+    }
+  }
+  return info;
 }
 
 // ---------------------------------------------------------------------------
@@ -923,8 +1091,16 @@ __device__ __forceinline__ void raise_error(const KArgs& a, int code) {
 // every panel the updates stream is 16-byte transferable; SEG = 32 serves
 // every other case.  One transfer width per kernel instance keeps the
 // update loops free of per-item branches.
-template <int SEG>
+// MODE 0: FP64 factorization and solve.  MODE 1 / 2: the mixed-precision
+// factorization / its solves: the matrix is the FP32 working copy (a.A points
+// to it), factored with FP32 MFMA updates and FP64 diagonal tiles kept in
+// a.D; solves run in FP64 reading L in FP32 off the diagonal and in FP64 on
+// it.  A mixed launch runs only its own task kinds (keeping each instance
+// small) and is always a 16-byte one.
+template <int SEG, int MODE>
 __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
+  constexpr bool MIXED = MODE != 0;
+  constexpr bool FACTOR_KINDS = MODE != 2, SOLVE_KINDS = MODE != 1;
   __shared__ double lds[LDS_DOUBLES];
   __shared__ int s_claim[3];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -962,7 +1138,8 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     // the task's system: base pointers, order, tile size, leading dimension
     const int sid = uniform_i(d[7]);
     const int64_t* sr = a.sys + SYS_WORDS * (int64_t)sid;
-    double* const Abase = a.A + sr[0];
+    using E = typename std::conditional<MIXED, float, double>::type;
+    E* const Abase = reinterpret_cast<E*>(a.A) + sr[0];
     double* const Bbase = a.B + sr[1];
     const int64_t sn = sr[2], nb = sr[3], ld = sr[4], ldb = sn;
     auto tsz = [&](int t) __attribute__((always_inline)) { return (int)tile_size(sn, nb, t); };
@@ -974,8 +1151,16 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
       case -1:
         break;
       case TK_POTRF: {
-        double* Akk = Abase + (tk * nb) * ld + tk * nb;
-        const int info = uniform_i(potrf_tile<SEG>(Akk, ld, tsz(tk), lds));
+        if constexpr (!FACTOR_KINDS) {
+          ok = 0;
+          break;
+        }
+        E* Akk = Abase + (tk * nb) * ld + tk * nb;
+        int info;
+        if constexpr (MIXED)
+          info = uniform_i(potrf_tile_mixed(Akk, ld, tsz(tk), a.D + (int64_t)tk * nb * nb, nb, lds));
+        else
+          info = uniform_i(potrf_tile<SEG>(Akk, ld, tsz(tk), lds));
         if (info != 0 && tid == 0) {
           if (a.batched) {
             __hip_atomic_store(&a.sinfo[sid], (int)(tk * nb) + info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -988,14 +1173,25 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         break;
       }
       case TK_TRSM: {
+        if constexpr (!FACTOR_KINDS) {
+          ok = 0;
+          break;
+        }
         const int r0 = part * a.trsm_rows;
         const int S = imin(a.trsm_rows, tsz(ti) - r0);
-        trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, Abase + (tk * nb) * ld + tk * nb, ld, S, tsz(tk),
-                   lds);
+        if constexpr (MIXED)
+          trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, a.D + (int64_t)tk * nb * nb, nb, S, tsz(tk), lds);
+        else
+          trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Abase + (tk * nb) * ld + tk * nb, ld, S, tsz(tk),
+                     lds);
         break;
       }
       case TK_SYRK:
       case TK_GEMM: {
+        if constexpr (!FACTOR_KINDS) {
+          ok = 0;
+          break;
+        }
         int si, sj;
         if (kind == TK_SYRK) {
           si = 0;
@@ -1008,24 +1204,44 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         }
         const int M = imin(a.gemm_m, tsz(ti) - si * a.gemm_m);
         const int N = imin(a.gemm_n, tsz(tj) - sj * a.gemm_n);
-        double* C = Abase + (tj * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m;
-        const double* Ap = Abase + (tk * nb) * ld + ti * nb + si * a.gemm_m;
-        const double* Bp = Abase + (tk * nb) * ld + tj * nb + sj * a.gemm_n;
-        if (SEG == 128 && (((int)ld & 1) != 0 || (((M | N) & 1) != 0 && ld <= sn) ||
-                           ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) != 0)) {
-          raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
-          ok = 0;
-          break;
+        E* C = Abase + (tj * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m;
+        const E* Ap = Abase + (tk * nb) * ld + ti * nb + si * a.gemm_m;
+        const E* Bp = Abase + (tk * nb) * ld + tj * nb + sj * a.gemm_n;
+        const bool misaligned = ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) != 0;
+        if constexpr (MIXED) {
+          // four rows per 16-byte lane: ld a multiple of 4 and three rows after the order
+          if ((((int)ld & 3) != 0) || ld < sn + 3 || misaligned) {
+            raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
+            ok = 0;
+            break;
+          }
+          gemm_nt_f32(C, Ap, Bp, ld, M, N, tsz(tk), kind == TK_SYRK && si == sj, lds);
+        } else {
+          if (SEG == 128 && (((int)ld & 1) != 0 || (((M | N) & 1) != 0 && ld <= sn) || misaligned)) {
+            raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
+            ok = 0;
+            break;
+          }
+          gemm_nt<SEG>(C, Ap, Bp, ld, M, N, tsz(tk), kind == TK_SYRK && si == sj, lds);
         }
-        gemm_nt<SEG>(C, Ap, Bp, ld, M, N, tsz(tk), kind == TK_SYRK && si == sj, lds);
         break;
       }
       case TK_FTRSV:
       case TK_BTRSV:
-        tile_solve(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
-                   kind == TK_BTRSV, lds);
+        if constexpr (!SOLVE_KINDS)
+          ok = 0;
+        else if constexpr (MIXED)
+          tile_solve(a.D + (int64_t)tk * nb * nb, nb, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs, kind == TK_BTRSV,
+                     lds);
+        else
+          tile_solve(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
+                     kind == TK_BTRSV, lds);
         break;
       case TK_FGEMV: {
+        if constexpr (!SOLVE_KINDS) {
+          ok = 0;
+          break;
+        }
         const int r0 = part * a.gemv_rows;
         const int rows = imin(a.gemv_rows, tsz(ti) - r0);
         fgemv(Abase + (tk * nb) * ld + ti * nb + r0, ld, Bbase + ti * nb + r0, Bbase + tk * nb, ldb, rows, tsz(tk),
@@ -1033,6 +1249,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         break;
       }
       case TK_BGEMV: {
+        if constexpr (!SOLVE_KINDS) {
+          ok = 0;
+          break;
+        }
         const int c0 = part * a.gemv_rows;
         const int cols = imin(a.gemv_rows, tsz(ti) - c0);
         bgemv(Abase + (ti * nb + c0) * ld + tk * nb, ld, Bbase + ti * nb + c0, Bbase + tk * nb, ldb, cols, tsz(tk),
@@ -1100,10 +1320,14 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
     e = hipEventRecord(ev0, stream);
     if (e != hipSuccess) return e;
   }
-  if (wide)
-    hipLaunchKernelGGL(tchol_persistent<128>, dim3(grid), dim3(NT), 0, stream, *a);
+  if (a->mixed == 1)
+    hipLaunchKernelGGL((tchol_persistent<128, 1>), dim3(grid), dim3(NT), 0, stream, *a);
+  else if (a->mixed == 2)
+    hipLaunchKernelGGL((tchol_persistent<128, 2>), dim3(grid), dim3(NT), 0, stream, *a);
+  else if (wide)
+    hipLaunchKernelGGL((tchol_persistent<128, 0>), dim3(grid), dim3(NT), 0, stream, *a);
   else
-    hipLaunchKernelGGL(tchol_persistent<32>, dim3(grid), dim3(NT), 0, stream, *a);
+    hipLaunchKernelGGL((tchol_persistent<32, 0>), dim3(grid), dim3(NT), 0, stream, *a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev1) e = hipEventRecord(ev1, stream);
@@ -1116,11 +1340,18 @@ extern "C" hipError_t tchol_dev_max_grid(int device, int* grid) {
   if (e != hipSuccess) return e;
   // both instances share the LDS size and launch bounds; take the smaller occupancy
   int occ32 = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tchol_persistent<128>, NT, 0);
+  int occm = 0, occs = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tchol_persistent<128, 0>, NT, 0);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ32, tchol_persistent<32>, NT, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ32, tchol_persistent<32, 0>, NT, 0);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occm, tchol_persistent<128, 1>, NT, 0);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occs, tchol_persistent<128, 2>, NT, 0);
   if (e != hipSuccess) return e;
   occ = occ < occ32 ? occ : occ32;
+  occ = occ < occm ? occ : occm;
+  occ = occ < occs ? occ : occs;
   *grid = cus * (occ > 0 ? occ : 1);
   return hipSuccess;
 }

@@ -37,7 +37,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_internal_symbols_are_not_exported(lib):
-    for name in ["tchol_dev_launch", "tchol_dev_max_grid"]:
+    for name in ["tchol_dev_launch", "tchol_dev_max_grid", "tchol_refine_convert", "tchol_refine_residual",
+                 "tchol_refine_colmax", "tchol_refine_axpy"]:
         with pytest.raises(AttributeError):
             getattr(lib, name)
 
@@ -84,8 +85,38 @@ def test_solve_validation_before_any_hip_call(lib):
     assert lib.tchol_solve(FAKE, 256, 64, FAKE, 4, FAKE_MISALIGNED, need, None) == -6
 
 
+def test_mixed_validation_before_any_hip_call(lib):
+    n, nb, k = 256, 64, 4
+    need = lib.tchol_mixed_workspace_bytes(n, nb, k)
+    # the FP32 working copy (ld n + 3 rounded up to 4) and the FP64 diagonal tiles dominate
+    assert need >= 4 * 260 * n + 8 * 4 * nb * nb + 2 * 8 * n * k
+    assert lib.tchol_mixed_workspace_bytes(-1, nb, k) == -1
+    assert lib.tchol_mixed_workspace_bytes(n, 24, k) == -2
+    assert lib.tchol_mixed_workspace_bytes(n, nb, -1) == -3
+    berr = (ctypes.c_double * k)()
+    it = ctypes.c_int32(-7)
+
+    def call(A=FAKE, n_=n, nb_=nb, B=FAKE, k_=k, lowp=1, tol=1e-12, maxit=10, ws=FAKE, wsb=need):
+        return lib.tchol_solve_mixed(A, n_, nb_, B, k_, lowp, tol, maxit, berr, ctypes.byref(it), ws, wsb, None, None)
+
+    assert call(n_=-1) == -2
+    assert call(nb_=40) == -3
+    assert call(k_=-1) == -5
+    assert call(lowp=0) == -6 and call(lowp=2) == -6
+    assert call(tol=0.0) == -7 and call(tol=float("nan")) == -7
+    assert call(maxit=-1) == -8
+    assert call(n_=0) == 0 and it.value == 0
+    assert call(k_=0) == 0
+    assert call(A=None) == -1
+    assert call(B=None) == -4
+    assert call(ws=None) == -11
+    assert call(ws=FAKE_MISALIGNED) == -11
+    assert call(wsb=0) == -12
+    assert call(wsb=need - 256) == -12
+
+
 def test_strerror_and_version(lib):
-    for code in (0, 5, -3, tc.E_HIP, tc.E_TIMEOUT, tc.E_UNSUPPORTED, tc.E_INTERNAL, -999):
+    for code in (0, 5, -3, tc.E_HIP, tc.E_TIMEOUT, tc.E_UNSUPPORTED, tc.E_INTERNAL, tc.E_NOCONV, -999):
         assert isinstance(tc.strerror(code), str) and tc.strerror(code)
     assert "gfx950" in tc.version()
 
