@@ -208,6 +208,134 @@ def run_batched(args):
     }
     print(json.dumps(out), flush=True)
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def measure_mixed(torch, tc, dev, n, nb, nrhs, seed, shift, K, Wm, policy, fp64_ms=None, tol=1e-12, maxit=30):
+    """Mixed-precision solve with refinement to eta <= tol of nrhs right-hand
+    sides of A = B B^T / n + shift I (B ~ U[-1, 1], seed), timed per step
+    (factor + refinement, A resident; every step starts from the original
+    right-hand sides).  fp64_ms: FP64 factor + solve time of the same order
+    to compare against; None measures it here on the same matrix.  Returns
+    a dict of the results."""
+    import spd_inputs
+    t0 = time.time()
+    A, rng = spd_inputs.spd_matrix_device(n, seed, shift, device=dev)
+    B0 = torch.from_numpy(spd_inputs.rhs(rng, n, nrhs)).to(dev)
+    B0c = B0.t().contiguous()
+    torch.cuda.synchronize()
+    log("mixed: inputs ready in %.1f s (n=%d nb=%d nrhs=%d shift=%g seed=%d)" % (time.time() - t0, n, nb, nrhs,
+                                                                                 shift, seed))
+    ws = torch.empty(tc.mixed_workspace_bytes(n, nb, nrhs), dtype=torch.uint8, device=dev)
+    X = torch.empty_like(B0c)
+    for w in range(Wm):
+        X.copy_(B0c)
+        rc, it, berr = tc.solve_mixed_(A, X, nb, tol=tol, maxit=maxit, policy=policy, ws=ws)
+        log("mixed warmup %d: rc=%d iterations=%d max eta=%.3g" % (w + 1, rc, it, float(np.max(berr))))
+    steps = []
+    for s_ in range(K):
+        X.copy_(B0c)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        rc, it, berr, fms = tc.solve_mixed_(A, X, nb, tol=tol, maxit=maxit, policy=policy, ws=ws,
+                                             want_kernel_ms=True)
+        torch.cuda.synchronize()
+        steps.append(((time.perf_counter() - ts) * 1e3, rc, it, float(np.max(berr)), fms))
+        log("mixed step %d: %.3f ms rc=%d iterations=%d max eta=%.3g factor kernel %.3f ms"
+            % (s_ + 1, steps[-1][0], rc, it, steps[-1][3], fms))
+    if any(st[1] != 0 for st in steps):
+        raise RuntimeError("mixed solve did not converge: %s" % [st[1] for st in steps])
+    ms = float(np.mean([st[0] for st in steps]))
+    fms = float(np.mean([st[4] for st in steps]))
+    # independent check of the last solution: FP64 residual with torch's product
+    # (whole matrix), and 64 sampled rows with long-double sums on the host
+    R = B0 - A @ X.t()
+    anorm = float(A.abs().sum(dim=1).max().item())
+    eta_full = (R.abs().amax(dim=0) / (anorm * X.t().abs().amax(dim=0) + B0.abs().amax(dim=0))).cpu().numpy()
+    rng_s = np.random.default_rng(7)
+    Xh = X.t().cpu().numpy().astype(np.longdouble)
+    Bh = B0.cpu().numpy()
+    worst_row = 0.0
+    for i in rng_s.integers(0, n, size=64):
+        row = A[int(i)].cpu().numpy().astype(np.longdouble)
+        r = Bh[int(i)] - row @ Xh
+        worst_row = max(worst_row, float(np.max(np.abs(r))))
+    out = {"ms_per_solve": round(ms, 3), "factor_kernel_ms": round(fms, 3),
+           "refinement_iterations": [st[2] for st in steps], "eta_reported_max": max(st[3] for st in steps),
+           "eta_check_max": float(np.max(eta_full)), "abs_residual_sampled_rows_max": worst_row,
+           "value": round(n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3), "tol": tol}
+    out["factor_roofline"] = {"bound": "mfma", "achieved": round(n ** 3 / 3.0 / (fms * 1e-3) / 1e12, 3),
+                              "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(n ** 3 / 3.0 / (fms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
+                              "note": "trailing updates on FP32 matrix cores; POTRF and TRSM in FP64"}
+    del ws
+    if fp64_ms is None:
+        ws_f = torch.empty(tc.workspace_bytes(tc.OP_FACTOR, n, nb), dtype=torch.uint8, device=dev)
+        ws_s = torch.empty(tc.workspace_bytes(tc.OP_SOLVE, n, nb, nrhs), dtype=torch.uint8, device=dev)
+        Wt = torch.empty_like(A)
+        t64 = []
+        for s_ in range(max(1, K)):
+            Wt.copy_(A)
+            X.copy_(B0c)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            if tc.factor_(Wt, nb, policy=policy, ws=ws_f) != 0:
+                raise RuntimeError("fp64 factorization failed")
+            tc.solve_(Wt, X, nb, ws=ws_s)
+            torch.cuda.synchronize()
+            t64.append((time.perf_counter() - ts) * 1e3)
+        fp64_ms = float(np.mean(t64))
+        R = B0 - A @ X.t()
+        out["fp64_eta_max"] = float((R.abs().amax(dim=0) / (anorm * X.t().abs().amax(dim=0) +
+                                                           B0.abs().amax(dim=0))).max().item())
+        out["fp64_measured_on"] = "the same matrix"
+        del Wt, ws_f, ws_s
+    else:
+        out["fp64_measured_on"] = "the fp64 workload's matrix of the same order (its time does not depend on values)"
+    out["fp64_ms_per_solve"] = round(fp64_ms, 3)
+    out["speedup_vs_fp64"] = round(fp64_ms / ms, 3)
+    del A, X
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_mixed(args):
+    """The mixed-precision workload alone: n = 32768, nb = 512, A = B B^T/n + 1e-4 I
+    (seed 2), 16 right-hand sides refined to eta <= 1e-12, against FP64 on the
+    same matrix."""
+    import torch
+    import paper_1402_6601_amd as tc
+    tc.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    seed = 2 if args.seed == 1 else args.seed
+    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM}[args.policy]
+    r = measure_mixed(torch, tc, dev, args.n, args.nb, args.nrhs, seed, 1e-4, args.steps, args.warmup, policy)
+    out = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "mixed fp32/fp64 Cholesky + iterative refinement of %d RHS to eta<=1e-12, "
+                               "n=%d, nb=%d, A=B*B^T/n+1e-4*I, B~U[-1,1] (seed %d)"
+                               % (args.nrhs, args.n, args.nb, seed),
+                   "n": args.n, "nb": args.nb, "nrhs": args.nrhs, "seed": seed, "shift": 1e-4},
+        "roofline": r["factor_roofline"],
+        "mixed": r,
+    }
+    print(json.dumps(out), flush=True)
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -222,8 +350,11 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=8192,
                     help="order of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a device copy of this many bytes")
-    ap.add_argument("--workload", choices=["factor", "batched"], default="factor",
-                    help="factor: the n=32768 factor + solve (default); batched: 4096 systems in one launch")
+    ap.add_argument("--workload", choices=["factor", "batched", "mixed"], default="factor",
+                    help="factor: the n=32768 factor + solve (default); batched: 4096 systems in one launch; "
+                         "mixed: the mixed-precision solve with refinement alone")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="factor workload: skip the mixed-precision comparison appended to the line")
     ap.add_argument("--count", type=int, default=4096, help="batched: number of systems")
     args = ap.parse_args()
 
@@ -237,6 +368,9 @@ def main():
         return
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "mixed":
+        run_mixed(args)
         return
 
     import torch
@@ -346,6 +480,15 @@ def main():
         "reconstruction_err_sampled": recon,
     }
     del work, rhs
+
+    if not args.no_mixed:
+        # the mixed-precision solve of the same order (its own matrix family: shift 1e-4,
+        # seed 2), compared with this run's FP64 factor + solve time
+        del ws_s
+        torch.cuda.empty_cache()
+        out["mixed_refined"] = measure_mixed(torch, tc, dev, n, nb, nrhs, 2, 1e-4, 2, 1, policy,
+                                             fp64_ms=ms_per_step)
+        ws_s = None
 
     if args.cpu_sample_n > 0:
         import oracle
