@@ -53,6 +53,8 @@ def _load():
     lib.oracle_potrs.argtypes = [i64, vp, i64, i64, vp, i64]
     lib.oracle_residual.restype = None
     lib.oracle_residual.argtypes = [i64, vp, i64, i64, vp, i64, vp, i64, vp, i64]
+    lib.oracle_chol_adjoint.restype = None
+    lib.oracle_chol_adjoint.argtypes = [i64, vp, i64, vp, i64]
     lib.oracle_llt_entry.restype = ctypes.c_double
     lib.oracle_llt_entry.argtypes = [vp, i64, i64, i64]
     lib.oracle_num_threads.restype = ctypes.c_int
@@ -122,6 +124,19 @@ def residual(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> np.ndarray:
     _load().oracle_residual(n, _ptr(Af), max(n, 1), Xf.shape[1], _ptr(Xf), max(n, 1), _ptr(Bf), max(n, 1),
                             _ptr(Rf), max(n, 1))
     return Rf[:, 0].copy() if vec else Rf
+
+
+def chol_adjoint(L: np.ndarray, Lbar: np.ndarray) -> np.ndarray:
+    """Abar = df/dA (symmetric, returned in full) for the Cholesky factor L of
+    A and the upstream Lbar = df/dL (lower triangles used), by the reverse of
+    the oracle's own factorization steps (see oracle_chol_adjoint)."""
+    L = np.asarray(L, dtype=np.float64)
+    n = L.shape[0]
+    Lf = np.array(np.tril(L), dtype=np.float64, order="F", copy=True)
+    Pf = np.array(np.tril(np.asarray(Lbar, dtype=np.float64)), order="F", copy=True)
+    _load().oracle_chol_adjoint(n, _ptr(Lf), max(n, 1), _ptr(Pf), max(n, 1))
+    low = np.tril(Pf)
+    return low + np.tril(low, -1).T
 
 
 def llt_entry(L: np.ndarray, i: int, j: int) -> float:

@@ -135,3 +135,49 @@ double oracle_llt_entry(const double *L, int64_t ldl, int64_t i, int64_t j) {
     for (int64_t k = 0; k <= m; ++k) s += (long double)AT(L, ldl, i, k) * (long double)AT(L, ldl, j, k);
     return (double)s;
 }
+
+/*
+ * Adjoint of the Cholesky factorization (reverse-mode derivative).  Given
+ * the factor L of A and Lbar = df/dL for a scalar f (both lower triangles),
+ * computes Abar = df/dA for the symmetric A and overwrites the lower
+ * triangle of Lbar with the lower triangle of Abar.
+ *
+ * The derivative of the factorization is not stated in the paper; the
+ * oracle takes the plainest definition: the reverse of each arithmetic step
+ * of oracle_potrf above, run in the opposite order (reverse-mode
+ * differentiation of that program, with every value it reverses read from
+ * the final L, which is where oracle_potrf leaves it).  The forward step k
+ *     l = sqrt(a_kk);  a_ik := a_ik / l  (i > k);
+ *     a_ij := a_ij - a_ik a_jk  (j > k, i >= j)
+ * has the reverse (adjoints p, starting from Lbar)
+ *     p_ik -= p_ij l_jk  and  p_jk -= p_ij l_ik   for j > k, i >= j
+ *     p_ik := p_ik / l_kk,  p_kk -= p_ik l_ik      for i > k
+ *     p_kk := p_kk / (2 l_kk).
+ * The first line, collected per row r > k of column k:
+ *     p_rk -= sum_{k<j<=r} p_rj l_jk + sum_{i>=r} p_ir l_ik
+ * (the term i = j = r appears in both sums: the square in the update of
+ * a_rr).  p is then the derivative with respect to the entries the program
+ * reads, the lower triangle of A; since a_ij for i > j stands for both
+ * a_ij and a_ji of the symmetric matrix, Abar_ij = p_ij / 2 off the
+ * diagonal and Abar_ii = p_ii, which is the last step.
+ */
+void oracle_chol_adjoint(int64_t n, const double *L, int64_t ldl, double *P, int64_t ldp) {
+    for (int64_t k = n - 1; k >= 0; --k) {
+#pragma omp parallel for schedule(static) if (n - k > 256)
+        for (int64_t r = k + 1; r < n; ++r) {
+            double s = 0.0;
+            for (int64_t j = k + 1; j <= r; ++j) s = s + AT(P, ldp, r, j) * AT(L, ldl, j, k);
+            for (int64_t i = r; i < n; ++i) s = s + AT(P, ldp, i, r) * AT(L, ldl, i, k);
+            AT(P, ldp, r, k) = AT(P, ldp, r, k) - s;
+        }
+        double l_kk = AT(L, ldl, k, k);
+        double t = AT(P, ldp, k, k);
+        for (int64_t i = k + 1; i < n; ++i) {
+            AT(P, ldp, i, k) = AT(P, ldp, i, k) / l_kk;
+            t = t - AT(P, ldp, i, k) * AT(L, ldl, i, k);
+        }
+        AT(P, ldp, k, k) = t / (2.0 * l_kk);
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = j + 1; i < n; ++i) AT(P, ldp, i, j) = AT(P, ldp, i, j) * 0.5;
+}
