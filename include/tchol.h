@@ -50,6 +50,7 @@ extern "C" {
 #define TCHOL_OP_FACTOR 0
 #define TCHOL_OP_SOLVE 1
 #define TCHOL_OP_BATCHED 2 /* factor + solve of many systems (plan introspection only) */
+#define TCHOL_OP_BACKWARD 3 /* adjoint of the factorization */
 
 #define TCHOL_POLICY_RANK 0   /* decreasing upward rank (default)          */
 #define TCHOL_POLICY_FIFO 1   /* step-major: (k, kind, i, j) ascending      */
@@ -79,8 +80,8 @@ typedef struct tchol_opts {
                           {start, end} wall clock (100 MHz), {task, part | wg<<32} */
 } tchol_opts;
 
-/* Bytes of device workspace needed by `op` (TCHOL_OP_*) for order n and tile
-   size nb (nrhs is ignored by TCHOL_OP_FACTOR).  Returns -i for an invalid
+/* Bytes of device workspace needed by `op` (TCHOL_OP_FACTOR, _SOLVE or
+   _BACKWARD) for order n and tile size nb (nrhs is read by TCHOL_OP_SOLVE only).  Returns -i for an invalid
    argument i, TCHOL_E_UNSUPPORTED beyond the supported sizes. */
 TCHOL_API int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs);
 
@@ -100,6 +101,30 @@ TCHOL_API int32_t tchol_solve(const double *L, int64_t n, int64_t nb, double *B,
                     int64_t ws_bytes, void *stream);
 TCHOL_API int32_t tchol_solve_ex(const double *L, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
                        int64_t ws_bytes, void *stream, const tchol_opts *opts);
+
+/* Adjoint of the factorization (reverse-mode derivative): given the factor L
+   of A (from tchol_factor) and Lbar = df/dL for a scalar f, overwrites the
+   lower triangle of Lbar with that of Abar = df/dA, the symmetric gradient
+   (off-diagonal entries of a symmetric perturbation count once in each
+   triangle, so f(A + h (E_ij + E_ji)) changes by 2 h Abar_ij).  For
+   f = log det A (Lbar = diag(2 / L_ii)) the result is A^{-1}.
+   The derivative of the paper's tile Cholesky DAG (section 4.1) taken in
+   reverse: the steps from the last to the first, the GEMM / SYRK updates
+   of each step reversed as GEMMs into the adjoints of its panel (chained
+   per tile in a fixed order), its TRSMs as triangular solves with L_kk, its
+   POTRF as the adjoint of the diagonal tile's factorization, on the same
+   persistent scheduler in upward-rank order.  Results do not depend on the
+   claim order.  L must have a positive diagonal (a factor tchol_factor
+   returned with info 0); only lower triangles are read or written.
+   Workspace: tchol_workspace_bytes(TCHOL_OP_BACKWARD, n, nb, 0) bytes
+   (about 2 n^2 + n^2 / 2 doubles: the transposed factor, twice the
+   adjoint, and per-tile partial products).
+   Arguments: 1 L, 2 n, 3 nb (as for tchol_factor; n / nb at most 160),
+   4 Lbar (n x n, ld n), 5 ws, 6 ws_bytes, 7 stream, 8 opts (_ex). */
+TCHOL_API int32_t tchol_backward(const double *L, int64_t n, int64_t nb, double *Lbar, void *ws, int64_t ws_bytes,
+                                 void *stream);
+TCHOL_API int32_t tchol_backward_ex(const double *L, int64_t n, int64_t nb, double *Lbar, void *ws,
+                                    int64_t ws_bytes, void *stream, const tchol_opts *opts);
 
 /* Batched factor + solve of `batch` independent SPD systems in ONE launch
    of the persistent kernel.  Paper: the same tile DAG (section 4.1) per

@@ -22,11 +22,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
-OP_FACTOR, OP_SOLVE, OP_BATCHED = 0, 1, 2
+OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD = 0, 1, 2, 3
 POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV = -100, -101, -102, -103, -104
 LOWP_FP32 = 1
-KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV"]
+KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV"]
 
 _lib = None
 
@@ -64,6 +64,10 @@ def load() -> ctypes.CDLL:
     lib.tchol_solve.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp]
     lib.tchol_solve_ex.restype = i32
     lib.tchol_solve_ex.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, ctypes.POINTER(Opts)]
+    lib.tchol_backward.restype = i32
+    lib.tchol_backward.argtypes = [vp, i64, i64, vp, vp, i64, vp]
+    lib.tchol_backward_ex.restype = i32
+    lib.tchol_backward_ex.argtypes = [vp, i64, i64, vp, vp, i64, vp, ctypes.POINTER(Opts)]
     lib.tchol_mixed_workspace_bytes.restype = i64
     lib.tchol_mixed_workspace_bytes.argtypes = [i64, i64, i64]
     lib.tchol_solve_mixed.restype = i32
@@ -398,3 +402,72 @@ def solve_mixed(A, B, nb: int, *, fallback: bool = True, **kw):
         raise TcholError(int(rc), "tchol_solve_mixed")
     X = Bc.mT
     return (X.reshape(-1) if vec else X), {"rc": int(rc), "iters": iters, "berr": berr, "fallback": used}
+
+
+def backward_(Lbuf, Gb, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+              want_kernel_ms: bool = False, check: bool = True):
+    """Adjoint of the factorization, in place.  Lbuf: the (n, n) buffer factored
+    by factor_ (column-major lower = L).  Gb: CUDA float64 (n, n) contiguous
+    whose column-major lower triangle is Lbar = df/dL (i.e. Gb = Lbar^T in
+    row-major terms); on return its column-major lower triangle holds that of
+    the symmetric Abar = df/dA.  Returns rc, or (rc, kernel_ms)."""
+    torch = _torch()
+    n = Lbuf.shape[0]
+    for t in (Lbuf, Gb):
+        if t.dtype != torch.float64 or t.dim() != 2 or tuple(t.shape) != (n, n) or not t.is_contiguous():
+            raise ValueError("L and Lbar must be contiguous float64 (n, n) tensors")
+    lib = load()
+    with torch.cuda.device(Lbuf.device):
+        need = workspace_bytes(OP_BACKWARD, n, nb) if n else 256
+        if ws is None or ws.numel() < need:
+            ws = _workspace(torch, need, Lbuf.device)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, None)
+        rc = lib.tchol_backward_ex(ctypes.c_void_p(Lbuf.data_ptr()), n, nb, ctypes.c_void_p(Gb.data_ptr()),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(torch, Lbuf.device),
+                                   ctypes.byref(o))
+    if rc != 0 and check:
+        raise TcholError(rc, "tchol_backward")
+    return (rc, ms.value) if want_kernel_ms else rc
+
+
+_CHOL_FN = None
+
+
+def _chol_function():
+    global _CHOL_FN
+    if _CHOL_FN is not None:
+        return _CHOL_FN
+    import torch
+
+    class _Cholesky(torch.autograd.Function):
+        """L = chol(A) (lower) by the tile factorization; its backward runs the
+        library's adjoint and returns the symmetric gradient with respect to A."""
+
+        @staticmethod
+        def forward(ctx, A, nb):
+            W = A.detach().to(torch.float64).contiguous().clone()
+            info = factor_(W, nb)
+            if info != 0:
+                raise TcholError(int(info), "tchol_factor (matrix not positive definite)")
+            ctx.save_for_backward(W)
+            ctx.nb = nb
+            return torch.tril(W.mT)
+
+        @staticmethod
+        def backward(ctx, gL):
+            (W,) = ctx.saved_tensors
+            Gb = torch.tril(gL.to(torch.float64)).mT.contiguous()   # column-major lower = Lbar
+            backward_(W, Gb, ctx.nb)
+            low = torch.tril(Gb.mT)
+            return low + torch.tril(low, -1).mT, None
+
+    _CHOL_FN = _Cholesky
+    return _CHOL_FN
+
+
+def cholesky(A, nb: int):
+    """Differentiable lower Cholesky factor of the symmetric positive definite
+    A (CUDA float64; its lower triangle is read).  Gradients flow back to A as
+    the symmetric adjoint computed by tchol_backward."""
+    _torch()
+    return _chol_function().apply(A, nb)

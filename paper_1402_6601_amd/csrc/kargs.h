@@ -35,8 +35,12 @@ typedef struct KArgs {
   int32_t nsys;
   double *D;            /* mixed precision: FP64 diagonal tiles, nb x nb each, T of them */
   int32_t mixed;        /* 0: FP64; 1: mixed-precision factor, 2: its solves (A is the
-                           FP32 working copy)                                       */
+                           FP32 working copy); 3: the adjoint of the factorization
+                           (A = L, B = Lbar, D = partial-product slots)              */
   int32_t pad1;
+  double *Q;            /* adjoint: Q = twice the symmetric adjoint, ld ldq        */
+  double *LT;           /* adjoint: L^T, ld ldq                                   */
+  int64_t ldq;
   int64_t wait_limit;   /* bound on one dependency wait, in 100 MHz clock ticks   */
   uint64_t *trace;      /* optional: 4 words per work item                        */
 } KArgs;

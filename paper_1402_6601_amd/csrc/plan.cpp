@@ -84,6 +84,10 @@ int64_t weight(int32_t kind) {
     case TK_SYRK: return 3;
     case TK_GEMM: return 6;
     case TK_FTRSV: case TK_BTRSV: return 1;
+    case TK_GREV: return 6;
+    case TK_TREV: return 3;
+    case TK_DPART: return 3;
+    case TK_PREV: return 4;
     default: return 2;
   }
 }
@@ -163,6 +167,56 @@ void build_solve(Builder& b, const FactorIds* after = nullptr) {
   }
 }
 
+// Adjoint of the factorization: the reverse of the factor DAG, steps k
+// from T-1 down to 0, in lower-parameter form (P: derivative with respect to
+// the lower triangle of A; Q = P + P^T, whose tile Q_ij is P_ij, P_ji^T or
+// P_ii + P_ii^T).  Reversing TRSM(i, k), SYRK(i, k) and GEMM(i, j, k) of the
+// forward DAG gives, per step k,
+//   GREV(i, k, j)  Lbar_ik -= Q_ij L_jk     i > k, j = T-1 down to k+1: a
+//                  chain per (i, k) in a fixed order; after the task that
+//                  produced Q_ij: TREV(i, j) (j < i), PREV(i) (j = i) or
+//                  TREV(j, i) (j > i)
+//   TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}  after GREV(i, k, k+1)
+//   DPART(i, k)    S_ik = tril(P_ik^T L_ik)  after TREV(i, k)
+//   PREV(k)        Lbar_kk -= sum_i S_ik (i ascending), then the diagonal
+//                  tile's adjoint          after every DPART(i, k)
+// The partial products S_ik give the diagonal tile's update one task per
+// term instead of a chain of T - k - 1 dependent ones on the critical path.
+void build_backward(Builder& b) {
+  auto& succ = b.succ;
+  const int32_t T = b.T;
+  std::vector<int32_t> id_prev(T), id_trev((size_t)T * T, -1), id_dpart((size_t)T * T, -1);
+  std::vector<int32_t> id_grev((size_t)T * T * T, -1);
+  auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
+  auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
+  for (int32_t k = T - 1; k >= 0; --k) {
+    for (int32_t i = k + 1; i < T; ++i)
+      for (int32_t j = T - 1; j > k; --j)
+        id_grev[ix3(i, j, k)] = b.add(TK_GREV, i, j, k,
+                                      Builder::cdiv(b.tile_size(i), b.s.gemm_m) *
+                                          Builder::cdiv(b.tile_size(k), b.s.gemm_n));
+    for (int32_t i = k + 1; i < T; ++i)
+      id_trev[ix2(i, k)] = b.add(TK_TREV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
+    const int32_t sb = Builder::cdiv(b.tile_size(k), b.s.gemm_m);
+    for (int32_t i = k + 1; i < T; ++i) id_dpart[ix2(i, k)] = b.add(TK_DPART, i, k, k, sb * (sb + 1) / 2);
+    id_prev[k] = b.add(TK_PREV, k, k, k, 1);
+  }
+  auto producer = [&](int32_t i, int32_t j) {
+    return j < i ? id_trev[ix2(i, j)] : (j == i ? id_prev[i] : id_trev[ix2(j, i)]);
+  };
+  for (int32_t k = T - 1; k >= 0; --k) {
+    for (int32_t i = k + 1; i < T; ++i) {
+      for (int32_t j = T - 1; j > k; --j) {
+        const int32_t g = id_grev[ix3(i, j, k)];
+        succ[producer(i, j)].push_back(g);
+        succ[g].push_back(j > k + 1 ? id_grev[ix3(i, j - 1, k)] : id_trev[ix2(i, k)]);
+      }
+      succ[id_trev[ix2(i, k)]].push_back(id_dpart[ix2(i, k)]);
+      succ[id_dpart[ix2(i, k)]].push_back(id_prev[k]);
+    }
+  }
+}
+
 // tie-break key: (step, kind, i, j); the backward sweep of the solve comes
 // after the forward one and runs k downwards.
 std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, int32_t t) {
@@ -170,12 +224,15 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   int32_t kind = p.kind[t], step = p.tk[t];
   if (kind == TK_BTRSV || kind == TK_BGEMV) step = T + (T - 1 - p.tk[t]);
   if (p.op == TCHOL_OP_BATCHED && kind >= TK_FTRSV) step += T;  // a system's solve after its factor
+  if (kind >= TK_GREV) step = T - 1 - p.tk[t];  // the adjoint runs its steps downwards
   int32_t kord = kind;
   if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV
   if (kind == TK_BGEMV) kord = 1;
   if (kind == TK_FTRSV) kord = 0;
   if (kind == TK_FGEMV) kord = 1;
-  return std::make_tuple(p.sys[t], step, kord, p.ti[t], p.tj[t]);
+  // the chain of GREV(i, k, j) into Lbar_ik runs j downwards
+  const int32_t tj = kind == TK_GREV ? T - 1 - p.tj[t] : p.tj[t];
+  return std::make_tuple(p.sys[t], step, kord, p.ti[t], tj);
 }
 
 uint32_t xorshift32(uint32_t& x) {
@@ -273,8 +330,8 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
   p.policy = policy;
   p.seed = seed;
   int64_t T64 = n == 0 ? 0 : (n + nb - 1) / nb;
-  // the largest DAG is the factorization's, about T^3/6 tasks and T^3/2 edges
-  if (T64 > 1200) return nullptr;
+  // the factorization's DAG has about T^3/6 tasks, the adjoint's T^3/3
+  if (T64 > 1200 || (op == TCHOL_OP_BACKWARD && T64 > 160)) return nullptr;
   p.T = (int32_t)T64;
   System sy;
   sy.n = n;
@@ -292,6 +349,8 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
     build_factor(b);
   else if (op == TCHOL_OP_SOLVE)
     build_solve(b);
+  else if (op == TCHOL_OP_BACKWARD)
+    build_backward(b);
   else
     return nullptr;
   if (!finalize(p, succ, policy, seed)) return nullptr;

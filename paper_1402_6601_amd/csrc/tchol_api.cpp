@@ -17,6 +17,8 @@
 extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid, int wide,
                                        hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 extern "C" hipError_t tchol_dev_max_grid(int device, int* grid);
+extern "C" hipError_t tchol_dev_backward_prep(const double* L, int64_t n, double* LT, double* Q, int64_t ldq,
+                                              int64_t np, hipStream_t stream);
 extern "C" hipError_t tchol_refine_convert(const double* A, int64_t lda, float* W, int64_t ldw, int64_t n,
                                            hipStream_t s);
 extern "C" hipError_t tchol_refine_residual(const double* A, int64_t lda, int64_t n, const double* X,
@@ -189,7 +191,8 @@ const tchol_opts kDefaultOpts = {TCHOL_POLICY_RANK, 0u, 0, nullptr, nullptr};
 // the library code.
 int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_t nrhs, bool wide, bool batched,
                 void* ws, int64_t ws_bytes, void* stream_v, const tchol_opts& o, int32_t ws_arg,
-                int32_t* sinfo_out, double* D = nullptr, int mixed = 0) {
+                int32_t* sinfo_out, double* D = nullptr, int mixed = 0, double* Qp = nullptr,
+                double* LTp = nullptr, int64_t ldq = 0) {
   const Layout& L = img.lay;
   if (ws_bytes < L.end) return -(ws_arg + 1);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
@@ -225,6 +228,9 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.nsys = (int32_t)plan.systems.size();
   a.D = D;
   a.mixed = mixed;
+  a.Q = Qp;
+  a.LT = LTp;
+  a.ldq = ldq;
   const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
   a.wait_limit = limit_us * di.clock_khz / 1000;
   a.trace = o.trace;
@@ -340,6 +346,27 @@ int32_t batched_systems(const int64_t* a_off, const int32_t* lda, const int64_t*
 }
 
 
+// Adjoint: workspace regions (byte offsets).  LT (the transposed factor) and
+// Q (twice the symmetric adjoint) are np x np with np = n rounded up to 16
+// and ldq = np, zero past the order; the partial-product slots hold
+// T (T - 1) / 2 tiles of nb x nb.
+struct BackLayout {
+  int64_t np = 0, ldq = 0, lt = 0, q = 0, slots = 0, sched = 0, end = 0;
+};
+
+BackLayout back_layout(int64_t n, int64_t nb, const Plan& p) {
+  BackLayout B;
+  const int64_t T = (n + nb - 1) / nb;
+  B.np = (n + 15) / 16 * 16;
+  B.ldq = B.np;
+  B.lt = 0;
+  B.q = align_up(B.lt + 8 * B.ldq * B.np);
+  B.slots = align_up(B.q + 8 * B.ldq * B.np);
+  B.sched = align_up(B.slots + 8 * (T * (T - 1) / 2) * nb * nb);
+  B.end = B.sched + layout_of(p).end;
+  return B;
+}
+
 // Mixed-precision solve: workspace regions (byte offsets).  The FP32 working
 // copy has ld = n + 3 rounded up to a multiple of 4 (its matrix-core loads
 // move four rows per 16-byte lane, so three rows past the order are read;
@@ -368,12 +395,13 @@ MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, co
 extern "C" {
 
 int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs) {
-  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE) return -1;
+  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE && op != TCHOL_OP_BACKWARD) return -1;
   if (n < 0) return -2;
   if (!nb_ok(nb)) return -3;
   if (op == TCHOL_OP_SOLVE && nrhs < 0) return -4;
   auto plan = tchol::get_plan(op, n, nb, TCHOL_POLICY_RANK, 0);
   if (!plan) return TCHOL_E_UNSUPPORTED;
+  if (op == TCHOL_OP_BACKWARD) return back_layout(n, nb, *plan).end;
   // every policy yields the same task, edge and item counts, hence the same layout
   return layout_of(*plan).end;
 }
@@ -409,6 +437,38 @@ int32_t tchol_solve_ex(const double* L, int64_t n, int64_t nb, double* B, int64_
 int32_t tchol_solve(const double* L, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
                     void* stream) {
   return tchol_solve_ex(L, n, nb, B, nrhs, ws, ws_bytes, stream, nullptr);
+}
+
+int32_t tchol_backward_ex(const double* L, int64_t n, int64_t nb, double* Lbar, void* ws, int64_t ws_bytes,
+                          void* stream_v, const tchol_opts* opts) {
+  if (n < 0) return -2;
+  if (!nb_ok(nb)) return -3;
+  if (n == 0) return 0;
+  if (!L) return -1;
+  if (!Lbar) return -4;
+  if (!ws) return -5;
+  if (ws_bytes <= 0) return -6;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -5;
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
+  auto plan = tchol::get_plan(TCHOL_OP_BACKWARD, n, nb, o.policy, o.seed);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  const BackLayout B = back_layout(n, nb, *plan);
+  if (ws_bytes < B.end) return -6;
+  auto img = image_of(plan);
+  char* w = static_cast<char*>(ws);
+  double* LT = reinterpret_cast<double*>(w + B.lt);
+  double* Q = reinterpret_cast<double*>(w + B.q);
+  double* slots = reinterpret_cast<double*>(w + B.slots);
+  if (tchol_dev_backward_prep(L, n, LT, Q, B.ldq, B.np, reinterpret_cast<hipStream_t>(stream_v)) != hipSuccess)
+    return TCHOL_E_HIP;
+  return execute(*plan, *img, const_cast<double*>(L), Lbar, 0, true, false, w + B.sched, ws_bytes - B.sched,
+                 stream_v, o, 5, nullptr, slots, 3, Q, LT, B.ldq);
+}
+
+int32_t tchol_backward(const double* L, int64_t n, int64_t nb, double* Lbar, void* ws, int64_t ws_bytes,
+                       void* stream) {
+  return tchol_backward_ex(L, n, nb, Lbar, ws, ws_bytes, stream, nullptr);
 }
 
 int64_t tchol_batched_workspace_bytes(const int32_t* n, const int32_t* nb, int32_t batch) {
@@ -583,7 +643,7 @@ const char* tchol_version(void) { return "tchol 0.1 (gfx950)"; }
 int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed, int64_t* counts,
                          int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* parts, int32_t* dep0,
                          int64_t* rank, int32_t* succ_off, int32_t* succ, int32_t* item_task, int32_t* item_part) {
-  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE) return -1;
+  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE && op != TCHOL_OP_BACKWARD) return -1;
   if (n < 0) return -2;
   if (!nb_ok(nb)) return -3;
   if (policy < TCHOL_POLICY_RANK || policy > TCHOL_POLICY_RANDOM) return -4;

@@ -232,10 +232,14 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
   }
 }
 
+// ldc: leading dimension of C when it differs from the panels' (< 0: ld);
+// zero_c: start from C = 0 instead of loading C.
 template <int SEG, int BM, int BN, int KC, int WGM, int NST, int PAD = 8>
 __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* __restrict__ Ap,
                                           const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
-                                          bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0) {
+                                          bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0,
+                                          int64_t ldc = -1, bool zero_c = false) {
+  const int64_t ldC = ldc < 0 ? ld : ldc;
   using S = GemmShape<BM, BN, KC, WGM, NST, PAD>;
   constexpr int RB = S::RB, CB = S::CB;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -251,7 +255,7 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
-        acc[rb][cb][i] = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
+        acc[rb][cb][i] = zero_c ? 0.0 : C[(int64_t)imin(col, N - 1) * ldC + imin(row, M - 1)];
       }
 
   gemm_kloop<BM, BN, KC, WGM, NST, PAD, SEG>(acc, Ap, Bp, ld, M, N, K, lds);
@@ -268,7 +272,7 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
           if (Cl)
             Cl[col * ldl + row] = acc[rb][cb][i];  // result kept in LDS (column-major, ld ldl)
           else
-            st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
+            st_dev(C + (int64_t)col * ldC + row, acc[rb][cb][i]);
         }
       }
 }
@@ -284,6 +288,16 @@ __device__ __forceinline__ void gemm_nt(double* C, const double* Ap, const doubl
     gemm_core<SEG, GB, GB, 32, 2, 2>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
   else
     gemm_core<SEG, GB, GB, 16, 2, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+}
+
+// The same product with C at its own leading dimension ldc (the panels at
+// ld), optionally starting from C = 0.
+__device__ __forceinline__ void gemm_nt_ex(double* C, int64_t ldc, const double* Ap, const double* Bp, int64_t ld,
+                                           int M, int N, int K, bool lower_only, bool zero_c, double* lds) {
+  if (K % 32 == 0)
+    gemm_core<128, GB, GB, 32, 2, 2>(C, Ap, Bp, ld, M, N, K, lower_only, lds, nullptr, 0, ldc, zero_c);
+  else
+    gemm_core<128, GB, GB, 16, 2, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds, nullptr, 0, ldc, zero_c);
 }
 
 // ---------------------------------------------------------------------------
@@ -528,16 +542,30 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 // contribution from its later column blocks.  The solver's L data for the
 // next step is requested one step ahead; the update fragments at the start
 // of the step, to land during the solve.
+//
+// REV = 1 (the adjoint's TRSM): X := X L^{-1} instead.  With J the order
+// reversal, X L^{-1} J = (X J) L'^{-T} for the lower-triangular
+// L' = J L^T J, so the same forward solve runs on the reversed columns of X
+// with L'(r, c) = L(mk-1-c, mk-1-r), read from the transposed copy LT of L
+// passed as Lkk (L'(r, c) sits at LT[(mk-1-c) ld + mk-1-r]).  The result P
+// is stored three times: X := P / 2 (the adjoint's output), Qa := P and
+// Qb := P^T (both at leading dimension ldq).
 #define TS 32
 
-template <typename TX>
+template <typename TX, int REV = 0>
 __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, const double* __restrict__ Lkk, int64_t ld,
-                                           int S, int mk, double* lds) {
+                                           int S, int mk, double* lds, double* Qa = nullptr, double* Qb = nullptr,
+                                           int64_t ldq = 0) {
   double* Xs = lds;  // [2][512][16]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
   const int nblk = mk >> 4;
+  // L(row, col) of the operator the forward solve applies
+  auto lat = [&](int row, int col) __attribute__((always_inline)) {
+    return REV ? Lkk[(int64_t)(mk - 1 - col) * ld + (mk - 1 - row)] : Lkk[(int64_t)col * ld + row];
+  };
+  auto xcol = [&](int c) __attribute__((always_inline)) { return REV ? mk - 1 - c : c; };
   // the strip: thread (r, c0) moves rows r of columns c0 + 8u, 16 loads in flight
   {
     const int r = tid & 31, c0 = tid >> 5, rr = imin(r, S - 1);
@@ -545,7 +573,7 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     for (int part = 0; part < 4; ++part) {
       double v[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = (double)X[(int64_t)imin(c0 + 8 * (u + 16 * part), mk - 1) * ldx + rr];
+      for (int u = 0; u < 16; ++u) v[u] = (double)X[(int64_t)xcol(imin(c0 + 8 * (u + 16 * part), mk - 1)) * ldx + rr];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int c = c0 + 8 * (u + 16 * part);
@@ -569,9 +597,9 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int bq = 0; bq <= a; ++bq) sd.d[n++] = Lkk[(int64_t)(sb + bq) * ld + sb + a];
+      for (int bq = 0; bq <= a; ++bq) sd.d[n++] = lat(sb + a, sb + bq);
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) sd.fd[s4] = Lkk[(int64_t)(q0 + 4 * s4 + lg) * ld + q0 + l16];
+    for (int s4 = 0; s4 < 4; ++s4) sd.fd[s4] = lat(q0 + l16, q0 + 4 * s4 + lg);
   };
   auto step = [&](int rb, const SolveData& sd, SolveData& sdn) __attribute__((always_inline)) {
     const int q0 = rb * 16;
@@ -581,7 +609,7 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     for (int t = 0; t < 8; ++t) {
       const int crow = imin(q0 + 16 + (wave + 4 * t) * 16 + l16, mk - 1);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) fl[t][kk] = Lkk[(int64_t)(q0 + kk * 4 + lg) * ld + crow];
+      for (int kk = 0; kk < 4; ++kk) fl[t][kk] = lat(crow, q0 + kk * 4 + lg);
     }
     if (wave < 2) {
       if (rb + 1 < nblk) fetch_solve(rb + 1, sdn);
@@ -648,10 +676,25 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     if (rb + 1 < nblk) step(rb + 1, sb, sa);
   }
   __syncthreads();
-  {
+  if constexpr (REV == 0) {
     const int r = tid & 31, c0 = tid >> 5;
     if (r < S)
       for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ldx + r, (TX)Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
+  } else {
+    {
+      const int r = tid & 31, c0 = tid >> 5;
+      if (r < S)
+        for (int c = c0; c < mk; c += 8) {
+          const double v = Xs[(r >> 4) * 8192 + c * 16 + (r & 15)];
+          st_dev(X + (int64_t)(mk - 1 - c) * ldx + r, (TX)(0.5 * v));
+          st_dev(Qa + (int64_t)(mk - 1 - c) * ldq + r, v);
+        }
+    }
+    // the transpose, consecutive threads along its columns
+    for (int idx = tid; idx < S * mk; idx += NT) {
+      const int r = idx / mk, c = idx - r * mk;
+      st_dev(Qb + (int64_t)r * ldq + c, Xs[(r >> 4) * 8192 + (mk - 1 - c) * 16 + (r & 15)]);
+    }
   }
 }
 
@@ -1041,6 +1084,187 @@ __device__ __forceinline__ int potrf_tile_mixed(float* __restrict__ Wkk, int64_t
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the factorization of a diagonal tile.  In lower-parameter form
+// (the derivative with respect to the entries the factorization reads, the
+// lower triangle; Q = P + P^T is twice the symmetric adjoint), the reverse of
+// a right-looking tile factorization with tiles of w has, per step k taken
+// from the last to the first,
+//   Lbar_ik -= sum_{j > k} Q_ij L_jk             (i > k)
+//   P_ik     = Lbar_ik L_kk^{-1}                 (i > k)
+//   Lbar_kk -= tril(sum_{i > k} P_ik^T L_ik)
+//   P_kk     = the adjoint of the w x w factorization:
+//              tril(G + G^T) - diag(G),  G = L_kk^{-T} Phi(L_kk^T Lbar_kk) L_kk^{-1}
+//              (Phi: lower triangle with the diagonal halved).
+// The tile's own adjoint applies this with w = 16 inside the tile, panels
+// from the right: the matrix cores form the first line for the panel's rows
+// below its diagonal block (Q of the tile as far as it is known, from the
+// workspace), one thread per row solves the second, every thread takes one
+// entry of the 16 x 16 third and fourth (the 16 x 16 inverse by substitution),
+// and the panel's P is written to Q in both orientations and, halved off the
+// diagonal (the symmetric adjoint), over Lbar.  Before the panels, the
+// partial products of the tile's column are applied to Lbar_kk in a fixed
+// order; each slot holds -tril(P_ik^T L_ik) (the tile product subtracts from
+// a zero start), so they are added.  Lkk, Bkk: the factor and Lbar tiles (ld);
+// LTkk, Qkk: the transposed factor and Q tiles (ldq, zero beyond the order).
+__device__ __forceinline__ void prev_tile(const double* __restrict__ Lkk, const double* __restrict__ LTkk,
+                                          double* __restrict__ Bkk, int64_t ld, double* __restrict__ Qkk, int64_t ldq,
+                                          int m, const double* __restrict__ slots, int64_t slot_stride, int nslots,
+                                          int64_t ldslot, double* lds) {
+  const int tid = threadIdx.x;
+  double* Ps = lds + P_STAGE_DOUBLES;  // [PW][PPLD] the panel's rows below its diagonal block
+  double* Ls = Ps + PW * PPLD;         // [16][17] L of the diagonal block, identity-padded
+  double* Bs = Ls + 16 * 17;           // [16][17] its Lbar
+  double* Ms = Bs + 16 * 17;
+  double* Is = Ms + 16 * 17;           // L^{-1} of the block
+  double* Ys = Is + 16 * 17;
+  double* Gs = Ys + 16 * 17;
+  const int ta = tid >> 4, tb = tid & 15;  // the entry (row, column) a thread owns in 16 x 16 steps
+
+  // Lbar_kk -= tril(P_ik^T L_ik), slot by slot (each slot holds the negated product)
+  if (nslots > 0) {
+    const int tot = m * m;
+    for (int base = 0; base < tot; base += 16 * NT) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int idx = imin(base + u * NT + tid, tot - 1), c = idx / m, r = idx - c * m;
+        v[u] = Bkk[(int64_t)c * ld + r];
+      }
+      for (int sl = 0; sl < nslots; ++sl) {
+        const double* S0 = slots + (int64_t)sl * slot_stride;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int idx = imin(base + u * NT + tid, tot - 1), c = idx / m, r = idx - c * m;
+          v[u] += (r >= c) ? S0[(int64_t)c * ldslot + r] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int idx = base + u * NT + tid, c = idx / m, r = idx - c * m;
+        if (idx < tot && r >= c) st_dev(Bkk + (int64_t)c * ld + r, v[u]);
+      }
+    }
+    wait_vmcnt<0>();
+    __syncthreads();
+  }
+  const int mpad = (m + 15) & ~15;
+  for (int c0 = ((m - 1) >> 4) << 4; c0 >= 0; c0 -= PW) {
+    const int w = imin(PW, m - c0), R = m - c0;
+    // (1) rows below the block: Lbar - Q L over the columns right of the panel, into LDS
+    for (int s0 = 16; s0 < R; s0 += 256) {
+      gemm_core<128, 256, PW, 8, 4, 4, 0>(Bkk + (int64_t)c0 * ld + c0 + s0, Qkk + (int64_t)(c0 + 16) * ldq + c0 + s0,
+                                          LTkk + (int64_t)(c0 + 16) * ldq + c0, ldq, imin(256, R - s0), w,
+                                          mpad - c0 - 16, false, lds, Ps + s0, PPLD, ld);
+      __syncthreads();
+    }
+    {
+      const bool in = ta < w && tb < w;
+      Ls[ta * 17 + tb] = in ? (ta >= tb ? Lkk[(int64_t)(c0 + tb) * ld + c0 + ta] : 0.0) : (ta == tb ? 1.0 : 0.0);
+      Bs[ta * 17 + tb] = (in && ta >= tb) ? Bkk[(int64_t)(c0 + tb) * ld + c0 + ta] : 0.0;
+    }
+    // the panel's L rows below the block, for the diagonal block's update (stage area is free)
+    for (int idx = tid; idx < w * (R - 16); idx += NT) {
+      const int c = idx / (R - 16), r = 16 + idx - c * (R - 16);
+      lds[c * PPLD + r] = Lkk[(int64_t)(c0 + c) * ld + c0 + r];
+    }
+    __syncthreads();
+    // (2) P rows := Lbar rows L_dd^{-1}: back substitution over the block's columns
+    for (int r = 16 + tid; r < R; r += NT) {
+      double y[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) y[c] = (c < w) ? Ps[c * PPLD + r] : 0.0;
+#pragma unroll
+      for (int c = PW - 1; c >= 0; --c) {
+#pragma unroll
+        for (int c2 = c + 1; c2 < PW; ++c2) y[c] -= y[c2] * Ls[c2 * 17 + c];
+        y[c] = y[c] / Ls[c * 17 + c];
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) Ps[c * PPLD + r] = y[c];
+    }
+    __syncthreads();
+    // (3) Lbar_dd -= tril(P^T L) over the rows below the block
+    if (ta >= tb && ta < w) {
+      double acc = 0.0;
+      for (int r = 16; r < R; ++r) acc += Ps[ta * PPLD + r] * lds[tb * PPLD + r];
+      Bs[ta * 17 + tb] -= acc;
+    }
+    __syncthreads();
+    // (4) the 16 x 16 adjoint
+    {
+      double acc = 0.0;
+      if (ta >= tb)
+        for (int t = ta; t < 16; ++t) acc += Ls[t * 17 + ta] * Bs[t * 17 + tb];
+      Ms[ta * 17 + tb] = (ta == tb) ? 0.5 * acc : acc;
+    }
+    if (tid < 16) {
+      const int c = tid;
+      for (int r = 0; r < 16; ++r) {
+        double v = (r == c) ? 1.0 : 0.0;
+        for (int t = c; t < r; ++t) v -= Ls[r * 17 + t] * Is[t * 17 + c];
+        Is[r * 17 + c] = (r < c) ? 0.0 : v / Ls[r * 17 + r];
+      }
+    }
+    __syncthreads();
+    {
+      double acc = 0.0;
+      for (int t = 0; t < 16; ++t) acc += Ms[ta * 17 + t] * Is[t * 17 + tb];
+      Ys[ta * 17 + tb] = acc;
+    }
+    __syncthreads();
+    {
+      double acc = 0.0;
+      for (int t = 0; t < 16; ++t) acc += Is[t * 17 + ta] * Ys[t * 17 + tb];
+      Gs[ta * 17 + tb] = acc;
+    }
+    __syncthreads();
+    // (5) write: Q (both orientations) and the symmetric adjoint over Lbar
+    if (ta < w && tb < w) {
+      const double g = Gs[ta * 17 + tb] + Gs[tb * 17 + ta];  // P_ab + P_ba off the diagonal, 2 P_aa on it
+      st_dev(Qkk + (int64_t)(c0 + tb) * ldq + c0 + ta, g);
+      if (ta >= tb) st_dev(Bkk + (int64_t)(c0 + tb) * ld + c0 + ta, (ta == tb) ? Gs[ta * 17 + ta] : 0.5 * g);
+    }
+    for (int idx = tid; idx < w * (R - 16); idx += NT) {
+      const int c = idx / (R - 16), r = 16 + idx - c * (R - 16);
+      const double v = Ps[c * PPLD + r];
+      st_dev(Qkk + (int64_t)(c0 + c) * ldq + c0 + r, v);
+      st_dev(Bkk + (int64_t)(c0 + c) * ld + c0 + r, 0.5 * v);
+    }
+    for (int idx = tid; idx < w * (R - 16); idx += NT) {
+      const int r = 16 + idx / w, c = idx - (r - 16) * w;
+      st_dev(Qkk + (int64_t)(c0 + r) * ldq + c0 + c, Ps[c * PPLD + r]);
+    }
+    wait_vmcnt<0>();
+    __syncthreads();
+  }
+}
+
+// Adjoint preparation: LT := L^T over the padded order np (LT(c, t) = L(t, c)
+// at t * ldq + c, zero outside the lower triangle of the n x n factor), and
+// the padding rows and columns of Q set to zero.  32 x 32 tiles through LDS.
+__global__ void tchol_backward_prep(const double* __restrict__ L, int64_t n, double* __restrict__ LT,
+                                    double* __restrict__ Q, int64_t ldq, int64_t np) {
+  __shared__ double t32[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  const int64_t c0 = (int64_t)blockIdx.x * 32, t0 = (int64_t)blockIdx.y * 32;
+  // read L(t0 + j, c0 + i) for i = row of the transposed tile: columns c of L, rows t contiguous
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t c = c0 + i, t = t0 + tx;
+    t32[i][tx] = (c < n && t < n && t >= c) ? L[c * n + t] : 0.0;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t t = t0 + j, c = c0 + tx;
+    if (t < np && c < np) LT[t * ldq + c] = t32[tx][j];
+  }
+  // Q padding: rows or columns at or past n
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t t = t0 + j, r = c0 + tx;
+    if (t < np && r < np && (t >= n || r >= n)) Q[t * ldq + r] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // scheduler
 __device__ __forceinline__ int ld_relaxed(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1099,8 +1323,9 @@ __device__ __forceinline__ void raise_error(const KArgs& a, int code) {
 // small) and is always a 16-byte one.
 template <int SEG, int MODE>
 __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
-  constexpr bool MIXED = MODE != 0;
-  constexpr bool FACTOR_KINDS = MODE != 2, SOLVE_KINDS = MODE != 1;
+  constexpr bool MIXED = MODE == 1 || MODE == 2;
+  constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1, SOLVE_KINDS = MODE == 0 || MODE == 2;
+  constexpr bool ADJOINT_KINDS = MODE == 3;
   __shared__ double lds[LDS_DOUBLES];
   __shared__ int s_claim[3];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -1259,6 +1484,60 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
               (int)a.nrhs, lds);
         break;
       }
+      case TK_GREV:
+      case TK_TREV:
+      case TK_DPART:
+      case TK_PREV: {
+        if constexpr (!ADJOINT_KINDS) {
+          ok = 0;
+        } else {
+          // A = L, B = Lbar (both at ld); Q and LT at ldq, zero past the order
+          // (padded to a multiple of 16, so every K below is one)
+          const int64_t ldq = a.ldq;
+          const int T = (int)((sn + nb - 1) / nb);
+          const int64_t np = (sn + 15) & ~(int64_t)15;
+          if ((ldq & 1) != 0 || ldq < np) {
+            raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
+            ok = 0;
+            break;
+          }
+          // partial-product slots, column k after column k - 1: S_ik at base(k) + i - k - 1
+          auto slot = [&](int i, int k) __attribute__((always_inline)) {
+            return (int64_t)k * (T - 1) - (int64_t)k * (k - 1) / 2 + (i - k - 1);
+          };
+          if (kind == TK_GREV) {
+            const int ncj = (tsz(tk) + a.gemm_n - 1) / a.gemm_n;
+            const int si = part / ncj, sj = part % ncj;
+            const int M = imin(a.gemm_m, tsz(ti) - si * a.gemm_m);
+            const int N = imin(a.gemm_n, tsz(tk) - sj * a.gemm_n);
+            const int K = (int)(np - (int64_t)tj * nb < nb ? np - (int64_t)tj * nb : nb);
+            gemm_nt_ex(Bbase + (tk * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m, ld,
+                       a.Q + (tj * nb) * ldq + ti * nb + si * a.gemm_m, a.LT + (tj * nb) * ldq + tk * nb + sj * a.gemm_n,
+                       ldq, M, N, K, false, false, lds);
+          } else if (kind == TK_TREV) {
+            const int r0 = part * a.trsm_rows;
+            const int S = imin(a.trsm_rows, tsz(ti) - r0);
+            trsm_strip<double, 1>(Bbase + (tk * nb) * ld + ti * nb + r0, ld, a.LT + (tk * nb) * ldq + tk * nb, ldq, S,
+                                  tsz(tk), lds, a.Q + (tk * nb) * ldq + ti * nb + r0,
+                                  a.Q + (ti * nb + r0) * ldq + tk * nb, ldq);
+          } else if (kind == TK_DPART) {
+            int si = 0;
+            while ((si + 1) * (si + 2) / 2 <= part) ++si;
+            const int sj = part - si * (si + 1) / 2;
+            const int M = imin(a.gemm_m, tsz(tk) - si * a.gemm_m);
+            const int N = imin(a.gemm_n, tsz(tk) - sj * a.gemm_n);
+            const int K = (int)(np - (int64_t)ti * nb < nb ? np - (int64_t)ti * nb : nb);
+            gemm_nt_ex(a.D + slot(ti, tk) * nb * nb + (sj * a.gemm_n) * nb + si * a.gemm_m, nb,
+                       a.Q + (ti * nb) * ldq + tk * nb + si * a.gemm_m, a.LT + (ti * nb) * ldq + tk * nb + sj * a.gemm_n,
+                       ldq, M, N, K, si == sj, true, lds);
+          } else {
+            prev_tile(Abase + (tk * nb) * ld + tk * nb, a.LT + (tk * nb) * ldq + tk * nb,
+                      Bbase + (tk * nb) * ld + tk * nb, ld, a.Q + (tk * nb) * ldq + tk * nb, ldq, tsz(tk),
+                      tk + 1 < T ? a.D + slot(tk + 1, tk) * nb * nb : a.D, nb * nb, T - 1 - tk, nb, lds);
+          }
+        }
+        break;
+      }
       default:
         ok = 0;
         break;
@@ -1320,7 +1599,9 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
     e = hipEventRecord(ev0, stream);
     if (e != hipSuccess) return e;
   }
-  if (a->mixed == 1)
+  if (a->mixed == 3)
+    hipLaunchKernelGGL((tchol_persistent<128, 3>), dim3(grid), dim3(NT), 0, stream, *a);
+  else if (a->mixed == 1)
     hipLaunchKernelGGL((tchol_persistent<128, 1>), dim3(grid), dim3(NT), 0, stream, *a);
   else if (a->mixed == 2)
     hipLaunchKernelGGL((tchol_persistent<128, 2>), dim3(grid), dim3(NT), 0, stream, *a);
@@ -1332,6 +1613,15 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
   if (e != hipSuccess) return e;
   if (ev1) e = hipEventRecord(ev1, stream);
   return e;
+}
+
+// The adjoint's preparation (LT and the padding of Q), before its persistent launch.
+extern "C" hipError_t tchol_dev_backward_prep(const double* L, int64_t n, double* LT, double* Q, int64_t ldq,
+                                              int64_t np, hipStream_t stream) {
+  if (np == 0) return hipSuccess;
+  const unsigned g = (unsigned)((np + 31) / 32);
+  hipLaunchKernelGGL(tchol_backward_prep, dim3(g, g), dim3(256), 0, stream, L, n, LT, Q, ldq, np);
+  return hipGetLastError();
 }
 
 extern "C" hipError_t tchol_dev_max_grid(int device, int* grid) {
@@ -1349,6 +1639,10 @@ extern "C" hipError_t tchol_dev_max_grid(int device, int* grid) {
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occs, tchol_persistent<128, 2>, NT, 0);
   if (e != hipSuccess) return e;
+  int occa = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occa, tchol_persistent<128, 3>, NT, 0);
+  if (e != hipSuccess) return e;
+  occ = occ < occa ? occ : occa;
   occ = occ < occ32 ? occ : occ32;
   occ = occ < occm ? occ : occm;
   occ = occ < occs ? occ : occs;

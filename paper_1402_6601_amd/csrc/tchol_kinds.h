@@ -12,5 +12,11 @@
 #define TK_FGEMV 5   /* B_i <- B_i - L_ik Y_k,   i > k          */
 #define TK_BTRSV 6   /* X_k <- L_kk^{-T} Y_k                    */
 #define TK_BGEMV 7   /* Y_i <- Y_i - L_ki^T X_k, i < k          */
-#define TK_NKINDS 8
+/* adjoint of the factorization (reverse tile DAG); P: the adjoint in
+   lower-parameter form, Q = P + P^T (twice the symmetric adjoint) */
+#define TK_GREV  8   /* Lbar_ik <- Lbar_ik - Q_ij L_jk, i > k, j > k        */
+#define TK_TREV  9   /* P_ik = Lbar_ik L_kk^{-1}, i > k                     */
+#define TK_DPART 10  /* S_ik = -tril(P_ik^T L_ik), i > k (partial product)   */
+#define TK_PREV  11  /* Lbar_kk += sum_i S_ik; P_kk = the tile's adjoint      */
+#define TK_NKINDS 12
 #endif

@@ -115,6 +115,21 @@ def test_mixed_validation_before_any_hip_call(lib):
     assert call(wsb=need - 256) == -12
 
 
+def test_backward_validation_before_any_hip_call(lib):
+    need = lib.tchol_workspace_bytes(3, 256, 64, 0)
+    assert need >= 2 * 8 * 256 * 256 + 8 * 6 * 64 * 64
+    assert lib.tchol_backward(FAKE, -1, 64, FAKE, FAKE, need, None) == -2
+    assert lib.tchol_backward(FAKE, 256, 40, FAKE, FAKE, need, None) == -3
+    assert lib.tchol_backward(None, 0, 64, None, None, 0, None) == 0
+    assert lib.tchol_backward(None, 256, 64, FAKE, FAKE, need, None) == -1
+    assert lib.tchol_backward(FAKE, 256, 64, None, FAKE, need, None) == -4
+    assert lib.tchol_backward(FAKE, 256, 64, FAKE, None, need, None) == -5
+    assert lib.tchol_backward(FAKE, 256, 64, FAKE, FAKE_MISALIGNED, need, None) == -5
+    assert lib.tchol_backward(FAKE, 256, 64, FAKE, FAKE, 0, None) == -6
+    assert lib.tchol_backward(FAKE, 256, 64, FAKE, FAKE, need - 256, None) == -6
+    assert lib.tchol_backward(FAKE, 16 * 161, 16, FAKE, FAKE, need, None) == tc.E_UNSUPPORTED
+
+
 def test_strerror_and_version(lib):
     for code in (0, 5, -3, tc.E_HIP, tc.E_TIMEOUT, tc.E_UNSUPPORTED, tc.E_INTERNAL, tc.E_NOCONV, -999):
         assert isinstance(tc.strerror(code), str) and tc.strerror(code)
