@@ -337,6 +337,119 @@ def run_mixed(args):
     print(json.dumps(out), flush=True)
 
 
+def measure_adjoint(torch, tc, dev, n, nb, seed, K, Wm, policy, cpu_sample_n=0):
+    """The adjoint of the factorization (tchol_backward) of A = B B^T / n + I
+    (B ~ U[-1, 1], seed) for an upstream Lbar = tril(N(0, 1)) drawn after B.
+    Timed per call with every step starting from the original Lbar (copies
+    made beforehand).  Nominal flops (2/3) n^3: the two GEMM updates of each
+    reversed step.  Check at full size: the bilinear identity
+    <Abar, E> = <Lbar, dL> for a random symmetric E, with
+    dL = L Phi(L^{-1} E L^{-T}) from torch's triangular solves."""
+    import spd_inputs
+    t0 = time.time()
+    A, rng = spd_inputs.spd_matrix_device(n, seed, 1.0, device=dev)
+    Lbar = torch.from_numpy(spd_inputs.lower_upstream(rng, n)).to(dev)
+    W = A.clone()
+    if tc.factor_(W, nb, policy=policy) != 0:
+        raise RuntimeError("factorization failed")
+    Gb0 = Lbar.mT.contiguous()                 # column-major lower = Lbar
+    torch.cuda.synchronize()
+    log("adjoint: inputs ready in %.1f s (n=%d nb=%d seed=%d)" % (time.time() - t0, n, nb, seed))
+    ws = torch.empty(tc.workspace_bytes(tc.OP_BACKWARD, n, nb), dtype=torch.uint8, device=dev)
+    G = torch.empty_like(Gb0)
+    for w in range(Wm):
+        G.copy_(Gb0)
+        tc.backward_(W, G, nb, policy=policy, ws=ws)
+    Gs = [Gb0.clone() for _ in range(K)]
+    torch.cuda.synchronize()
+    kms = []
+    ts = time.perf_counter()
+    for s_ in range(K):
+        _, ms = tc.backward_(W, Gs[s_], nb, policy=policy, ws=ws, want_kernel_ms=True)
+        kms.append(ms)
+    torch.cuda.synchronize()
+    ms_call = (time.perf_counter() - ts) * 1e3 / K
+    kmean = float(np.mean(kms))
+    flops = 2.0 * n ** 3 / 3.0
+    # check: <Abar, E> against <Lbar, L Phi(L^{-1} E L^{-T})>
+    L = torch.tril(W.mT)
+    low = torch.tril(Gs[-1].mT)
+    Abar = low + torch.tril(low, -1).mT
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(17)
+    E = torch.randn(n, n, dtype=torch.float64, device=dev, generator=gen)
+    E = E + E.mT
+    X = torch.linalg.solve_triangular(L, E, upper=False)          # L^{-1} E
+    Y = torch.linalg.solve_triangular(L, X.mT, upper=False).mT    # L^{-1} E L^{-T}
+    Phi = torch.tril(Y) - 0.5 * torch.diag_embed(torch.diagonal(Y))
+    dL = L @ Phi
+    lhs = float((Abar * E).sum().item())
+    rhs = float((torch.tril(Lbar) * dL).sum().item())
+    out = {"ms_per_call": round(ms_call, 3), "kernel_ms_mean": round(kmean, 3),
+           "kernel_ms": [round(x, 3) for x in kms],
+           "value": round(flops / (ms_call * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "flops_nominal": flops,
+           "bilinear_check_rel": abs(lhs - rhs) / max(abs(rhs), 1e-300)}
+    out["roofline"] = {"bound": "mfma", "achieved": round(flops / (kmean * 1e-3) / 1e12, 3),
+                       "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(flops / (kmean * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+                       "kernel": "tchol_persistent (reverse factorization DAG)"}
+    if cpu_sample_n > 0:
+        import oracle
+        m = min(cpu_sample_n, n)
+        Ah, rs = spd_inputs.spd_matrix(m, seed)
+        Lh = oracle.cholesky(Ah)
+        Lbh = spd_inputs.lower_upstream(rs, m)
+        tcpu = time.perf_counter()
+        oracle.chol_adjoint(Lh, Lbh)
+        tcpu = time.perf_counter() - tcpu
+        out["cpu_baseline"] = {"value": round(2.0 * m ** 3 / 3.0 / tcpu / 1e12, 6), "unit": "TFLOP/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "oracle adjoint (reverse of the unblocked factorization) at n=%d of the "
+                                         "same matrix family; %.2f s" % (m, tcpu)}
+    del A, W, Gs, G, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_adjoint(args):
+    """The adjoint workload alone: n = 8192, nb = 256, A = B B^T/n + I (seed 3)."""
+    import torch
+    import paper_1402_6601_amd as tc
+    tc.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    seed = 3 if args.seed == 1 else args.seed
+    n = 8192 if args.n == 32768 else args.n
+    nb = 256 if args.nb == 512 else args.nb
+    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM}[args.policy]
+    r = measure_adjoint(torch, tc, dev, n, nb, seed, args.steps, args.warmup, policy,
+                        cpu_sample_n=min(args.cpu_sample_n, 3072))
+    out = {
+        "metric": "Cholesky adjoint TFLOP/s ((2/3) n^3 nominal), n=%d" % n,
+        "value": r["value"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_call"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fp64 blocked Cholesky adjoint, n=%d, nb=%d, A=B*B^T/n+I, B~U[-1,1] (seed %d), "
+                               "Lbar=tril(N(0,1))" % (n, nb, seed), "n": n, "nb": nb, "seed": seed},
+        "roofline": r["roofline"],
+        "adjoint": r,
+    }
+    if "cpu_baseline" in r:
+        out["cpu_baseline"] = r["cpu_baseline"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,9 +463,11 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=8192,
                     help="order of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a device copy of this many bytes")
-    ap.add_argument("--workload", choices=["factor", "batched", "mixed"], default="factor",
+    ap.add_argument("--workload", choices=["factor", "batched", "mixed", "adjoint"], default="factor",
                     help="factor: the n=32768 factor + solve (default); batched: 4096 systems in one launch; "
                          "mixed: the mixed-precision solve with refinement alone")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="factor workload: skip the adjoint measurement appended to the line")
     ap.add_argument("--no-mixed", action="store_true",
                     help="factor workload: skip the mixed-precision comparison appended to the line")
     ap.add_argument("--count", type=int, default=4096, help="batched: number of systems")
@@ -371,6 +486,9 @@ def main():
         return
     if args.workload == "mixed":
         run_mixed(args)
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args)
         return
 
     import torch
@@ -489,6 +607,10 @@ def main():
         out["mixed_refined"] = measure_mixed(torch, tc, dev, n, nb, nrhs, 2, 1e-4, 2, 1, policy,
                                              fp64_ms=ms_per_step)
         ws_s = None
+
+    if not args.no_adjoint:
+        # the adjoint workload (n = 8192, nb = 256, seed 3), summarised on the same line
+        out["adjoint"] = measure_adjoint(torch, tc, dev, 8192, 256, 3, 3, 1, policy)
 
     if args.cpu_sample_n > 0:
         import oracle
