@@ -174,8 +174,8 @@ TCHOL_API int32_t tchol_factor_solve_batched(double *A, const int64_t *a_off, co
    (corrections at most), 9 berr_out (host, nrhs entries or NULL: final eta
    per column), 10 iters_out (host or NULL: corrections applied), 11 ws,
    12 ws_bytes >= tchol_mixed_workspace_bytes(n, nb, nrhs), 13 stream,
-   14 opts (NULL or as for tchol_factor_ex; kernel_ms receives the
-   factorization kernel's time).
+   14 opts (NULL or as for tchol_factor_ex; kernel_ms and trace describe the
+   factorization's launch).
    Returns 0 when every column met tol; k > 0 when the low-precision
    factorization found the leading minor of order k not positive definite
    (B unchanged); TCHOL_E_NOCONV when maxit corrections did not reach tol (B

@@ -342,7 +342,7 @@ def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: 
 
 def solve_mixed_(A, Bc, nb: int, *, tol: float = 1e-12, maxit: int = 30, lowp: int = LOWP_FP32,
                  policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
-                 want_kernel_ms: bool = False, check: bool = True):
+                 want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Mixed-precision solve with iterative refinement, in place on Bc.
 
     A: CUDA float64 (n, n) contiguous symmetric (read only).  Bc: CUDA float64
@@ -365,7 +365,7 @@ def solve_mixed_(A, Bc, nb: int, *, tol: float = 1e-12, maxit: int = 30, lowp: i
         need = mixed_workspace_bytes(n, nb, nrhs) if n else 256
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, A.device)
-        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, None)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
         rc = lib.tchol_solve_mixed(ctypes.c_void_p(A.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()), nrhs,
                                    lowp, float(tol), int(maxit), berr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                    ctypes.byref(iters), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -405,7 +405,7 @@ def solve_mixed(A, B, nb: int, *, fallback: bool = True, **kw):
 
 
 def backward_(Lbuf, Gb, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
-              want_kernel_ms: bool = False, check: bool = True):
+              want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Adjoint of the factorization, in place.  Lbuf: the (n, n) buffer factored
     by factor_ (column-major lower = L).  Gb: CUDA float64 (n, n) contiguous
     whose column-major lower triangle is Lbar = df/dL (i.e. Gb = Lbar^T in
@@ -421,7 +421,7 @@ def backward_(Lbuf, Gb, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wa
         need = workspace_bytes(OP_BACKWARD, n, nb) if n else 256
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, Lbuf.device)
-        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, None)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
         rc = lib.tchol_backward_ex(ctypes.c_void_p(Lbuf.data_ptr()), n, nb, ctypes.c_void_p(Gb.data_ptr()),
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(torch, Lbuf.device),
                                    ctypes.byref(o))

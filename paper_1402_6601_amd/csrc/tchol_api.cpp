@@ -578,8 +578,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
 
   // the working copy, then its factorization (FP32 updates, FP64 diagonal tiles)
   if (tchol_refine_convert(A, n, W, M.ldw, n, s) != hipSuccess) return TCHOL_E_HIP;
-  tchol_opts fo = o;
-  fo.trace = nullptr;
+  const tchol_opts& fo = o;  // kernel_ms and trace describe the factorization launch
   int32_t rc = execute(*fplan, *fimg, reinterpret_cast<double*>(W), nullptr, 0, true, false, sched, sched_bytes,
                        stream_v, fo, 11, nullptr, D, 1);
   if (rc != 0) return rc;

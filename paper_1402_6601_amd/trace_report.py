@@ -1,0 +1,106 @@
+"""Per-kind work-item timing of one launch, from the kernel's trace buffer.
+
+    python -m paper_1402_6601_amd.trace_report [--op factor|mixed|adjoint] [--n N] [--nb NB]
+
+The persistent kernel can record, per work item, the wall clock (100 MHz)
+when its ticket was claimed, when its wait ended, when it finished, and the
+task and workgroup (``tchol_opts.trace``).  This tool runs one launch of the
+chosen DAG on a synthetic input of the benchmark family (factor: shift 1,
+seed 1; mixed: shift 1e-4, seed 2, the factorization launch of the
+mixed-precision solve; adjoint: shift 1, seed 3, Lbar = tril N(0, 1)), and
+prints the makespan, the fraction of worker time spent running and waiting,
+per task kind the item count and mean / median / max duration and mean wait,
+and the busy fraction over time in 20 buckets.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def report(tc, plan, trace, tag, out=print):
+    tr = trace.cpu().numpy().reshape(-1, 4).astype(np.int64)
+    claim, start, end, tw = tr[:, 0], tr[:, 1], tr[:, 2], tr[:, 3]
+    task = tw & 0xffffffff
+    wg = tw >> 32
+    kind = plan["kind"][task]
+    t0 = claim.min()
+    span = (end.max() - t0) / 100.0
+    busy = (end - start) / 100.0
+    wait = (start - claim) / 100.0
+    nwg = len(np.unique(wg))
+    out("[%s] makespan %.2f ms, workgroups %d, busy %.3f, waiting %.3f"
+        % (tag, span / 1000, nwg, busy.sum() / (nwg * span), wait.sum() / (nwg * span)))
+    out("  %-6s %8s %10s %10s %10s %11s %10s" % ("kind", "items", "mean us", "p50 us", "max us", "sum ms", "wait us"))
+    for k in range(len(tc.KIND_NAMES)):
+        m = kind == k
+        if m.any():
+            out("  %-6s %8d %10.1f %10.1f %10.1f %11.1f %10.1f" % (
+                tc.KIND_NAMES[k], m.sum(), busy[m].mean(), np.median(busy[m]), busy[m].max(), busy[m].sum() / 1000,
+                wait[m].mean()))
+    edges = np.linspace(0, span, 21)
+    s_rel, e_rel = (start - t0) / 100.0, (end - t0) / 100.0
+    util = []
+    for b in range(20):
+        ov = np.clip(np.minimum(e_rel, edges[b + 1]) - np.maximum(s_rel, edges[b]), 0, None)
+        util.append(ov.sum() / (nwg * (edges[b + 1] - edges[b])))
+    out("  busy over time: " + " ".join("%.2f" % u for u in util))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--op", choices=["factor", "mixed", "adjoint"], default="factor")
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--nb", type=int, default=0)
+    args = ap.parse_args(argv)
+    import torch
+    import paper_1402_6601_amd as tc
+    import spd_inputs
+    tc.load()
+    if not torch.cuda.is_available():
+        print("trace_report needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    if args.op == "adjoint":
+        n, nb = args.n or 8192, args.nb or 256
+        A, rng = spd_inputs.spd_matrix_device(n, 3, 1.0, device=dev)
+        Lb = torch.from_numpy(spd_inputs.lower_upstream(rng, n)).to(dev).mT.contiguous()
+        W = A.clone()
+        tc.factor_(W, nb)
+        plan = tc.plan_query(tc.OP_BACKWARD, n, nb)
+        trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
+        G = Lb.clone()
+        tc.backward_(W, G, nb)
+        G.copy_(Lb)
+        _, ms = tc.backward_(W, G, nb, want_kernel_ms=True, trace=trace)
+    else:
+        n, nb = args.n or 32768, args.nb or 512
+        mixed = args.op == "mixed"
+        A, rng = spd_inputs.spd_matrix_device(n, 2 if mixed else 1, 1e-4 if mixed else 1.0, device=dev)
+        plan = tc.plan_query(tc.OP_FACTOR, n, nb)
+        trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
+        if mixed:
+            B = torch.from_numpy(spd_inputs.rhs(rng, n, 16)).to(dev).t().contiguous()
+            X = B.clone()
+            tc.solve_mixed_(A, X, nb, maxit=0)
+            X.copy_(B)
+            _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, want_kernel_ms=True, trace=trace)
+        else:
+            W = A.clone()
+            tc.factor_(W, nb)
+            W.copy_(A)
+            _, ms = tc.factor_(W, nb, want_kernel_ms=True, trace=trace)
+    print("kernel %.3f ms (HIP events), n=%d nb=%d" % (ms, n, nb), flush=True)
+    report(tc, plan, trace, args.op)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
