@@ -38,6 +38,9 @@ typedef struct KArgs {
                            FP32 working copy); 3: the adjoint of the factorization
                            (A = L, B = Lbar, D = partial-product slots)              */
   int32_t pad1;
+  double *Dinv;         /* mixed precision: L_kk^{-1}, nb x nb each (FP64)         */
+  double *DinvT;        /* mixed precision: L_kk^{-T}, nb x nb each (FP64)         */
+  double *S;            /* mixed precision: the solve's intermediate y, like B     */
   double *Q;            /* adjoint: Q = twice the symmetric adjoint, ld ldq        */
   double *LT;           /* adjoint: L^T, ld ldq                                   */
   int64_t ldq;

@@ -88,11 +88,14 @@ int64_t weight(int32_t kind) {
     case TK_TREV: return 3;
     case TK_DPART: return 3;
     case TK_PREV: return 4;
+    case TK_TRTRI: return 3;
     default: return 2;
   }
 }
 
-void build_factor(Builder& b, FactorIds* ids = nullptr) {
+// trtri: add TRTRI(k) after POTRF(k) (explicit inverses for the
+// mixed-precision solve; no task of the factorization waits for them).
+void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
   auto& succ = b.succ;
   const int32_t T = b.T;
   std::vector<int32_t> id_potrf(T, -1), id_trsm((size_t)T * T, -1), id_syrk((size_t)T * T, -1);
@@ -124,24 +127,34 @@ void build_factor(Builder& b, FactorIds* ids = nullptr) {
         succ[id_gemm[ix3(i, j, k)]].push_back(k + 1 < j ? id_gemm[ix3(i, j, k + 1)] : id_trsm[ix2(i, j)]);
     }
   }
+  if (trtri)
+    for (int32_t k = 0; k < T; ++k) {
+      const int64_t mpad = (b.tile_size(k) + 15) / 16 * 16;
+      // add() appends to succ, so take the id before indexing succ
+      const int32_t id = b.add(TK_TRTRI, k, k, k, Builder::cdiv(mpad, b.s.trsm_rows));
+      succ[id_potrf[k]].push_back(id);
+    }
   if (ids) {
     ids->potrf = id_potrf;
     ids->trsm = id_trsm;
   }
 }
 
-void build_solve(Builder& b, const FactorIds* after = nullptr) {
+// split_diag: the diagonal steps are split into row strips like the updates
+// (the mixed-precision solve applies explicit inverses there).
+void build_solve(Builder& b, const FactorIds* after = nullptr, bool split_diag = false) {
   auto& succ = b.succ;
   const int32_t T = b.T;
   std::vector<int32_t> id_ft(T), id_bt(T), id_fg((size_t)T * T, -1), id_bg((size_t)T * T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
+  auto dparts = [&](int32_t k) { return split_diag ? Builder::cdiv(b.tile_size(k), b.s.gemv_rows) : 1; };
   for (int32_t k = 0; k < T; ++k) {
-    id_ft[k] = b.add(TK_FTRSV, k, k, k, 1);
+    id_ft[k] = b.add(TK_FTRSV, k, k, k, dparts(k));
     for (int32_t i = k + 1; i < T; ++i)
       id_fg[ix2(i, k)] = b.add(TK_FGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
   }
   for (int32_t k = T - 1; k >= 0; --k) {
-    id_bt[k] = b.add(TK_BTRSV, k, k, k, 1);
+    id_bt[k] = b.add(TK_BTRSV, k, k, k, dparts(k));
     for (int32_t i = 0; i < k; ++i)
       id_bg[ix2(i, k)] = b.add(TK_BGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
   }
@@ -347,8 +360,12 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
   Builder b(p, split, succ, 0);
   if (op == TCHOL_OP_FACTOR)
     build_factor(b);
+  else if (op == OP_FACTOR_INV)
+    build_factor(b, nullptr, true);
   else if (op == TCHOL_OP_SOLVE)
     build_solve(b);
+  else if (op == OP_SOLVE_INV)
+    build_solve(b, nullptr, true);
   else if (op == TCHOL_OP_BACKWARD)
     build_backward(b);
   else

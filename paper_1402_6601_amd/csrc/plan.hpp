@@ -50,6 +50,13 @@ struct Plan {
   int64_t nedge() const { return (int64_t)succ.size(); }
 };
 
+// Plan operations used only inside the library (beyond the public TCHOL_OP_*):
+// the mixed-precision factorization, whose DAG adds TRTRI(k) after POTRF(k),
+// and its solve, whose diagonal steps are split into row strips (they apply
+// explicit inverses).
+constexpr int32_t OP_FACTOR_INV = 16;
+constexpr int32_t OP_SOLVE_INV = 17;
+
 // Work-item granularity (rows x cols of one work item of each task kind).
 struct Split {
   int32_t gemm_m = 128, gemm_n = 128;   // GEMM/SYRK output sub-tile

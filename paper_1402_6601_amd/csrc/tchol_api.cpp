@@ -192,7 +192,8 @@ const tchol_opts kDefaultOpts = {TCHOL_POLICY_RANK, 0u, 0, nullptr, nullptr};
 int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_t nrhs, bool wide, bool batched,
                 void* ws, int64_t ws_bytes, void* stream_v, const tchol_opts& o, int32_t ws_arg,
                 int32_t* sinfo_out, double* D = nullptr, int mixed = 0, double* Qp = nullptr,
-                double* LTp = nullptr, int64_t ldq = 0) {
+                double* LTp = nullptr, int64_t ldq = 0, double* Dinv = nullptr, double* DinvT = nullptr,
+                double* Sx = nullptr) {
   const Layout& L = img.lay;
   if (ws_bytes < L.end) return -(ws_arg + 1);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
@@ -231,6 +232,9 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.Q = Qp;
   a.LT = LTp;
   a.ldq = ldq;
+  a.Dinv = Dinv;
+  a.DinvT = DinvT;
+  a.S = Sx;
   const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
   a.wait_limit = limit_us * di.clock_khz / 1000;
   a.trace = o.trace;
@@ -372,7 +376,7 @@ BackLayout back_layout(int64_t n, int64_t nb, const Plan& p) {
 // move four rows per 16-byte lane, so three rows past the order are read;
 // they hold zeros).
 struct MixedLayout {
-  int64_t ldw = 0, w = 0, d = 0, b0 = 0, r = 0, norms = 0, sched = 0, end = 0;
+  int64_t ldw = 0, w = 0, d = 0, dinv = 0, dinvt = 0, b0 = 0, r = 0, sx = 0, norms = 0, sched = 0, end = 0;
 };
 
 MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, const Plan& sp) {
@@ -381,10 +385,13 @@ MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, co
   M.ldw = (n + 3 + 3) / 4 * 4;
   M.w = 0;
   M.d = align_up(M.w + 4 * M.ldw * n);
-  M.b0 = align_up(M.d + 8 * T * nb * nb);
+  M.dinv = align_up(M.d + 8 * T * nb * nb);        // L_kk^{-1} per diagonal tile (FP64)
+  M.dinvt = align_up(M.dinv + 8 * T * nb * nb);    // L_kk^{-T}
+  M.b0 = align_up(M.dinvt + 8 * T * nb * nb);
   M.r = align_up(M.b0 + 8 * n * nrhs);
   // the residual region first holds the row sums of |A| (n entries)
-  M.norms = align_up(M.r + 8 * n * std::max<int64_t>(nrhs, 1));
+  M.sx = align_up(M.r + 8 * n * std::max<int64_t>(nrhs, 1));   // the solves' intermediate y
+  M.norms = align_up(M.sx + 8 * n * nrhs);
   M.sched = align_up(M.norms + 8 * (1 + 3 * nrhs));
   M.end = M.sched + std::max(layout_of(fp).end, layout_of(sp).end);
   return M;
@@ -530,8 +537,8 @@ int64_t tchol_mixed_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs) {
   if (n < 0) return -1;
   if (!nb_ok(nb)) return -2;
   if (nrhs < 0) return -3;
-  auto fp = tchol::get_plan(TCHOL_OP_FACTOR, n, nb, TCHOL_POLICY_RANK, 0);
-  auto sp = tchol::get_plan(TCHOL_OP_SOLVE, n, nb, TCHOL_POLICY_RANK, 0);
+  auto fp = tchol::get_plan(tchol::OP_FACTOR_INV, n, nb, TCHOL_POLICY_RANK, 0);
+  auto sp = tchol::get_plan(tchol::OP_SOLVE_INV, n, nb, TCHOL_POLICY_RANK, 0);
   if (!fp || !sp) return TCHOL_E_UNSUPPORTED;
   return mixed_layout(n, nb, nrhs, *fp, *sp).end;
 }
@@ -558,8 +565,8 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -11;
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
   if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
-  auto fplan = tchol::get_plan(TCHOL_OP_FACTOR, n, nb, o.policy, o.seed);
-  auto splan = tchol::get_plan(TCHOL_OP_SOLVE, n, nb, o.policy, o.seed);
+  auto fplan = tchol::get_plan(tchol::OP_FACTOR_INV, n, nb, o.policy, o.seed);
+  auto splan = tchol::get_plan(tchol::OP_SOLVE_INV, n, nb, o.policy, o.seed);
   if (!fplan || !splan) return TCHOL_E_UNSUPPORTED;
   const MixedLayout M = mixed_layout(n, nb, nrhs, *fplan, *splan);
   if (ws_bytes < M.end) return -12;
@@ -568,6 +575,9 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   char* w = static_cast<char*>(ws);
   float* W = reinterpret_cast<float*>(w + M.w);
   double* D = reinterpret_cast<double*>(w + M.d);
+  double* Dinv = reinterpret_cast<double*>(w + M.dinv);
+  double* DinvT = reinterpret_cast<double*>(w + M.dinvt);
+  double* Sx = reinterpret_cast<double*>(w + M.sx);
   double* B0 = reinterpret_cast<double*>(w + M.b0);
   double* R = reinterpret_cast<double*>(w + M.r);
   double* norms = reinterpret_cast<double*>(w + M.norms);  // {||A||, ||b_j||, ||x_j||, ||r_j||}
@@ -580,7 +590,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   if (tchol_refine_convert(A, n, W, M.ldw, n, s) != hipSuccess) return TCHOL_E_HIP;
   const tchol_opts& fo = o;  // kernel_ms and trace describe the factorization launch
   int32_t rc = execute(*fplan, *fimg, reinterpret_cast<double*>(W), nullptr, 0, true, false, sched, sched_bytes,
-                       stream_v, fo, 11, nullptr, D, 1);
+                       stream_v, fo, 11, nullptr, D, 1, nullptr, nullptr, 0, Dinv, DinvT, nullptr);
   if (rc != 0) return rc;
   tchol_opts so = o;
   so.trace = nullptr;
@@ -595,7 +605,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
 
   // x_0
   rc = execute(*splan, *simg, reinterpret_cast<double*>(W), B, nrhs, true, false, sched, sched_bytes, stream_v, so,
-               11, nullptr, D, 2);
+               11, nullptr, D, 2, nullptr, nullptr, 0, Dinv, DinvT, Sx);
   if (rc != 0) return rc;
   std::vector<double> hn(1 + 3 * (size_t)nrhs);
   for (int32_t it = 0;; ++it) {
@@ -619,7 +629,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
     if (it >= maxit || !finite) return TCHOL_E_NOCONV;
     // correction: R := L~^{-T} L~^{-1} R, then X += R
     rc = execute(*splan, *simg, reinterpret_cast<double*>(W), R, nrhs, true, false, sched, sched_bytes, stream_v, so,
-                 11, nullptr, D, 2);
+                 11, nullptr, D, 2, nullptr, nullptr, 0, Dinv, DinvT, Sx);
     if (rc != 0) return rc;
     if (tchol_refine_axpy(B, R, n * nrhs, s) != hipSuccess) return TCHOL_E_HIP;
   }

@@ -543,6 +543,8 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 // next step is requested one step ahead; the update fragments at the start
 // of the step, to land during the solve.
 //
+// REV = 2: the same solve, also storing P^T at Qb (ld ldq): the explicit
+// inverse of the mixed-precision solve, from identity strips.
 // REV = 1 (the adjoint's TRSM): X := X L^{-1} instead.  With J the order
 // reversal, X L^{-1} J = (X J) L'^{-T} for the lower-triangular
 // L' = J L^T J, so the same forward solve runs on the reversed columns of X
@@ -563,9 +565,9 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
   const int nblk = mk >> 4;
   // L(row, col) of the operator the forward solve applies
   auto lat = [&](int row, int col) __attribute__((always_inline)) {
-    return REV ? Lkk[(int64_t)(mk - 1 - col) * ld + (mk - 1 - row)] : Lkk[(int64_t)col * ld + row];
+    return REV == 1 ? Lkk[(int64_t)(mk - 1 - col) * ld + (mk - 1 - row)] : Lkk[(int64_t)col * ld + row];
   };
-  auto xcol = [&](int c) __attribute__((always_inline)) { return REV ? mk - 1 - c : c; };
+  auto xcol = [&](int c) __attribute__((always_inline)) { return REV == 1 ? mk - 1 - c : c; };
   // the strip: thread (r, c0) moves rows r of columns c0 + 8u, 16 loads in flight
   {
     const int r = tid & 31, c0 = tid >> 5, rr = imin(r, S - 1);
@@ -676,10 +678,16 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     if (rb + 1 < nblk) step(rb + 1, sb, sa);
   }
   __syncthreads();
-  if constexpr (REV == 0) {
+  if constexpr (REV != 1) {
     const int r = tid & 31, c0 = tid >> 5;
     if (r < S)
       for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ldx + r, (TX)Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
+    if constexpr (REV == 2) {
+      for (int idx = tid; idx < S * mk; idx += NT) {
+        const int rr = idx / mk, c = idx - rr * mk;
+        st_dev(Qb + (int64_t)rr * ldq + c, Xs[(rr >> 4) * 8192 + c * 16 + (rr & 15)]);
+      }
+    }
   } else {
     {
       const int r = tid & 31, c0 = tid >> 5;
@@ -938,7 +946,9 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
 // B_i[rows] -= L_ik[rows, :] Y_k  (forward update), rows = a strip of <= 128.
 // Each wavefront owns two 16-row blocks of the strip; the L fragments are
 // read straight from HBM (16 consecutive rows of a column per lane group).
-template <typename TL>
+// ASSIGN: Bi := Lik Yk instead (no load of Bi, no negation): the diagonal
+// steps of the mixed-precision solve, with Lik an explicit inverse.
+template <typename TL, bool ASSIGN = false>
 __device__ __forceinline__ void fgemv(const TL* __restrict__ Lik, int64_t ld, double* Bi, const double* Yk,
                                       int64_t ldb, int rows, int mk, int nrhs, double* lds) {
   double* Ys = lds;
@@ -956,7 +966,7 @@ __device__ __forceinline__ void fgemv(const TL* __restrict__ Lik, int64_t ld, do
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = (wave * 2 + t) * 16 + 4 * i + lg;
-        acc[t][i] = Bi[(int64_t)(j0 + jc) * ldb + imin(r, rows - 1)];
+        acc[t][i] = ASSIGN ? 0.0 : Bi[(int64_t)(j0 + jc) * ldb + imin(r, rows - 1)];
       }
     const int ra = imin((wave * 2) * 16 + l16, rows - 1), rbb = imin((wave * 2 + 1) * 16 + l16, rows - 1);
     // K in batches of 32: the batch's 16 L fragments are requested together
@@ -973,8 +983,8 @@ __device__ __forceinline__ void fgemv(const TL* __restrict__ Lik, int64_t ld, do
       for (int u = 0; u < 8; ++u) {
         const int k = kb + 4 * u + lg;
         const double fy = (k < mk) ? Ys[l16 * YLD + imin(k, 511)] : 0.0;
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[u], fy, acc[0], 0, 0, 2 /* neg B */);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[u], fy, acc[1], 0, 0, 2);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[u], fy, acc[0], 0, 0, ASSIGN ? 0 : 2 /* neg B */);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[u], fy, acc[1], 0, 0, ASSIGN ? 0 : 2);
       }
     }
     if (l16 < jn) {
@@ -1067,6 +1077,13 @@ __device__ __forceinline__ int potrf_tile_mixed(float* __restrict__ Wkk, int64_t
   wait_vmcnt<0>();
   __syncthreads();
   const int info = __builtin_amdgcn_readfirstlane(potrf_tile<128>(Dk, ldd, m, lds));
+  // a ragged tile is padded to a multiple of 16 with the identity (for its
+  // explicit inverse, which then holds L^{-1} in its leading m x m block)
+  const int mpad = (m + 15) & ~15;
+  for (int idx = tid; idx < mpad * mpad; idx += NT) {
+    const int c = idx / mpad, r = idx - c * mpad;
+    if (r >= c && (r >= m || c >= m)) st_dev(Dk + (int64_t)c * ldd + r, r == c ? 1.0 : 0.0);
+  }
   for (int base = 0; base < m * m; base += 16 * NT) {
     double v[16];
 #pragma unroll
@@ -1453,14 +1470,24 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
       }
       case TK_FTRSV:
       case TK_BTRSV:
-        if constexpr (!SOLVE_KINDS)
+        if constexpr (!SOLVE_KINDS) {
           ok = 0;
-        else if constexpr (MIXED)
-          tile_solve(a.D + (int64_t)tk * nb * nb, nb, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs, kind == TK_BTRSV,
-                     lds);
-        else
+        } else if constexpr (MIXED) {
+          // explicit FP64 inverses, 128-row strips: forward y_k := L_kk^{-1} b_k into
+          // the scratch vector, backward x_k := L_kk^{-T} y_k back into B
+          const int r0 = part * a.gemv_rows;
+          const int rows = imin(a.gemv_rows, tsz(tk) - r0);
+          double* const Sbase = a.S + sr[1];
+          if (kind == TK_FTRSV)
+            fgemv<double, true>(a.Dinv + (int64_t)tk * nb * nb + r0, nb, Sbase + tk * nb + r0, Bbase + tk * nb, ldb,
+                                rows, tsz(tk), (int)a.nrhs, lds);
+          else
+            fgemv<double, true>(a.DinvT + (int64_t)tk * nb * nb + r0, nb, Bbase + tk * nb + r0, Sbase + tk * nb, ldb,
+                                rows, tsz(tk), (int)a.nrhs, lds);
+        } else {
           tile_solve(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
                      kind == TK_BTRSV, lds);
+        }
         break;
       case TK_FGEMV: {
         if constexpr (!SOLVE_KINDS) {
@@ -1469,8 +1496,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         }
         const int r0 = part * a.gemv_rows;
         const int rows = imin(a.gemv_rows, tsz(ti) - r0);
-        fgemv(Abase + (tk * nb) * ld + ti * nb + r0, ld, Bbase + ti * nb + r0, Bbase + tk * nb, ldb, rows, tsz(tk),
-              (int)a.nrhs, lds);
+        // the mixed-precision solve keeps y in the scratch vector
+        const double* Yk = MIXED ? a.S + sr[1] + tk * nb : Bbase + tk * nb;
+        fgemv(Abase + (tk * nb) * ld + ti * nb + r0, ld, Bbase + ti * nb + r0, Yk, ldb, rows, tsz(tk), (int)a.nrhs,
+              lds);
         break;
       }
       case TK_BGEMV: {
@@ -1480,8 +1509,30 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         }
         const int c0 = part * a.gemv_rows;
         const int cols = imin(a.gemv_rows, tsz(ti) - c0);
-        bgemv(Abase + (ti * nb + c0) * ld + tk * nb, ld, Bbase + ti * nb + c0, Bbase + tk * nb, ldb, cols, tsz(tk),
+        double* Yi = MIXED ? a.S + sr[1] + ti * nb + c0 : Bbase + ti * nb + c0;
+        bgemv(Abase + (ti * nb + c0) * ld + tk * nb, ld, Yi, Bbase + tk * nb, ldb, cols, tsz(tk),
               (int)a.nrhs, lds);
+        break;
+      }
+      case TK_TRTRI: {
+        if constexpr (MODE != 1) {
+          ok = 0;
+        } else {
+          // L_kk^{-T} by 32-row strips: identity rows solved in place (into DinvT, ld nb),
+          // their transposes stored as L_kk^{-1} (Dinv); ragged tiles are identity-padded
+          const int mpad = (tsz(tk) + 15) & ~15;
+          const int r0 = part * a.trsm_rows;
+          const int S = imin(a.trsm_rows, mpad - r0);
+          double* X = a.DinvT + (int64_t)tk * nb * nb + r0;
+          for (int idx = tid; idx < S * mpad; idx += NT) {
+            const int c = idx / S, r = idx - c * S;
+            st_dev(X + (int64_t)c * nb + r, (r0 + r == c) ? 1.0 : 0.0);
+          }
+          wait_vmcnt<0>();
+          __syncthreads();
+          trsm_strip<double, 2>(X, nb, a.D + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,
+                                a.Dinv + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
+        }
         break;
       }
       case TK_GREV:

@@ -18,5 +18,7 @@
 #define TK_TREV  9   /* P_ik = Lbar_ik L_kk^{-1}, i > k                     */
 #define TK_DPART 10  /* S_ik = -tril(P_ik^T L_ik), i > k (partial product)   */
 #define TK_PREV  11  /* Lbar_kk += sum_i S_ik; P_kk = the tile's adjoint      */
-#define TK_NKINDS 12
+/* mixed precision: the explicit inverse of a diagonal tile, for its solves */
+#define TK_TRTRI 12  /* Dinv_k = L_kk^{-1}, DinvT_k = L_kk^{-T} (FP64)        */
+#define TK_NKINDS 13
 #endif

@@ -115,6 +115,17 @@ def test_mixed_validation_before_any_hip_call(lib):
     assert call(wsb=need - 256) == -12
 
 
+def test_mixed_workspace_query_over_sizes(lib):
+    # ragged last tiles of every shape (one row, odd, padded), one-tile and multi-tile plans
+    prev = 0
+    for n, nb in [(1, 16), (17, 16), (513, 512), (999, 160), (1000, 128), (1024, 256), (2048, 512), (4097, 512)]:
+        b = lib.tchol_mixed_workspace_bytes(n, nb, 4)
+        assert b > 0 and b % 256 == 0
+        if nb == 512:
+            assert b > prev
+            prev = b
+
+
 def test_backward_validation_before_any_hip_call(lib):
     need = lib.tchol_workspace_bytes(3, 256, 64, 0)
     assert need >= 2 * 8 * 256 * 256 + 8 * 6 * 64 * 64
