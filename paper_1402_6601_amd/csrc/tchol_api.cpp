@@ -23,7 +23,7 @@ extern "C" hipError_t tchol_refine_convert(const double* A, int64_t lda, float* 
                                            hipStream_t s);
 extern "C" hipError_t tchol_refine_residual(const double* A, int64_t lda, int64_t n, const double* X,
                                             const double* Bin, double* Out, int64_t ldb, int nrhs, int absmode,
-                                            hipStream_t s);
+                                            double* P, hipStream_t s);
 extern "C" hipError_t tchol_refine_colmax(const double* V, int64_t ldv, int64_t n, int ncols, double* out,
                                           hipStream_t s);
 extern "C" hipError_t tchol_refine_axpy(double* X, const double* D, int64_t count, hipStream_t s);
@@ -376,7 +376,8 @@ BackLayout back_layout(int64_t n, int64_t nb, const Plan& p) {
 // move four rows per 16-byte lane, so three rows past the order are read;
 // they hold zeros).
 struct MixedLayout {
-  int64_t ldw = 0, w = 0, d = 0, dinv = 0, dinvt = 0, b0 = 0, r = 0, sx = 0, norms = 0, sched = 0, end = 0;
+  int64_t ldw = 0, w = 0, d = 0, dinv = 0, dinvt = 0, b0 = 0, r = 0, sx = 0, part = 0, norms = 0, sched = 0,
+          end = 0;
 };
 
 MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, const Plan& sp) {
@@ -391,7 +392,8 @@ MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, co
   M.r = align_up(M.b0 + 8 * n * nrhs);
   // the residual region first holds the row sums of |A| (n entries)
   M.sx = align_up(M.r + 8 * n * std::max<int64_t>(nrhs, 1));   // the solves' intermediate y
-  M.norms = align_up(M.sx + 8 * n * nrhs);
+  M.part = align_up(M.sx + 8 * n * nrhs);                        // the residual's partial sums
+  M.norms = align_up(M.part + 8 * 2 * 8 * n * std::max<int64_t>(nrhs, 1));
   M.sched = align_up(M.norms + 8 * (1 + 3 * nrhs));
   M.end = M.sched + std::max(layout_of(fp).end, layout_of(sp).end);
   return M;
@@ -578,6 +580,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   double* Dinv = reinterpret_cast<double*>(w + M.dinv);
   double* DinvT = reinterpret_cast<double*>(w + M.dinvt);
   double* Sx = reinterpret_cast<double*>(w + M.sx);
+  double* Part = reinterpret_cast<double*>(w + M.part);
   double* B0 = reinterpret_cast<double*>(w + M.b0);
   double* R = reinterpret_cast<double*>(w + M.r);
   double* norms = reinterpret_cast<double*>(w + M.norms);  // {||A||, ||b_j||, ||x_j||, ||r_j||}
@@ -599,7 +602,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   // ||A||_inf (row sums of |A|, A symmetric) and ||b_j||_inf, kept with b
   const size_t bbytes = 8 * (size_t)n * (size_t)nrhs;
   if (hipMemcpyAsync(B0, B, bbytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return TCHOL_E_HIP;
-  if (tchol_refine_residual(A, n, n, B0, B0, R, n, 1, 1, s) != hipSuccess) return TCHOL_E_HIP;
+  if (tchol_refine_residual(A, n, n, B0, B0, R, n, 1, 1, Part, s) != hipSuccess) return TCHOL_E_HIP;
   if (tchol_refine_colmax(R, n, n, 1, norms, s) != hipSuccess) return TCHOL_E_HIP;
   if (tchol_refine_colmax(B0, n, n, nr, norms + 1, s) != hipSuccess) return TCHOL_E_HIP;
 
@@ -609,7 +612,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   if (rc != 0) return rc;
   std::vector<double> hn(1 + 3 * (size_t)nrhs);
   for (int32_t it = 0;; ++it) {
-    if (tchol_refine_residual(A, n, n, B, B0, R, n, nr, 0, s) != hipSuccess) return TCHOL_E_HIP;
+    if (tchol_refine_residual(A, n, n, B, B0, R, n, nr, 0, Part, s) != hipSuccess) return TCHOL_E_HIP;
     if (tchol_refine_colmax(B, n, n, nr, norms + 1 + nrhs, s) != hipSuccess) return TCHOL_E_HIP;
     if (tchol_refine_colmax(R, n, n, nr, norms + 1 + 2 * nrhs, s) != hipSuccess) return TCHOL_E_HIP;
     if (hipMemcpyAsync(hn.data(), norms, 8 * hn.size(), hipMemcpyDeviceToHost, s) != hipSuccess) return TCHOL_E_HIP;

@@ -30,27 +30,37 @@ __global__ void refine_convert(const double* __restrict__ A, int64_t lda, float*
     }
 }
 
-// Row pass: for the 128-row strip [r0, r0 + 128) and 16 right-hand sides
-// starting at j0, Out = Bin - sum over columns c <= r of A[r][c] X[c][:]
-// (rows below the strip's diagonal block are not read: entries above the
-// diagonal are masked).  With absmode, |A| and X = 1 give row sums of the
-// lower triangle (Bin, X ignored).  MFMA layout: A operand = A fragment
-// (rows on lanes % 16), B operand = X fragment (right-hand sides on lanes % 16).
+// The residual R = B - A X reads A by its lower triangle in two passes, each
+// split into (128-row or 128-column strip) x (chunk of at most ck
+// rows/columns of the other index) blocks so that every workgroup streams a
+// similar amount of A; each block writes its partial product to a slot of
+// its chunk, and a last kernel combines the slots in a fixed order
+// (deterministic).  MFMA layout: A operand = the A fragment (rows on
+// lanes % 16), B operand = the X fragment (right-hand sides on lanes % 16).
+
+// Row pass: rows [r0, r0 + 128), columns [c*ck, ...) up to the strip's
+// diagonal block: P1[c][j][r] = sum over those columns cc <= r of A[r][cc] X[cc][j].
+// absmode: |A| and X = 1 (row sums of |A|, one column).
 __global__ void __launch_bounds__(RT, 1) refine_rows(const double* __restrict__ A, int64_t lda, int64_t n,
-                                                     const double* __restrict__ X, const double* __restrict__ Bin,
-                                                     double* __restrict__ Out, int64_t ldb, int nrhs, int absmode) {
+                                                     const double* __restrict__ X, double* __restrict__ P1,
+                                                     int64_t ldb, int nrhs, int absmode, int64_t ck) {
   __shared__ double Xs[16 * 516];  // X chunk: 512 rows x 16 RHS, Xs[j * 516 + k]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * 128;
-  const int64_t kend = r0 + 128 < n ? r0 + 128 : n;  // columns 0 .. kend-1 may hold lower entries of the strip
-  for (int j0 = 0; j0 < (absmode ? 1 : nrhs); j0 += 16) {
-    const int jn = absmode ? 1 : rimin(16, nrhs - j0);
+  const int64_t kend = r0 + 128 < n ? r0 + 128 : n;  // columns past the strip's diagonal block hold no lower entries
+  const int64_t cbeg = (int64_t)blockIdx.y * ck;
+  if (cbeg >= kend) return;
+  const int64_t cend = cbeg + ck < kend ? cbeg + ck : kend;
+  double* const Pc = P1 + (int64_t)blockIdx.y * n * (absmode ? 1 : nrhs);
+  const int nj = absmode ? 1 : nrhs;
+  for (int j0 = 0; j0 < nj; j0 += 16) {
+    const int jn = rimin(16, nj - j0);
     r4 acc[2] = {r4{0, 0, 0, 0}, r4{0, 0, 0, 0}};
     const int64_t ra = r0 + (wave * 2) * 16 + l16, rb = ra + 16;  // A-fragment rows of the wave's two blocks
-    for (int64_t kc = 0; kc < kend; kc += 512) {
-      const int kw = (int)((kend - kc) < 512 ? (kend - kc) : 512);
+    for (int64_t kc = cbeg; kc < cend; kc += 512) {
+      const int kw = (int)((cend - kc) < 512 ? (cend - kc) : 512);
       __syncthreads();
       for (int idx = tid; idx < 16 * 512; idx += RT) {
         const int j = idx >> 9, k = idx & 511;
@@ -89,34 +99,37 @@ __global__ void __launch_bounds__(RT, 1) refine_rows(const double* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int64_t r = r0 + (wave * 2 + t) * 16 + 4 * i + lg;
-          if (r < n) {
-            const int64_t o = (int64_t)(j0 + l16) * ldb + r;
-            Out[o] = absmode ? acc[t][i] : Bin[o] - acc[t][i];
-          }
+          if (r < n) Pc[(int64_t)(j0 + l16) * n + r] = acc[t][i];
         }
     }
   }
 }
 
-// Column pass: for the 128-column strip [c0, c0 + 128), Out[c][:] -=
-// sum over rows r > c of A[r][c] X[r][:] (the strictly lower part read by
-// columns, i.e. the strictly upper part of the symmetric A applied to X).
-// With absmode, Out[c] += sum over r > c of |A[r][c]| (row sums of |A|).
+// Column pass: columns [c0, c0 + 128) of A, rows [max(c0, c*ck), ...):
+// P2[c][j][cc] = sum over those rows r > cc of A[r][cc] X[r][j] (the
+// strictly lower part read by columns: the strictly upper part of the
+// symmetric A applied to X).  absmode: row sums of |A| as above.
 __global__ void __launch_bounds__(RT, 1) refine_cols(const double* __restrict__ A, int64_t lda, int64_t n,
-                                                     const double* __restrict__ X, double* __restrict__ Out,
-                                                     int64_t ldb, int nrhs, int absmode) {
+                                                     const double* __restrict__ X, double* __restrict__ P2,
+                                                     int64_t ldb, int nrhs, int absmode, int64_t ck) {
   __shared__ double Xs[16 * 516];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
   const int64_t c0 = (int64_t)blockIdx.x * 128;
-  for (int j0 = 0; j0 < (absmode ? 1 : nrhs); j0 += 16) {
-    const int jn = absmode ? 1 : rimin(16, nrhs - j0);
+  const int64_t rb0 = (int64_t)blockIdx.y * ck;
+  const int64_t rbeg = rb0 > c0 ? rb0 : c0;
+  const int64_t rend = rb0 + ck < n ? rb0 + ck : n;
+  if (rbeg >= rend) return;
+  double* const Pc = P2 + (int64_t)blockIdx.y * n * (absmode ? 1 : nrhs);
+  const int nj = absmode ? 1 : nrhs;
+  for (int j0 = 0; j0 < nj; j0 += 16) {
+    const int jn = rimin(16, nj - j0);
     r4 acc[2] = {r4{0, 0, 0, 0}, r4{0, 0, 0, 0}};
     const int64_t ca = c0 + (wave * 2) * 16 + l16, cb = ca + 16;  // A^T fragment rows = columns of A
     const int64_t caa = ca < n ? ca : n - 1, cbb = cb < n ? cb : n - 1;
-    for (int64_t kc = c0; kc < n; kc += 512) {  // rows of A
-      const int kw = (int)((n - kc) < 512 ? (n - kc) : 512);
+    for (int64_t kc = rbeg; kc < rend; kc += 512) {  // rows of A
+      const int kw = (int)((rend - kc) < 512 ? (rend - kc) : 512);
       __syncthreads();
       for (int idx = tid; idx < 16 * 512; idx += RT) {
         const int j = idx >> 9, k = idx & 511;
@@ -155,12 +168,32 @@ __global__ void __launch_bounds__(RT, 1) refine_cols(const double* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int64_t c = c0 + (wave * 2 + t) * 16 + 4 * i + lg;
-          if (c < n) {
-            const int64_t o = (int64_t)(j0 + l16) * ldb + c;
-            Out[o] = absmode ? Out[o] + acc[t][i] : Out[o] - acc[t][i];
-          }
+          if (c < n) Pc[(int64_t)(j0 + l16) * n + c] = acc[t][i];
         }
     }
+  }
+}
+
+// Out = Bin - (sum of the row pass's slots) - (sum of the column pass's
+// slots), chunks ascending; absmode: Out = the sums (row sums of |A|).
+// A chunk's slot holds a value for row r only if that chunk has a block
+// covering r; the same rules as the passes decide which.
+__global__ void refine_combine(const double* __restrict__ Bin, double* __restrict__ Out, const double* __restrict__ P1,
+                               const double* __restrict__ P2, int64_t n, int64_t ldb, int nrhs, int absmode,
+                               int64_t ck, int nchunk) {
+  const int nj = absmode ? 1 : nrhs;
+  const int64_t tot = n * nj;
+  for (int64_t idx = (int64_t)blockIdx.x * RT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * RT) {
+    const int64_t j = idx / n, r = idx - j * n;
+    const int64_t s0 = r / 128 * 128;
+    const int64_t kend = s0 + 128 < n ? s0 + 128 : n;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+      if ((int64_t)c * ck < kend) acc += P1[(int64_t)c * n * nj + j * n + r];
+      const int64_t rb0 = (int64_t)c * ck, rbeg = rb0 > s0 ? rb0 : s0, rend = rb0 + ck < n ? rb0 + ck : n;
+      if (rbeg < rend) acc += P2[(int64_t)c * n * nj + j * n + r];
+    }
+    Out[j * ldb + r] = absmode ? acc : Bin[j * ldb + r] - acc;
   }
 }
 
@@ -192,16 +225,35 @@ extern "C" hipError_t tchol_refine_convert(const double* A, int64_t lda, float* 
   return hipGetLastError();
 }
 
-// Out = Bin - A X (absmode: Out = |A| 1, row sums of |A|); Out may equal Bin.
+// Chunk length of the residual's passes: at most 8 chunks, each a multiple of 512.
+extern "C" int64_t tchol_refine_chunk(int64_t n) {
+  const int64_t c = (n + 7) / 8;
+  const int64_t ck = (c + 511) / 512 * 512;
+  return ck < 4096 ? 4096 : ck;
+}
+
+// Out = Bin - A X (absmode: Out = |A| 1, the row sums of |A|); Out may equal
+// Bin.  P: scratch of 2 * 8 * n * max(nrhs, 1) doubles for the partial sums.
 extern "C" hipError_t tchol_refine_residual(const double* A, int64_t lda, int64_t n, const double* X,
                                             const double* Bin, double* Out, int64_t ldb, int nrhs, int absmode,
-                                            hipStream_t s) {
+                                            double* P, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  const int64_t ck = tchol_refine_chunk(n);
+  const int nchunk = (int)((n + ck - 1) / ck);
+  const int64_t slot = 8 * n * (int64_t)(nrhs > 1 ? nrhs : 1);
+  double* P1 = P;
+  double* P2 = P + slot;
   const unsigned g = (unsigned)((n + 127) / 128);
-  hipLaunchKernelGGL(refine_rows, dim3(g), dim3(RT), 0, s, A, lda, n, X, Bin, Out, ldb, nrhs, absmode);
+  hipLaunchKernelGGL(refine_rows, dim3(g, (unsigned)nchunk), dim3(RT), 0, s, A, lda, n, X, P1, ldb, nrhs, absmode, ck);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(refine_cols, dim3(g), dim3(RT), 0, s, A, lda, n, X, Out, ldb, nrhs, absmode);
+  hipLaunchKernelGGL(refine_cols, dim3(g, (unsigned)nchunk), dim3(RT), 0, s, A, lda, n, X, P2, ldb, nrhs, absmode, ck);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = n * (absmode ? 1 : nrhs);
+  const int64_t gb = (tot + RT - 1) / RT;
+  hipLaunchKernelGGL(refine_combine, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(RT), 0, s, Bin, Out, P1, P2, n, ldb,
+                     nrhs, absmode, ck, nchunk);
   return hipGetLastError();
 }
 
