@@ -26,7 +26,8 @@ OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD = 0, 1, 2, 3
 POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV = -100, -101, -102, -103, -104
 LOWP_FP32 = 1
-KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV"]
+KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV",
+              "TRTRI", "DRED"]
 
 _lib = None
 

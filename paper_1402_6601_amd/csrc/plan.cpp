@@ -89,6 +89,7 @@ int64_t weight(int32_t kind) {
     case TK_DPART: return 3;
     case TK_PREV: return 4;
     case TK_TRTRI: return 3;
+    case TK_DRED: return 1;
     default: return 2;
   }
 }
@@ -191,14 +192,16 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, bool split_diag =
 //                  TREV(j, i) (j > i)
 //   TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}  after GREV(i, k, k+1)
 //   DPART(i, k)    S_ik = tril(P_ik^T L_ik)  after TREV(i, k)
-//   PREV(k)        Lbar_kk -= sum_i S_ik (i ascending), then the diagonal
-//                  tile's adjoint          after every DPART(i, k)
+//   DRED(k)        Lbar_kk -= sum_i S_ik (i ascending), by 16-row strips,
+//                  after every DPART(i, k)   (k < T-1)
+//   PREV(k)        the diagonal tile's adjoint, after DRED(k)
 // The partial products S_ik give the diagonal tile's update one task per
-// term instead of a chain of T - k - 1 dependent ones on the critical path.
+// term instead of a chain of T - k - 1 dependent ones on the critical path,
+// and their sum is spread over workgroups by row strips.
 void build_backward(Builder& b) {
   auto& succ = b.succ;
   const int32_t T = b.T;
-  std::vector<int32_t> id_prev(T), id_trev((size_t)T * T, -1), id_dpart((size_t)T * T, -1);
+  std::vector<int32_t> id_prev(T), id_dred(T, -1), id_trev((size_t)T * T, -1), id_dpart((size_t)T * T, -1);
   std::vector<int32_t> id_grev((size_t)T * T * T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
@@ -212,6 +215,7 @@ void build_backward(Builder& b) {
       id_trev[ix2(i, k)] = b.add(TK_TREV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
     const int32_t sb = Builder::cdiv(b.tile_size(k), b.s.gemm_m);
     for (int32_t i = k + 1; i < T; ++i) id_dpart[ix2(i, k)] = b.add(TK_DPART, i, k, k, sb * (sb + 1) / 2);
+    if (k + 1 < T) id_dred[k] = b.add(TK_DRED, k, k, k, Builder::cdiv(b.tile_size(k), 16));
     id_prev[k] = b.add(TK_PREV, k, k, k, 1);
   }
   auto producer = [&](int32_t i, int32_t j) {
@@ -225,8 +229,9 @@ void build_backward(Builder& b) {
         succ[g].push_back(j > k + 1 ? id_grev[ix3(i, j - 1, k)] : id_trev[ix2(i, k)]);
       }
       succ[id_trev[ix2(i, k)]].push_back(id_dpart[ix2(i, k)]);
-      succ[id_dpart[ix2(i, k)]].push_back(id_prev[k]);
+      succ[id_dpart[ix2(i, k)]].push_back(id_dred[k]);
     }
+    if (k + 1 < T) succ[id_dred[k]].push_back(id_prev[k]);
   }
 }
 
@@ -237,12 +242,18 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   int32_t kind = p.kind[t], step = p.tk[t];
   if (kind == TK_BTRSV || kind == TK_BGEMV) step = T + (T - 1 - p.tk[t]);
   if (p.op == TCHOL_OP_BATCHED && kind >= TK_FTRSV) step += T;  // a system's solve after its factor
-  if (kind >= TK_GREV) step = T - 1 - p.tk[t];  // the adjoint runs its steps downwards
+  if (kind >= TK_GREV && kind != TK_TRTRI) step = T - 1 - p.tk[t];  // the adjoint runs its steps downwards
   int32_t kord = kind;
   if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV
   if (kind == TK_BGEMV) kord = 1;
   if (kind == TK_FTRSV) kord = 0;
   if (kind == TK_FGEMV) kord = 1;
+  // within an adjoint step: the updates, the solves, the partial products, their sum, the tile
+  if (kind == TK_GREV) kord = 0;
+  if (kind == TK_TREV) kord = 1;
+  if (kind == TK_DPART) kord = 2;
+  if (kind == TK_DRED) kord = 3;
+  if (kind == TK_PREV) kord = 4;
   // the chain of GREV(i, k, j) into Lbar_ik runs j downwards
   const int32_t tj = kind == TK_GREV ? T - 1 - p.tj[t] : p.tj[t];
   return std::make_tuple(p.sys[t], step, kord, p.ti[t], tj);

@@ -1054,9 +1054,10 @@ __device__ __forceinline__ void bgemv(const TL* __restrict__ Lki, int64_t ld, do
 
 // ---------------------------------------------------------------------------
 // POTRF of the mixed-precision factorization: the FP32 diagonal tile Wkk is
-// promoted to an FP64 tile Dk (ld nb, in the workspace), factored there in
-// FP64 by the same tile kernel, and rounded back into Wkk.  Dk is kept: the
-// TRSM strips of step k and the tile solves read L_kk from it in FP64.
+// promoted to an FP64 tile Dk (ld nb, in the workspace) and factored there in
+// FP64 by the same tile kernel.  Dk is the factor's diagonal tile from then
+// on: the TRSM strips of step k and the tile's inverses (TRTRI) read L_kk
+// from it; nothing reads the FP32 diagonal tile again, so it is not updated.
 __device__ __forceinline__ int potrf_tile_mixed(float* __restrict__ Wkk, int64_t ldw, int m,
                                                 double* __restrict__ Dk, int64_t ldd, double* lds) {
   const int tid = threadIdx.x;
@@ -1084,20 +1085,47 @@ __device__ __forceinline__ int potrf_tile_mixed(float* __restrict__ Wkk, int64_t
     const int c = idx / mpad, r = idx - c * mpad;
     if (r >= c && (r >= m || c >= m)) st_dev(Dk + (int64_t)c * ldd + r, r == c ? 1.0 : 0.0);
   }
-  for (int base = 0; base < m * m; base += 16 * NT) {
-    double v[16];
+  return info;
+}
+
+// ---------------------------------------------------------------------------
+// DRED work item: rows [r0, r0 + 16) of the diagonal tile's Lbar (ld) get
+// the tile's partial products added, slot by slot in a fixed order (each slot
+// holds -tril(P_ik^T L_ik), nb x nb at stride slot_stride, ld ldslot; only
+// the lower triangle is read and written).  Eight entries per thread and
+// four slots per round keep 32 loads in flight.
+__device__ __forceinline__ void dred_strip(double* __restrict__ Bkk, int64_t ld, const double* __restrict__ slots,
+                                           int64_t slot_stride, int nslots, int64_t ldslot, int m, int r0) {
+  const int tid = threadIdx.x;
+  const int ncol = imin(r0 + 16, m);          // columns that hold lower entries of these rows
+  const int tot = 16 * ncol;                  // (row, column) pairs, rows fastest
+  for (int base = 0; base < tot; base += 8 * NT) {
+    double v[8];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = imin(base + u * NT + tid, m * m - 1), c = idx / m, r = idx % m;
-      v[u] = Dk[(int64_t)c * ldd + r];
+    for (int u = 0; u < 8; ++u) {
+      const int idx = imin(base + u * NT + tid, tot - 1), c = idx >> 4, r = imin(r0 + (idx & 15), m - 1);
+      v[u] = Bkk[(int64_t)c * ld + r];
+    }
+    for (int s0 = 0; s0 < nslots; s0 += 4) {
+      double t[4][8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int idx = imin(base + u * NT + tid, tot - 1), c = idx >> 4, r = imin(r0 + (idx & 15), m - 1);
+          t[q][u] = (s0 + q < nslots) ? slots[(int64_t)(s0 + q) * slot_stride + (int64_t)c * ldslot + r] : 0.0;
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] += t[q][u];
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * NT + tid, c = idx / m, r = idx % m;
-      if (idx < m * m && r >= c) st_dev(Wkk + (int64_t)c * ldw + r, (float)v[u]);
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * NT + tid, c = idx >> 4, r = r0 + (idx & 15);
+      if (idx < tot && r < m && r >= c) st_dev(Bkk + (int64_t)c * ld + r, v[u]);
     }
   }
-  return info;
 }
 
 // ---------------------------------------------------------------------------
@@ -1538,6 +1566,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
       case TK_GREV:
       case TK_TREV:
       case TK_DPART:
+      case TK_DRED:
       case TK_PREV: {
         if constexpr (!ADJOINT_KINDS) {
           ok = 0;
@@ -1581,10 +1610,14 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
             gemm_nt_ex(a.D + slot(ti, tk) * nb * nb + (sj * a.gemm_n) * nb + si * a.gemm_m, nb,
                        a.Q + (ti * nb) * ldq + tk * nb + si * a.gemm_m, a.LT + (ti * nb) * ldq + tk * nb + sj * a.gemm_n,
                        ldq, M, N, K, si == sj, true, lds);
+          } else if (kind == TK_DRED) {
+            dred_strip(Bbase + (tk * nb) * ld + tk * nb, ld, a.D + slot(tk + 1, tk) * nb * nb, nb * nb, T - 1 - tk, nb,
+                       tsz(tk), part * 16);
           } else {
+            // the partial products were applied by DRED(k)
             prev_tile(Abase + (tk * nb) * ld + tk * nb, a.LT + (tk * nb) * ldq + tk * nb,
-                      Bbase + (tk * nb) * ld + tk * nb, ld, a.Q + (tk * nb) * ldq + tk * nb, ldq, tsz(tk),
-                      tk + 1 < T ? a.D + slot(tk + 1, tk) * nb * nb : a.D, nb * nb, T - 1 - tk, nb, lds);
+                      Bbase + (tk * nb) * ld + tk * nb, ld, a.Q + (tk * nb) * ldq + tk * nb, ldq, tsz(tk), a.D,
+                      nb * nb, 0, nb, lds);
           }
         }
         break;

@@ -17,8 +17,10 @@
 #define TK_GREV  8   /* Lbar_ik <- Lbar_ik - Q_ij L_jk, i > k, j > k        */
 #define TK_TREV  9   /* P_ik = Lbar_ik L_kk^{-1}, i > k                     */
 #define TK_DPART 10  /* S_ik = -tril(P_ik^T L_ik), i > k (partial product)   */
-#define TK_PREV  11  /* Lbar_kk += sum_i S_ik; P_kk = the tile's adjoint      */
+#define TK_PREV  11  /* P_kk = the diagonal tile's adjoint                    */
 /* mixed precision: the explicit inverse of a diagonal tile, for its solves */
 #define TK_TRTRI 12  /* Dinv_k = L_kk^{-1}, DinvT_k = L_kk^{-T} (FP64)        */
-#define TK_NKINDS 13
+/* adjoint: the diagonal tile's partial products, summed by row strips */
+#define TK_DRED  13  /* Lbar_kk += sum_i S_ik (i ascending)                  */
+#define TK_NKINDS 14
 #endif

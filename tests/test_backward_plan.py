@@ -4,7 +4,8 @@ The reverse program, per step k from T-1 down to 0,
     GREV(i, k, j)  Lbar_ik -= Q_ij L_jk      i > k, j = T-1 .. k+1
     TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}   (writes Q_ik and Q_ki)
     DPART(i, k)    S_ik = tril(P_ik^T L_ik)
-    PREV(k)        Lbar_kk -= sum_i S_ik; P_kk (writes Q_kk)
+    DRED(k)        Lbar_kk -= sum_i S_ik     (k < T-1)
+    PREV(k)        P_kk (writes Q_kk)
 is replayed in program order with its data (Lbar tiles, the P tile behind
 each Q tile, the partial products S) and every read-after-write,
 write-after-read and write-after-write conflict becomes an edge (section 2,
@@ -20,8 +21,8 @@ import pytest
 
 tc = pytest.importorskip("paper_1402_6601_amd")
 
-GREV, TREV, DPART, PREV = 8, 9, 10, 11
-WEIGHT = {GREV: 6, TREV: 3, DPART: 3, PREV: 4}
+GREV, TREV, DPART, PREV, DRED = 8, 9, 10, 11, 13
+WEIGHT = {GREV: 6, TREV: 3, DPART: 3, PREV: 4, DRED: 1}
 
 
 def bplan(n, nb, policy=0, seed=0):
@@ -83,8 +84,9 @@ def dataflow_edges(T):
             access((TREV, i, k, k), [("Lbar", i, k)], [("Lbar", i, k), ("P", i, k)])
         for i in range(k + 1, T):
             access((DPART, i, k, k), [("P", i, k)], [("S", i, k)])
-        access((PREV, k, k, k), [("S", i, k) for i in range(k + 1, T)] + [("Lbar", k, k)],
-               [("Lbar", k, k), ("P", k, k)])
+        if k + 1 < T:
+            access((DRED, k, k, k), [("S", i, k) for i in range(k + 1, T)] + [("Lbar", k, k)], [("Lbar", k, k)])
+        access((PREV, k, k, k), [("Lbar", k, k)], [("Lbar", k, k), ("P", k, k)])
     return reduce_transitively(out)
 
 
@@ -102,7 +104,7 @@ def test_backward_edges_equal_dataflow(n, nb):
             edges.add((key(p, t), key(p, int(p["succ"][e]))))
     assert reduce_transitively(edges) == dataflow_edges(T)
     cnt = collections.Counter(int(x) for x in p["kind"])
-    assert cnt[PREV] == T
+    assert cnt[PREV] == T and cnt[DRED] == T - 1
     assert cnt[TREV] == cnt[DPART] == T * (T - 1) // 2
     assert cnt[GREV] == sum((T - k - 1) ** 2 for k in range(T))
 
@@ -128,7 +130,7 @@ def test_backward_ranks_and_parts():
     for t in range(p["ntask"]):
         kind, i, k = int(p["kind"][t]), int(p["i"][t]), int(p["k"][t])
         want = {GREV: -(-tsz(i) // 128) * -(-tsz(k) // 128), TREV: -(-tsz(i) // 32),
-                DPART: (lambda s: s * (s + 1) // 2)(-(-tsz(k) // 128)), PREV: 1}[kind]
+                DPART: (lambda s: s * (s + 1) // 2)(-(-tsz(k) // 128)), PREV: 1, DRED: -(-tsz(k) // 16)}[kind]
         assert p["parts"][t] == want
     # the first task claimed is the adjoint of the last diagonal tile
     assert int(p["kind"][p["item_task"][0]]) == PREV and int(p["k"][p["item_task"][0]]) == 2
