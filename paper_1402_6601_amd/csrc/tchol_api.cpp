@@ -27,6 +27,8 @@ extern "C" hipError_t tchol_refine_residual(const double* A, int64_t lda, int64_
 extern "C" hipError_t tchol_refine_colmax(const double* V, int64_t ldv, int64_t n, int ncols, double* out,
                                           hipStream_t s);
 extern "C" hipError_t tchol_refine_axpy(double* X, const double* D, int64_t count, hipStream_t s);
+extern "C" hipError_t tchol_refine_diag(const double* A, int64_t lda, int64_t n, int64_t nb, double* D,
+                                        hipStream_t s);
 
 namespace {
 
@@ -591,6 +593,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
 
   // the working copy, then its factorization (FP32 updates, FP64 diagonal tiles)
   if (tchol_refine_convert(A, n, W, M.ldw, n, s) != hipSuccess) return TCHOL_E_HIP;
+  if (tchol_refine_diag(A, n, n, nb, D, s) != hipSuccess) return TCHOL_E_HIP;
   const tchol_opts& fo = o;  // kernel_ms and trace describe the factorization launch
   int32_t rc = execute(*fplan, *fimg, reinterpret_cast<double*>(W), nullptr, 0, true, false, sched, sched_bytes,
                        stream_v, fo, 11, nullptr, D, 1, nullptr, nullptr, 0, Dinv, DinvT, nullptr);

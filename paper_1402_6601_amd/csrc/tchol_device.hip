@@ -314,11 +314,14 @@ __device__ __forceinline__ void gemm_nt_ex(double* C, int64_t ldc, const double*
 // The f32 MFMA has no operand negation, so the A fragment is negated.  Its
 // 16 x 16 result differs in layout from the f64 instruction's: element i of
 // lane l holds row 4 (l / 16) + i (not 4 i + l / 16) of column l % 16.
+// CD: the product is added to an FP64 C (Cd, ld ldcd) instead: the diagonal
+// tiles of the mixed-precision factorization stay in FP64 throughout.
 #define F32_LD 272
-template <int KC, int NST>
+template <int KC, int NST, bool CD = false>
 __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float* __restrict__ Ap,
                                               const float* __restrict__ Bp, int64_t ld, int M, int N, int K,
-                                              bool lower_only, double* lds_d) {
+                                              bool lower_only, double* lds_d, double* __restrict__ Cd = nullptr,
+                                              int64_t ldcd = 0) {
   constexpr int STAGE = KC * F32_LD;  // floats per stage
   constexpr int W = KC / 4;           // transfers per wavefront and chunk
   static_assert(NST * STAGE <= 2 * LDS_DOUBLES, "stages must fit the workgroup LDS");
@@ -339,7 +342,7 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = wm * 64 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
-        acc[rb][cb][i] = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
+        acc[rb][cb][i] = CD ? 0.f : C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
       }
 
   static_assert(STAGE % 2 == 0 && F32_LD % 2 == 0, "destinations are addressed in doubles");
@@ -404,7 +407,14 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = wm * 64 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
-        if (row < M && col < N && (!lower_only || row >= col)) st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
+        if (row < M && col < N && (!lower_only || row >= col)) {
+          if constexpr (CD) {
+            double* p = Cd + (int64_t)col * ldcd + row;
+            st_dev(p, *p + (double)acc[rb][cb][i]);
+          } else {
+            st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
+          }
+        }
       }
 }
 
@@ -414,6 +424,15 @@ __device__ __forceinline__ void gemm_nt_f32(float* C, const float* Ap, const flo
     gemm_f32_core<32, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
   else
     gemm_f32_core<16, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
+}
+
+// The same with the result added to an FP64 C (Cd, ld ldcd).
+__device__ __forceinline__ void gemm_nt_f32_d(double* Cd, int64_t ldcd, const float* Ap, const float* Bp, int64_t ld,
+                                              int M, int N, int K, bool lower_only, double* lds) {
+  if (K % 32 == 0)
+    gemm_f32_core<32, 4, true>(nullptr, Ap, Bp, ld, M, N, K, lower_only, lds, Cd, ldcd);
+  else
+    gemm_f32_core<16, 4, true>(nullptr, Ap, Bp, ld, M, N, K, lower_only, lds, Cd, ldcd);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,30 +1072,13 @@ __device__ __forceinline__ void bgemv(const TL* __restrict__ Lki, int64_t ld, do
 }
 
 // ---------------------------------------------------------------------------
-// POTRF of the mixed-precision factorization: the FP32 diagonal tile Wkk is
-// promoted to an FP64 tile Dk (ld nb, in the workspace) and factored there in
-// FP64 by the same tile kernel.  Dk is the factor's diagonal tile from then
-// on: the TRSM strips of step k and the tile's inverses (TRTRI) read L_kk
-// from it; nothing reads the FP32 diagonal tile again, so it is not updated.
-__device__ __forceinline__ int potrf_tile_mixed(float* __restrict__ Wkk, int64_t ldw, int m,
-                                                double* __restrict__ Dk, int64_t ldd, double* lds) {
+// POTRF of the mixed-precision factorization: the diagonal tiles live in
+// FP64 in the workspace (Dk, ld nb) from the start (copied from A) and take
+// their SYRK updates there, so the tile is factored in place by the FP64
+// tile kernel.  Dk then holds L_kk for the TRSM strips of step k and the
+// tile's inverses (TRTRI); the FP32 copy's diagonal tiles are never read.
+__device__ __forceinline__ int potrf_tile_mixed(double* __restrict__ Dk, int64_t ldd, int m, double* lds) {
   const int tid = threadIdx.x;
-  // lower triangle (and diagonal) to FP64; 16 loads of a thread in flight
-  for (int base = 0; base < m * m; base += 16 * NT) {
-    float v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = imin(base + u * NT + tid, m * m - 1), c = idx / m, r = idx % m;
-      v[u] = Wkk[(int64_t)c * ldw + r];
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * NT + tid, c = idx / m, r = idx % m;
-      if (idx < m * m && r >= c) st_dev(Dk + (int64_t)c * ldd + r, (double)v[u]);
-    }
-  }
-  wait_vmcnt<0>();
-  __syncthreads();
   const int info = __builtin_amdgcn_readfirstlane(potrf_tile<128>(Dk, ldd, m, lds));
   // a ragged tile is padded to a multiple of 16 with the identity (for its
   // explicit inverse, which then holds L^{-1} in its leading m x m block)
@@ -1428,7 +1430,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         E* Akk = Abase + (tk * nb) * ld + tk * nb;
         int info;
         if constexpr (MIXED)
-          info = uniform_i(potrf_tile_mixed(Akk, ld, tsz(tk), a.D + (int64_t)tk * nb * nb, nb, lds));
+          info = uniform_i(potrf_tile_mixed(a.D + (int64_t)tk * nb * nb, nb, tsz(tk), lds));
         else
           info = uniform_i(potrf_tile<SEG>(Akk, ld, tsz(tk), lds));
         if (info != 0 && tid == 0) {
@@ -1485,7 +1487,11 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
             ok = 0;
             break;
           }
-          gemm_nt_f32(C, Ap, Bp, ld, M, N, tsz(tk), kind == TK_SYRK && si == sj, lds);
+          if (kind == TK_SYRK)
+            gemm_nt_f32_d(a.D + (int64_t)ti * nb * nb + (int64_t)(sj * a.gemm_n) * nb + si * a.gemm_m, nb, Ap, Bp,
+                          ld, M, N, tsz(tk), si == sj, lds);
+          else
+            gemm_nt_f32(C, Ap, Bp, ld, M, N, tsz(tk), false, lds);
         } else {
           if (SEG == 128 && (((int)ld & 1) != 0 || (((M | N) & 1) != 0 && ld <= sn) || misaligned)) {
             raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract

@@ -30,6 +30,18 @@ __global__ void refine_convert(const double* __restrict__ A, int64_t lda, float*
     }
 }
 
+// D_k := the lower triangle of A's diagonal tile k in FP64 (D: T tiles of
+// nb x nb, ld nb): the diagonal tiles of the mixed-precision factorization.
+__global__ void refine_diag(const double* __restrict__ A, int64_t lda, int64_t n, int64_t nb,
+                            double* __restrict__ D) {
+  const int64_t k = blockIdx.y;
+  const int64_t m = n - k * nb < nb ? n - k * nb : nb;
+  for (int64_t idx = (int64_t)blockIdx.x * RT + threadIdx.x; idx < m * m; idx += (int64_t)gridDim.x * RT) {
+    const int64_t c = idx / m, r = idx - c * m;
+    if (r >= c) D[k * nb * nb + c * nb + r] = A[(k * nb + c) * lda + k * nb + r];
+  }
+}
+
 // The residual R = B - A X reads A by its lower triangle in two passes, each
 // split into (128-row or 128-column strip) x (chunk of at most ck
 // rows/columns of the other index) blocks so that every workgroup streams a
@@ -216,6 +228,15 @@ __global__ void __launch_bounds__(RT) refine_colmax(const double* __restrict__ V
 // X += D (count elements).
 __global__ void refine_axpy(double* __restrict__ X, const double* __restrict__ D, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < count; i += (int64_t)gridDim.x * RT) X[i] += D[i];
+}
+
+extern "C" hipError_t tchol_refine_diag(const double* A, int64_t lda, int64_t n, int64_t nb, double* D,
+                                        hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t T = (n + nb - 1) / nb;
+  const int64_t g = (nb * nb + RT - 1) / RT;
+  hipLaunchKernelGGL(refine_diag, dim3((unsigned)(g < 64 ? g : 64), (unsigned)T), dim3(RT), 0, s, A, lda, n, nb, D);
+  return hipGetLastError();
 }
 
 extern "C" hipError_t tchol_refine_convert(const double* A, int64_t lda, float* W, int64_t ldw, int64_t n,
