@@ -111,20 +111,28 @@ def run_batched(args):
     seed = 4 if args.seed == 1 else args.seed
     nrhs = 4
     K, Wm = args.steps, args.warmup
+    fp32 = args.dtype == "f32"
     t0 = time.time()
-    ns, A0, a_off, lda, B0, b_off = spd_inputs.batched_systems_device(args.count, seed, nrhs, device=dev)
+    if fp32:
+        # FP32 storage: lda = n + 3 rounded up to 4, systems 16-byte aligned
+        ns, A0, a_off, lda, B0, b_off = spd_inputs.batched_systems_device(args.count, seed, nrhs, device=dev,
+                                                                          align=4, pad=3, fp32=True)
+    else:
+        ns, A0, a_off, lda, B0, b_off = spd_inputs.batched_systems_device(args.count, seed, nrhs, device=dev)
+    run = tc.factor_solve_batched_f32_ if fp32 else tc.factor_solve_batched_
     table = autotune.load_table()
     nb = autotune.tile_sizes(ns, table)
     torch.cuda.synchronize()
     log("batched inputs ready in %.1f s (%d systems, sum n = %d)" % (time.time() - t0, len(ns), int(ns.sum())))
-    ws = torch.empty(tc.batched_workspace_bytes(ns, nb), dtype=torch.uint8, device=dev)
+    wsb = tc.batched_f32_workspace_bytes(ns, nb, nrhs) if fp32 else tc.batched_workspace_bytes(ns, nb)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     As = [torch.empty_like(A0) for _ in range(K)]
     Bs = [torch.empty_like(B0) for _ in range(K)]
     Aw, Bw = torch.empty_like(A0), torch.empty_like(B0)
     for w in range(Wm):
         Aw.copy_(A0)
         Bw.copy_(B0)
-        info = tc.factor_solve_batched_(Aw, a_off, lda, Bw, b_off, ns, nb, nrhs, ws=ws)
+        info = run(Aw, a_off, lda, Bw, b_off, ns, nb, nrhs, ws=ws)
         if np.any(info != 0):
             raise RuntimeError("batched factorization failed")
         log("warmup %d done" % (w + 1))
@@ -135,8 +143,7 @@ def run_batched(args):
     kernel_ms = []
     t_start = time.perf_counter()
     for s_ in range(K):
-        info, ms = tc.factor_solve_batched_(As[s_], a_off, lda, Bs[s_], b_off, ns, nb, nrhs, ws=ws,
-                                            want_kernel_ms=True)
+        info, ms = run(As[s_], a_off, lda, Bs[s_], b_off, ns, nb, nrhs, ws=ws, want_kernel_ms=True)
         kernel_ms.append(ms)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
@@ -148,19 +155,20 @@ def run_batched(args):
     flops = float(np.sum(n64 ** 3) / 3.0)
     # algorithmic bytes: read the lower triangle of A, write L, read L in each
     # of the two substitutions, read and write the right-hand sides twice
-    tri = float(np.sum(n64 * (n64 + 1) / 2.0)) * 8.0
-    bytes_alg = 4.0 * tri + 4.0 * float(np.sum(n64)) * nrhs * 8.0
+    elem = 4.0 if fp32 else 8.0
+    tri = float(np.sum(n64 * (n64 + 1) / 2.0)) * elem
+    bytes_alg = 4.0 * tri + 4.0 * float(np.sum(n64)) * nrhs * elem
     achieved = bytes_alg / (kmean * 1e-3) / 1e9
 
     # checks on a sample of systems, and the oracle timed on the host on it
     import oracle
     rng = np.random.default_rng(0)
     sample = np.sort(rng.choice(len(ns), size=min(64, len(ns)), replace=False))
-    Ah0 = A0.cpu().numpy()
-    Bh0 = B0.cpu().numpy()
-    Ah = As[K - 1].cpu().numpy()
-    Bh = Bs[K - 1].cpu().numpy()
-    worst_l, worst_x = 0.0, 0.0
+    Ah0 = A0.cpu().numpy().astype(np.float64)
+    Bh0 = B0.cpu().numpy().astype(np.float64)
+    Ah = As[K - 1].cpu().numpy().astype(np.float64)
+    Bh = Bs[K - 1].cpu().numpy().astype(np.float64)
+    worst_l, worst_x, worst_beta = 0.0, 0.0, 0.0
     tcpu = 0.0
     for i in sample:
         n_, o, l, ob = int(ns[i]), int(a_off[i]), int(lda[i]), int(b_off[i])
@@ -174,9 +182,14 @@ def run_batched(args):
         tcpu += time.perf_counter() - tc0
         worst_l = max(worst_l, oracle.factor_error(Lg, F))
         worst_x = max(worst_x, float(np.max(np.abs(Xg - Xo)) / np.max(np.abs(Xo))))
+        if fp32:
+            S_ = oracle.sym_from_lower(Ai)
+            worst_beta = max(worst_beta, float(np.linalg.norm(S_ - Lg @ Lg.T) /
+                                               (n_ * 2.0 ** -23 * np.linalg.norm(S_))))
     sample_flops = float(np.sum(n64[sample] ** 3) / 3.0)
     out = {
-        "metric": "Cholesky TFLOP/s (sum of n_i^3/3), batched factor + 4-RHS solve in one launch",
+        "metric": "Cholesky TFLOP/s (sum of n_i^3/3), batched factor + 4-RHS solve in one launch"
+                  + (", FP32 storage" if fp32 else ""),
         "value": round(flops / (ms_per_step * 1e-3) / 1e12, 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -186,10 +199,12 @@ def run_batched(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": "batched fp64 factor + solve, %d systems, n_i ~ U{16..512} (seed %d), "
-                               "A_i = B_i B_i^T/n_i + I, 4 RHS, one persistent launch" % (len(ns), seed),
+        "config": {"workload": "batched %s factor + solve, %d systems, n_i ~ U{16..512} (seed %d), "
+                               "A_i = B_i B_i^T/n_i + I, 4 RHS, one persistent launch"
+                               % ("fp32 (fp32 updates, fp64 diagonal tiles and solves)" if fp32 else "fp64",
+                                  len(ns), seed),
                    "count": int(len(ns)), "seed": seed, "nrhs": nrhs,
                    "tile_table": "tuned" if table else "one tile per system",
                    "systems_split_into_tiles": int(np.sum(nb < ns))},
@@ -201,6 +216,7 @@ def run_batched(args):
         "kernel_ms": [round(x, 3) for x in kernel_ms],
         "e_L_max_sampled": worst_l,
         "e_x_max_sampled": worst_x,
+        "beta32_max_sampled": worst_beta if fp32 else None,
         "cpu_baseline": {"value": round(sample_flops / tcpu / 1e12, 6), "unit": "TFLOP/s",
                          "cores": oracle.num_threads(), "kind": "oracle",
                          "sample": "oracle FP64 factor + solve of %d sampled systems of the same batch "
@@ -471,6 +487,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="factor workload: skip the mixed-precision comparison appended to the line")
     ap.add_argument("--count", type=int, default=4096, help="batched: number of systems")
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64", help="batched: storage precision")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -156,6 +156,26 @@ TCHOL_API int32_t tchol_factor_solve_batched(double *A, const int64_t *a_off, co
                                              int32_t nrhs, int32_t batch, int32_t *info, void *ws,
                                              int64_t ws_bytes, void *stream, const tchol_opts *opts);
 
+/* Batched factor + solve of `batch` independent SPD systems stored in FP32,
+   in ONE launch of the persistent kernel (the DAG and priority as for
+   tchol_factor_solve_batched).  Precision: the trailing SYRK / GEMM updates
+   run on FP32 matrix cores on the FP32 storage; each system's diagonal tiles
+   are kept in FP64 in the workspace (their SYRK updates added in FP64, POTRF
+   in FP64); TRSM and the solves compute in FP64 against them (the
+   right-hand sides are staged in FP64); results are rounded to FP32 when
+   written back.  No refinement.
+   Arguments as for tchol_factor_solve_batched with FP32 A and B (offsets in
+   floats), except: every non-empty system needs lda[s] a multiple of 4 and
+   lda[s] >= n[s] + 3 (the FP32 tile loads move four rows per 16-byte lane and
+   may read three rows past the order), a_off[s] a multiple of 4 and A 16-byte
+   aligned (else -3, -2, -1).  Workspace: tchol_batched_f32_workspace_bytes
+   (n, nb, batch, nrhs) bytes (about sum_s T_s nb_s^2 + n_s nrhs doubles). */
+TCHOL_API int64_t tchol_batched_f32_workspace_bytes(const int32_t *n, const int32_t *nb, int32_t batch, int32_t nrhs);
+TCHOL_API int32_t tchol_factor_solve_batched_f32(float *A, const int64_t *a_off, const int32_t *lda, float *B,
+                                                 const int64_t *b_off, const int32_t *n, const int32_t *nb,
+                                                 int32_t nrhs, int32_t batch, int32_t *info, void *ws,
+                                                 int64_t ws_bytes, void *stream, const tchol_opts *opts);
+
 /* Mixed-precision solve with iterative refinement: X = A^{-1} B to FP64
    accuracy from a factorization whose trailing updates run in low precision.
    A (n x n, column-major, ld n, lower triangle read, not modified) is first

@@ -86,6 +86,11 @@ def load() -> ctypes.CDLL:
                                              P32, P32, P32, P32]
     lib.tchol_batched_workspace_bytes.restype = i64
     lib.tchol_batched_workspace_bytes.argtypes = [P32, P32, i32]
+    lib.tchol_batched_f32_workspace_bytes.restype = i64
+    lib.tchol_batched_f32_workspace_bytes.argtypes = [P32, P32, i32, i32]
+    lib.tchol_factor_solve_batched_f32.restype = i32
+    lib.tchol_factor_solve_batched_f32.argtypes = [vp, P64, P32, vp, P64, P32, P32, i32, i32, P32, vp, i64, vp,
+                                                   ctypes.POINTER(Opts)]
     lib.tchol_factor_solve_batched.restype = i32
     lib.tchol_factor_solve_batched.argtypes = [vp, P64, P32, vp, P64, P32, P32, i32, i32, P32, vp, i64, vp,
                                                ctypes.POINTER(Opts)]
@@ -472,3 +477,51 @@ def cholesky(A, nb: int):
     the symmetric adjoint computed by tchol_backward."""
     _torch()
     return _chol_function().apply(A, nb)
+
+
+def batched_f32_workspace_bytes(n, nb, nrhs: int) -> int:
+    n32, nb32 = _i32(n), _i32(nb)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    r = load().tchol_batched_f32_workspace_bytes(n32.ctypes.data_as(P32), nb32.ctypes.data_as(P32), len(n32), nrhs)
+    if r < 0:
+        raise TcholError(int(r), "tchol_batched_f32_workspace_bytes")
+    return int(r)
+
+
+def factor_solve_batched_f32_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: int = POLICY_RANK,
+                              seed: int = 0, wait_limit_us: int = 0, ws=None, want_kernel_ms: bool = False,
+                              trace=None, check: bool = True):
+    """Factor and solve many FP32 systems in one launch, in place (FP32 updates,
+    FP64 diagonal tiles and solves; see tchol_factor_solve_batched_f32).  A, B:
+    CUDA float32 1-D tensors; lda[s] a multiple of 4 and >= n[s] + 3, a_off[s]
+    a multiple of 4 (spd_inputs packs them so with align=4, pad=3).  Returns
+    the per-system info (numpy int32), or (info, kernel_ms)."""
+    torch = _torch()
+    if A.dtype != torch.float32 or B.dtype != torch.float32 or not A.is_contiguous() or not B.is_contiguous():
+        raise ValueError("A and B must be contiguous float32 tensors")
+    a_off, b_off, lda, n, nb = _i64(a_off), _i64(b_off), _i32(lda), _i32(n), _i32(nb)
+    batch = len(n)
+    if not (len(a_off) == len(b_off) == len(lda) == len(nb) == batch):
+        raise ValueError("per-system arrays must have the same length")
+    if batch and (int(np.max(a_off + lda.astype(np.int64) * n)) > A.numel() or
+                  (nrhs and int(np.max(b_off + n.astype(np.int64) * nrhs)) > B.numel())):
+        raise ValueError("a system extends past the end of A or B")
+    info = np.zeros(max(batch, 1), dtype=np.int32)
+    lib = load()
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    with torch.cuda.device(A.device):
+        need = batched_f32_workspace_bytes(n, nb, nrhs) if batch else 256
+        if ws is None or ws.numel() < need:
+            ws = _workspace(torch, need, A.device)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        rc = lib.tchol_factor_solve_batched_f32(ctypes.c_void_p(A.data_ptr()), a_off.ctypes.data_as(P64),
+                                                lda.ctypes.data_as(P32), ctypes.c_void_p(B.data_ptr()),
+                                                b_off.ctypes.data_as(P64), n.ctypes.data_as(P32),
+                                                nb.ctypes.data_as(P32), int(nrhs), batch, info.ctypes.data_as(P32),
+                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                                _stream_ptr(torch, A.device), ctypes.byref(o))
+    if rc != 0 and check:
+        raise TcholError(rc, "tchol_factor_solve_batched_f32")
+    info = info[:batch]
+    return (info, ms.value) if want_kernel_ms else info

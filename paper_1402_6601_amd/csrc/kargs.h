@@ -34,9 +34,9 @@ typedef struct KArgs {
   int32_t batched;      /* 1: a failing system stops only its own work             */
   int32_t nsys;
   double *D;            /* mixed precision: FP64 diagonal tiles, nb x nb each, T of them */
-  int32_t mixed;        /* 0: FP64; 1: mixed-precision factor, 2: its solves (A is the
-                           FP32 working copy); 3: the adjoint of the factorization
-                           (A = L, B = Lbar, D = partial-product slots)              */
+  int32_t mixed;        /* 0: FP64; 1: mixed-precision factor, 2: its solves, 4: both
+                           (A is the FP32 working copy); 3: the adjoint of the
+                           factorization (A = L, B = Lbar, D = partial-product slots) */
   int32_t pad1;
   double *Dinv;         /* mixed precision: L_kk^{-1}, nb x nb each (FP64)         */
   double *DinvT;        /* mixed precision: L_kk^{-T}, nb x nb each (FP64)         */
@@ -49,6 +49,7 @@ typedef struct KArgs {
 } KArgs;
 
 #define DESC_WORDS 8   /* kind, i, j, k, parts, succ_begin, succ_end, system */
-#define SYS_WORDS 8    /* a_off, b_off, n, nb, ld, 0, 0, 0                    */
+#define SYS_WORDS 8    /* a_off, b_off, n, nb, ld, d_off (mixed precision: offset of the
+                          system's FP64 diagonal tiles and inverses), 0, 0     */
 
 #endif

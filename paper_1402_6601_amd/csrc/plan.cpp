@@ -241,7 +241,7 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   const int32_t T = p.systems[p.sys[t]].T;
   int32_t kind = p.kind[t], step = p.tk[t];
   if (kind == TK_BTRSV || kind == TK_BGEMV) step = T + (T - 1 - p.tk[t]);
-  if (p.op == TCHOL_OP_BATCHED && kind >= TK_FTRSV) step += T;  // a system's solve after its factor
+  if (p.op == TCHOL_OP_BATCHED && kind >= TK_FTRSV && kind <= TK_BGEMV) step += T;  // a system's solve after its factor
   if (kind >= TK_GREV && kind != TK_TRTRI) step = T - 1 - p.tk[t];  // the adjoint runs its steps downwards
   int32_t kord = kind;
   if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV

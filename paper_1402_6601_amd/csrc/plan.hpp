@@ -25,6 +25,7 @@ struct System {
   int64_t a_off = 0, b_off = 0;  // A_s at A + a_off (column-major, ld), B_s at B + b_off (ld n)
   int64_t n = 0, nb = 0, ld = 0;
   int32_t T = 0;                 // tiles per side
+  int64_t d_off = 0;             // mixed precision: offset (doubles) of its FP64 diagonal tiles
 };
 
 struct Plan {

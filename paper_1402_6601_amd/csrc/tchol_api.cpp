@@ -27,6 +27,10 @@ extern "C" hipError_t tchol_refine_residual(const double* A, int64_t lda, int64_
 extern "C" hipError_t tchol_refine_colmax(const double* V, int64_t ldv, int64_t n, int ncols, double* out,
                                           hipStream_t s);
 extern "C" hipError_t tchol_refine_axpy(double* X, const double* D, int64_t count, hipStream_t s);
+extern "C" hipError_t tchol_b32_prepare(const int64_t* desc, int32_t batch, const float* A, const float* B, double* D,
+                                        double* Bd, int nrhs, hipStream_t s);
+extern "C" hipError_t tchol_b32_finish(const int64_t* desc, int32_t batch, float* A, float* B, const double* D,
+                                       const double* Bd, int nrhs, hipStream_t s);
 extern "C" hipError_t tchol_refine_diag(const double* A, int64_t lda, int64_t n, int64_t nb, double* D,
                                         hipStream_t s);
 
@@ -122,6 +126,7 @@ std::shared_ptr<Image> make_image(const Plan& p, bool pin, const std::vector<tch
     r[2] = sy.n;
     r[3] = sy.nb;
     r[4] = sy.ld;
+    r[5] = sy.d_off;
   }
   return img;
 }
@@ -371,6 +376,32 @@ BackLayout back_layout(int64_t n, int64_t nb, const Plan& p) {
   B.sched = align_up(B.slots + 8 * (T * (T - 1) / 2) * nb * nb);
   B.end = B.sched + layout_of(p).end;
   return B;
+}
+
+// Batched FP32: workspace regions (byte offsets): the per-system descriptor
+// table, the FP64 diagonal tiles (d_off per system) and the compact FP64
+// right-hand sides.
+struct B32Layout {
+  int64_t desc = 0, d = 0, bd = 0, sched = 0, end = 0;
+};
+
+// Fills d_off and the compact right-hand-side offsets (b_off) of the systems.
+B32Layout b32_layout(std::vector<tchol::System>* sys, int64_t nrhs, const Plan& p) {
+  int64_t dtot = 0, btot = 0;
+  for (auto& sy : *sys) {
+    const int64_t T = sy.n == 0 ? 0 : (sy.n + sy.nb - 1) / sy.nb;
+    sy.d_off = dtot;
+    dtot += T * sy.nb * sy.nb;
+    sy.b_off = btot;
+    btot += sy.n * nrhs;
+  }
+  B32Layout L;
+  L.desc = 0;
+  L.d = align_up(L.desc + 8 * 8 * (int64_t)sys->size());
+  L.bd = align_up(L.d + 8 * dtot);
+  L.sched = align_up(L.bd + 8 * btot);
+  L.end = L.sched + layout_of(p).end;
+  return L;
 }
 
 // Mixed-precision solve: workspace regions (byte offsets).  The FP32 working
@@ -639,6 +670,85 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
     if (rc != 0) return rc;
     if (tchol_refine_axpy(B, R, n * nrhs, s) != hipSuccess) return TCHOL_E_HIP;
   }
+}
+
+int64_t tchol_batched_f32_workspace_bytes(const int32_t* n, const int32_t* nb, int32_t batch, int32_t nrhs) {
+  std::vector<tchol::System> systems;
+  if (batch < 0) return -3;
+  if (batch > 0 && !n) return -1;
+  if (batch > 0 && !nb) return -2;
+  if (nrhs < 0) return -4;
+  const int32_t rc = batched_systems(nullptr, nullptr, nullptr, n, nb, batch, &systems);
+  if (rc == -6) return -1;
+  if (rc == -7) return -2;
+  if (rc != 0) return rc;
+  auto plan = tchol::get_batched_plan(systems, TCHOL_POLICY_RANK, 0);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  return b32_layout(&systems, nrhs, *plan).end;
+}
+
+int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int32_t* lda, float* B,
+                                       const int64_t* b_off, const int32_t* n, const int32_t* nb, int32_t nrhs,
+                                       int32_t batch, int32_t* info, void* ws, int64_t ws_bytes, void* stream_v,
+                                       const tchol_opts* opts) {
+  if (nrhs < 0) return -8;
+  if (batch < 0) return -9;
+  if (batch == 0) return 0;
+  if (!a_off) return -2;
+  if (!lda) return -3;
+  if (!b_off) return -5;
+  if (!info) return -10;
+  std::vector<tchol::System> systems;
+  const int32_t rc0 = batched_systems(a_off, lda, b_off, n, nb, batch, &systems);
+  if (rc0 != 0) return rc0;
+  bool any = false;
+  for (auto& sy : systems) {
+    if (sy.n == 0) continue;
+    any = true;
+    // the FP32 tile products move four rows per 16-byte lane: ld a multiple
+    // of 4, three readable rows after the order, 16-byte aligned systems
+    if (sy.ld % 4 != 0 || sy.ld < sy.n + 3) return -3;
+    if (sy.a_off % 4 != 0) return -2;
+  }
+  for (int32_t s = 0; s < batch; ++s) info[s] = 0;
+  if (!any) return 0;
+  if (!A || reinterpret_cast<uintptr_t>(A) % 16 != 0) return -1;
+  if (nrhs > 0 && !B) return -4;
+  if (!ws) return -11;
+  if (ws_bytes <= 0) return -12;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -11;
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
+  auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  std::vector<int64_t> desc(8 * (size_t)batch, 0);
+  for (int32_t s = 0; s < batch; ++s) {
+    desc[8 * s + 0] = a_off[s];
+    desc[8 * s + 1] = lda[s];
+    desc[8 * s + 2] = n[s];
+    desc[8 * s + 3] = nb[s];
+    desc[8 * s + 5] = b_off[s];
+  }
+  const B32Layout L = b32_layout(&systems, nrhs, *plan);  // d_off, compact b_off
+  if (ws_bytes < L.end) return -12;
+  for (int32_t s = 0; s < batch; ++s) {
+    desc[8 * s + 4] = systems[s].d_off;
+    desc[8 * s + 6] = systems[s].b_off;
+  }
+  auto img = make_image(*plan, false, &systems);
+  char* w = static_cast<char*>(ws);
+  int64_t* ddesc = reinterpret_cast<int64_t*>(w + L.desc);
+  double* D = reinterpret_cast<double*>(w + L.d);
+  double* Bd = reinterpret_cast<double*>(w + L.bd);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream_v);
+  if (hipMemcpyAsync(ddesc, desc.data(), 8 * desc.size(), hipMemcpyHostToDevice, s) != hipSuccess) return TCHOL_E_HIP;
+  if (tchol_b32_prepare(ddesc, batch, A, B, D, Bd, nrhs, s) != hipSuccess) return TCHOL_E_HIP;
+  const int32_t rc = execute(*plan, *img, reinterpret_cast<double*>(A), Bd, nrhs, true, true, w + L.sched,
+                             ws_bytes - L.sched, stream_v, o, 11, info, D, 4, nullptr, nullptr, 0, D, D, Bd);
+  if (rc != 0) return rc;
+  if (tchol_b32_finish(ddesc, batch, A, B, D, Bd, nrhs, s) != hipSuccess) return TCHOL_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TCHOL_E_HIP;
+  return 0;
 }
 
 const char* tchol_strerror(int32_t code) {

@@ -1,0 +1,66 @@
+// Data movement around the batched FP32 launch.  The systems live in FP32
+// (A_s with leading dimension lda_s, B_s with leading dimension n_s); the
+// persistent kernel keeps each system's diagonal tiles in FP64 (their
+// SYRK updates, POTRF, inverses) and runs the solves in FP64 on a compact
+// FP64 copy of the right-hand sides.  Before the launch: diagonal tiles
+// A_s,kk -> D (lower triangles) and B -> Bd.  After it: the factored
+// diagonal tiles D -> A (lower, rounded) and the solutions Bd -> B.
+//
+// desc: per system, 8 words: a_off, lda, n, nb, d_off, b_off, bd_off, 0
+// (a_off and b_off in floats from A and B, d_off and bd_off in doubles
+// from D and Bd; D holds T_s tiles of nb_s x nb_s per system).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BT 256
+
+__global__ void b32_prepare(const int64_t* __restrict__ desc, int32_t batch, const float* __restrict__ A,
+                            const float* __restrict__ B, double* __restrict__ D, double* __restrict__ Bd, int nrhs) {
+  for (int32_t sy = blockIdx.y; sy < batch; sy += gridDim.y) {
+  const int64_t* d = desc + 8 * (int64_t)sy;
+  const int64_t a_off = d[0], lda = d[1], n = d[2], nb = d[3], d_off = d[4], b_off = d[5], bd_off = d[6];
+  const int64_t T = (n + nb - 1) / nb;
+  // diagonal tiles: T tiles of up to nb x nb
+  const int64_t per = nb * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < T * per; idx += (int64_t)gridDim.x * BT) {
+    const int64_t k = idx / per, e = idx - k * per, c = e / nb, r = e - c * nb;
+    const int64_t m = n - k * nb < nb ? n - k * nb : nb;
+    if (c < m && r < m && r >= c) D[d_off + k * per + c * nb + r] = (double)A[a_off + (k * nb + c) * lda + k * nb + r];
+  }
+  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < n * nrhs; idx += (int64_t)gridDim.x * BT)
+    Bd[bd_off + idx] = (double)B[b_off + idx];
+  }
+}
+
+__global__ void b32_finish(const int64_t* __restrict__ desc, int32_t batch, float* __restrict__ A,
+                           float* __restrict__ B, const double* __restrict__ D, const double* __restrict__ Bd, int nrhs) {
+  for (int32_t sy = blockIdx.y; sy < batch; sy += gridDim.y) {
+  const int64_t* d = desc + 8 * (int64_t)sy;
+  const int64_t a_off = d[0], lda = d[1], n = d[2], nb = d[3], d_off = d[4], b_off = d[5], bd_off = d[6];
+  const int64_t T = (n + nb - 1) / nb;
+  const int64_t per = nb * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < T * per; idx += (int64_t)gridDim.x * BT) {
+    const int64_t k = idx / per, e = idx - k * per, c = e / nb, r = e - c * nb;
+    const int64_t m = n - k * nb < nb ? n - k * nb : nb;
+    if (c < m && r < m && r >= c) A[a_off + (k * nb + c) * lda + k * nb + r] = (float)D[d_off + k * per + c * nb + r];
+  }
+  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < n * nrhs; idx += (int64_t)gridDim.x * BT)
+    B[b_off + idx] = (float)Bd[bd_off + idx];
+  }
+}
+
+extern "C" hipError_t tchol_b32_prepare(const int64_t* desc, int32_t batch, const float* A, const float* B, double* D,
+                                        double* Bd, int nrhs, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  const unsigned gy = (unsigned)(batch < 32768 ? batch : 32768);
+  hipLaunchKernelGGL(b32_prepare, dim3(16, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t tchol_b32_finish(const int64_t* desc, int32_t batch, float* A, float* B, const double* D,
+                                       const double* Bd, int nrhs, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  const unsigned gy = (unsigned)(batch < 32768 ? batch : 32768);
+  hipLaunchKernelGGL(b32_finish, dim3(16, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
+  return hipGetLastError();
+}

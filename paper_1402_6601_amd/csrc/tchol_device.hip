@@ -1362,6 +1362,9 @@ __device__ __forceinline__ void raise_error(const KArgs& a, int code) {
 // every panel the updates stream is 16-byte transferable; SEG = 32 serves
 // every other case.  One transfer width per kernel instance keeps the
 // update loops free of per-item branches.
+// MODE 4: the batched FP32 launch: the mixed-precision factor kinds and
+// the solve kinds with substitution against the FP64 diagonal tiles (one
+// solve of a few right-hand sides does not repay explicit inverses).
 // MODE 0: FP64 factorization and solve.  MODE 1 / 2: the mixed-precision
 // factorization / its solves: the matrix is the FP32 working copy (a.A points
 // to it), factored with FP32 MFMA updates and FP64 diagonal tiles kept in
@@ -1370,8 +1373,9 @@ __device__ __forceinline__ void raise_error(const KArgs& a, int code) {
 // small) and is always a 16-byte one.
 template <int SEG, int MODE>
 __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
-  constexpr bool MIXED = MODE == 1 || MODE == 2;
-  constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1, SOLVE_KINDS = MODE == 0 || MODE == 2;
+  constexpr bool MIXED = MODE == 1 || MODE == 2 || MODE == 4;
+  constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1 || MODE == 4;
+  constexpr bool SOLVE_KINDS = MODE == 0 || MODE == 2 || MODE == 4;
   constexpr bool ADJOINT_KINDS = MODE == 3;
   __shared__ double lds[LDS_DOUBLES];
   __shared__ int s_claim[3];
@@ -1414,6 +1418,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     E* const Abase = reinterpret_cast<E*>(a.A) + sr[0];
     double* const Bbase = a.B + sr[1];
     const int64_t sn = sr[2], nb = sr[3], ld = sr[4], ldb = sn;
+    // mixed precision: the system's FP64 diagonal tiles and their inverses
+    double* const Dsys = a.D + (MIXED ? sr[5] : 0);
+    double* const DinvSys = a.Dinv + (MIXED ? sr[5] : 0);
+    double* const DinvTSys = a.DinvT + (MIXED ? sr[5] : 0);
     auto tsz = [&](int t) __attribute__((always_inline)) { return (int)tile_size(sn, nb, t); };
     // in a batched launch a system whose factorization failed only passes
     // its remaining tasks on, so that the DAG drains
@@ -1430,7 +1438,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         E* Akk = Abase + (tk * nb) * ld + tk * nb;
         int info;
         if constexpr (MIXED)
-          info = uniform_i(potrf_tile_mixed(a.D + (int64_t)tk * nb * nb, nb, tsz(tk), lds));
+          info = uniform_i(potrf_tile_mixed(Dsys + (int64_t)tk * nb * nb, nb, tsz(tk), lds));
         else
           info = uniform_i(potrf_tile<SEG>(Akk, ld, tsz(tk), lds));
         if (info != 0 && tid == 0) {
@@ -1452,7 +1460,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         const int r0 = part * a.trsm_rows;
         const int S = imin(a.trsm_rows, tsz(ti) - r0);
         if constexpr (MIXED)
-          trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, a.D + (int64_t)tk * nb * nb, nb, S, tsz(tk), lds);
+          trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dsys + (int64_t)tk * nb * nb, nb, S, tsz(tk), lds);
         else
           trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Abase + (tk * nb) * ld + tk * nb, ld, S, tsz(tk),
                      lds);
@@ -1488,7 +1496,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
             break;
           }
           if (kind == TK_SYRK)
-            gemm_nt_f32_d(a.D + (int64_t)ti * nb * nb + (int64_t)(sj * a.gemm_n) * nb + si * a.gemm_m, nb, Ap, Bp,
+            gemm_nt_f32_d(Dsys + (int64_t)ti * nb * nb + (int64_t)(sj * a.gemm_n) * nb + si * a.gemm_m, nb, Ap, Bp,
                           ld, M, N, tsz(tk), si == sj, lds);
           else
             gemm_nt_f32(C, Ap, Bp, ld, M, N, tsz(tk), false, lds);
@@ -1506,6 +1514,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
       case TK_BTRSV:
         if constexpr (!SOLVE_KINDS) {
           ok = 0;
+        } else if constexpr (MODE == 4) {
+          // batched FP32 systems: substitution against the FP64 diagonal tile, in place
+          tile_solve(Dsys + (int64_t)tk * nb * nb, nb, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs, kind == TK_BTRSV,
+                     lds);
         } else if constexpr (MIXED) {
           // explicit FP64 inverses, 128-row strips: forward y_k := L_kk^{-1} b_k into
           // the scratch vector, backward x_k := L_kk^{-T} y_k back into B
@@ -1513,10 +1525,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           const int rows = imin(a.gemv_rows, tsz(tk) - r0);
           double* const Sbase = a.S + sr[1];
           if (kind == TK_FTRSV)
-            fgemv<double, true>(a.Dinv + (int64_t)tk * nb * nb + r0, nb, Sbase + tk * nb + r0, Bbase + tk * nb, ldb,
+            fgemv<double, true>(DinvSys + (int64_t)tk * nb * nb + r0, nb, Sbase + tk * nb + r0, Bbase + tk * nb, ldb,
                                 rows, tsz(tk), (int)a.nrhs, lds);
           else
-            fgemv<double, true>(a.DinvT + (int64_t)tk * nb * nb + r0, nb, Bbase + tk * nb + r0, Sbase + tk * nb, ldb,
+            fgemv<double, true>(DinvTSys + (int64_t)tk * nb * nb + r0, nb, Bbase + tk * nb + r0, Sbase + tk * nb, ldb,
                                 rows, tsz(tk), (int)a.nrhs, lds);
         } else {
           tile_solve(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
@@ -1531,7 +1543,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         const int r0 = part * a.gemv_rows;
         const int rows = imin(a.gemv_rows, tsz(ti) - r0);
         // the mixed-precision solve keeps y in the scratch vector
-        const double* Yk = MIXED ? a.S + sr[1] + tk * nb : Bbase + tk * nb;
+        const double* Yk = (MIXED && MODE != 4) ? a.S + sr[1] + tk * nb : Bbase + tk * nb;
         fgemv(Abase + (tk * nb) * ld + ti * nb + r0, ld, Bbase + ti * nb + r0, Yk, ldb, rows, tsz(tk), (int)a.nrhs,
               lds);
         break;
@@ -1543,7 +1555,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         }
         const int c0 = part * a.gemv_rows;
         const int cols = imin(a.gemv_rows, tsz(ti) - c0);
-        double* Yi = MIXED ? a.S + sr[1] + ti * nb + c0 : Bbase + ti * nb + c0;
+        double* Yi = (MIXED && MODE != 4) ? a.S + sr[1] + ti * nb + c0 : Bbase + ti * nb + c0;
         bgemv(Abase + (ti * nb + c0) * ld + tk * nb, ld, Yi, Bbase + tk * nb, ldb, cols, tsz(tk),
               (int)a.nrhs, lds);
         break;
@@ -1557,15 +1569,15 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           const int mpad = (tsz(tk) + 15) & ~15;
           const int r0 = part * a.trsm_rows;
           const int S = imin(a.trsm_rows, mpad - r0);
-          double* X = a.DinvT + (int64_t)tk * nb * nb + r0;
+          double* X = DinvTSys + (int64_t)tk * nb * nb + r0;
           for (int idx = tid; idx < S * mpad; idx += NT) {
             const int c = idx / S, r = idx - c * S;
             st_dev(X + (int64_t)c * nb + r, (r0 + r == c) ? 1.0 : 0.0);
           }
           wait_vmcnt<0>();
           __syncthreads();
-          trsm_strip<double, 2>(X, nb, a.D + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,
-                                a.Dinv + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
+          trsm_strip<double, 2>(X, nb, Dsys + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,
+                                DinvSys + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
         }
         break;
       }
@@ -1689,7 +1701,9 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
     e = hipEventRecord(ev0, stream);
     if (e != hipSuccess) return e;
   }
-  if (a->mixed == 3)
+  if (a->mixed == 4)
+    hipLaunchKernelGGL((tchol_persistent<128, 4>), dim3(grid), dim3(NT), 0, stream, *a);
+  else if (a->mixed == 3)
     hipLaunchKernelGGL((tchol_persistent<128, 3>), dim3(grid), dim3(NT), 0, stream, *a);
   else if (a->mixed == 1)
     hipLaunchKernelGGL((tchol_persistent<128, 1>), dim3(grid), dim3(NT), 0, stream, *a);
@@ -1729,10 +1743,13 @@ extern "C" hipError_t tchol_dev_max_grid(int device, int* grid) {
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occs, tchol_persistent<128, 2>, NT, 0);
   if (e != hipSuccess) return e;
-  int occa = 0;
+  int occa = 0, occb = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occa, tchol_persistent<128, 3>, NT, 0);
   if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occb, tchol_persistent<128, 4>, NT, 0);
+  if (e != hipSuccess) return e;
   occ = occ < occa ? occ : occa;
+  occ = occ < occb ? occ : occb;
   occ = occ < occ32 ? occ : occ32;
   occ = occ < occm ? occ : occm;
   occ = occ < occs ? occ : occs;

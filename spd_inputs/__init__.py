@@ -154,11 +154,12 @@ def batched_systems(count: int, seed: int, nrhs: int, shift: float = 1.0, lo: in
     return ns, As, bs
 
 
-def _layout(ns, nrhs: int, align: int):
-    """Column-major packing: lda_i = n_i rounded up to ``align`` (>= 1), every
-    A_i starting at a multiple of ``align`` elements; B_i packed with ld n_i."""
+def _layout(ns, nrhs: int, align: int, pad: int = 0):
+    """Column-major packing: lda_i = n_i + pad rounded up to ``align`` (>= 1),
+    every A_i starting at a multiple of ``align`` elements; B_i packed with
+    ld n_i.  (The FP32 batched launch takes align = 4, pad = 3.)"""
     ns = np.asarray(ns, dtype=np.int64)
-    lda = np.maximum(1, (ns + align - 1) // align * align)
+    lda = np.maximum(1, (ns + pad + align - 1) // align * align)
     sizes_a = lda * ns
     a_off = np.concatenate([[0], np.cumsum(sizes_a)[:-1]]) if len(ns) else np.zeros(0, np.int64)
     b_off = np.concatenate([[0], np.cumsum(ns * nrhs)[:-1]]) if len(ns) else np.zeros(0, np.int64)
@@ -166,14 +167,14 @@ def _layout(ns, nrhs: int, align: int):
         int((ns * nrhs).sum())
 
 
-def pack_batched(As, bs, align: int = 2):
-    """Pack host systems into flat column-major arrays.  Returns
+def pack_batched(As, bs, align: int = 2, pad: int = 0, dtype=np.float64):
+    """Pack host systems into flat column-major arrays of ``dtype``.  Returns
     (A_flat, a_off, lda, B_flat, b_off) as numpy arrays."""
     ns = [a.shape[0] for a in As]
     nrhs = bs[0].shape[1] if bs else 0
-    lda, a_off, b_off, na, nbt = _layout(ns, nrhs, align)
-    Af = np.zeros(max(na, 1))
-    Bf = np.zeros(max(nbt, 1))
+    lda, a_off, b_off, na, nbt = _layout(ns, nrhs, align, pad)
+    Af = np.zeros(max(na, 1), dtype=dtype)
+    Bf = np.zeros(max(nbt, 1), dtype=dtype)
     for A, b, o, l, ob in zip(As, bs, a_off, lda, b_off):
         n = A.shape[0]
         # column c of A (column-major) is row c of the symmetric A
@@ -183,17 +184,19 @@ def pack_batched(As, bs, align: int = 2):
 
 
 def batched_systems_device(count: int, seed: int, nrhs: int, shift: float = 1.0, lo: int = 16, hi: int = 512,
-                           align: int = 2, device="cuda", sizes=None):
+                           align: int = 2, device="cuda", sizes=None, pad: int = 0, fp32: bool = False):
     """The batched recipe with the products formed on the device (input
-    generation only), packed as :func:`pack_batched` does.  Returns
-    (ns, A_flat, a_off, lda, B_flat, b_off) with A_flat, B_flat device tensors."""
+    generation only, in FP64), packed as :func:`pack_batched` does (rounded to
+    FP32 with ``fp32``).  Returns (ns, A_flat, a_off, lda, B_flat, b_off) with
+    A_flat, B_flat device tensors."""
     import torch
 
     rng = np.random.default_rng(seed)
     ns = np.asarray(sizes, dtype=np.int64) if sizes is not None else rng.integers(lo, hi + 1, size=count)
-    lda, a_off, b_off, na, nbt = _layout(ns, nrhs, align)
-    Af = torch.zeros(max(na, 1), dtype=torch.float64, device=device)
-    Bf = torch.zeros(max(nbt, 1), dtype=torch.float64, device=device)
+    lda, a_off, b_off, na, nbt = _layout(ns, nrhs, align, pad)
+    dt = torch.float32 if fp32 else torch.float64
+    Af = torch.zeros(max(na, 1), dtype=dt, device=device)
+    Bf = torch.zeros(max(nbt, 1), dtype=dt, device=device)
     for n, o, l, ob in zip(ns, a_off, lda, b_off):
         n, o, l, ob = int(n), int(o), int(l), int(ob)
         B = torch.from_numpy(rng.uniform(-1.0, 1.0, (n, n))).to(device)
