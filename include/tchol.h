@@ -126,6 +126,22 @@ TCHOL_API int32_t tchol_backward(const double *L, int64_t n, int64_t nb, double 
 TCHOL_API int32_t tchol_backward_ex(const double *L, int64_t n, int64_t nb, double *Lbar, void *ws,
                                     int64_t ws_bytes, void *stream, const tchol_opts *opts);
 
+/* Factor A = L L^T and solve (L L^T) X = B in ONE launch: the factorization
+   DAG and the solve DAG merged as one DAG (the solve reads each tile of L as
+   soon as it is final: POTRF(k) before FTRSV(k), TRSM(i, k) before
+   FGEMV(i, k)), so the forward substitution runs while the factorization
+   still has work in flight; the claim order is decreasing upward rank over
+   both (section 3.1).  Results are identical to tchol_factor followed by
+   tchol_solve.  Arguments: 1 A (in/out as for tchol_factor), 2 n, 3 nb,
+   4 B (n x nrhs, ld n, in/out as for tchol_solve), 5 nrhs >= 0, 6 ws,
+   7 ws_bytes >= tchol_factor_solve_workspace_bytes(n, nb, nrhs), 8 stream,
+   9 opts (NULL or as for tchol_factor_ex).  Returns 0, k > 0 (leading minor
+   of order k not positive definite; B is then partly overwritten), or a
+   negative code. */
+TCHOL_API int64_t tchol_factor_solve_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs);
+TCHOL_API int32_t tchol_factor_solve(double *A, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
+                                     int64_t ws_bytes, void *stream, const tchol_opts *opts);
+
 /* Batched factor + solve of `batch` independent SPD systems in ONE launch
    of the persistent kernel.  Paper: the same tile DAG (section 4.1) per
    system; the systems' DAGs are merged into one, each system's solve

@@ -86,6 +86,10 @@ def load() -> ctypes.CDLL:
                                              P32, P32, P32, P32]
     lib.tchol_batched_workspace_bytes.restype = i64
     lib.tchol_batched_workspace_bytes.argtypes = [P32, P32, i32]
+    lib.tchol_factor_solve_workspace_bytes.restype = i64
+    lib.tchol_factor_solve_workspace_bytes.argtypes = [i64, i64, i64]
+    lib.tchol_factor_solve.restype = i32
+    lib.tchol_factor_solve.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, ctypes.POINTER(Opts)]
     lib.tchol_batched_f32_workspace_bytes.restype = i64
     lib.tchol_batched_f32_workspace_bytes.argtypes = [P32, P32, i32, i32]
     lib.tchol_factor_solve_batched_f32.restype = i32
@@ -525,3 +529,32 @@ def factor_solve_batched_f32_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, poli
         raise TcholError(rc, "tchol_factor_solve_batched_f32")
     info = info[:batch]
     return (info, ms.value) if want_kernel_ms else info
+
+
+def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+                  want_kernel_ms: bool = False, trace=None, check: bool = True):
+    """Factor A in place and solve in place on Bc in one launch (merged DAG).
+    A: CUDA float64 (n, n) contiguous symmetric; Bc: CUDA float64 (nrhs, n)
+    contiguous (B column-major).  Returns info (0, or the failing leading
+    minor), or (info, kernel_ms)."""
+    torch = _torch()
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+        raise ValueError("A must be a contiguous square float64 tensor")
+    n = A.shape[0]
+    if Bc.dtype != torch.float64 or not Bc.is_contiguous() or Bc.dim() != 2 or Bc.shape[1] != n:
+        raise ValueError("Bc must be a contiguous float64 (nrhs, n) tensor (B in column-major order)")
+    nrhs = Bc.shape[0]
+    lib = load()
+    with torch.cuda.device(A.device):
+        need = lib.tchol_factor_solve_workspace_bytes(n, nb, nrhs) if n else 256
+        if need < 0:
+            raise TcholError(int(need), "tchol_factor_solve_workspace_bytes")
+        if ws is None or ws.numel() < need:
+            ws = _workspace(torch, need, A.device)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        rc = lib.tchol_factor_solve(ctypes.c_void_p(A.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()), nrhs,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(torch, A.device),
+                                    ctypes.byref(o))
+    if rc < 0 and check:
+        raise TcholError(rc, "tchol_factor_solve")
+    return (rc, ms.value) if want_kernel_ms else rc

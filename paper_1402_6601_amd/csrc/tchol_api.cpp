@@ -513,6 +513,55 @@ int32_t tchol_backward(const double* L, int64_t n, int64_t nb, double* Lbar, voi
   return tchol_backward_ex(L, n, nb, Lbar, ws, ws_bytes, stream, nullptr);
 }
 
+int64_t tchol_factor_solve_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs) {
+  if (n < 0 || n > INT32_MAX) return -1;
+  if (!nb_ok(nb)) return -2;
+  if (nrhs < 0) return -3;
+  const int32_t n32 = (int32_t)n, nb32 = (int32_t)nb;
+  return tchol_batched_workspace_bytes(&n32, &nb32, 1);
+}
+
+int32_t tchol_factor_solve(double* A, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
+                           void* stream, const tchol_opts* opts) {
+  if (n < 0 || n > INT32_MAX) return -2;
+  if (!nb_ok(nb)) return -3;
+  if (nrhs < 0 || nrhs > INT32_MAX) return -5;
+  if (n == 0) return 0;
+  if (!A) return -1;
+  if (nrhs > 0 && !B) return -4;
+  if (!ws) return -6;
+  if (ws_bytes <= 0) return -7;
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_RANDOM) return TCHOL_E_UNSUPPORTED;
+  // one system of the merged factor + solve DAG: A at offset 0 with ld n, B at 0
+  std::vector<tchol::System> systems(1);
+  systems[0].n = n;
+  systems[0].nb = nb;
+  systems[0].ld = n;
+  auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  std::shared_ptr<const Image> img;
+  {
+    // the image depends only on the plan here (fixed offsets), so it is cached, pinned
+    static std::mutex mu;
+    static std::map<const Plan*, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(plan.get());
+    if (it != cache.end() && !it->second.first.expired()) {
+      img = it->second.second;
+    } else {
+      img = make_image(*plan, true, &systems);
+      if (cache.size() > 16) cache.clear();
+      cache[plan.get()] = std::make_pair(std::weak_ptr<const Plan>(plan), img);
+    }
+  }
+  const bool wide = (n % 2 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
+  int32_t info = 0;
+  const int32_t rc = execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 6, &info);
+  if (rc != 0) return rc;
+  return info;
+}
+
 int64_t tchol_batched_workspace_bytes(const int32_t* n, const int32_t* nb, int32_t batch) {
   std::vector<tchol::System> systems;
   if (batch < 0) return -3;

@@ -159,3 +159,43 @@ def test_kernel_time_reported(tc):
     W = _dev(A)
     rc, ms = tc.factor_(W, 128, want_kernel_ms=True)
     assert rc == 0 and ms > 0.0
+
+
+@pytest.mark.parametrize("n,nb,nrhs,seed", [(1000, 128, 5, 40), (1024, 256, 16, 41), (999, 160, 3, 42),
+                                            (513, 512, 1, 43), (17, 16, 2, 44), (300, 64, 0, 45)])
+def test_factor_solve_one_launch_equals_two(tc, n, nb, nrhs, seed):
+    """The merged factor + solve launch gives bitwise the results of the two
+    separate launches (every tile sees the same updates in the same order)."""
+    print("case n=%d nb=%d nrhs=%d" % (n, nb, nrhs), flush=True)
+    A, b = spd_inputs.spd_matrix_and_rhs(n, seed, nrhs=max(nrhs, 1))
+    b = b[:, :nrhs]
+    W1, W2 = _dev(A), _dev(A)
+    B1 = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
+    B2 = B1.clone()
+    assert tc.factor_solve_(W1, B1, nb) == 0
+    assert tc.factor_(W2, nb) == 0
+    if nrhs:
+        assert tc.solve_(W2, B2, nb) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(W1, W2) and torch.equal(B1, B2)
+    L = np.tril(W1.cpu().numpy().T)
+    assert oracle.factor_error(L, oracle.cholesky(A)) <= TOL
+    if nrhs:
+        Xo = oracle.potrs(oracle.cholesky(A), b)
+        X = B1.cpu().numpy().T
+        assert np.max(np.abs(X - Xo)) / np.max(np.abs(Xo)) <= TOL
+
+
+def test_factor_solve_one_launch_integer_and_breakdown(tc):
+    A, L0 = spd_inputs.integer_spd(300, seed=46)
+    b, x0 = spd_inputs.integer_rhs(A, 3, seed=46)
+    W = _dev(A)
+    Bc = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
+    assert tc.factor_solve_(W, Bc, 64) == 0
+    assert np.array_equal(np.tril(W.cpu().numpy().T), L0)
+    assert np.array_equal(Bc.cpu().numpy().T, x0)
+    j = 150
+    A[j, j] -= L0[j, j] ** 2
+    W = _dev(A)
+    Bc = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
+    assert tc.factor_solve_(W, Bc, 64) == j + 1
