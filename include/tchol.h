@@ -51,6 +51,7 @@ extern "C" {
 #define TCHOL_OP_SOLVE 1
 #define TCHOL_OP_BATCHED 2 /* factor + solve of many systems (plan introspection only) */
 #define TCHOL_OP_BACKWARD 3 /* adjoint of the factorization */
+#define TCHOL_OP_MIXED_FACTOR 4 /* the factorization launch of tchol_solve_mixed (plan introspection only) */
 
 #define TCHOL_POLICY_RANK 0   /* decreasing upward rank (default)          */
 #define TCHOL_POLICY_FIFO 1   /* step-major: (k, kind, i, j) ascending      */
@@ -76,8 +77,11 @@ typedef struct tchol_opts {
                             TCHOL_E_TIMEOUT                                      */
   float *kernel_ms;    /* out (host pointer, may be NULL): duration of the
                           persistent kernel measured with HIP events on `stream` */
-  uint64_t *trace;     /* device buffer of 4 x uint64 per work item, or NULL:
-                          {start, end} wall clock (100 MHz), {task, part | wg<<32} */
+  uint64_t *trace;     /* device buffer of 4 x uint64 per work item of the launch
+                          (tchol_plan_query counts[2] for its op; for
+                          tchol_solve_mixed, TCHOL_OP_MIXED_FACTOR), or NULL:
+                          {claim, start} and {end} wall clock (100 MHz),
+                          {task, part | wg<<32}                                  */
 } tchol_opts;
 
 /* Bytes of device workspace needed by `op` (TCHOL_OP_FACTOR, _SOLVE or

@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
-OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD = 0, 1, 2, 3
+OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD, OP_MIXED_FACTOR = 0, 1, 2, 3, 4
 POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV = -100, -101, -102, -103, -104
 LOWP_FP32 = 1

@@ -817,11 +817,12 @@ const char* tchol_version(void) { return "tchol 0.1 (gfx950)"; }
 int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed, int64_t* counts,
                          int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* parts, int32_t* dep0,
                          int64_t* rank, int32_t* succ_off, int32_t* succ, int32_t* item_task, int32_t* item_part) {
-  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE && op != TCHOL_OP_BACKWARD) return -1;
+  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE && op != TCHOL_OP_BACKWARD && op != TCHOL_OP_MIXED_FACTOR)
+    return -1;
   if (n < 0) return -2;
   if (!nb_ok(nb)) return -3;
   if (policy < TCHOL_POLICY_RANK || policy > TCHOL_POLICY_RANDOM) return -4;
-  auto p = tchol::get_plan(op, n, nb, policy, seed);
+  auto p = tchol::get_plan(op == TCHOL_OP_MIXED_FACTOR ? tchol::OP_FACTOR_INV : op, n, nb, policy, seed);
   if (!p) return TCHOL_E_UNSUPPORTED;
   fill_query(*p, counts, kind, ti, tj, tk, nullptr, parts, dep0, rank, succ_off, succ, item_task, item_part);
   return 0;

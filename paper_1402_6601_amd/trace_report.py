@@ -84,7 +84,8 @@ def main(argv=None):
         n, nb = args.n or 32768, args.nb or 512
         mixed = args.op == "mixed"
         A, rng = spd_inputs.spd_matrix_device(n, 2 if mixed else 1, 1e-4 if mixed else 1.0, device=dev)
-        plan = tc.plan_query(tc.OP_FACTOR, n, nb)
+        # the mixed-precision factorization's DAG also holds the TRTRI tasks
+        plan = tc.plan_query(tc.OP_MIXED_FACTOR if mixed else tc.OP_FACTOR, n, nb)
         trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
         if mixed:
             B = torch.from_numpy(spd_inputs.rhs(rng, n, 16)).to(dev).t().contiguous()
