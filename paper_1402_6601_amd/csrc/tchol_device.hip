@@ -49,15 +49,28 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 
 // ---------------------------------------------------------------------------
 // Direct global -> LDS loads.  One instruction moves 16 (or 4) bytes per lane
-// into LDS at a wave-uniform base + lane * size, without passing through
+// into LDS at a wave-uniform base (M0) + lane * size, without passing through
 // registers, so the K panels stream in while the matrix cores run.
+//
+// They are issued as inline assembly rather than through the compiler's
+// builtin: for the builtin, the compiler cannot tell which LDS stage a load
+// writes, so it waits for every outstanding load (vmcnt(0)) before the next
+// LDS read, which serialises each chunk's load with the previous chunk's
+// products.  Issued this way the compiler does not track them at all, and
+// every consumer waits for them explicitly (vmcnt counts, then a workgroup
+// barrier) before reading the stage they fill.  M0 is set in the same
+// statement, right before the load; it is a reserved register the compiler
+// sets itself before each of its own uses (these kernels have none).
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+__device__ __forceinline__ uint32_t lds_addr(double* l) {
+  return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t*)l);
+}
 __device__ __forceinline__ void dma16(const void* g, double* l) {
-  __builtin_amdgcn_global_load_lds(g, (lds_void_t*)l, 16, 0, 0);
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" : : "s"(lds_addr(l)), "v"(g) : "memory");
 }
 __device__ __forceinline__ void dma4(const void* g, double* l) {
-  __builtin_amdgcn_global_load_lds(g, (lds_void_t*)l, 4, 0, 0);
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, off" : : "s"(lds_addr(l)), "v"(g) : "memory");
 }
 
 constexpr int imin_c(int a, int b) { return a < b ? a : b; }
@@ -211,11 +224,20 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
   // outstanding.  A wavefront issues W (or, when not UNIFORM, W + 1)
   // transfers per chunk; waiting for "at most W per later chunk" (capped at
   // the counter's range) is exact or stricter, never short.
+  //
+  // The first chunk waits for everything outstanding: the caller's loads of
+  // C are then known complete, and the compiler (which tracks those loads but
+  // not the direct-to-LDS ones) inserts no waits of its own into the loop.
   const int nch = K / KC;
+  if (nch <= 0) return;
 #pragma unroll
   for (int p = 0; p < NST - 1; ++p)
     if (p < nch) issue(p);
-  int ch = 0;
+  wait_vmcnt<0>();
+  __syncthreads();
+  if (NST - 1 < nch) issue(NST - 1);
+  compute(0);
+  int ch = 1;
   for (; ch + NST - 1 < nch; ++ch) {  // steady state: NST - 2 later chunks in flight
     wait_vmcnt<imin_c((NST - 2) * W, 63)>();
     __syncthreads();
@@ -380,24 +402,31 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
           acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[cur][cb], fa[cur][rb], acc[rb][cb], 0, 0, 0);
     }
   };
+  // as in gemm_kloop: the first chunk waits for everything, the loads of C included
   const int nch = K / KC;
 #pragma unroll
   for (int p = 0; p < NST - 1; ++p)
     if (p < nch) issue(p);
-  int ch = 0;
-  for (; ch + NST - 1 < nch; ++ch) {
-    wait_vmcnt<imin_c((NST - 2) * W, 63)>();
+  if (nch > 0) {  // (every loop below is reached only through the first chunk's full wait)
+    wait_vmcnt<0>();
     __syncthreads();
-    issue(ch + NST - 1);
-    compute(ch);
-  }
-  for (; ch < nch; ++ch) {
-    const int later = nch - 1 - ch;
-    if (later >= 2) wait_vmcnt<imin_c(2 * W, 63)>();
-    else if (later == 1) wait_vmcnt<imin_c(W, 63)>();
-    else wait_vmcnt<0>();
-    __syncthreads();
-    compute(ch);
+    if (NST - 1 < nch) issue(NST - 1);
+    compute(0);
+    int ch = 1;
+    for (; ch + NST - 1 < nch; ++ch) {
+      wait_vmcnt<imin_c((NST - 2) * W, 63)>();
+      __syncthreads();
+      issue(ch + NST - 1);
+      compute(ch);
+    }
+    for (; ch < nch; ++ch) {
+      const int later = nch - 1 - ch;
+      if (later >= 2) wait_vmcnt<imin_c(2 * W, 63)>();
+      else if (later == 1) wait_vmcnt<imin_c(W, 63)>();
+      else wait_vmcnt<0>();
+      __syncthreads();
+      compute(ch);
+    }
   }
   __syncthreads();
 #pragma unroll
