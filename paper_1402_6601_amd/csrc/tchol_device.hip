@@ -1359,7 +1359,8 @@ __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfi
 // task's counter reaches zero; false when the run is being aborted or the
 // wait exceeded its bound.
 __device__ __forceinline__ bool wait_ready(const KArgs& a, int task, int lane) {
-  if (uniform_i(ld_relaxed(&a.dep[task])) == 0) return uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) == 0;
+  const int dep0 = ld_relaxed(&a.dep[task]), abort0 = ld_relaxed(&a.hdr[HDR_ABORT]);  // both in flight at once
+  if (uniform_i(dep0) == 0) return uniform_i(abort0) == 0;
   const uint64_t t0 = wall_clock64();
   for (;;) {
     __builtin_amdgcn_s_sleep(2);
@@ -1408,13 +1409,34 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
   constexpr bool ADJOINT_KINDS = MODE == 3;
   __shared__ double lds[LDS_DOUBLES];
   __shared__ int s_claim[3];
+  __shared__ int32_t s_desc[DESC_WORDS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = uniform_i(tid >> 6);
+  // wavefront 0's record of the work item it ran last, published at the
+  // start of the next claim, and of the items this worker completed
+  int p_task = -1, p_ticket = 0, p_parts = 0, p_e0 = 0, p_e1 = 0, ndone = 0;
+  uint64_t p_end = 0;
   for (;;) {
-    // claim: wavefront 0 takes the next ticket and waits for its task
+    // publish + claim: wavefront 0 marks the previous item done and takes the
+    // next ticket in the same round trip, then waits for the new task while
+    // its descriptor is fetched
     if (wave == 0) {
-      int t = 0;
-      if (lane == 0) t = __hip_atomic_fetch_add(&a.hdr[HDR_TICKET], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int prev = 0, t = 0;
+      if (lane == 0) {
+        if (p_task >= 0) prev = __hip_atomic_fetch_add(&a.done[p_task], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = __hip_atomic_fetch_add(&a.hdr[HDR_TICKET], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (p_task >= 0) {
+        // the last work item of a task activates its successors
+        if (uniform_i(prev) == p_parts - 1)
+          for (int e = p_e0 + lane; e < p_e1; e += 64)
+            __hip_atomic_fetch_sub(&a.dep[a.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ++ndone;
+        if (a.trace && lane == 0) {
+          a.trace[4 * (int64_t)p_ticket + 2] = p_end;
+          a.trace[4 * (int64_t)p_ticket + 3] = (uint64_t)(uint32_t)p_task | ((uint64_t)(uint32_t)blockIdx.x << 32);
+        }
+      }
       t = uniform_i(t);
       int task = -1, part = 0;
       uint64_t tw = 0;
@@ -1422,7 +1444,9 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         task = uniform_i(a.items[2 * t]);
         part = uniform_i(a.items[2 * t + 1]);
         if (a.trace) tw = wall_clock64();
+        const int dv = lane < DESC_WORDS ? a.desc[DESC_WORDS * (int64_t)task + lane] : 0;
         if (!wait_ready(a, task, lane)) task = -1;
+        if (lane < DESC_WORDS) s_desc[lane] = dv;
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (lane == 0) {
@@ -1433,15 +1457,19 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           a.trace[4 * (int64_t)t + 0] = tw;
           a.trace[4 * (int64_t)t + 1] = wall_clock64();
         }
+        // the completed-item count, added once per worker
+        if (task < 0 && ndone > 0)
+          __hip_atomic_fetch_add(&a.hdr[HDR_DONE], ndone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     __syncthreads();
     const int task = uniform_i(s_claim[0]), part = uniform_i(s_claim[1]), ticket = uniform_i(s_claim[2]);
     if (task < 0) break;
-    const int32_t* d = a.desc + DESC_WORDS * (int64_t)task;
-    const int kind = uniform_i(d[0]), ti = uniform_i(d[1]), tj = uniform_i(d[2]), tk = uniform_i(d[3]);
+    const int kind = uniform_i(s_desc[0]), ti = uniform_i(s_desc[1]), tj = uniform_i(s_desc[2]),
+              tk = uniform_i(s_desc[3]);
+    const int d_parts = uniform_i(s_desc[4]), d_e0 = uniform_i(s_desc[5]), d_e1 = uniform_i(s_desc[6]);
     // the task's system: base pointers, order, tile size, leading dimension
-    const int sid = uniform_i(d[7]);
+    const int sid = uniform_i(s_desc[7]);
     const int64_t* sr = a.sys + SYS_WORDS * (int64_t)sid;
     using E = typename std::conditional<MIXED, float, double>::type;
     E* const Abase = reinterpret_cast<E*>(a.A) + sr[0];
@@ -1673,31 +1701,23 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         ok = 0;
         break;
     }
-    // Publish, then activate.  Every global store of a work item is a
-    // device-scope store (st_dev), written through to the device's point of
-    // coherence; once each wavefront has seen its stores complete (vmcnt 0)
-    // the item's results are visible to any CU that invalidates its caches
-    // before reading them (the acquire after each wait).  This replaces an
+    // Publish.  Every global store of a work item is a device-scope store
+    // (st_dev), written through to the device's point of coherence; once
+    // each wavefront has seen its stores complete (vmcnt 0) the item's
+    // results are visible to any CU that invalidates its caches before
+    // reading them (the acquire after each wait).  This replaces an
     // agent-scope release fence, whose L2 write-back costs tens of
-    // microseconds per work item on this part.
+    // microseconds per work item on this part.  The completion counter is
+    // incremented at the start of the next claim.
     wait_vmcnt<0>();
     __syncthreads();
-    if (wave == 0 && ok) {
-      int prev = 0;
-      if (lane == 0) prev = __hip_atomic_fetch_add(&a.done[task], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      prev = uniform_i(prev);
-      if (prev == uniform_i(d[4]) - 1) {
-        const int e0 = uniform_i(d[5]), e1 = uniform_i(d[6]);
-        for (int e = e0 + lane; e < e1; e += 64)
-          __hip_atomic_fetch_sub(&a.dep[a.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (lane == 0) {
-        __hip_atomic_fetch_add(&a.hdr[HDR_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (a.trace) {
-          a.trace[4 * (int64_t)ticket + 2] = wall_clock64();
-          a.trace[4 * (int64_t)ticket + 3] = (uint64_t)(uint32_t)task | ((uint64_t)(uint32_t)blockIdx.x << 32);
-        }
-      }
+    if (wave == 0) {
+      p_task = ok ? task : -1;
+      p_ticket = ticket;
+      p_parts = d_parts;
+      p_e0 = d_e0;
+      p_e1 = d_e1;
+      if (a.trace) p_end = wall_clock64();
     }
   }
 }
