@@ -193,9 +193,15 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
       for (int j = 0; j < J; ++j) slot(j, k0, As, Bs);
     }
   };
-  auto compute = [&](int ch) __attribute__((always_inline)) {
+  // compute(ch, nx): the products of chunk ch; with nx >= 0 the transfers of
+  // chunk nx are issued along the way, a few per k-step, so that the matrix
+  // cores are not idle while a whole chunk's transfers are issued
+  auto compute = [&](int ch, int nx) __attribute__((always_inline)) {
     const double* as = lds + (ch % NST) * STAGE;
     const double* bs = as + KC * ALD;
+    double* nAs = lds + ((nx < 0 ? 0 : nx) % NST) * STAGE;
+    double* nBs = nAs + KC * ALD;
+    constexpr int PER = (J + KC / 4 - 1) / (KC / 4);  // transfer slots per k-step
     // fragments of k-step ks + 1 are read while the MFMAs of ks run
     double fa[2][RB], fb[2][CB];
 #pragma unroll
@@ -205,6 +211,11 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int cur = ks & 1, nxt = cur ^ 1;
+      if (nx >= 0) {
+#pragma unroll
+        for (int jj = 0; jj < PER; ++jj)
+          if (ks * PER + jj < J) slot(ks * PER + jj, nx * KC, nAs, nBs);
+      }
       if (ks + 1 < KC / 4) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) fa[nxt][rb] = as[((ks + 1) * 4 + lg) * ALD + wm * S::WTM + rb * 16 + l16];
@@ -235,14 +246,12 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
     if (p < nch) issue(p);
   wait_vmcnt<0>();
   __syncthreads();
-  if (NST - 1 < nch) issue(NST - 1);
-  compute(0);
+  compute(0, NST - 1 < nch ? NST - 1 : -1);
   int ch = 1;
   for (; ch + NST - 1 < nch; ++ch) {  // steady state: NST - 2 later chunks in flight
     wait_vmcnt<imin_c((NST - 2) * W, 63)>();
     __syncthreads();
-    issue(ch + NST - 1);
-    compute(ch);
+    compute(ch, ch + NST - 1);
   }
   for (; ch < nch; ++ch) {  // the last NST - 1 chunks: nothing more to issue
     const int later = nch - 1 - ch;
@@ -250,7 +259,7 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
     else if (later == 1) wait_vmcnt<imin_c(W, 63)>();
     else wait_vmcnt<0>();
     __syncthreads();
-    compute(ch);
+    compute(ch, -1);
   }
 }
 
@@ -378,8 +387,12 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
       dma16(src0 + (int64_t)(k0 + q) * ld, st + q * (F32_LD / 2));
     }
   };
-  auto compute = [&](int ch) __attribute__((always_inline)) {
+  // as in gemm_kloop: the transfers of chunk nx (if any) are issued along the
+  // products of chunk ch, one k-row per k-step
+  auto compute = [&](int ch, int nx) __attribute__((always_inline)) {
     const float* st = lds + (ch % NST) * STAGE;
+    double* nst = lds_d + ((nx < 0 ? 0 : nx) % NST) * (STAGE / 2);
+    constexpr int PER = (W + KC / 4 - 1) / (KC / 4);
     float fa[2][4], fb[2][4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) fa[0][rb] = -st[lg * F32_LD + wm * 64 + rb * 16 + l16];
@@ -388,6 +401,14 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int cur = ks & 1, nxt = cur ^ 1;
+      if (nx >= 0) {
+#pragma unroll
+        for (int jj = 0; jj < PER; ++jj)
+          if (ks * PER + jj < W) {
+            const int q = wave + 4 * (ks * PER + jj);
+            dma16(src0 + (int64_t)(nx * KC + q) * ld, nst + q * (F32_LD / 2));
+          }
+      }
       if (ks + 1 < KC / 4) {
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) fa[nxt][rb] = -st[((ks + 1) * 4 + lg) * F32_LD + wm * 64 + rb * 16 + l16];
@@ -410,14 +431,12 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
   if (nch > 0) {  // (every loop below is reached only through the first chunk's full wait)
     wait_vmcnt<0>();
     __syncthreads();
-    if (NST - 1 < nch) issue(NST - 1);
-    compute(0);
+    compute(0, NST - 1 < nch ? NST - 1 : -1);
     int ch = 1;
     for (; ch + NST - 1 < nch; ++ch) {
       wait_vmcnt<imin_c((NST - 2) * W, 63)>();
       __syncthreads();
-      issue(ch + NST - 1);
-      compute(ch);
+      compute(ch, ch + NST - 1);
     }
     for (; ch < nch; ++ch) {
       const int later = nch - 1 - ch;
@@ -425,7 +444,7 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
       else if (later == 1) wait_vmcnt<imin_c(W, 63)>();
       else wait_vmcnt<0>();
       __syncthreads();
-      compute(ch);
+      compute(ch, -1);
     }
   }
   __syncthreads();
