@@ -72,6 +72,21 @@ __device__ __forceinline__ void dma16(const void* g, double* l) {
 __device__ __forceinline__ void dma4(const void* g, double* l) {
   asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, off" : : "s"(lds_addr(l)), "v"(g) : "memory");
 }
+// The same from a wave-uniform base (scalar registers) plus a per-lane byte
+// offset below 4 GB: one 32-bit register per lane instead of a 64-bit address.
+__device__ __forceinline__ const void* uniform_ptr(const void* p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ void dma16s(const void* base, uint32_t off, double* l) {
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2" : : "s"(lds_addr(l)), "v"(off), "s"(uniform_ptr(base))
+               : "memory");
+}
+__device__ __forceinline__ void dma4s(const void* base, uint32_t off, double* l) {
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, %2" : : "s"(lds_addr(l)), "v"(off), "s"(uniform_ptr(base))
+               : "memory");
+}
 
 constexpr int imin_c(int a, int b) { return a < b ? a : b; }
 
@@ -155,21 +170,29 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
   // panel: part of one k row, or whole k rows when the row is shorter than
   // the segment (then the rows are unpadded and contiguous).  Each 16-byte
   // lane moves rows (r, r + 1); each 4-byte lane half of one double.
+  //
+  // The address is split into a wave-uniform base and a per-lane offset.
+  // Either a segment lies within one k row (R a multiple of SEG; it starts at
+  // row u = e0 % R of k row e0 / R) or it covers whole k rows (R divides
+  // SEG, u = 0; lane element le falls in k row e0 / R + le / R).  Rows are
+  // clamped to the last valid start row Vc; the base takes min(u, Vc), so
+  // the lane offsets are never negative.
   auto xfer = [&](const double* X, int R, int XLD, int V, int q, int k0, double* dst) __attribute__((always_inline)) {
     const int e0 = q * SEG;
-    const int e = e0 + (SEG == 128 ? 2 * lane : (lane >> 1));
-    const int c = e / R;
-    const double* src;
-    if (SEG == 128) {
-      // a pair starts at an even row no later than V - 1; for odd V the
-      // pair (V - 1, V) reads the row after the panel, which the launch
-      // contract guarantees to exist (leading dimension above the order)
-      src = X + (int64_t)(k0 + c) * ld + imin(e % R, (V - 1) & ~1);
-      dma16(src, dst + (e0 / R) * XLD + e0 % R);
-    } else {
-      src = X + (int64_t)(k0 + c) * ld + imin(e % R, V - 1);
-      dma4(reinterpret_cast<const float*>(src) + (lane & 1), dst + (e0 / R) * XLD + e0 % R);
-    }
+    const int le = SEG == 128 ? 2 * lane : (lane >> 1);
+    // a pair starts at an even row no later than V - 1; for odd V the pair
+    // (V - 1, V) reads the row after the panel, which the launch contract
+    // guarantees to exist (leading dimension above the order)
+    const int Vc = SEG == 128 ? ((V - 1) & ~1) : V - 1;
+    const int u = e0 % R, cu = e0 / R, ru = imin(u, Vc);
+    const int cl = (R % SEG == 0) ? 0 : le / R;
+    const int rl = ((R % SEG == 0) ? imin(u + le, Vc) : imin(le % R, Vc)) - ru;
+    const double* base = X + (int64_t)(k0 + cu) * ld + ru;
+    const uint32_t off = (uint32_t)(((int64_t)cl * ld + rl) * 8);
+    if (SEG == 128)
+      dma16s(base, off, dst + cu * XLD + u);
+    else
+      dma4s(base, off + 4 * (lane & 1), dst + cu * XLD + u);
   };
   auto slot = [&](int j, int k0, double* As, double* Bs) __attribute__((always_inline)) {
     const int q = wave + 4 * j;
