@@ -49,6 +49,19 @@ def device_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def ci95(xs):
+    """Mean and the half-width of its 95 % confidence interval (Student t)."""
+    if not xs:
+        return None
+    a = np.asarray(xs, dtype=np.float64)
+    half = 0.0
+    if len(a) > 1:
+        from scipy import stats
+        half = float(stats.t.ppf(0.975, len(a) - 1) * a.std(ddof=1) / np.sqrt(len(a)))
+    return {"reps": len(a), "mean": round(float(a.mean()), 3), "ci95_half_width": round(half, 3),
+            "min": round(float(a.min()), 3), "max": round(float(a.max()), 3)}
+
+
 def load_traffic(n, nb):
     """Per-launch HBM bytes of the merged factor + solve launch from the
     committed rocprofv3 counter summary, if it was taken on the current kernel
@@ -472,6 +485,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ci-reps", type=int, default=30,
+                    help="factor workload: extra launches (restored in between) for the mean and its 95%% interval")
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--nrhs", type=int, default=16)
@@ -586,6 +601,17 @@ def main():
     _, solve_kernel_ms = tc.solve_(Wt, Bt, nb, ws=ws_s, want_kernel_ms=True)
     solve_ms = (time.perf_counter() - ts) * 1e3
 
+    # repeated launches for a confidence interval: A and B restored (untimed)
+    # before each one, the kernel timed by HIP events on the launch stream
+    rep_ms = []
+    for r in range(args.ci_reps):
+        work[0].copy_(A0)
+        rhs[0].copy_(B0c)
+        step(work[0], rhs[0], rep_ms)
+    torch.cuda.synchronize()
+    if args.ci_reps:
+        log("repeated %d launches: kernel mean %.3f ms" % (args.ci_reps, float(np.mean(rep_ms))))
+
     # checks on the result of the last timed step
     recon = sampled_reconstruction(torch, work[K - 1], A0, n)
     out = {
@@ -610,6 +636,7 @@ def main():
                      "kernel_ms_mean": round(kmean, 3), "flops_per_launch": flops,
                      "flops_note": "n^3/3; the solve's 4 n^2 nrhs flops in the same launch are not counted"},
         "step_kernel_ms": [round(x, 3) for x in kernel_ms],
+        "kernel_ms_repeated": ci95(rep_ms),
         "factor_alone_kernel_ms": round(factor_alone_ms, 3),
         "factor_alone_frac": round(flops / (factor_alone_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
         "solve_ms": round(solve_ms, 3),

@@ -37,7 +37,7 @@ typedef struct KArgs {
   int32_t mixed;        /* 0: FP64; 1: mixed-precision factor, 2: its solves, 4: both
                            (A is the FP32 working copy); 3: the adjoint of the
                            factorization (A = L, B = Lbar, D = partial-product slots) */
-  int32_t pad1;
+  int32_t syrk_b;       /* SYRK output sub-tile (square)                          */
   double *Dinv;         /* mixed precision: L_kk^{-1}, nb x nb each (FP64)         */
   double *DinvT;        /* mixed precision: L_kk^{-T}, nb x nb each (FP64)         */
   double *S;            /* mixed precision: the solve's intermediate y, like B     */

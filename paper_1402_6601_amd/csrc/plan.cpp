@@ -108,7 +108,7 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
     for (int32_t i = k + 1; i < T; ++i)
       id_trsm[ix2(i, k)] = b.add(TK_TRSM, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
     for (int32_t i = k + 1; i < T; ++i) {
-      int32_t sb = Builder::cdiv(b.tile_size(i), b.s.gemm_m);
+      int32_t sb = Builder::cdiv(b.tile_size(i), b.s.syrk_b);
       id_syrk[ix2(i, k)] = b.add(TK_SYRK, i, i, k, sb * (sb + 1) / 2);
       for (int32_t j = k + 1; j < i; ++j)
         id_gemm[ix3(i, j, k)] = b.add(TK_GEMM, i, j, k,
@@ -273,6 +273,15 @@ const Split& default_split() {
   return s;
 }
 
+const Split& split_for(int32_t op) {
+  static const Split mixed = [] {
+    Split s;
+    s.gemm_m = 256;
+    return s;
+  }();
+  return op == OP_FACTOR_INV ? mixed : default_split();
+}
+
 namespace {
 
 // dependency counters, CSR successors, upward ranks, claim order and work items
@@ -426,7 +435,7 @@ std::shared_ptr<const Plan> get_plan(int32_t op, int64_t n, int64_t nb, int32_t 
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
   }
-  std::shared_ptr<const Plan> p = build_plan(op, n, nb, policy, seed, default_split());
+  std::shared_ptr<const Plan> p = build_plan(op, n, nb, policy, seed, split_for(op));
   if (!p) return nullptr;
   std::lock_guard<std::mutex> g(mu);
   if (cache.size() > 64) cache.clear();

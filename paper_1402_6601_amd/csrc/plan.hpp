@@ -60,7 +60,8 @@ constexpr int32_t OP_SOLVE_INV = 17;
 
 // Work-item granularity (rows x cols of one work item of each task kind).
 struct Split {
-  int32_t gemm_m = 128, gemm_n = 128;   // GEMM/SYRK output sub-tile
+  int32_t gemm_m = 128, gemm_n = 128;   // GEMM output sub-tile (also the adjoint's products)
+  int32_t syrk_b = 128;                 // SYRK output sub-tile (square; the lower ones of the tile)
   int32_t trsm_rows = 32;               // TRSM row strip
   int32_t gemv_rows = 128;              // solve update row strip
 };
@@ -86,5 +87,10 @@ std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int
 std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed);
 
 const Split& default_split();
+// The split a single-system plan of this operation is built with: the
+// mixed-precision factorization (OP_FACTOR_INV) takes 256 x 128 GEMM
+// sub-tiles, whose FP32 products need twice the rows per work item to
+// amortise its fixed costs; every other operation the default.
+const Split& split_for(int32_t op);
 
 }  // namespace tchol

@@ -219,9 +219,10 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.nrhs = nrhs;
   a.T = plan.T;
   a.nitem = (int32_t)plan.nitem();
-  const tchol::Split& sp = tchol::default_split();
+  const tchol::Split& sp = tchol::split_for(plan.op);
   a.gemm_m = sp.gemm_m;
   a.gemm_n = sp.gemm_n;
+  a.syrk_b = sp.syrk_b;
   a.trsm_rows = sp.trsm_rows;
   a.gemv_rows = sp.gemv_rows;
   a.hdr = reinterpret_cast<int32_t*>(w + L.hdr);

@@ -497,6 +497,115 @@ __device__ __forceinline__ void gemm_nt_f32(float* C, const float* Ap, const flo
     gemm_f32_core<16, 4>(C, Ap, Bp, ld, M, N, K, lower_only, lds);
 }
 
+// FP32 GEMM item with a 256 x 128 output, C[M x N] -= Ap[M x K] Bp[N x K]^T,
+// M <= 256, N <= 128 (the mixed-precision factorization's GEMM items): the
+// scheme of gemm_f32_core with twice the rows per wavefront (2 x 2
+// wavefronts of 128 x 64).  Per k-row of a chunk one 16-byte transfer of all
+// 64 lanes moves the 256 A rows and one of lanes 0-31 the 128 B rows into an
+// LDS row [A 256 | B 128 | 16 pad]; three stages of 32 k-rows.
+#define F32W_LD 400
+template <int KC, int NST>
+__device__ __forceinline__ void gemm_f32_wide(float* __restrict__ C, const float* __restrict__ Ap,
+                                              const float* __restrict__ Bp, int64_t ld, int M, int N, int K,
+                                              double* lds_d) {
+  constexpr int STAGE = KC * F32W_LD;  // floats per stage
+  constexpr int W = 2 * (KC / 4);      // transfers per wavefront and chunk: two per k-row, KC / 4 k-rows
+  static_assert(NST * STAGE <= 2 * LDS_DOUBLES, "stages must fit the workgroup LDS");
+  static_assert(KC % 4 == 0 && W <= 63, "every wavefront transfers whole k-rows");
+  float* lds = reinterpret_cast<float*>(lds_d);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 wavefronts, 128 x 64 each
+  const int l16 = lane & 15, lg = lane >> 4;
+  const float* srcA = Ap + imin(4 * lane, (M - 1) & ~3);
+  const float* srcB = Bp + imin(4 * (lane & 31), (N - 1) & ~3);
+
+  f4 acc[8][4];
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 128 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+        acc[rb][cb][i] = C[(int64_t)imin(col, N - 1) * ld + imin(row, M - 1)];
+      }
+
+  static_assert(STAGE % 2 == 0 && F32W_LD % 2 == 0, "destinations are addressed in doubles");
+  // the two transfers of k-row q of chunk ch (doubles: a row is F32W_LD / 2, B starts at 128)
+  auto xfer = [&](int ch, int q) __attribute__((always_inline)) {
+    double* st = lds_d + (ch % NST) * (STAGE / 2) + q * (F32W_LD / 2);
+    const int64_t k = (int64_t)(ch * KC + q) * ld;
+    dma16(srcA + k, st);
+    if (lane < 32) dma16(srcB + k, st + 128);
+  };
+  auto issue = [&](int ch) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < KC / 4; ++j) xfer(ch, wave + 4 * j);
+  };
+  // the products of chunk ch; the transfers of chunk nx (if any) go out along
+  // them, one k-row per k-step
+  auto compute = [&](int ch, int nx) __attribute__((always_inline)) {
+    const float* st = lds + (ch % NST) * STAGE;
+    float fa[2][8], fb[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) fa[0][rb] = -st[lg * F32W_LD + wm * 128 + rb * 16 + l16];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) fb[0][cb] = st[lg * F32W_LD + 256 + wn * 64 + cb * 16 + l16];
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int cur = ks & 1, nxt = cur ^ 1;
+      if (nx >= 0) xfer(nx, wave + 4 * ks);
+      if (ks + 1 < KC / 4) {
+#pragma unroll
+        for (int rb = 0; rb < 8; ++rb)
+          fa[nxt][rb] = -st[((ks + 1) * 4 + lg) * F32W_LD + wm * 128 + rb * 16 + l16];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) fb[nxt][cb] = st[((ks + 1) * 4 + lg) * F32W_LD + 256 + wn * 64 + cb * 16 + l16];
+      }
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[cur][cb], fa[cur][rb], acc[rb][cb], 0, 0, 0);
+    }
+  };
+  // as in gemm_kloop: the first chunk waits for everything, the loads of C included
+  const int nch = K / KC;
+#pragma unroll
+  for (int p = 0; p < NST - 1; ++p)
+    if (p < nch) issue(p);
+  if (nch > 0) {  // (every loop below is reached only through the first chunk's full wait)
+    wait_vmcnt<0>();
+    __syncthreads();
+    compute(0, NST - 1 < nch ? NST - 1 : -1);
+    int ch = 1;
+    for (; ch + NST - 1 < nch; ++ch) {
+      wait_vmcnt<imin_c((NST - 2) * W, 63)>();
+      __syncthreads();
+      compute(ch, ch + NST - 1);
+    }
+    for (; ch < nch; ++ch) {
+      const int later = nch - 1 - ch;
+      if (later >= 2) wait_vmcnt<imin_c(2 * W, 63)>();
+      else if (later == 1) wait_vmcnt<imin_c(W, 63)>();
+      else wait_vmcnt<0>();
+      __syncthreads();
+      compute(ch, -1);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 128 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+        if (row < M && col < N) st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
+      }
+}
+
 // The same with the result added to an FP64 C (Cd, ld ldcd).
 __device__ __forceinline__ void gemm_nt_f32_d(double* Cd, int64_t ldcd, const float* Ap, const float* Bp, int64_t ld,
                                               int M, int N, int K, bool lower_only, double* lds) {
@@ -1571,21 +1680,25 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           ok = 0;
           break;
         }
-        int si, sj;
+        // the work item's output sub-tile: row block si of bm rows, column block sj of bn
+        int si, sj, bm, bn;
         if (kind == TK_SYRK) {
           si = 0;
           while ((si + 1) * (si + 2) / 2 <= part) ++si;
           sj = part - si * (si + 1) / 2;
+          bm = bn = a.syrk_b;
         } else {
           const int ncj = (tsz(tj) + a.gemm_n - 1) / a.gemm_n;
           si = part / ncj;
           sj = part % ncj;
+          bm = a.gemm_m;
+          bn = a.gemm_n;
         }
-        const int M = imin(a.gemm_m, tsz(ti) - si * a.gemm_m);
-        const int N = imin(a.gemm_n, tsz(tj) - sj * a.gemm_n);
-        E* C = Abase + (tj * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m;
-        const E* Ap = Abase + (tk * nb) * ld + ti * nb + si * a.gemm_m;
-        const E* Bp = Abase + (tk * nb) * ld + tj * nb + sj * a.gemm_n;
+        const int M = imin(bm, tsz(ti) - si * bm);
+        const int N = imin(bn, tsz(tj) - sj * bn);
+        E* C = Abase + (tj * nb + sj * bn) * ld + ti * nb + si * bm;
+        const E* Ap = Abase + (tk * nb) * ld + ti * nb + si * bm;
+        const E* Bp = Abase + (tk * nb) * ld + tj * nb + sj * bn;
         const bool misaligned = ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) != 0;
         if constexpr (MIXED) {
           // four rows per 16-byte lane: ld a multiple of 4 and three rows after the order
@@ -1595,10 +1708,13 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
             break;
           }
           if (kind == TK_SYRK)
-            gemm_nt_f32_d(Dsys + (int64_t)ti * nb * nb + (int64_t)(sj * a.gemm_n) * nb + si * a.gemm_m, nb, Ap, Bp,
-                          ld, M, N, tsz(tk), si == sj, lds);
-          else
-            gemm_nt_f32(C, Ap, Bp, ld, M, N, tsz(tk), false, lds);
+            gemm_nt_f32_d(Dsys + (int64_t)ti * nb * nb + (int64_t)(sj * bn) * nb + si * bm, nb, Ap, Bp, ld, M, N,
+                          tsz(tk), si == sj, lds);
+          else if (bm == 256 && bn == 128 && tsz(tk) % 32 == 0)
+            gemm_f32_wide<32, 3>(C, Ap, Bp, ld, M, N, tsz(tk), lds);
+          else  // 128-row products (a 256-row item whose K is not a multiple of 32 takes two)
+            for (int r0 = 0; r0 < M; r0 += 128)
+              gemm_nt_f32(C + r0, Ap + r0, Bp, ld, imin(128, M - r0), N, tsz(tk), false, lds);
         } else {
           if (SEG == 128 && (((int)ld & 1) != 0 || (((M | N) & 1) != 0 && ld <= sn) || misaligned)) {
             raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
