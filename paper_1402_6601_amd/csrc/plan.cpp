@@ -24,10 +24,14 @@
 // POTRF(k) -> FTRSV(k) and TRSM(i, k) -> FGEMV(i, k).
 //
 // Priority: the upward rank of HEFT (section 3.1): rank(t) = w(t) + max over
-// successors s of rank(s), with w the task's flop count in units of nb^3/3
-// (POTRF 1, TRSM 3, SYRK 3, GEMM 6; TRSV 1, GEMV 2) and no communication
-// term (one device).  Every weight is positive, so a task's rank exceeds each
-// successor's and the decreasing-rank order is topological.
+// successors s of rank(s), with w HEFT's computation cost of the task: the
+// time of its work items summed over its parts, in units of about 200 us at
+// nb = 512 on this part (POTRF 5, TRSM 10, SYRK 4, GEMM 6; TRSV 1, GEMV 2),
+// and no communication term (one device).  Flop counts (1, 3, 3, 6) would
+// undervalue POTRF and TRSM, whose tile kernels run far below the GEMM's
+// efficiency, and start the critical path late.  Every weight is positive, so
+// a task's rank exceeds each successor's and the decreasing-rank order is
+// topological.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -79,9 +83,9 @@ struct FactorIds {
 
 int64_t weight(int32_t kind) {
   switch (kind) {
-    case TK_POTRF: return 1;
-    case TK_TRSM: return 3;
-    case TK_SYRK: return 3;
+    case TK_POTRF: return 5;
+    case TK_TRSM: return 10;
+    case TK_SYRK: return 4;
     case TK_GEMM: return 6;
     case TK_FTRSV: case TK_BTRSV: return 1;
     case TK_GREV: return 6;

@@ -20,7 +20,7 @@ from tests import tiled_ref
 tc = pytest.importorskip("paper_1402_6601_amd")
 
 POTRF, TRSM, SYRK, GEMM, FTRSV, FGEMV, BTRSV, BGEMV = range(8)
-WEIGHT = {POTRF: 1, TRSM: 3, SYRK: 3, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2}
+WEIGHT = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2}
 
 
 def plan(op, n, nb, policy=0, seed=0):
