@@ -246,3 +246,38 @@ def test_simulated_protocol_times_out_on_a_corrupted_counter():
     victim = int(np.where((p["kind"] == POTRF) & (p["k"] == 3))[0][0])
     _, status = simulate(p, np.array(A), n, nb, corrupt=victim, spin_limit=2000)
     assert status == "timeout"
+
+
+TRTRI = 12
+
+
+@pytest.mark.parametrize("n,nb", [(1000, 128), (2048, 512), (513, 512), (1100, 160), (300, 16)])
+def test_mixed_factor_plan_split(n, nb):
+    """The mixed-precision factorization's DAG is the factorization's plus
+    TRTRI(k) after POTRF(k) (no task waits for it); its GEMM tasks are split
+    into 256 x 128 output sub-tiles, its SYRK tasks into the lower 128 x 128
+    blocks of the diagonal tile, its TRSM tasks into 32-row strips."""
+    pm = plan(tc.OP_MIXED_FACTOR, n, nb)
+    pf = plan(0, n, nb)
+    T = -(-n // nb)
+    tsz = lambda i: min(nb, n - nb * i)
+    trtri = {task_key(pm, t) for t in range(pm["ntask"]) if int(pm["kind"][t]) == TRTRI}
+    assert trtri == {(TRTRI, k, k, k) for k in range(T)}
+    em = edges(pm)
+    assert {e for e in em if e[1][0] != TRTRI} == edges(pf)
+    assert {e for e in em if e[1][0] == TRTRI} == {((POTRF, k, k, k), (TRTRI, k, k, k)) for k in range(T)}
+    assert not any(e[0][0] == TRTRI for e in em)
+    for t in range(pm["ntask"]):
+        kind, i, j = int(pm["kind"][t]), int(pm["i"][t]), int(pm["j"][t])
+        if kind == GEMM:
+            want = -(-tsz(i) // 256) * -(-tsz(j) // 128)
+        elif kind == SYRK:
+            s = -(-tsz(i) // 128)
+            want = s * (s + 1) // 2
+        elif kind == TRSM:
+            want = -(-tsz(i) // 32)
+        else:
+            continue
+        assert pm["parts"][t] == want, (kind, i, j)
+    # every item of every task is listed once, in claim order
+    assert pm["nitem"] == int(np.sum(pm["parts"][:pm["ntask"]]))
