@@ -663,20 +663,42 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
       // code is fully unrolled and x stays in registers).
       double x[PW];
       const int r = imin(lane, w - 1);
+      // every load is issued before any is used (kept out of the selects below)
+      double v[PW];
 #pragma unroll
       for (int c = 0; c < PW; ++c) {
-        const double v = Ps[imin(c, w - 1) * PPLD + r];
-        x[c] = (lane < w) ? (((c <= lane) & (c < w)) ? v : 0.0) : (c == lane ? 1.0 : 0.0);
+        v[c] = Ps[imin(c, w - 1) * PPLD + r];
+        asm volatile("" : "+v"(v[c]));
       }
+#pragma unroll
+      for (int c = 0; c < PW; ++c)
+        x[c] = (lane < w) ? (((c <= lane) & (c < w)) ? v[c] : 0.0) : (c == lane ? 1.0 : 0.0);
       int info = 0;
+      double pinv[PW];  // the pivots' reciprocals, also used for the rows below the block
 #pragma unroll
       for (int cc = 0; cc < PW; ++cc) {
         const double d = readlane_f64(x[cc], cc);
         // the first column whose pivot is not positive; the arithmetic goes on
         // (its results are discarded when info != 0)
         info = (info == 0 && !(d > 0.0)) ? c0 + cc + 1 : info;
-        const double l = sqrt(d);
-        const double inv = 1.0 / l;
+        // l = sqrt(d) and 1/l from the hardware reciprocal square root and two
+        // Newton steps (y to about an ulp; then l = d y with one residual
+        // correction), a far shorter dependent chain than a correctly rounded
+        // square root and division; exact for powers of four.  Tiny (and
+        // non-positive) pivots take the correctly rounded path.
+        double l, inv;
+        if (d >= 0x1p-900) {
+          double y = __builtin_amdgcn_rsq(d);
+          y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
+          y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
+          l = d * y;
+          l = fma(fma(-l, l, d), 0.5 * y, l);
+          inv = y;
+        } else {
+          l = sqrt(d);
+          inv = 1.0 / l;
+        }
+        pinv[cc] = inv;
         x[cc] = (lane == cc) ? l : ((lane > cc) ? x[cc] * inv : x[cc]);
 #pragma unroll
         for (int c2 = cc + 1; c2 < PW; ++c2) {
@@ -693,7 +715,10 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
       if (lane < PW) {
 #pragma unroll
         for (int c = 0; c < PW; ++c) Ldd[lane * (PW + 1) + c] = (c <= lane) ? x[c] : 0.0;
-        Linv[lane] = 1.0 / x[lane];
+        double li = pinv[0];
+#pragma unroll
+        for (int c = 1; c < PW; ++c) li = (lane == c) ? pinv[c] : li;
+        Linv[lane] = li;
       }
     }
     __syncthreads();
