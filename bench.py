@@ -342,7 +342,7 @@ def run_mixed(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     seed = 2 if args.seed == 1 else args.seed
-    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM}[args.policy]
+    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM, "list": tc.POLICY_LIST}[args.policy]
     r = measure_mixed(torch, tc, dev, args.n, args.nb, args.nrhs, seed, 1e-4, args.steps, args.warmup, policy)
     out = {
         "metric": METRIC,
@@ -454,7 +454,7 @@ def run_adjoint(args):
     seed = 3 if args.seed == 1 else args.seed
     n = 8192 if args.n == 32768 else args.n
     nb = 256 if args.nb == 512 else args.nb
-    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM}[args.policy]
+    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM, "list": tc.POLICY_LIST}[args.policy]
     r = measure_adjoint(torch, tc, dev, n, nb, seed, args.steps, args.warmup, policy,
                         cpu_sample_n=min(args.cpu_sample_n, 3072))
     out = {
@@ -491,7 +491,7 @@ def main():
     ap.add_argument("--nb", type=int, default=512)
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--policy", choices=["rank", "fifo", "random"], default="rank")
+    ap.add_argument("--policy", choices=["rank", "fifo", "random", "list"], default="list")
     ap.add_argument("--cpu-sample-n", type=int, default=8192,
                     help="order of the leading block the CPU oracle factors (0 = skip)")
     ap.add_argument("--calib-copy", type=int, default=0, help="only run a device copy of this many bytes")
@@ -533,7 +533,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     n, nb, nrhs, K, Wm = args.n, args.nb, args.nrhs, args.steps, args.warmup
-    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM}[args.policy]
+    policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM, "list": tc.POLICY_LIST}[args.policy]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 

@@ -53,9 +53,13 @@ extern "C" {
 #define TCHOL_OP_BACKWARD 3 /* adjoint of the factorization */
 #define TCHOL_OP_MIXED_FACTOR 4 /* the factorization launch of tchol_solve_mixed (plan introspection only) */
 
-#define TCHOL_POLICY_RANK 0   /* decreasing upward rank (default)          */
+#define TCHOL_POLICY_RANK 0   /* decreasing upward rank                    */
 #define TCHOL_POLICY_FIFO 1   /* step-major: (k, kind, i, j) ascending      */
 #define TCHOL_POLICY_RANDOM 2 /* a seeded random topological order          */
+#define TCHOL_POLICY_LIST 3   /* HEFT's list schedule (default): ready items by
+                                 decreasing upward rank on 256 identical workers
+                                 with the rank weights as costs, in simulated
+                                 start order                                    */
 
 #define TCHOL_E_HIP (-100)         /* a HIP runtime call failed              */
 #define TCHOL_E_TIMEOUT (-101)     /* the kernel's bounded wait expired      */

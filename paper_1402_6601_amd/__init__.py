@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
 OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD, OP_MIXED_FACTOR = 0, 1, 2, 3, 4
-POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2
+POLICY_RANK, POLICY_FIFO, POLICY_RANDOM, POLICY_LIST = 0, 1, 2, 3
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV = -100, -101, -102, -103, -104
 LOWP_FP32 = 1
 KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV",
@@ -119,7 +119,7 @@ def workspace_bytes(op: int, n: int, nb: int, nrhs: int = 0) -> int:
 
 # ---------------------------------------------------------------- plan introspection (host only)
 
-def plan_query(op: int, n: int, nb: int, policy: int = POLICY_RANK, seed: int = 0) -> dict:
+def plan_query(op: int, n: int, nb: int, policy: int = POLICY_LIST, seed: int = 0) -> dict:
     """The task DAG, ranks and claim order the library would execute (no GPU needed)."""
     lib = load()
     counts = np.zeros(4, dtype=np.int64)
@@ -158,7 +158,7 @@ def _i64(x):
     return np.ascontiguousarray(np.asarray(x, dtype=np.int64))
 
 
-def batched_plan_query(n, nb, policy: int = POLICY_RANK, seed: int = 0) -> dict:
+def batched_plan_query(n, nb, policy: int = POLICY_LIST, seed: int = 0) -> dict:
     """The merged factor + solve DAG of a batched launch (no GPU needed); as
     plan_query, plus "sys", the system of every task."""
     lib = load()
@@ -242,7 +242,7 @@ def _opts(policy, seed, wait_limit_us, want_ms, trace):
     return o, ms
 
 
-def factor_(A, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+def factor_(A, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
             want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Factor in place.  A: CUDA float64 (n, n) contiguous, symmetric (only the
     lower triangle of its column-major reading, i.e. the row-major upper
@@ -276,7 +276,7 @@ def factor(A, nb: int, **kw):
     return torch.tril(W.mT), info
 
 
-def solve_(L, Bc, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+def solve_(L, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
            want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Solve in place.  L: the (n, n) buffer factored by factor_ (column-major
     lower = L).  Bc: CUDA float64 (nrhs, n) contiguous, i.e. B column-major.
@@ -310,7 +310,7 @@ def solve(Lbuf, B, nb: int, **kw):
     return X.reshape(-1) if vec else X
 
 
-def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: int = POLICY_RANK, seed: int = 0,
+def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: int = POLICY_LIST, seed: int = 0,
                           wait_limit_us: int = 0, ws=None, want_kernel_ms: bool = False, trace=None,
                           check: bool = True):
     """Factor and solve many systems in one launch, in place.
@@ -351,7 +351,7 @@ def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: 
 
 
 def solve_mixed_(A, Bc, nb: int, *, tol: float = 1e-12, maxit: int = 30, lowp: int = LOWP_FP32,
-                 policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+                 policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
                  want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Mixed-precision solve with iterative refinement, in place on Bc.
 
@@ -414,7 +414,7 @@ def solve_mixed(A, B, nb: int, *, fallback: bool = True, **kw):
     return (X.reshape(-1) if vec else X), {"rc": int(rc), "iters": iters, "berr": berr, "fallback": used}
 
 
-def backward_(Lbuf, Gb, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+def backward_(Lbuf, Gb, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
               want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Adjoint of the factorization, in place.  Lbuf: the (n, n) buffer factored
     by factor_ (column-major lower = L).  Gb: CUDA float64 (n, n) contiguous
@@ -492,7 +492,7 @@ def batched_f32_workspace_bytes(n, nb, nrhs: int) -> int:
     return int(r)
 
 
-def factor_solve_batched_f32_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: int = POLICY_RANK,
+def factor_solve_batched_f32_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: int = POLICY_LIST,
                               seed: int = 0, wait_limit_us: int = 0, ws=None, want_kernel_ms: bool = False,
                               trace=None, check: bool = True):
     """Factor and solve many FP32 systems in one launch, in place (FP32 updates,
@@ -531,7 +531,7 @@ def factor_solve_batched_f32_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, poli
     return (info, ms.value) if want_kernel_ms else info
 
 
-def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_RANK, seed: int = 0, wait_limit_us: int = 0, ws=None,
+def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
                   want_kernel_ms: bool = False, trace=None, check: bool = True):
     """Factor A in place and solve in place on Bc in one launch (merged DAG).
     A: CUDA float64 (n, n) contiguous symmetric; Bc: CUDA float64 (nrhs, n)

@@ -35,6 +35,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <queue>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -288,6 +289,74 @@ const Split& split_for(int32_t op) {
 
 namespace {
 
+// HEFT's list scheduling (section 3.1) on P identical workers: whenever a
+// worker is free, it takes the next work item of the ready task of highest
+// upward rank (ties as in the rank order); an item lasts its task's weight
+// divided by the task's parts.  The work items, in the order the simulation
+// starts them, are the ticket list: a worker that claims a ticket then tends
+// to find it ready, instead of waiting on a high-rank task whose
+// predecessors are still running.  Start times respect the dependences, so
+// the list is topological.  The task order records each task's first item.
+constexpr int kListWorkers = 256;
+
+bool list_schedule(Plan& p, int64_t ni) {
+  const int64_t nt = p.ntask();
+  std::vector<double> dur(nt);
+  for (int64_t t = 0; t < nt; ++t) {
+    double w = (double)weight(p.kind[t]);
+    if (p.op == TCHOL_OP_BATCHED) {
+      const double u = (double)(p.systems[p.sys[t]].nb / 16);
+      w *= u * u * u;
+    }
+    dur[t] = w / (double)std::max(1, p.parts[t]);
+  }
+  auto lower = [&](int32_t a, int32_t c) {  // priority_queue: true when a ranks below c
+    if (p.rank[a] != p.rank[c]) return p.rank[a] < p.rank[c];
+    return tie_key(p, c) < tie_key(p, a);
+  };
+  std::priority_queue<int32_t, std::vector<int32_t>, decltype(lower)> ready(lower);
+  using Ev = std::pair<double, int32_t>;  // (time, task) of an item's end
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> ends;
+  std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+  for (int w = 0; w < kListWorkers; ++w) free_at.push(0.0);
+  std::vector<int32_t> indeg = p.dep0, next_part(nt, 0), left(p.parts.begin(), p.parts.end());
+  for (int64_t t = 0; t < nt; ++t)
+    if (indeg[t] == 0) ready.push((int32_t)t);
+  auto finish = [&](int32_t t) {
+    if (--left[t] == 0)
+      for (int32_t e = p.succ_off[t]; e < p.succ_off[t + 1]; ++e)
+        if (--indeg[p.succ[e]] == 0) ready.push(p.succ[e]);
+  };
+  std::vector<char> listed(nt, 0);
+  p.order.clear();
+  while ((int64_t)p.item_task.size() < ni) {
+    const double tw = free_at.top();
+    while (!ends.empty() && ends.top().first <= tw) {
+      finish(ends.top().second);
+      ends.pop();
+    }
+    if (ready.empty()) {  // idle until the next item ends
+      if (ends.empty()) return false;  // unreachable for an acyclic graph
+      free_at.pop();
+      free_at.push(ends.top().first);
+      continue;
+    }
+    const int32_t t = ready.top();
+    const int32_t q = next_part[t]++;
+    if (next_part[t] == p.parts[t]) ready.pop();
+    free_at.pop();
+    free_at.push(tw + dur[t]);
+    ends.push(Ev(tw + dur[t], t));
+    p.item_task.push_back(t);
+    p.item_part.push_back(q);
+    if (!listed[t]) {
+      listed[t] = 1;
+      p.order.push_back(t);
+    }
+  }
+  return (int64_t)p.order.size() == nt;
+}
+
 // dependency counters, CSR successors, upward ranks, claim order and work items
 bool finalize(Plan& p, std::vector<std::vector<int32_t>>& succ, int32_t policy, uint32_t seed) {
   const int64_t nt = p.ntask();
@@ -325,7 +394,7 @@ bool finalize(Plan& p, std::vector<std::vector<int32_t>>& succ, int32_t policy, 
   } else if (policy == TCHOL_POLICY_FIFO) {
     std::stable_sort(p.order.begin(), p.order.end(),
                      [&](int32_t a, int32_t c) { return tie_key(p, a) < tie_key(p, c); });
-  } else {
+  } else if (policy == TCHOL_POLICY_RANDOM) {
     // Kahn's algorithm, choosing uniformly among the ready tasks
     std::vector<int32_t> indeg = p.dep0, ready;
     for (int64_t t = 0; t < nt; ++t)
@@ -347,6 +416,7 @@ bool finalize(Plan& p, std::vector<std::vector<int32_t>>& succ, int32_t policy, 
   if (ni > (int64_t)INT32_MAX / 2) return false;
   p.item_task.reserve(ni);
   p.item_part.reserve(ni);
+  if (policy == TCHOL_POLICY_LIST) return list_schedule(p, ni);
   for (int32_t t : p.order)
     for (int32_t q = 0; q < p.parts[t]; ++q) {
       p.item_task.push_back(t);

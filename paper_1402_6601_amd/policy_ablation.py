@@ -3,15 +3,18 @@
     python -m paper_1402_6601_amd.policy_ablation [--n 32768] [--nb 512] [--reps 5]
 
 The persistent kernel's workers claim work items in a ticket order fixed
-by the host planner.  Three orders are compared:
+by the host planner.  Four orders are compared:
 
 * rank   -- decreasing upward rank, the priority rule of HEFT that the
             paper's scheduler recalls (section 3.1); ties by (step, kind, i, j);
 * fifo   -- step-major order (k ascending, then kind, i, j): the order a
             sequential tile algorithm issues its tasks in;
 * random -- a random topological order (seeded).
+* list   -- HEFT's list schedule: the work items in the order a simulation
+            of 256 identical workers, each taking the ready item of highest
+            upward rank, starts them.
 
-Every order is topological, so all three compute the same tile operations
+Every order is topological, so all four compute the same tile operations
 in the same per-tile order; the factor must be bitwise identical and only
 the time may differ.  Prints one JSON line per policy and a summary line.
 """
@@ -51,7 +54,7 @@ def main(argv=None):
     A0, _ = spd_inputs.spd_matrix_device(n, args.seed, 1.0, device=dev)
     W = torch.empty_like(A0)
     ws = torch.empty(tc.workspace_bytes(tc.OP_FACTOR, n, nb), dtype=torch.uint8, device=dev)
-    runs = [("rank", tc.POLICY_RANK, 0), ("fifo", tc.POLICY_FIFO, 0)]
+    runs = [("rank", tc.POLICY_RANK, 0), ("list", tc.POLICY_LIST, 0), ("fifo", tc.POLICY_FIFO, 0)]
     runs += [("random", tc.POLICY_RANDOM, s) for s in args.random_seeds]
     ref = None
     results = []

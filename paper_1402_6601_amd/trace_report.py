@@ -1,6 +1,6 @@
 """Per-kind work-item timing of one launch, from the kernel's trace buffer.
 
-    python -m paper_1402_6601_amd.trace_report [--op factor|mixed|adjoint] [--n N] [--nb NB]
+    python -m paper_1402_6601_amd.trace_report [--op factor|mixed|adjoint] [--n N] [--nb NB] [--policy P]
 
 The persistent kernel can record, per work item, the wall clock (100 MHz)
 when its ticket was claimed, when its wait ended, when it finished, and the
@@ -59,6 +59,7 @@ def main(argv=None):
     ap.add_argument("--op", choices=["factor", "mixed", "adjoint"], default="factor")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--nb", type=int, default=0)
+    ap.add_argument("--policy", choices=["rank", "list", "fifo", "random"], default="list")
     args = ap.parse_args(argv)
     import torch
     import paper_1402_6601_amd as tc
@@ -68,36 +69,37 @@ def main(argv=None):
         print("trace_report needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    pol = {"rank": tc.POLICY_RANK, "list": tc.POLICY_LIST, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM}[args.policy]
     if args.op == "adjoint":
         n, nb = args.n or 8192, args.nb or 256
         A, rng = spd_inputs.spd_matrix_device(n, 3, 1.0, device=dev)
         Lb = torch.from_numpy(spd_inputs.lower_upstream(rng, n)).to(dev).mT.contiguous()
         W = A.clone()
         tc.factor_(W, nb)
-        plan = tc.plan_query(tc.OP_BACKWARD, n, nb)
+        plan = tc.plan_query(tc.OP_BACKWARD, n, nb, pol)
         trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
         G = Lb.clone()
-        tc.backward_(W, G, nb)
+        tc.backward_(W, G, nb, policy=pol)
         G.copy_(Lb)
-        _, ms = tc.backward_(W, G, nb, want_kernel_ms=True, trace=trace)
+        _, ms = tc.backward_(W, G, nb, policy=pol, want_kernel_ms=True, trace=trace)
     else:
         n, nb = args.n or 32768, args.nb or 512
         mixed = args.op == "mixed"
         A, rng = spd_inputs.spd_matrix_device(n, 2 if mixed else 1, 1e-4 if mixed else 1.0, device=dev)
         # the mixed-precision factorization's DAG also holds the TRTRI tasks
-        plan = tc.plan_query(tc.OP_MIXED_FACTOR if mixed else tc.OP_FACTOR, n, nb)
+        plan = tc.plan_query(tc.OP_MIXED_FACTOR if mixed else tc.OP_FACTOR, n, nb, pol)
         trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
         if mixed:
             B = torch.from_numpy(spd_inputs.rhs(rng, n, 16)).to(dev).t().contiguous()
             X = B.clone()
-            tc.solve_mixed_(A, X, nb, maxit=0)
+            tc.solve_mixed_(A, X, nb, maxit=0, policy=pol)
             X.copy_(B)
-            _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, want_kernel_ms=True, trace=trace)
+            _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, policy=pol, want_kernel_ms=True, trace=trace)
         else:
             W = A.clone()
-            tc.factor_(W, nb)
+            tc.factor_(W, nb, policy=pol)
             W.copy_(A)
-            _, ms = tc.factor_(W, nb, want_kernel_ms=True, trace=trace)
+            _, ms = tc.factor_(W, nb, policy=pol, want_kernel_ms=True, trace=trace)
     print("kernel %.3f ms (HIP events), n=%d nb=%d" % (ms, n, nb), flush=True)
     report(tc, plan, trace, args.op)
     return 0

@@ -106,7 +106,7 @@ def test_adjoint_bitwise_across_policies(tc):
     L = oracle.cholesky(A)
     Lbar = spd_inputs.lower_upstream(rng, 700)
     ref = _adjoint(tc, L, Lbar, 128)
-    for pol, seed in [(tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 3)]:
+    for pol, seed in [(tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 3)]:
         got = _adjoint(tc, L, Lbar, 128, policy=pol, seed=seed)
         assert np.array_equal(got, ref)
 

@@ -117,7 +117,7 @@ def test_batched_bitwise_across_policies(tc):
     As, bs = _systems(13, sizes)
     nb = [_nb_single(400), 16, 128, 128, 64]
     ref = _run(tc, As, bs, nb)
-    for pol, seed in [(tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 5)]:
+    for pol, seed in [(tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 5)]:
         got = _run(tc, As, bs, nb, policy=pol, seed=seed)
         assert np.array_equal(got[0], ref[0])
         assert all(np.array_equal(a, b) for a, b in zip(got[1], ref[1]))

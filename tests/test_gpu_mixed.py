@@ -94,7 +94,7 @@ def test_mixed_reported_error_matches_oracle_without_refinement(tc):
 def test_mixed_bitwise_across_policies(tc):
     A, b = spd_inputs.spd_matrix_and_rhs(900, 28, nrhs=3, shift=1e-4)
     ref = _mixed(tc, A, b, 128)
-    for pol, seed in [(tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 9)]:
+    for pol, seed in [(tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 9)]:
         got = _mixed(tc, A, b, 128, policy=pol, seed=seed)
         assert got[0] == ref[0] and got[1] == ref[1]
         assert np.array_equal(got[3], ref[3])

@@ -129,7 +129,7 @@ def test_bitwise_determinism_across_runs_and_policies(tc):
     for _ in range(4):
         L, info, _ = _factor(tc, A, 128)
         assert info == 0 and np.array_equal(L, ref)
-    for pol, seed in [(tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 1), (tc.POLICY_RANDOM, 2)]:
+    for pol, seed in [(tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 1), (tc.POLICY_RANDOM, 2)]:
         L, info, _ = _factor(tc, A, 128, policy=pol, seed=seed)
         assert info == 0 and np.array_equal(L, ref)
 

@@ -160,10 +160,47 @@ def check_topological(p):
             assert first[s] < first[t]
 
 
-@pytest.mark.parametrize("policy,seed", [(0, 0), (1, 0), (2, 1), (2, 7)])
+@pytest.mark.parametrize("policy,seed", [(0, 0), (1, 0), (2, 1), (2, 7), (3, 0)])
 @pytest.mark.parametrize("op,n,nb", [(0, 1024, 128), (0, 1000, 96), (1, 1000, 128)])
 def test_claim_order_is_topological(policy, seed, op, n, nb):
     check_topological(plan(op, n, nb, policy, seed))
+
+
+@pytest.mark.parametrize("op,n,nb", [(0, 4096, 256), (0, 1000, 96), (tc.OP_MIXED_FACTOR, 2048, 512)])
+def test_list_schedule_order(op, n, nb):
+    """HEFT's list schedule (policy 3): every work item listed exactly once, in
+    a topological order that starts with POTRF(0); an item's ready time in the
+    simulation never exceeds the simulated start of the items listed after it,
+    so that, simulated again with the same costs, the list order is the start
+    order (each item starts no later than the one after it)."""
+    p = plan(op, n, nb, 3)
+    check_topological(p)
+    cnt = np.bincount(p["item_task"], minlength=p["ntask"])
+    assert np.array_equal(cnt, p["parts"][:p["ntask"]])
+    assert int(p["kind"][p["item_task"][0]]) == POTRF and int(p["k"][p["item_task"][0]]) == 0
+    # replay: 256 workers take the tickets in order; a ticket's item starts
+    # when both its worker is free and its task's predecessors are done
+    w = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, 12: 3}
+    dur = np.array([w.get(int(k), 2) / max(1, int(q)) for k, q in zip(p["kind"], p["parts"])])
+    import heapq
+    free = [0.0] * 256
+    heapq.heapify(free)
+    done_at = np.zeros(p["ntask"])
+    left = p["parts"][:p["ntask"]].copy()
+    preds = [[] for _ in range(p["ntask"])]
+    for t in range(p["ntask"]):
+        for e in range(p["succ_off"][t], p["succ_off"][t + 1]):
+            preds[int(p["succ"][e])].append(t)
+    last = 0.0
+    for t in p["item_task"]:
+        t = int(t)
+        ready = max((done_at[q] for q in preds[t]), default=0.0)
+        start = max(heapq.heappop(free), ready)
+        assert start >= last - 1e-9   # the list is in start order
+        last = start
+        heapq.heappush(free, start + dur[t])
+        left[t] -= 1
+        done_at[t] = max(done_at[t], start + dur[t])
 
 
 def test_rank_order_ties_are_deterministic():
