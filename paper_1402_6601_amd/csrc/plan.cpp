@@ -82,7 +82,20 @@ struct FactorIds {
   std::vector<int32_t> potrf, trsm;  // trsm[i * T + k]
 };
 
-int64_t weight(int32_t kind) {
+// The mixed-precision factorization (OP_FACTOR_INV) has its own costs: its
+// GEMM items are FP32 products (256 x 128 sub-tiles), its TRTRI tasks as
+// long as a TRSM: POTRF 5, TRSM 11, SYRK 4, GEMM 4, TRTRI 11.
+int64_t weight(int32_t kind, int32_t op) {
+  if (op == OP_FACTOR_INV) {
+    switch (kind) {
+      case TK_POTRF: return 5;
+      case TK_TRSM: return 11;
+      case TK_SYRK: return 4;
+      case TK_GEMM: return 4;
+      case TK_TRTRI: return 11;
+      default: break;
+    }
+  }
   switch (kind) {
     case TK_POTRF: return 5;
     case TK_TRSM: return 10;
@@ -303,7 +316,7 @@ bool list_schedule(Plan& p, int64_t ni) {
   const int64_t nt = p.ntask();
   std::vector<double> dur(nt);
   for (int64_t t = 0; t < nt; ++t) {
-    double w = (double)weight(p.kind[t]);
+    double w = (double)weight(p.kind[t], p.op);
     if (p.op == TCHOL_OP_BATCHED) {
       const double u = (double)(p.systems[p.sys[t]].nb / 16);
       w *= u * u * u;
@@ -376,7 +389,7 @@ bool finalize(Plan& p, std::vector<std::vector<int32_t>>& succ, int32_t policy, 
   for (int64_t t = nt - 1; t >= 0; --t) {
     int64_t best = 0;
     for (int32_t e = p.succ_off[t]; e < p.succ_off[t + 1]; ++e) best = std::max(best, p.rank[p.succ[e]]);
-    int64_t w = weight(p.kind[t]);
+    int64_t w = weight(p.kind[t], p.op);
     if (p.op == TCHOL_OP_BATCHED) {
       const int64_t u = p.systems[p.sys[t]].nb / 16;
       w *= u * u * u;

@@ -180,7 +180,7 @@ def test_list_schedule_order(op, n, nb):
     assert int(p["kind"][p["item_task"][0]]) == POTRF and int(p["k"][p["item_task"][0]]) == 0
     # replay: 256 workers take the tickets in order; a ticket's item starts
     # when both its worker is free and its task's predecessors are done
-    w = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, 12: 3}
+    w = {POTRF: 5, TRSM: 11, SYRK: 4, GEMM: 4, 12: 11} if op == tc.OP_MIXED_FACTOR else {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, 12: 3}
     dur = np.array([w.get(int(k), 2) / max(1, int(q)) for k, q in zip(p["kind"], p["parts"])])
     import heapq
     free = [0.0] * 256
