@@ -56,10 +56,10 @@ extern "C" {
 #define TCHOL_POLICY_RANK 0   /* decreasing upward rank                    */
 #define TCHOL_POLICY_FIFO 1   /* step-major: (k, kind, i, j) ascending      */
 #define TCHOL_POLICY_RANDOM 2 /* a seeded random topological order          */
-#define TCHOL_POLICY_LIST 3   /* HEFT's list schedule (default): ready items by
-                                 decreasing upward rank on 256 identical workers
-                                 with the rank weights as costs, in simulated
-                                 start order                                    */
+#define TCHOL_POLICY_LIST 3   /* HEFT's list schedule (section 3.1; the default
+                                 with NULL options): ready items by decreasing
+                                 upward rank on 256 identical workers with the
+                                 rank weights as costs, in simulated start order */
 
 #define TCHOL_E_HIP (-100)         /* a HIP runtime call failed              */
 #define TCHOL_E_TIMEOUT (-101)     /* the kernel's bounded wait expired      */
@@ -74,7 +74,8 @@ extern "C" {
 
 /* Optional knobs; pass NULL to the _ex entry points for the defaults. */
 typedef struct tchol_opts {
-  int32_t policy;      /* TCHOL_POLICY_*                                         */
+  int32_t policy;      /* TCHOL_POLICY_* (a zeroed struct means TCHOL_POLICY_RANK;
+                          NULL options mean TCHOL_POLICY_LIST)                    */
   uint32_t seed;       /* seed of TCHOL_POLICY_RANDOM                             */
   int64_t wait_limit_us; /* bound on any single dependency wait inside the kernel;
                             0 = default (30 s); it turns a hang into
