@@ -1083,14 +1083,19 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
   build_block_fragments(Lkk, ld, m, trans, Fr);
   // fragments of the updates by solved block rb of the owned blocks ub = wave + 4t:
   // forward L[ub rows][rb cols], backward L[rb rows][ub cols]^T
+  // Only the blocks the solved block rb still updates are fetched (forward:
+  // ub > rb, backward: ub < rb): the same blocks that use the fragments.
   auto fetch = [&](int rb, double (&fl)[8][4]) __attribute__((always_inline)) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int ur = imin((wave + 4 * t) * 16 + l16, m - 1);
+      const int ub = wave + 4 * t;
+      if (trans ? (ub < rb) : (ub > rb && ub < nblk)) {
+        const int ur = imin(ub * 16 + l16, m - 1);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int q = imin(rb * 16 + 4 * kk + lg, m - 1);
-        fl[t][kk] = trans ? Lkk[(int64_t)ur * ld + q] : Lkk[(int64_t)q * ld + ur];
+        for (int kk = 0; kk < 4; ++kk) {
+          const int q = imin(rb * 16 + 4 * kk + lg, m - 1);
+          fl[t][kk] = trans ? Lkk[(int64_t)ur * ld + q] : Lkk[(int64_t)q * ld + ur];
+        }
       }
     }
   };
