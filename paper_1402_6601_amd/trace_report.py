@@ -1,13 +1,15 @@
 """Per-kind work-item timing of one launch, from the kernel's trace buffer.
 
-    python -m paper_1402_6601_amd.trace_report [--op factor|mixed|adjoint] [--n N] [--nb NB] [--policy P]
+    python -m paper_1402_6601_amd.trace_report [--op factor|mixed|solve|adjoint] [--n N] [--nb NB] [--policy P]
 
 The persistent kernel can record, per work item, the wall clock (100 MHz)
 when its ticket was claimed, when its wait ended, when it finished, and the
 task and workgroup (``tchol_opts.trace``).  This tool runs one launch of the
 chosen DAG on a synthetic input of the benchmark family (factor: shift 1,
 seed 1; mixed: shift 1e-4, seed 2, the factorization launch of the
-mixed-precision solve; adjoint: shift 1, seed 3, Lbar = tril N(0, 1)), and
+mixed-precision solve; solve: the 16-RHS forward and backward solve launch
+on the factor of the seed-1 matrix; adjoint: shift 1, seed 3,
+Lbar = tril N(0, 1)), and
 prints the makespan, the fraction of worker time spent running and waiting,
 per task kind the item count and mean / median / max duration and mean wait,
 and the busy fraction over time in 20 buckets.
@@ -56,7 +58,7 @@ def report(tc, plan, trace, tag, out=print):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", choices=["factor", "mixed", "adjoint"], default="factor")
+    ap.add_argument("--op", choices=["factor", "mixed", "solve", "adjoint"], default="factor")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--policy", choices=["rank", "list", "fifo", "random"], default="list")
@@ -95,6 +97,15 @@ def main(argv=None):
             tc.solve_mixed_(A, X, nb, maxit=0, policy=pol)
             X.copy_(B)
             _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, policy=pol, want_kernel_ms=True, trace=trace)
+        elif args.op == "solve":
+            plan = tc.plan_query(tc.OP_SOLVE, n, nb, pol)
+            trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
+            tc.factor_(A, nb, policy=pol)
+            B = torch.from_numpy(spd_inputs.rhs(rng, n, 16)).to(dev).t().contiguous()
+            X = B.clone()
+            tc.solve_(A, X, nb, policy=pol)
+            X.copy_(B)
+            _, ms = tc.solve_(A, X, nb, policy=pol, want_kernel_ms=True, trace=trace)
         else:
             W = A.clone()
             tc.factor_(W, nb, policy=pol)
