@@ -94,6 +94,58 @@ def sampled_reconstruction(torch, W, A0, n, count=64, seed=123):
     return worst / (n * 2.0 ** -52 * amax)
 
 
+def sampled_solve_eta(torch, A0, B0, Xc, n, count=64, seed=321):
+    """Normwise backward error of each right-hand side's solution over sampled
+    rows of the residual b - A x, with the sums in long double on the host.
+    B0: (n, nrhs) row-major right-hand sides; Xc: (nrhs, n), the solutions in
+    column-major order; A0 the pristine symmetric input."""
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(n, min(count, n), replace=False)
+    Ar = A0[torch.as_tensor(rows, device=A0.device)].cpu().numpy().astype(np.longdouble)
+    Xh = Xc.t().cpu().numpy()
+    Bh = B0.cpu().numpy()
+    R = Bh[rows].astype(np.longdouble) - Ar @ Xh.astype(np.longdouble)
+    anorm = float(A0.abs().sum(dim=1).max().item())
+    den = anorm * np.max(np.abs(Xh), axis=0) + np.max(np.abs(Bh), axis=0)
+    return [float(v) for v in np.max(np.abs(R).astype(np.float64), axis=0) / den]
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the record beside the oracle timings."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_small_config(oracle, reps=30):
+    """The oracle on the small FP64 workload (n = 1024, seed 0, shift 1): factor
+    plus one-RHS solve, `reps` runs on all host threads (mean and 95 % interval)
+    and one run on a single thread."""
+    import spd_inputs
+    A, b = spd_inputs.spd_matrix_and_rhs(1024, 0, nrhs=1)
+    def once():
+        t = time.perf_counter()
+        F, info = oracle.potrf(A)
+        oracle.potrs(F, b)
+        return (time.perf_counter() - t) * 1e3
+    once()
+    ms_all = [once() for _ in range(reps)]
+    nthr = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        ms_one = once()
+    finally:
+        oracle.set_num_threads(nthr)
+    return {"workload": "n=1024 factor + 1-RHS solve (seed 0)", "threads": nthr, "ms_all_threads": ci95(ms_all),
+            "ms_one_thread": round(ms_one, 3)}
+
+
 def run_calib_copy(nbytes: int, reps: int):
     """A plain elementwise copy kernel (b = a * 1) that reads and writes
     nbytes each, to scale the PMC byte counters (a same-dtype copy_ may be
@@ -155,14 +207,17 @@ def run_batched(args):
         Bs[s_].copy_(B0)
     torch.cuda.synchronize()
     kernel_ms = []
+    failed = []
     t_start = time.perf_counter()
     for s_ in range(K):
         info, ms = run(As[s_], a_off, lda, Bs[s_], b_off, ns, nb, nrhs, ws=ws, want_kernel_ms=True)
         kernel_ms.append(ms)
+        if np.any(info != 0):   # the info array is read back by the call itself (host memory)
+            failed.append(s_)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    if np.any(info != 0):
-        raise RuntimeError("batched factorization failed")
+    if failed:
+        raise RuntimeError("batched factorization failed in timed steps %s" % failed)
     ms_per_step = (t_end - t_start) * 1e3 / K
     kmean = float(np.mean(kernel_ms))
     n64 = ns.astype(np.float64)
@@ -584,6 +639,20 @@ def main():
     log("timed %d steps: %.3f ms/step (events %.3f ms/step), factor + solve kernel mean %.3f ms"
         % (K, ms_per_step, ev0.elapsed_time(ev1) / K, float(np.mean(kernel_ms))))
 
+    # checks on the result of the last timed step (before any later launch):
+    # sampled entries of L L^T and sampled rows of its solve's residual, both
+    # in long double; the leading block of its L is kept for the oracle
+    recon = sampled_reconstruction(torch, work[K - 1], A0, n)
+    eta_rows = sampled_solve_eta(torch, A0, B0, rhs[K - 1], n)
+    m_lead = min(args.cpu_sample_n, n) if args.cpu_sample_n > 0 else 0
+    L_lead = np.tril(work[K - 1][:m_lead, :m_lead].cpu().numpy().T) if m_lead else None
+    log("last timed step: sampled reconstruction %.3e (bound 10), sampled solve eta %.3e"
+        % (recon, max(eta_rows)))
+    if not recon <= 10.0:
+        raise RuntimeError("sampled reconstruction error %.3e exceeds the backward-error bound 10" % recon)
+    if not max(eta_rows) <= 1e-14:
+        raise RuntimeError("sampled solve backward error %.3e above FP64 level" % max(eta_rows))
+
     flops = n ** 3 / 3.0
     value = flops / (ms_per_step * 1e-3) / 1e12
     kmean = float(np.mean(kernel_ms))
@@ -612,8 +681,6 @@ def main():
     if args.ci_reps:
         log("repeated %d launches: kernel mean %.3f ms" % (args.ci_reps, float(np.mean(rep_ms))))
 
-    # checks on the result of the last timed step
-    recon = sampled_reconstruction(torch, work[K - 1], A0, n)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -643,6 +710,7 @@ def main():
         "solve_kernel_ms": round(solve_kernel_ms, 3),
         "solve_hbm_gbs": round(n * n * 8.0 / (solve_kernel_ms * 1e-3) / 1e9, 1),
         "reconstruction_err_sampled": recon,
+        "solve_eta_sampled_max": max(eta_rows),
     }
     del work, rhs
 
@@ -668,16 +736,17 @@ def main():
         tcpu = time.perf_counter()
         F, info = oracle.potrf(Ahost)
         tcpu = time.perf_counter() - tcpu
-        Wt.copy_(A0)
-        tc.factor_(Wt, nb, policy=policy, ws=ws_f)
-        Lg = np.tril(Wt[:m, :m].cpu().numpy().T)
+        Lg = L_lead   # the leading block of the last timed step's L
         out["cpu_baseline"] = {"value": round((m ** 3 / 3.0) / tcpu / 1e12, 6), "unit": "TFLOP/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": "oracle FP64 unblocked Cholesky of the leading %dx%d principal block of "
                                          "the same n=%d matrix (its factor is the leading block of L); %.2f s"
                                          % (m, m, n, tcpu),
-                               "seconds": round(tcpu, 3)}
+                               "seconds": round(tcpu, 3), "cpu_model": cpu_model(),
+                               "small_config": oracle_small_config(oracle)}
         out["e_L_leading_block"] = oracle.factor_error(Lg, F) if info == 0 else None
+        if out["e_L_leading_block"] is None or not out["e_L_leading_block"] <= 1e-10:
+            raise RuntimeError("leading block of L disagrees with the oracle: %s" % out["e_L_leading_block"])
     print(json.dumps(out), flush=True)
 
 

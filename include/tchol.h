@@ -53,13 +53,14 @@ extern "C" {
 #define TCHOL_OP_BACKWARD 3 /* adjoint of the factorization */
 #define TCHOL_OP_MIXED_FACTOR 4 /* the factorization launch of tchol_solve_mixed (plan introspection only) */
 
-#define TCHOL_POLICY_RANK 0   /* decreasing upward rank                    */
-#define TCHOL_POLICY_FIFO 1   /* step-major: (k, kind, i, j) ascending      */
-#define TCHOL_POLICY_RANDOM 2 /* a seeded random topological order          */
-#define TCHOL_POLICY_LIST 3   /* HEFT's list schedule (section 3.1; the default
-                                 with NULL options): ready items by decreasing
-                                 upward rank on 256 identical workers with the
-                                 rank weights as costs, in simulated start order */
+#define TCHOL_POLICY_LIST 0   /* HEFT's list schedule (section 3.1), the default
+                                 (NULL options or a zeroed struct): ready items by
+                                 decreasing upward rank on 256 identical workers,
+                                 with measured task times as costs, in simulated
+                                 start order */
+#define TCHOL_POLICY_RANK 1   /* decreasing upward rank (task by task)      */
+#define TCHOL_POLICY_FIFO 2   /* step-major: (k, kind, i, j) ascending      */
+#define TCHOL_POLICY_RANDOM 3 /* a seeded random topological order          */
 
 #define TCHOL_E_HIP (-100)         /* a HIP runtime call failed              */
 #define TCHOL_E_TIMEOUT (-101)     /* the kernel's bounded wait expired      */
@@ -74,8 +75,8 @@ extern "C" {
 
 /* Optional knobs; pass NULL to the _ex entry points for the defaults. */
 typedef struct tchol_opts {
-  int32_t policy;      /* TCHOL_POLICY_* (a zeroed struct means TCHOL_POLICY_RANK;
-                          NULL options mean TCHOL_POLICY_LIST)                    */
+  int32_t policy;      /* TCHOL_POLICY_*; 0 (a zeroed struct, like NULL options)
+                          is TCHOL_POLICY_LIST                                   */
   uint32_t seed;       /* seed of TCHOL_POLICY_RANDOM                             */
   int64_t wait_limit_us; /* bound on any single dependency wait inside the kernel;
                             0 = default (30 s); it turns a hang into
@@ -155,8 +156,10 @@ TCHOL_API int32_t tchol_factor_solve(double *A, int64_t n, int64_t nb, double *B
    of the persistent kernel.  Paper: the same tile DAG (section 4.1) per
    system; the systems' DAGs are merged into one, each system's solve
    joined to its factorization by data flow (POTRF(k) before FTRSV(k),
-   TRSM(i, k) before FGEMV(i, k)), and claimed in decreasing upward rank
-   (section 3.1) measured in flops, so long critical paths start first.
+   TRSM(i, k) before FGEMV(i, k)), and claimed in HEFT's list-schedule
+   order over decreasing upward rank (section 3.1), with each task's cost its
+   kind's measured time scaled by the cube of its tile size, so that long
+   critical paths start first.
    Host arrays, one entry per system s:
      a_off[s]  element offset of A_s from A; A_s is n[s] x n[s], column-major,
                leading dimension lda[s] >= max(1, n[s]); lower triangle used;

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
 OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD, OP_MIXED_FACTOR = 0, 1, 2, 3, 4
-POLICY_RANK, POLICY_FIFO, POLICY_RANDOM, POLICY_LIST = 0, 1, 2, 3
+POLICY_LIST, POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2, 3
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV = -100, -101, -102, -103, -104
 LOWP_FP32 = 1
 KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV",
@@ -558,3 +558,4 @@ def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, w
     if rc < 0 and check:
         raise TcholError(rc, "tchol_factor_solve")
     return (rc, ms.value) if want_kernel_ms else rc
+

@@ -187,6 +187,8 @@ hipError_t device_info(DeviceInfo* out) {
   return hipSuccess;
 }
 
+bool policy_ok(int32_t p) { return p >= TCHOL_POLICY_LIST && p <= TCHOL_POLICY_RANDOM; }
+
 bool nb_ok(int64_t nb) { return nb >= TCHOL_NB_MIN && nb <= TCHOL_NB_MAX && nb % 16 == 0; }
 
 const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr};
@@ -285,7 +287,7 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
 int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrhs, void* ws, int64_t ws_bytes,
             void* stream_v, const tchol_opts* opts, int32_t ws_arg) {
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_LIST) return TCHOL_E_UNSUPPORTED;
+  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
   auto plan = tchol::get_plan(op, n, nb, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
   auto img = image_of(plan);
@@ -493,7 +495,7 @@ int32_t tchol_backward_ex(const double* L, int64_t n, int64_t nb, double* Lbar, 
   if (ws_bytes <= 0) return -6;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -5;
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_LIST) return TCHOL_E_UNSUPPORTED;
+  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
   auto plan = tchol::get_plan(TCHOL_OP_BACKWARD, n, nb, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
   const BackLayout B = back_layout(n, nb, *plan);
@@ -533,7 +535,7 @@ int32_t tchol_factor_solve(double* A, int64_t n, int64_t nb, double* B, int64_t 
   if (!ws) return -6;
   if (ws_bytes <= 0) return -7;
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_LIST) return TCHOL_E_UNSUPPORTED;
+  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
   // one system of the merged factor + solve DAG: A at offset 0 with ld n, B at 0
   std::vector<tchol::System> systems(1);
   systems[0].n = n;
@@ -543,17 +545,18 @@ int32_t tchol_factor_solve(double* A, int64_t n, int64_t nb, double* B, int64_t 
   if (!plan) return TCHOL_E_UNSUPPORTED;
   std::shared_ptr<const Image> img;
   {
-    // the image depends only on the plan here (fixed offsets), so it is cached, pinned
+    // the image depends only on the plan here (fixed offsets), so it is cached
     static std::mutex mu;
     static std::map<const Plan*, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
     std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(plan.get());
+    const auto key = plan.get();
+    auto it = cache.find(key);
     if (it != cache.end() && !it->second.first.expired()) {
       img = it->second.second;
     } else {
       img = make_image(*plan, true, &systems);
       if (cache.size() > 16) cache.clear();
-      cache[plan.get()] = std::make_pair(std::weak_ptr<const Plan>(plan), img);
+      cache[key] = std::make_pair(std::weak_ptr<const Plan>(plan), img);
     }
   }
   const bool wide = (n % 2 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
@@ -608,7 +611,7 @@ int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_
   if (!ws) return -11;
   if (ws_bytes <= 0) return -12;
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_LIST) return TCHOL_E_UNSUPPORTED;
+  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
   if (nrhs == 0) {
     // nothing to solve: the plan still holds the solve tasks, which then have no columns
   }
@@ -649,7 +652,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   if (ws_bytes <= 0) return -12;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -11;
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_LIST) return TCHOL_E_UNSUPPORTED;
+  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
   auto fplan = tchol::get_plan(tchol::OP_FACTOR_INV, n, nb, o.policy, o.seed);
   auto splan = tchol::get_plan(tchol::OP_SOLVE_INV, n, nb, o.policy, o.seed);
   if (!fplan || !splan) return TCHOL_E_UNSUPPORTED;
@@ -768,7 +771,7 @@ int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int
   if (ws_bytes <= 0) return -12;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -11;
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (o.policy < TCHOL_POLICY_RANK || o.policy > TCHOL_POLICY_LIST) return TCHOL_E_UNSUPPORTED;
+  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
   auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
   std::vector<int64_t> desc(8 * (size_t)batch, 0);
@@ -822,7 +825,7 @@ int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint
     return -1;
   if (n < 0) return -2;
   if (!nb_ok(nb)) return -3;
-  if (policy < TCHOL_POLICY_RANK || policy > TCHOL_POLICY_LIST) return -4;
+  if (!policy_ok(policy)) return -4;
   auto p = tchol::get_plan(op == TCHOL_OP_MIXED_FACTOR ? tchol::OP_FACTOR_INV : op, n, nb, policy, seed);
   if (!p) return TCHOL_E_UNSUPPORTED;
   fill_query(*p, counts, kind, ti, tj, tk, nullptr, parts, dep0, rank, succ_off, succ, item_task, item_part);
@@ -836,7 +839,7 @@ int32_t tchol_batched_plan_query(const int32_t* n, const int32_t* nb, int32_t ba
   if (batch < 0) return -3;
   if (batch > 0 && !n) return -1;
   if (batch > 0 && !nb) return -2;
-  if (policy < TCHOL_POLICY_RANK || policy > TCHOL_POLICY_LIST) return -4;
+  if (!policy_ok(policy)) return -4;
   std::vector<tchol::System> systems;
   const int32_t rc = batched_systems(nullptr, nullptr, nullptr, n, nb, batch, &systems);
   if (rc == -6) return -1;

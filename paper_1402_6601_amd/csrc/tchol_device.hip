@@ -6,8 +6,13 @@
 //   wait    until dep[task] == 0 (agent-scope acquire; bounded by a watchdog)
 //   run     the work item (a POTRF tile, a TRSM row strip, a GEMM/SYRK
 //           sub-tile, a solve block)
-//   release agent-scope release, then done[task] += 1; the last work item
-//           of a task decrements dep[s] of every successor s ("activate")
+//   publish every global store of the item is a device-scope (write-through)
+//           store (st_dev; no result may be written with a plain global
+//           store); each wavefront waits for them (vmcnt(0)), then a barrier,
+//           then done[task] += 1; the last work item of a task decrements
+//           dep[s] of every successor s ("activate").  Readers acquire at
+//           agent scope after their wait, so they see the written-through
+//           results; no release fence (an L2 write-back) is needed.
 // Tickets are handed out in a topological order, so the worker holding the
 // oldest unfinished ticket always has its predecessors finished or held by
 // running workers: the loop cannot deadlock, whatever the grid size.

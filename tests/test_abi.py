@@ -158,3 +158,22 @@ def test_plan_query_validation(lib):
 
 def test_unsupported_size(lib):
     assert lib.tchol_workspace_bytes(0, 16 * 2000, 16, 0) == tc.E_UNSUPPORTED
+
+
+def test_zeroed_options_select_the_default_policy(lib):
+    """A zero-initialised tchol_opts and NULL options select the same claim
+    order: the header numbers the list schedule 0, the binding agrees, and the
+    plan built for policy 0 is the list schedule, whose ticket order differs
+    from the task-by-task rank order."""
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+TCHOL_POLICY_LIST\s+(\d+)", text)
+    assert m and int(m.group(1)) == 0 == tc.POLICY_LIST
+    assert tc.Opts().policy == tc.POLICY_LIST
+    values = {int(v) for v in re.findall(r"#define\s+TCHOL_POLICY_\w+\s+(\d+)", text)}
+    assert values == {0, 1, 2, 3}
+    a = tc.plan_query(0, 2048, 128, 0)
+    b = tc.plan_query(0, 2048, 128, tc.POLICY_LIST)
+    r = tc.plan_query(0, 2048, 128, tc.POLICY_RANK)
+    assert (a["item_task"] == b["item_task"]).all()
+    assert not (a["item_task"] == r["item_task"]).all()
+

@@ -109,7 +109,8 @@ def test_backward_edges_equal_dataflow(n, nb):
     assert cnt[GREV] == sum((T - k - 1) ** 2 for k in range(T))
 
 
-@pytest.mark.parametrize("policy,seed", [(0, 0), (1, 0), (2, 7)])
+@pytest.mark.parametrize("policy,seed", [(tc.POLICY_LIST, 0), (tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0),
+                                         (tc.POLICY_RANDOM, 7)])
 def test_backward_claim_order_is_topological(policy, seed):
     p = bplan(700, 128, policy, seed)
     first = {}

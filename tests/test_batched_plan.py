@@ -119,7 +119,8 @@ def test_batched_edges_equal_dataflow(n, nb):
         assert cnt.get(GEMM, 0) == ng
 
 
-@pytest.mark.parametrize("policy,seed", [(0, 0), (1, 0), (2, 3)])
+@pytest.mark.parametrize("policy,seed", [(tc.POLICY_LIST, 0), (tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0),
+                                         (tc.POLICY_RANDOM, 3)])
 def test_batched_claim_order_is_topological(policy, seed):
     n, nb = [1, 17, 200, 512, 513, 300], [16, 16, 64, 128, 512, 128]
     p = bplan(n, nb, policy, seed)
@@ -135,7 +136,7 @@ def test_batched_claim_order_is_topological(policy, seed):
 
 def test_batched_ranks_follow_scaled_recurrence():
     n, nb = [64, 600, 300, 1000], [16, 256, 128, 512]
-    p = bplan(n, nb)
+    p = bplan(n, nb, tc.POLICY_RANK)
     for t in range(p["ntask"]):
         u = nb[int(p["sys"][t])] // 16
         succ = [p["rank"][p["succ"][e]] for e in range(p["succ_off"][t], p["succ_off"][t + 1])]

@@ -160,7 +160,8 @@ def check_topological(p):
             assert first[s] < first[t]
 
 
-@pytest.mark.parametrize("policy,seed", [(0, 0), (1, 0), (2, 1), (2, 7), (3, 0)])
+@pytest.mark.parametrize("policy,seed", [(tc.POLICY_LIST, 0), (tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0),
+                                         (tc.POLICY_RANDOM, 1), (tc.POLICY_RANDOM, 7)])
 @pytest.mark.parametrize("op,n,nb", [(0, 1024, 128), (0, 1000, 96), (1, 1000, 128)])
 def test_claim_order_is_topological(policy, seed, op, n, nb):
     check_topological(plan(op, n, nb, policy, seed))
@@ -168,12 +169,12 @@ def test_claim_order_is_topological(policy, seed, op, n, nb):
 
 @pytest.mark.parametrize("op,n,nb", [(0, 4096, 256), (0, 1000, 96), (tc.OP_MIXED_FACTOR, 2048, 512)])
 def test_list_schedule_order(op, n, nb):
-    """HEFT's list schedule (policy 3): every work item listed exactly once, in
+    """HEFT's list schedule (the default policy): every work item listed exactly once, in
     a topological order that starts with POTRF(0); an item's ready time in the
     simulation never exceeds the simulated start of the items listed after it,
     so that, simulated again with the same costs, the list order is the start
     order (each item starts no later than the one after it)."""
-    p = plan(op, n, nb, 3)
+    p = plan(op, n, nb, tc.POLICY_LIST)
     check_topological(p)
     cnt = np.bincount(p["item_task"], minlength=p["ntask"])
     assert np.array_equal(cnt, p["parts"][:p["ntask"]])
@@ -204,8 +205,8 @@ def test_list_schedule_order(op, n, nb):
 
 
 def test_rank_order_ties_are_deterministic():
-    a = plan(0, 2048, 128)
-    b = plan(0, 2048, 128)
+    a = plan(0, 2048, 128, tc.POLICY_RANK)
+    b = plan(0, 2048, 128, tc.POLICY_RANK)
     assert np.array_equal(a["item_task"], b["item_task"])
     # decreasing rank along the claim order
     r = a["rank"][a["item_task"]]
@@ -213,8 +214,8 @@ def test_rank_order_ties_are_deterministic():
 
 
 def test_random_policy_depends_on_seed():
-    a = plan(0, 1024, 128, 2, 1)
-    b = plan(0, 1024, 128, 2, 2)
+    a = plan(0, 1024, 128, tc.POLICY_RANDOM, 1)
+    b = plan(0, 1024, 128, tc.POLICY_RANDOM, 2)
     assert not np.array_equal(a["item_task"], b["item_task"])
 
 
@@ -262,7 +263,7 @@ def simulate(p, A, n, nb, workers=8, spin_limit=10_000, corrupt=None):
     return A, "ok"
 
 
-@pytest.mark.parametrize("policy", [0, 1, 2])
+@pytest.mark.parametrize("policy", [tc.POLICY_LIST, tc.POLICY_RANK, tc.POLICY_FIFO, tc.POLICY_RANDOM])
 @pytest.mark.parametrize("n,nb", [(64, 16), (80, 16)])
 def test_simulated_protocol_matches_oracle_bitwise(oracle_lib, policy, n, nb):
     A, _ = spd_inputs.spd_matrix(n, seed=n + policy)
