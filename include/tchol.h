@@ -67,6 +67,8 @@ extern "C" {
 #define TCHOL_E_UNSUPPORTED (-102) /* size beyond what the planner supports  */
 #define TCHOL_E_INTERNAL (-103)    /* inconsistent device state at exit      */
 #define TCHOL_E_NOCONV (-104)      /* refinement missed its target in maxit  */
+#define TCHOL_E_SCRATCH (-105)     /* the problem needs more scheduler scratch than
+                                      tchol_factor_solve_noalloc's fixed array  */
 
 #define TCHOL_LOWP_FP32 1 /* mixed precision: FP32 working copy, FP32 matrix-core updates */
 
@@ -151,6 +153,28 @@ TCHOL_API int32_t tchol_backward_ex(const double *L, int64_t n, int64_t nb, doub
 TCHOL_API int64_t tchol_factor_solve_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs);
 TCHOL_API int32_t tchol_factor_solve(double *A, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
                                      int64_t ws_bytes, void *stream, const tchol_opts *opts);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   merged factor + solve launch as tchol_factor_solve with the default options,
+   bitwise the same results, but with no workspace argument.  Its scheduler
+   scratch (header, dependency counters, task descriptors, successor lists,
+   ticket list) lives in a fixed device array of the library,
+   TCHOL_NOALLOC_SCRATCH_BYTES per GPU, held by every GPU the library runs on
+   until the process ends.  The call itself allocates nothing on the device
+   and no pinned host memory (the plan, built on the first call for an
+   (n, nb), is kept in ordinary host memory).  Every call on one GPU shares
+   that GPU's array and leaves its contents behind; each call clears what
+   must start at zero.  Calls that overlap on one GPU (other host threads,
+   other streams) race on the array and must be serialised by the caller.
+   Arguments: 1 A, 2 n, 3 nb, 4 B, 5 nrhs (as for tchol_factor_solve),
+   6 stream.  Returns as tchol_factor_solve, or TCHOL_E_SCRATCH (checked
+   before any HIP call) when tchol_factor_solve_workspace_bytes(n, nb, nrhs)
+   exceeds TCHOL_NOALLOC_SCRATCH_BYTES (n = 32768 with nb = 512 needs
+   8.3 MiB; nb = 256 about 31 MiB). */
+#define TCHOL_NOALLOC_SCRATCH_BYTES (16 << 20)
+TCHOL_API int32_t tchol_factor_solve_noalloc(double *A, int64_t n, int64_t nb, double *B, int64_t nrhs,
+                                             void *stream);
 
 /* Batched factor + solve of `batch` independent SPD systems in ONE launch
    of the persistent kernel.  Paper: the same tile DAG (section 4.1) per

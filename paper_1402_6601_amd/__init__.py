@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
 OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD, OP_MIXED_FACTOR = 0, 1, 2, 3, 4
 POLICY_LIST, POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2, 3
-E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV = -100, -101, -102, -103, -104
+E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV, E_SCRATCH = -100, -101, -102, -103, -104, -105
+NOALLOC_SCRATCH_BYTES = 16 << 20
 LOWP_FP32 = 1
 KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV",
               "TRTRI", "DRED"]
@@ -90,6 +91,8 @@ def load() -> ctypes.CDLL:
     lib.tchol_factor_solve_workspace_bytes.argtypes = [i64, i64, i64]
     lib.tchol_factor_solve.restype = i32
     lib.tchol_factor_solve.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, ctypes.POINTER(Opts)]
+    lib.tchol_factor_solve_noalloc.restype = i32
+    lib.tchol_factor_solve_noalloc.argtypes = [vp, i64, i64, vp, i64, vp]
     lib.tchol_batched_f32_workspace_bytes.restype = i64
     lib.tchol_batched_f32_workspace_bytes.argtypes = [P32, P32, i32, i32]
     lib.tchol_factor_solve_batched_f32.restype = i32
@@ -559,3 +562,21 @@ def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, w
         raise TcholError(rc, "tchol_factor_solve")
     return (rc, ms.value) if want_kernel_ms else rc
 
+
+def factor_solve_noalloc_(A, Bc, nb: int, *, check: bool = True):
+    """As factor_solve_ (default options) through tchol_factor_solve_noalloc:
+    the library's fixed per-GPU scratch array instead of a workspace, so
+    nothing is allocated on the device by the call.  Returns info."""
+    torch = _torch()
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+        raise ValueError("A must be a contiguous square float64 tensor")
+    n = A.shape[0]
+    if Bc.dtype != torch.float64 or not Bc.is_contiguous() or Bc.dim() != 2 or Bc.shape[1] != n:
+        raise ValueError("Bc must be a contiguous float64 (nrhs, n) tensor (B in column-major order)")
+    lib = load()
+    with torch.cuda.device(A.device):
+        rc = lib.tchol_factor_solve_noalloc(ctypes.c_void_p(A.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()),
+                                            Bc.shape[0], _stream_ptr(torch, A.device))
+    if rc < 0 and check:
+        raise TcholError(rc, "tchol_factor_solve_noalloc")
+    return rc

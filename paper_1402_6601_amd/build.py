@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libtchol.so")
 ARCH = os.environ.get("TCHOL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["tchol_device.hip", "tchol_refine.hip", "tchol_batched32.hip", "tchol_api.cpp",
-           "plan.cpp"]
+           "plan.cpp", "tchol_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for all device code.  Matrix-core
 # accumulators are allocated in ordinary vector registers: with the default

@@ -437,6 +437,49 @@ MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, co
 
 }  // namespace
 
+namespace tchol {
+
+// The merged factor + solve launch on validated arguments (n > 0).  pinned:
+// keep the plan's constant image in pinned host memory (allocated once per
+// plan); otherwise in pageable memory, so that the call allocates no device
+// or pinned memory once the plan is cached.
+int32_t factor_solve_run(double* A, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
+                         void* stream, const tchol_opts* opts, bool pinned) {
+  const tchol_opts& o = opts ? *opts : kDefaultOpts;
+  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
+  // one system of the merged factor + solve DAG: A at offset 0 with ld n, B at 0
+  std::vector<tchol::System> systems(1);
+  systems[0].n = n;
+  systems[0].nb = nb;
+  systems[0].ld = n;
+  auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  std::shared_ptr<const Image> img;
+  {
+    // the image depends only on the plan here (fixed offsets), so it is cached
+    using Key = std::pair<const Plan*, bool>;
+    static std::mutex mu;
+    static std::map<Key, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
+    std::lock_guard<std::mutex> g(mu);
+    const Key key(plan.get(), pinned);
+    auto it = cache.find(key);
+    if (it != cache.end() && !it->second.first.expired()) {
+      img = it->second.second;
+    } else {
+      img = make_image(*plan, pinned, &systems);
+      if (cache.size() > 16) cache.clear();
+      cache[key] = std::make_pair(std::weak_ptr<const Plan>(plan), img);
+    }
+  }
+  const bool wide = (n % 2 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
+  int32_t info = 0;
+  const int32_t rc = execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 6, &info);
+  if (rc != 0) return rc;
+  return info;
+}
+
+}  // namespace tchol
+
 extern "C" {
 
 int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs) {
@@ -534,36 +577,7 @@ int32_t tchol_factor_solve(double* A, int64_t n, int64_t nb, double* B, int64_t 
   if (nrhs > 0 && !B) return -4;
   if (!ws) return -6;
   if (ws_bytes <= 0) return -7;
-  const tchol_opts& o = opts ? *opts : kDefaultOpts;
-  if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
-  // one system of the merged factor + solve DAG: A at offset 0 with ld n, B at 0
-  std::vector<tchol::System> systems(1);
-  systems[0].n = n;
-  systems[0].nb = nb;
-  systems[0].ld = n;
-  auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
-  if (!plan) return TCHOL_E_UNSUPPORTED;
-  std::shared_ptr<const Image> img;
-  {
-    // the image depends only on the plan here (fixed offsets), so it is cached
-    static std::mutex mu;
-    static std::map<const Plan*, std::pair<std::weak_ptr<const Plan>, std::shared_ptr<const Image>>> cache;
-    std::lock_guard<std::mutex> g(mu);
-    const auto key = plan.get();
-    auto it = cache.find(key);
-    if (it != cache.end() && !it->second.first.expired()) {
-      img = it->second.second;
-    } else {
-      img = make_image(*plan, true, &systems);
-      if (cache.size() > 16) cache.clear();
-      cache[key] = std::make_pair(std::weak_ptr<const Plan>(plan), img);
-    }
-  }
-  const bool wide = (n % 2 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
-  int32_t info = 0;
-  const int32_t rc = execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 6, &info);
-  if (rc != 0) return rc;
-  return info;
+  return tchol::factor_solve_run(A, n, nb, B, nrhs, ws, ws_bytes, stream, opts, true);
 }
 
 int64_t tchol_batched_workspace_bytes(const int32_t* n, const int32_t* nb, int32_t batch) {
@@ -812,6 +826,8 @@ const char* tchol_strerror(int32_t code) {
   if (code == TCHOL_E_UNSUPPORTED) return "unsupported size or option";
   if (code == TCHOL_E_INTERNAL) return "work items left unfinished at kernel exit";
   if (code == TCHOL_E_NOCONV) return "iterative refinement did not reach its tolerance";
+  if (code == TCHOL_E_SCRATCH)
+    return "the problem needs more scheduler scratch than the fixed array of tchol_factor_solve_noalloc holds";
   if (code < 0 && code > -100) return "invalid argument (number -code)";
   return "unknown error";
 }

@@ -177,3 +177,20 @@ def test_zeroed_options_select_the_default_policy(lib):
     assert (a["item_task"] == b["item_task"]).all()
     assert not (a["item_task"] == r["item_task"]).all()
 
+
+
+def test_noalloc_validation_and_scratch_limit(lib):
+    f = lib.tchol_factor_solve_noalloc
+    assert f(FAKE, -1, 128, FAKE, 1, None) == -2
+    assert f(FAKE, 100, 24, FAKE, 1, None) == -3
+    assert f(FAKE, 100, 128, FAKE, -1, None) == -5
+    assert f(None, 0, 128, None, 1, None) == 0
+    assert f(None, 100, 128, FAKE, 1, None) == -1
+    assert f(FAKE, 100, 128, None, 1, None) == -4
+    # problems whose scheduler scratch exceeds the fixed array are refused
+    # before any HIP call; the bench configuration (n = 32768, nb = 512) fits
+    fs = lib.tchol_factor_solve_workspace_bytes
+    assert fs(32768, 512, 16) <= tc.NOALLOC_SCRATCH_BYTES
+    assert fs(32768, 256, 16) > tc.NOALLOC_SCRATCH_BYTES
+    assert f(FAKE, 32768, 256, FAKE, 16, None) == tc.E_SCRATCH
+    assert "scratch" in tc.strerror(tc.E_SCRATCH)
