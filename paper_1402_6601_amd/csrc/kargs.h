@@ -46,10 +46,15 @@ typedef struct KArgs {
   int64_t ldq;
   int64_t wait_limit;   /* bound on one dependency wait, in 100 MHz clock ticks   */
   uint64_t *trace;      /* optional: 4 words per work item                        */
+  int32_t *pool;        /* POOL_WORDS counters per diagonal tile of every system
+                           (the split POTRF's sub-unit pool), zeroed per launch */
 } KArgs;
 
 #define DESC_WORDS 8   /* kind, i, j, k, parts, succ_begin, succ_end, system */
 #define SYS_WORDS 8    /* a_off, b_off, n, nb, ld, d_off (mixed precision: offset of the
-                          system's FP64 diagonal tiles and inverses), 0, 0     */
+                          system's FP64 diagonal tiles and inverses), pool_off
+                          (index of the system's first diagonal tile among all
+                          systems' diagonal tiles, for the POTRF pools), 0     */
+#define POOL_WORDS 64  /* counters of one diagonal tile's POTRF pool          */
 
 #endif

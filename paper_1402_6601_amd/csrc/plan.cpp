@@ -112,6 +112,19 @@ int64_t weight(int32_t kind, int32_t op) {
   }
 }
 
+// Work items of the POTRF of a tile of order m in a system of several tiles
+// (on the critical path of the tile DAG).  Tiles above 128 are factored as a
+// small tile DAG over 128 x 128 sub-blocks whose sub-units the task's work
+// items share (the kernel's POTRF pool); as many items as the widest step of
+// that DAG offers (the strips of the sub-blocks below the first one), at
+// most 8.  Smaller tiles take one work item.
+int32_t potrf_parts(int64_t m) {
+  if (m <= 128) return 1;
+  int32_t strips = 0;
+  for (int64_t r0 = 128; r0 < m; r0 += 128) strips += (int32_t)((std::min<int64_t>(128, m - r0) + 31) / 32);
+  return std::min<int32_t>(8, strips);
+}
+
 // trtri: add TRTRI(k) after POTRF(k) (explicit inverses for the
 // mixed-precision solve; no task of the factorization waits for them).
 void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
@@ -122,7 +135,10 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
   for (int32_t k = 0; k < T; ++k) {
-    id_potrf[k] = b.add(TK_POTRF, k, k, k, 1);
+    // a single-tile system's POTRF is the whole factorization: in a batch of
+    // many such systems the workgroups have independent work enough, so it
+    // takes one work item; the diagonal tiles of tiled systems are split
+    id_potrf[k] = b.add(TK_POTRF, k, k, k, T > 1 ? potrf_parts(b.tile_size(k)) : 1);
     for (int32_t i = k + 1; i < T; ++i)
       id_trsm[ix2(i, k)] = b.add(TK_TRSM, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
     for (int32_t i = k + 1; i < T; ++i) {

@@ -14,8 +14,8 @@
 #include "kargs.h"
 #include "plan.hpp"
 
-extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid, int wide,
-                                       hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int64_t npool, int grid,
+                                       int wide, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 extern "C" hipError_t tchol_dev_max_grid(int device, int* grid);
 extern "C" hipError_t tchol_dev_backward_prep(const double* L, int64_t n, double* LT, double* Q, int64_t ldq,
                                               int64_t np, hipStream_t stream);
@@ -43,20 +43,31 @@ int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Byte offsets of the workspace regions.  [dep0, end) is a copy of the
 // plan's constant image (counters, descriptors, successors, ticket list and
-// the system table), uploaded in one transfer; hdr, dep, done and sinfo are
-// (re)initialised by a small kernel on every call.
+// the system table), uploaded in one transfer; hdr, dep, done, sinfo and the
+// POTRF pools are (re)initialised by a small kernel on every call.
 struct Layout {
-  int64_t hdr = 0, dep = 0, done = 0, sinfo = 0, dep0 = 0, desc = 0, succ = 0, items = 0, sys = 0, end = 0;
+  int64_t hdr = 0, dep = 0, done = 0, sinfo = 0, pool = 0, dep0 = 0, desc = 0, succ = 0, items = 0, sys = 0,
+          end = 0;
+  int64_t npool = 0;  // words of the POTRF pools
 };
+
+// Diagonal tiles over all systems of a plan (one POTRF pool each).
+int64_t diag_tiles(const Plan& p) {
+  int64_t t = 0;
+  for (const auto& sy : p.systems) t += sy.n == 0 ? 0 : (sy.n + sy.nb - 1) / sy.nb;
+  return t;
+}
 
 Layout layout_of(const Plan& p) {
   Layout L;
   const int64_t nt = p.ntask(), ns = (int64_t)p.systems.size();
+  L.npool = POOL_WORDS * diag_tiles(p);
   L.hdr = 0;
   L.dep = align_up(HDR_WORDS * 4);
   L.done = align_up(L.dep + 4 * nt);
   L.sinfo = align_up(L.done + 4 * nt);
-  L.dep0 = align_up(L.sinfo + 4 * ns);
+  L.pool = align_up(L.sinfo + 4 * ns);
+  L.dep0 = align_up(L.pool + 4 * L.npool);
   L.desc = align_up(L.dep0 + 4 * nt);
   L.succ = align_up(L.desc + 4 * DESC_WORDS * nt);
   L.items = align_up(L.succ + 4 * p.nedge());
@@ -118,6 +129,7 @@ std::shared_ptr<Image> make_image(const Plan& p, bool pin, const std::vector<tch
     items[2 * i] = p.item_task[i];
     items[2 * i + 1] = p.item_part[i];
   }
+  int64_t pool_off = 0;
   for (size_t s = 0; s < p.systems.size(); ++s) {
     const tchol::System& sy = sys_override ? (*sys_override)[s] : p.systems[s];
     int64_t* r = sys + SYS_WORDS * s;
@@ -127,6 +139,8 @@ std::shared_ptr<Image> make_image(const Plan& p, bool pin, const std::vector<tch
     r[3] = sy.nb;
     r[4] = sy.ld;
     r[5] = sy.d_off;
+    r[6] = pool_off;
+    pool_off += p.systems[s].n == 0 ? 0 : (p.systems[s].n + p.systems[s].nb - 1) / p.systems[s].nb;
   }
   return img;
 }
@@ -235,6 +249,7 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.items = reinterpret_cast<const int32_t*>(w + L.items);
   a.sys = reinterpret_cast<const int64_t*>(w + L.sys);
   a.sinfo = reinterpret_cast<int32_t*>(w + L.sinfo);
+  a.pool = reinterpret_cast<int32_t*>(w + L.pool);
   a.batched = batched ? 1 : 0;
   a.nsys = (int32_t)plan.systems.size();
   a.D = D;
@@ -259,7 +274,7 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   }
   const int grid = (int)std::min<int64_t>(di.grid, std::max<int64_t>(1, plan.nitem()));
   if (e == hipSuccess)
-    e = tchol_dev_launch(&a, (int32_t)plan.ntask(), reinterpret_cast<const int32_t*>(w + L.dep0), grid,
+    e = tchol_dev_launch(&a, (int32_t)plan.ntask(), reinterpret_cast<const int32_t*>(w + L.dep0), L.npool, grid,
                          wide ? 1 : 0, stream, ev0, ev1);
   if (e == hipSuccess) e = hipMemcpyAsync(hdr, a.hdr, sizeof(hdr), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess && sinfo_out && a.nsys > 0)

@@ -758,6 +758,180 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 }
 
 // ---------------------------------------------------------------------------
+// POTRF of a tile of order m <= 128 held in LDS for the whole factorization:
+// loaded once, factored right-looking by 16-column panels, stored once.  Per
+// panel: the 16 x 16 diagonal block is factored on wavefront 0 in registers
+// (as in potrf_tile), every thread solves one row below it, and the trailing
+// lower blocks take the panel's update on the matrix cores (16 x 16 blocks,
+// K = 16); wavefront 0 updates and factors the next diagonal block first,
+// while the other wavefronts update the rest.  Each element receives the
+// same sequence of matrix-core updates in the same order as in potrf_tile,
+// so the two agree bit for bit.  Returns 0, or the 1-based column (within
+// the tile) whose pivot is not positive.
+#define SLD 132   // LDS leading dimension of the resident tile
+
+// Factors the diagonal block at column c0 (width w) of the resident tile As
+// on one wavefront: lane r holds row r; pivots and column entries are
+// broadcast across lanes.  Writes L_dd back, a copy to Ldd[r][c] and the
+// reciprocal pivots to Linv.  Returns info (0 or the 1-based tile column).
+__device__ __forceinline__ int diag16_lds(double* As, int c0, int w, double* Ldd, double* Linv, int lane) {
+  double x[PW];
+  const int r = imin(lane, w - 1);
+  double v[PW];
+#pragma unroll
+  for (int c = 0; c < PW; ++c) {
+    v[c] = As[(c0 + imin(c, w - 1)) * SLD + c0 + r];
+    asm volatile("" : "+v"(v[c]));
+  }
+#pragma unroll
+  for (int c = 0; c < PW; ++c)
+    x[c] = (lane < w) ? (((c <= lane) & (c < w)) ? v[c] : 0.0) : (c == lane ? 1.0 : 0.0);
+  int info = 0;
+  double pinv[PW];
+#pragma unroll
+  for (int cc = 0; cc < PW; ++cc) {
+    const double d = readlane_f64(x[cc], cc);
+    info = (info == 0 && !(d > 0.0)) ? c0 + cc + 1 : info;
+    double l, inv;
+    if (d >= 0x1p-900) {
+      double y = __builtin_amdgcn_rsq(d);
+      y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
+      y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
+      l = d * y;
+      l = fma(fma(-l, l, d), 0.5 * y, l);
+      inv = y;
+    } else {
+      l = sqrt(d);
+      inv = 1.0 / l;
+    }
+    pinv[cc] = inv;
+    x[cc] = (lane == cc) ? l : ((lane > cc) ? x[cc] * inv : x[cc]);
+#pragma unroll
+    for (int c2 = cc + 1; c2 < PW; ++c2) {
+      const double vv = readlane_f64(x[cc], c2);
+      x[c2] = (lane >= c2) ? x[c2] - x[cc] * vv : x[c2];
+    }
+  }
+  if (lane < w) {
+#pragma unroll
+    for (int c = 0; c < PW; ++c)
+      if (c <= lane) As[(c0 + c) * SLD + c0 + lane] = x[c];
+  }
+  if (lane < PW) {
+#pragma unroll
+    for (int c = 0; c < PW; ++c) Ldd[lane * (PW + 1) + c] = (c <= lane) ? x[c] : 0.0;
+    double li = pinv[0];
+#pragma unroll
+    for (int c = 1; c < PW; ++c) li = (lane == c) ? pinv[c] : li;
+    Linv[lane] = li;
+  }
+  return info;
+}
+
+// Block (bi, bj) of the resident tile -= P(bi) P(bj)^T, P the 16 columns of
+// the panel at c0.  A operand: P(bi) (rows on lanes % 16), B operand: P(bj)^T;
+// element v of lane l is then row 4v + l/16, column l%16 of the block.
+__device__ __forceinline__ void upd16_lds(double* As, int c0, int bi, int bj, int lane) {
+  const int l16 = lane & 15, lg = lane >> 4;
+  d4 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = As[(bj * 16 + l16) * SLD + bi * 16 + 4 * v + lg];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double fa = As[(c0 + 4 * s + lg) * SLD + bi * 16 + l16];
+    const double fb = As[(c0 + 4 * s + lg) * SLD + bj * 16 + l16];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc, 0, 0, 2 /* neg B */);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) As[(bj * 16 + l16) * SLD + bi * 16 + 4 * v + lg] = acc[v];
+}
+
+__device__ __forceinline__ int potrf_small(double* __restrict__ Akk, int64_t ld, int m, double* lds) {
+  double* As = lds;                      // [128][SLD]
+  double* Ldd = As + 128 * SLD;          // [PW][PW + 1]
+  double* Linv = Ldd + PW * (PW + 1);    // [PW]
+  __shared__ int s_sinfo;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nblk = (m + 15) >> 4;
+  // the lower triangle into LDS, 16 loads in flight per thread; rows and
+  // columns past m hold the identity
+  {
+    constexpr int PER = 128 * 128 / NT, BATCH = 16;
+#pragma unroll 1
+    for (int u0 = 0; u0 < PER; u0 += BATCH) {
+      double v[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int idx = tid + (u0 + u) * NT, c = idx >> 7, r = idx & 127;
+        v[u] = Akk[(int64_t)imin(c, m - 1) * ld + imin(imax(r, c), m - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int idx = tid + (u0 + u) * NT, c = idx >> 7, r = idx & 127;
+        if (c < nblk * 16 && r < nblk * 16) As[c * SLD + r] = (r < m && c < m && r >= c) ? v[u] : (r == c ? 1.0 : 0.0);
+      }
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int info = diag16_lds(As, 0, imin(16, m), Ldd, Linv, lane);
+    if (lane == 0) s_sinfo = info;
+  }
+  __syncthreads();
+  for (int j = 0; j < nblk; ++j) {
+    const int c0 = j * 16;
+    const int info = __builtin_amdgcn_readfirstlane(s_sinfo);
+    if (info != 0) return info;
+    // rows below the diagonal block: y := y L_dd^{-T}, one row per thread
+#pragma unroll 1
+    for (int r = c0 + 16 + tid; r < nblk * 16; r += NT) {
+      double y[PW];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) y[c] = As[(c0 + c) * SLD + r];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        y[c] *= Linv[c];
+#pragma unroll
+        for (int c2 = c + 1; c2 < PW; ++c2) y[c2] -= y[c] * Ldd[c2 * (PW + 1) + c];
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) As[(c0 + c) * SLD + r] = y[c];
+    }
+    __syncthreads();
+    if (j + 1 >= nblk) break;
+    // the panel's update of the trailing lower blocks; wavefront 0 first
+    // updates and factors the next diagonal block (the critical path)
+    const int nb2 = nblk - j - 1;
+    const int npair = nb2 * (nb2 + 1) / 2;
+    if (wave == 0) {
+      upd16_lds(As, c0, j + 1, j + 1, lane);
+      const int info2 = diag16_lds(As, c0 + 16, imin(16, m - c0 - 16), Ldd, Linv, lane);
+      if (lane == 0) s_sinfo = info2;
+    }
+    // block pairs p >= 1 in column-major order of (bi >= bj), after (j+1, j+1),
+    // on the other three wavefronts (wavefront 0 is busy with the diagonal)
+#pragma unroll 1
+    for (int p = (wave == 0 ? npair : wave); p < npair; p += 3) {
+      int cj = 0, rem = p;
+      while (rem >= nb2 - cj) {
+        rem -= nb2 - cj;
+        ++cj;
+      }
+      const int bj = j + 1 + cj;
+      upd16_lds(As, c0, bj + rem, bj, lane);
+    }
+    __syncthreads();
+  }
+  // the factor to the tile, lower triangle only
+  for (int idx = tid; idx < m * 128; idx += NT) {
+    const int c = idx >> 7, r = idx & 127;
+    if (r < m && r >= c) st_dev(Akk + (int64_t)c * ld + r, As[c * SLD + r]);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // TRSM work item: a strip of S <= 32 rows of A_ik, X := X L_kk^{-T}
 // (mk = order of L_kk, a multiple of 16; X in FP64 or, in the mixed-precision
 // factorization, FP32 storage, computed in FP64 either way).  Transposed, X^T := L_kk^{-1} X^T
@@ -1294,7 +1468,7 @@ __device__ __forceinline__ void bgemv(const TL* __restrict__ Lki, int64_t ld, do
 // tile's inverses (TRTRI); the FP32 copy's diagonal tiles are never read.
 __device__ __forceinline__ int potrf_tile_mixed(double* __restrict__ Dk, int64_t ldd, int m, double* lds) {
   const int tid = threadIdx.x;
-  const int info = __builtin_amdgcn_readfirstlane(potrf_tile<128>(Dk, ldd, m, lds));
+  const int info = __builtin_amdgcn_readfirstlane(m <= 128 ? potrf_small(Dk, ldd, m, lds) : potrf_tile<128>(Dk, ldd, m, lds));
   // a ragged tile is padded to a multiple of 16 with the identity (for its
   // explicit inverse, which then holds L^{-1} in its leading m x m block)
   const int mpad = (m + 15) & ~15;
@@ -1573,6 +1747,97 @@ __device__ __forceinline__ void raise_error(const KArgs& a, int code) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// POTRF split over several workgroups.  A diagonal tile of order m > 128 is
+// factored as its own small tile Cholesky DAG over 128 x 128 sub-blocks
+// (T2 = ceil(m / 128) per side):
+//   P(b)        chol of sub-block (b, b)                  (potrf_small)
+//   S(r, b, s)  32-row strip s of sub-block (r, b) := . L_bb^{-T}, r > b   (trsm_strip)
+//   U(r, c, b)  sub-block (r, c) -= L_rb L_cb^T, r >= c > b  (SYRK / GEMM core)
+// The POTRF task has several work items; each one that starts joins the
+// tile's pool: the worker takes the next sub-unit from a counter in the
+// workspace, waits for that unit's predecessors through per-sub-block
+// counters, runs it through the same tile bodies as whole tasks and
+// publishes it (write-through stores, then the counter), until no unit is
+// left; then its work item is done.  Units are handed out in a topological order, so the oldest
+// unfinished unit always has its predecessors finished or running, and a
+// single work item drains the pool alone if no other joins: no workgroup
+// ever waits for one that has not started.  Updates of a sub-block are
+// applied in order of b, so the factor does not depend on which workgroup
+// runs what.
+#define PSB 128        // sub-block order
+#define PL_NEXT 0      // next unit to hand out
+#define PL_P 2         // + b: P(b) done
+#define PL_S 8         // + 4 r + b: strips of S(r, b) done
+#define PL_U 24        // + 4 r + c: updates applied to sub-block (r, c)
+
+struct PoolUnit {
+  int type, b, r, c, s;  // type 0: P(b); 1: S(r, b, s); 2: U(r, c, b); -1: none left
+};
+
+__device__ __forceinline__ int psb_size(int m, int i) { return imin(PSB, m - i * PSB); }
+__device__ __forceinline__ int psb_strips(int m, int i) { return (psb_size(m, i) + TS - 1) / TS; }
+
+// Unit u of the sub-DAG in claim order: step by step, P(b), then the strips
+// of each sub-block row below it, then its updates column by column (the
+// next diagonal sub-block's first: it leads to P(b + 1)).
+__device__ __forceinline__ PoolUnit pool_unit(int m, int u) {
+  const int T2 = (m + PSB - 1) / PSB;
+  for (int b = 0; b < T2; ++b) {
+    if (u == 0) return {0, b, b, b, 0};
+    --u;
+    for (int r = b + 1; r < T2; ++r) {
+      const int ns = psb_strips(m, r);
+      if (u < ns) return {1, b, r, b, u};
+      u -= ns;
+    }
+    for (int c = b + 1; c < T2; ++c)
+      for (int r = c; r < T2; ++r) {
+        if (u == 0) return {2, b, r, c, 0};
+        --u;
+      }
+  }
+  return {-1, 0, 0, 0, 0};
+}
+
+// Wavefront 0: waits until pool[q0] >= v0, pool[q1] >= v1 and pool[q2] >= v2
+// (agent-scope loads, s_sleep back-off); false on abort or when the wait
+// exceeds its bound (which then raises TCHOL_E_TIMEOUT like a task wait).
+__device__ __forceinline__ bool pool_wait(const KArgs& a, const int32_t* pool, int q0, int v0, int q1, int v1, int q2,
+                                          int v2, int lane) {
+  auto met = [&]() __attribute__((always_inline)) {
+    const int x0 = ld_relaxed(pool + q0), x1 = ld_relaxed(pool + q1), x2 = ld_relaxed(pool + q2);
+    return uniform_i((x0 >= v0) & (x1 >= v1) & (x2 >= v2)) != 0;
+  };
+  if (met()) return uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) == 0;
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    __builtin_amdgcn_s_sleep(2);
+    if (met()) break;
+    if (uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) != 0) return false;
+    if ((int64_t)(wall_clock64() - t0) > a.wait_limit) {
+      if (lane == 0) {
+        __hip_atomic_store(&a.hdr[HDR_ERROR], DEV_ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.hdr[HDR_ABORT], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return false;
+    }
+  }
+  return uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) == 0;
+}
+
+// Wavefront 0: waits for the predecessors of pool unit pu of a tile of order m.
+__device__ __forceinline__ bool pool_wait_unit(const KArgs& a, const int32_t* pool, int m, const PoolUnit& pu,
+                                               int lane) {
+  if (pu.type == 0)  // P(b): the diagonal sub-block has taken its b updates
+    return pool_wait(a, pool, PL_U + 5 * pu.b, pu.b, PL_U + 5 * pu.b, pu.b, PL_U + 5 * pu.b, pu.b, lane);
+  if (pu.type == 1)  // S(r, b, s): L_bb factored, sub-block (r, b) updated b times
+    return pool_wait(a, pool, PL_P + pu.b, 1, PL_U + 4 * pu.r + pu.b, pu.b, PL_P + pu.b, 1, lane);
+  // U(r, c, b): every strip of (r, b) and (c, b) solved, (r, c) updated b times
+  return pool_wait(a, pool, PL_S + 4 * pu.r + pu.b, psb_strips(m, pu.r), PL_S + 4 * pu.c + pu.b,
+                   psb_strips(m, pu.c), PL_U + 4 * pu.r + pu.c, pu.b, lane);
+}
+
 // SEG = 128: the launch guarantees even leading dimensions, 16-byte aligned
 // matrices and, for odd orders, a leading dimension above the order, so
 // every panel the updates stream is 16-byte transferable; SEG = 32 serves
@@ -1593,8 +1858,12 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
   constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1 || MODE == 4;
   constexpr bool SOLVE_KINDS = MODE == 0 || MODE == 2 || MODE == 4;
   constexpr bool ADJOINT_KINDS = MODE == 3;
+  // FP64 factorizations split large POTRF tasks over their work items (the
+  // tile's pool of sub-units); the mixed-precision instances factor each
+  // diagonal tile on one workgroup (only part 0 of a POTRF task works)
+  constexpr bool POOLED = MODE == 0;
   __shared__ double lds[LDS_DOUBLES];
-  __shared__ int s_claim[3];
+  __shared__ int s_claim[4];
   __shared__ int32_t s_desc[DESC_WORDS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = uniform_i(tid >> 6);
@@ -1602,44 +1871,101 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
   // start of the next claim, and of the items this worker completed
   int p_task = -1, p_ticket = 0, p_parts = 0, p_e0 = 0, p_e1 = 0, ndone = 0;
   uint64_t p_end = 0;
+  // wavefront 0: the POTRF pool this worker serves (pl_task < 0: none) and
+  // the POTRF work item's record, published when the pool has run dry
+  int pl_task = -1, pl_m = 0, pl_ticket = 0, pl_parts = 0, pl_e0 = 0, pl_e1 = 0;
+  int32_t* pl_pool = nullptr;
   for (;;) {
     // publish + claim: wavefront 0 marks the previous item done and takes the
     // next ticket in the same round trip, then waits for the new task while
-    // its descriptor is fetched
+    // its descriptor is fetched.  A worker in a POTRF pool takes the pool's
+    // next sub-unit instead, and returns to the tickets when none is left.
     if (wave == 0) {
-      int prev = 0, t = 0;
-      if (lane == 0) {
-        if (p_task >= 0) prev = __hip_atomic_fetch_add(&a.done[p_task], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        t = __hip_atomic_fetch_add(&a.hdr[HDR_TICKET], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (p_task >= 0) {
-        // the last work item of a task activates its successors
-        if (uniform_i(prev) == p_parts - 1)
-          for (int e = p_e0 + lane; e < p_e1; e += 64)
-            __hip_atomic_fetch_sub(&a.dep[a.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ++ndone;
-        if (a.trace && lane == 0) {
-          a.trace[4 * (int64_t)p_ticket + 2] = p_end;
-          a.trace[4 * (int64_t)p_ticket + 3] = (uint64_t)(uint32_t)p_task | ((uint64_t)(uint32_t)blockIdx.x << 32);
+      int task = -1, part = 0, unit = -1, t = 0;
+      bool claimed = false;
+      uint64_t tw = 0;
+      if (POOLED && pl_task >= 0) {
+        int u = 0;
+        if (lane == 0) u = __hip_atomic_fetch_add(pl_pool + PL_NEXT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        u = uniform_i(u);
+        const PoolUnit pu = pool_unit(pl_m, u);
+        if (pu.type >= 0) {
+          claimed = true;
+          task = pl_task;
+          t = pl_ticket;
+          unit = u;
+          if (!pool_wait_unit(a, pl_pool, pl_m, pu, lane)) task = -1;
+        } else {
+          // the pool has run dry: this worker's POTRF work item is complete
+          p_task = pl_task;
+          p_ticket = pl_ticket;
+          p_parts = pl_parts;
+          p_e0 = pl_e0;
+          p_e1 = pl_e1;
+          if (a.trace) p_end = wall_clock64();
+          pl_task = -1;
         }
       }
-      t = uniform_i(t);
-      int task = -1, part = 0;
-      uint64_t tw = 0;
-      if (t < a.nitem) {
-        task = uniform_i(a.items[2 * t]);
-        part = uniform_i(a.items[2 * t + 1]);
-        if (a.trace) tw = wall_clock64();
-        const int dv = lane < DESC_WORDS ? a.desc[DESC_WORDS * (int64_t)task + lane] : 0;
-        if (!wait_ready(a, task, lane)) task = -1;
-        if (lane < DESC_WORDS) s_desc[lane] = dv;
+      if (!claimed) {
+        int prev = 0;
+        if (lane == 0) {
+          if (p_task >= 0)
+            prev = __hip_atomic_fetch_add(&a.done[p_task], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          t = __hip_atomic_fetch_add(&a.hdr[HDR_TICKET], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (p_task >= 0) {
+          // the last work item of a task activates its successors
+          if (uniform_i(prev) == p_parts - 1)
+            for (int e = p_e0 + lane; e < p_e1; e += 64)
+              __hip_atomic_fetch_sub(&a.dep[a.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ++ndone;
+          if (a.trace && lane == 0) {
+            a.trace[4 * (int64_t)p_ticket + 2] = p_end;
+            a.trace[4 * (int64_t)p_ticket + 3] = (uint64_t)(uint32_t)p_task | ((uint64_t)(uint32_t)blockIdx.x << 32);
+          }
+          p_task = -1;
+        }
+        t = uniform_i(t);
+        if (t < a.nitem) {
+          task = uniform_i(a.items[2 * t]);
+          part = uniform_i(a.items[2 * t + 1]);
+          if (a.trace) tw = wall_clock64();
+          const int dv = lane < DESC_WORDS ? a.desc[DESC_WORDS * (int64_t)task + lane] : 0;
+          if (!wait_ready(a, task, lane)) task = -1;
+          if (lane < DESC_WORDS) s_desc[lane] = dv;
+          const int kd = uniform_i(__builtin_amdgcn_readlane(dv, 0)), pd = uniform_i(__builtin_amdgcn_readlane(dv, 4));
+          if (POOLED && task >= 0 && kd == TK_POTRF && pd > 1) {
+            // a work item of a split POTRF: join the tile's pool
+            const int tkd = uniform_i(__builtin_amdgcn_readlane(dv, 3)), sd = uniform_i(__builtin_amdgcn_readlane(dv, 7));
+            const int64_t* srd = a.sys + SYS_WORDS * (int64_t)sd;
+            pl_task = task;
+            pl_m = (int)tile_size(srd[2], srd[3], tkd);
+            pl_pool = a.pool + POOL_WORDS * (srd[6] + tkd);
+            pl_ticket = t;
+            pl_parts = pd;
+            pl_e0 = uniform_i(__builtin_amdgcn_readlane(dv, 5));
+            pl_e1 = uniform_i(__builtin_amdgcn_readlane(dv, 6));
+            int u = 0;
+            if (lane == 0) u = __hip_atomic_fetch_add(pl_pool + PL_NEXT, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            u = uniform_i(u);
+            const PoolUnit pu = pool_unit(pl_m, u);
+            if (pu.type >= 0) {
+              unit = u;
+              if (!pool_wait_unit(a, pl_pool, pl_m, pu, lane)) task = -1;
+            } else {
+              unit = -2;  // the pool ran dry before this item started: nothing to do
+              pl_task = -1;
+            }
+          }
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (lane == 0) {
         s_claim[0] = task;
         s_claim[1] = part;
         s_claim[2] = t;
-        if (a.trace && task >= 0) {
+        s_claim[3] = unit;
+        if (a.trace && task >= 0 && !claimed) {
           a.trace[4 * (int64_t)t + 0] = tw;
           a.trace[4 * (int64_t)t + 1] = wall_clock64();
         }
@@ -1650,6 +1976,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     }
     __syncthreads();
     const int task = uniform_i(s_claim[0]), part = uniform_i(s_claim[1]), ticket = uniform_i(s_claim[2]);
+    const int unit = uniform_i(s_claim[3]);
     if (task < 0) break;
     const int kind = uniform_i(s_desc[0]), ti = uniform_i(s_desc[1]), tj = uniform_i(s_desc[2]),
               tk = uniform_i(s_desc[3]);
@@ -1670,7 +1997,27 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     // its remaining tasks on, so that the DAG drains
     const bool skip = a.batched && uniform_i(ld_relaxed(&a.sinfo[sid])) != 0;
     int ok = 1;
-    switch (skip ? -1 : kind) {
+    // A unit of a POTRF pool runs the POTRF, TRSM or GEMM body on sub-blocks
+    // of the diagonal tile (tk, tk): po_* give the sub-block offsets (rows,
+    // columns, panel columns) and sizes; whole tasks take the tile's.
+    int body = kind;
+    int po_r = 0, po_c = 0, po_k = 0, po_m = 0, po_n = 0, po_kk = 0, po_s = 0;
+    PoolUnit pu = {-1, 0, 0, 0, 0};
+    if (POOLED && unit >= 0) {
+      const int m = tsz(tk);
+      pu = pool_unit(m, unit);
+      body = pu.type == 0 ? TK_POTRF : (pu.type == 1 ? TK_TRSM : TK_GEMM);
+      po_r = pu.r * PSB;
+      po_c = pu.c * PSB;
+      po_k = pu.b * PSB;
+      po_m = psb_size(m, pu.r);
+      po_n = psb_size(m, pu.c);
+      po_kk = psb_size(m, pu.b);
+      po_s = pu.s;
+    } else if (POOLED && unit == -2) {
+      body = -1;
+    }
+    switch (skip ? -1 : body) {
       case -1:
         break;
       case TK_POTRF: {
@@ -1678,12 +2025,23 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           ok = 0;
           break;
         }
-        E* Akk = Abase + (tk * nb) * ld + tk * nb;
+        // tiles of order <= 128 are factored by one workgroup in LDS; larger
+        // ones through the tile's pool of sub-units when the task has several
+        // work items (the plan's choice), else by the one-workgroup kernel
         int info;
-        if constexpr (MIXED)
+        if constexpr (MIXED) {
+          if (part > 0) break;  // one workgroup factors the tile
           info = uniform_i(potrf_tile_mixed(Dsys + (int64_t)tk * nb * nb, nb, tsz(tk), lds));
-        else
-          info = uniform_i(potrf_tile<SEG>(Akk, ld, tsz(tk), lds));
+        } else {
+          const bool sub = unit >= 0;
+          const int m = sub ? po_m : tsz(tk);
+          E* Akk = Abase + (tk * nb + po_k) * ld + tk * nb + po_k;
+          if (m <= PSB)
+            info = uniform_i(potrf_small(Akk, ld, m, lds));
+          else
+            info = uniform_i(potrf_tile<SEG>(Akk, ld, m, lds));
+          if (info != 0) info += po_k;
+        }
         if (info != 0 && tid == 0) {
           if (a.batched) {
             __hip_atomic_store(&a.sinfo[sid], (int)(tk * nb) + info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1700,13 +2058,20 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           ok = 0;
           break;
         }
-        const int r0 = part * a.trsm_rows;
-        const int S = imin(a.trsm_rows, tsz(ti) - r0);
-        if constexpr (MIXED)
+        if constexpr (MIXED) {
+          const int r0 = part * a.trsm_rows;
+          const int S = imin(a.trsm_rows, tsz(ti) - r0);
           trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dsys + (int64_t)tk * nb * nb, nb, S, tsz(tk), lds);
-        else
-          trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Abase + (tk * nb) * ld + tk * nb, ld, S, tsz(tk),
-                     lds);
+        } else {
+          // a strip of A_ik, or of sub-block (r, b) of the diagonal tile for a pool unit
+          const bool sub = unit >= 0;
+          const int rs = sub ? TS : a.trsm_rows;
+          const int r0 = (sub ? po_s : part) * rs;
+          const int64_t row0 = sub ? (int64_t)tk * nb + po_r + r0 : (int64_t)ti * nb + r0;
+          const int S = imin(rs, (sub ? po_m : tsz(ti)) - r0);
+          const int64_t col0 = (int64_t)tk * nb + po_k;
+          trsm_strip(Abase + col0 * ld + row0, ld, Abase + col0 * ld + col0, ld, S, sub ? po_kk : tsz(tk), lds);
+        }
         break;
       }
       case TK_SYRK:
@@ -1729,11 +2094,26 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           bm = a.gemm_m;
           bn = a.gemm_n;
         }
-        const int M = imin(bm, tsz(ti) - si * bm);
-        const int N = imin(bn, tsz(tj) - sj * bn);
-        E* C = Abase + (tj * nb + sj * bn) * ld + ti * nb + si * bm;
-        const E* Ap = Abase + (tk * nb) * ld + ti * nb + si * bm;
-        const E* Bp = Abase + (tk * nb) * ld + tj * nb + sj * bn;
+        int M = imin(bm, tsz(ti) - si * bm);
+        int N = imin(bn, tsz(tj) - sj * bn);
+        int K = tsz(tk);
+        bool lower = kind == TK_SYRK && si == sj;
+        int64_t crow = (int64_t)ti * nb + si * bm, ccol = (int64_t)tj * nb + sj * bn, kcol = (int64_t)tk * nb;
+        int64_t brow = (int64_t)tj * nb + sj * bn;
+        if (POOLED && unit >= 0) {
+          // sub-block (r, c) of the diagonal tile -= L_rb L_cb^T
+          M = po_m;
+          N = po_n;
+          K = po_kk;
+          lower = po_r == po_c;
+          crow = (int64_t)tk * nb + po_r;
+          ccol = (int64_t)tk * nb + po_c;
+          kcol = (int64_t)tk * nb + po_k;
+          brow = ccol;
+        }
+        E* C = Abase + ccol * ld + crow;
+        const E* Ap = Abase + kcol * ld + crow;
+        const E* Bp = Abase + kcol * ld + brow;
         const bool misaligned = ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) != 0;
         if constexpr (MIXED) {
           // four rows per 16-byte lane: ld a multiple of 4 and three rows after the order
@@ -1756,7 +2136,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
             ok = 0;
             break;
           }
-          gemm_nt<SEG>(C, Ap, Bp, ld, M, N, tsz(tk), kind == TK_SYRK && si == sj, lds);
+          gemm_nt<SEG>(C, Ap, Bp, ld, M, N, K, lower, lds);
         }
         break;
       }
@@ -1904,7 +2284,14 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     // incremented at the start of the next claim.
     wait_vmcnt<0>();
     __syncthreads();
-    if (wave == 0) {
+    if (POOLED && unit >= 0) {
+      // a pool unit: its sub-block counter tells the units that wait for it
+      if (tid == 0) {
+        const int ctr = pu.type == 0 ? PL_P + pu.b : (pu.type == 1 ? PL_S + 4 * pu.r + pu.b : PL_U + 4 * pu.r + pu.c);
+        __hip_atomic_fetch_add(a.pool + POOL_WORDS * (sr[6] + tk) + ctr, 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else if (wave == 0) {
       p_task = ok ? task : -1;
       p_ticket = ticket;
       p_parts = d_parts;
@@ -1918,7 +2305,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
 // Clears the header and the per-task completion counters and copies the
 // initial dependency counters; the plan's constant part is copied by the host.
 __global__ void tchol_reset(int32_t* hdr, int32_t* dep, int32_t* done, const int32_t* dep0, int32_t ntask,
-                            int32_t* sinfo, int32_t nsys) {
+                            int32_t* sinfo, int32_t nsys, int32_t* pool, int64_t npool) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < HDR_WORDS) hdr[i] = 0;
   if (i < ntask) {
@@ -1926,17 +2313,20 @@ __global__ void tchol_reset(int32_t* hdr, int32_t* dep, int32_t* done, const int
     done[i] = 0;
   }
   if (i < nsys) sinfo[i] = 0;
+  if (i < npool) pool[i] = 0;
 }
 
 // wide: every panel the launch streams is 16-byte transferable (even
 // leading dimensions, 16-byte aligned matrices), decided by the host.
-extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int grid, int wide,
-                                       hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+// npool: words of the POTRF pools (all zeroed by the reset kernel).
+extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int64_t npool, int grid,
+                                       int wide, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
   const int rb = 256;
   int64_t cover = ntask > HDR_WORDS ? ntask : HDR_WORDS;
   if (a->nsys > cover) cover = a->nsys;
+  if (npool > cover) cover = npool;
   hipLaunchKernelGGL(tchol_reset, dim3((unsigned)((cover + rb - 1) / rb)), dim3(rb), 0, stream, a->hdr, a->dep,
-                     a->done, dep0, ntask, a->sinfo, a->nsys);
+                     a->done, dep0, ntask, a->sinfo, a->nsys, a->pool, npool);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev0) {

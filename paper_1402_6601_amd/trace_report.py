@@ -1,12 +1,13 @@
 """Per-kind work-item timing of one launch, from the kernel's trace buffer.
 
-    python -m paper_1402_6601_amd.trace_report [--op factor|mixed|solve|adjoint] [--n N] [--nb NB] [--policy P]
+    python -m paper_1402_6601_amd.trace_report [--op factor|merged|mixed|solve|adjoint] [--n N] [--nb NB] [--policy P]
 
 The persistent kernel can record, per work item, the wall clock (100 MHz)
 when its ticket was claimed, when its wait ended, when it finished, and the
 task and workgroup (``tchol_opts.trace``).  This tool runs one launch of the
 chosen DAG on a synthetic input of the benchmark family (factor: shift 1,
-seed 1; mixed: shift 1e-4, seed 2, the factorization launch of the
+seed 1; merged: the same factorization and its 16-RHS solve as one
+launch; mixed: shift 1e-4, seed 2, the factorization launch of the
 mixed-precision solve; solve: the 16-RHS forward and backward solve launch
 on the factor of the seed-1 matrix; adjoint: shift 1, seed 3,
 Lbar = tril N(0, 1)), and
@@ -47,6 +48,21 @@ def report(tc, plan, trace, tag, out=print):
             out("  %-6s %8d %10.1f %10.1f %10.1f %11.1f %10.1f" % (
                 tc.KIND_NAMES[k], m.sum(), busy[m].mean(), np.median(busy[m]), busy[m].max(), busy[m].sum() / 1000,
                 wait[m].mean()))
+    # tasks split into several work items (the POTRF pools): the task's span,
+    # from its first item's start to its last item's end
+    for k in range(len(tc.KIND_NAMES)):
+        m = kind == k
+        if not m.any() or len(np.unique(task[m])) == m.sum():
+            continue
+        ids, inv = np.unique(task[m], return_inverse=True)
+        t_first = np.full(len(ids), np.iinfo(np.int64).max)
+        t_last = np.zeros(len(ids), dtype=np.int64)
+        np.minimum.at(t_first, inv, start[m])
+        np.maximum.at(t_last, inv, end[m])
+        sp = (t_last - t_first) / 100.0
+        if tc.KIND_NAMES[k] == "POTRF":
+            out("  %-6s task span: mean %.1f us, p50 %.1f us, max %.1f us over %d tasks, sum %.2f ms"
+                % (tc.KIND_NAMES[k], sp.mean(), np.median(sp), sp.max(), len(ids), sp.sum() / 1000))
     edges = np.linspace(0, span, 21)
     s_rel, e_rel = (start - t0) / 100.0, (end - t0) / 100.0
     util = []
@@ -58,7 +74,7 @@ def report(tc, plan, trace, tag, out=print):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", choices=["factor", "mixed", "solve", "adjoint"], default="factor")
+    ap.add_argument("--op", choices=["factor", "merged", "mixed", "solve", "adjoint"], default="factor")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--policy", choices=["rank", "list", "fifo", "random"], default="list")
@@ -97,6 +113,16 @@ def main(argv=None):
             tc.solve_mixed_(A, X, nb, maxit=0, policy=pol)
             X.copy_(B)
             _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, policy=pol, want_kernel_ms=True, trace=trace)
+        elif args.op == "merged":
+            # the benchmark's launch: factorization and 16-RHS solve as one DAG
+            plan = tc.batched_plan_query([n], [nb], pol)
+            trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
+            B = torch.from_numpy(spd_inputs.rhs(rng, n, 16)).to(dev).t().contiguous()
+            W, X = A.clone(), B.clone()
+            tc.factor_solve_(W, X, nb, policy=pol)
+            W.copy_(A)
+            X.copy_(B)
+            _, ms = tc.factor_solve_(W, X, nb, policy=pol, want_kernel_ms=True, trace=trace)
         elif args.op == "solve":
             plan = tc.plan_query(tc.OP_SOLVE, n, nb, pol)
             trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)

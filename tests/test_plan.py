@@ -319,3 +319,30 @@ def test_mixed_factor_plan_split(n, nb):
         assert pm["parts"][t] == want, (kind, i, j)
     # every item of every task is listed once, in claim order
     assert pm["nitem"] == int(np.sum(pm["parts"][:pm["ntask"]]))
+
+
+def _potrf_parts(m):
+    """Work items of a POTRF task of tile order m: one for m <= 128; above,
+    the strips of the 128-row sub-blocks below the first one, at most 8 (the
+    widest step of the tile's own sub-DAG)."""
+    if m <= 128:
+        return 1
+    strips = sum(-(-min(128, m - r0) // 32) for r0 in range(128, m, 128))
+    return min(8, strips)
+
+
+@pytest.mark.parametrize("op", [0, tc.OP_MIXED_FACTOR])
+@pytest.mark.parametrize("n,nb", [(1000, 128), (2048, 512), (513, 512), (1100, 160), (700, 256), (900, 384),
+                                  (400, 512)])
+def test_potrf_parts(op, n, nb):
+    p = plan(op, n, nb)
+    tsz = lambda i: min(nb, n - nb * i)
+    seen = 0
+    for t in range(p["ntask"]):
+        if int(p["kind"][t]) == POTRF:
+            k = int(p["k"][t])
+            T = -(-n // nb)
+            assert p["parts"][t] == (_potrf_parts(tsz(k)) if T > 1 else 1), (k, tsz(k))
+            seen += 1
+    assert seen == -(-n // nb)
+    assert _potrf_parts(512) == 8 and _potrf_parts(256) == 4 and _potrf_parts(200) == 3 and _potrf_parts(128) == 1
