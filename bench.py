@@ -296,7 +296,11 @@ def run_batched(args):
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
-def measure_mixed(torch, tc, dev, n, nb, nrhs, seed, shift, K, Wm, policy, fp64_ms=None, tol=1e-12, maxit=30):
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def measure_mixed(torch, tc, dev, n, nb, nrhs, seed, shift, K, Wm, policy, fp64_ms=None, tol=1e-12, maxit=30,
+                  lowp=None):
     """Mixed-precision solve with refinement to eta <= tol of nrhs right-hand
     sides of A = B B^T / n + shift I (B ~ U[-1, 1], seed), timed per step
     (factor + refinement, A resident; every step starts from the original
@@ -304,18 +308,20 @@ def measure_mixed(torch, tc, dev, n, nb, nrhs, seed, shift, K, Wm, policy, fp64_
     to compare against; None measures it here on the same matrix.  Returns
     a dict of the results."""
     import spd_inputs
+    lowp = tc.LOWP_FP32 if lowp is None else lowp
+    bf16 = lowp == tc.LOWP_BF16
     t0 = time.time()
     A, rng = spd_inputs.spd_matrix_device(n, seed, shift, device=dev)
     B0 = torch.from_numpy(spd_inputs.rhs(rng, n, nrhs)).to(dev)
     B0c = B0.t().contiguous()
     torch.cuda.synchronize()
-    log("mixed: inputs ready in %.1f s (n=%d nb=%d nrhs=%d shift=%g seed=%d)" % (time.time() - t0, n, nb, nrhs,
-                                                                                 shift, seed))
-    ws = torch.empty(tc.mixed_workspace_bytes(n, nb, nrhs), dtype=torch.uint8, device=dev)
+    log("mixed (%s updates): inputs ready in %.1f s (n=%d nb=%d nrhs=%d shift=%g seed=%d)"
+        % ("bf16" if bf16 else "fp32", time.time() - t0, n, nb, nrhs, shift, seed))
+    ws = torch.empty(tc.mixed_workspace_bytes(n, nb, nrhs, lowp), dtype=torch.uint8, device=dev)
     X = torch.empty_like(B0c)
     for w in range(Wm):
         X.copy_(B0c)
-        rc, it, berr = tc.solve_mixed_(A, X, nb, tol=tol, maxit=maxit, policy=policy, ws=ws)
+        rc, it, berr = tc.solve_mixed_(A, X, nb, tol=tol, maxit=maxit, policy=policy, ws=ws, lowp=lowp)
         log("mixed warmup %d: rc=%d iterations=%d max eta=%.3g" % (w + 1, rc, it, float(np.max(berr))))
     steps = []
     for s_ in range(K):
@@ -323,7 +329,7 @@ def measure_mixed(torch, tc, dev, n, nb, nrhs, seed, shift, K, Wm, policy, fp64_
         torch.cuda.synchronize()
         ts = time.perf_counter()
         rc, it, berr, fms = tc.solve_mixed_(A, X, nb, tol=tol, maxit=maxit, policy=policy, ws=ws,
-                                             want_kernel_ms=True)
+                                             want_kernel_ms=True, lowp=lowp)
         torch.cuda.synchronize()
         steps.append(((time.perf_counter() - ts) * 1e3, rc, it, float(np.max(berr)), fms))
         log("mixed step %d: %.3f ms rc=%d iterations=%d max eta=%.3g factor kernel %.3f ms"
@@ -349,10 +355,15 @@ def measure_mixed(torch, tc, dev, n, nb, nrhs, seed, shift, K, Wm, policy, fp64_
            "refinement_iterations": [st[2] for st in steps], "eta_reported_max": max(st[3] for st in steps),
            "eta_check_max": float(np.max(eta_full)), "abs_residual_sampled_rows_max": worst_row,
            "value": round(n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3), "tol": tol}
+    peak = BF16_MFMA_PEAK_TFLOPS if bf16 else FP32_MFMA_PEAK_TFLOPS
+    out["lowp"] = "bf16" if bf16 else "fp32"
     out["factor_roofline"] = {"bound": "mfma", "achieved": round(n ** 3 / 3.0 / (fms * 1e-3) / 1e12, 3),
-                              "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                              "frac": round(n ** 3 / 3.0 / (fms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
-                              "note": "trailing updates on FP32 matrix cores; POTRF and TRSM in FP64"}
+                              "peak": peak, "unit": "TFLOP/s",
+                              "frac": round(n ** 3 / 3.0 / (fms * 1e-3) / 1e12 / peak, 4),
+                              "note": ("GEMM updates on BF16 matrix cores (three BF16 terms per operand, six term "
+                                       "products, FP32 accumulation); SYRK FP32; POTRF and TRSM in FP64; achieved "
+                                       "counts n^3/3, not the six BF16 products" if bf16 else
+                                       "trailing updates on FP32 matrix cores; POTRF and TRSM in FP64")}
     del ws
     if fp64_ms is None:
         ws_f = torch.empty(tc.workspace_bytes(tc.OP_FACTOR, n, nb), dtype=torch.uint8, device=dev)
@@ -398,7 +409,9 @@ def run_mixed(args):
     torch.cuda.set_device(dev)
     seed = 2 if args.seed == 1 else args.seed
     policy = {"rank": tc.POLICY_RANK, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM, "list": tc.POLICY_LIST}[args.policy]
-    r = measure_mixed(torch, tc, dev, args.n, args.nb, args.nrhs, seed, 1e-4, args.steps, args.warmup, policy)
+    lowp = tc.LOWP_BF16 if args.lowp == "bf16" else tc.LOWP_FP32
+    r = measure_mixed(torch, tc, dev, args.n, args.nb, args.nrhs, seed, 1e-4, args.steps, args.warmup, policy,
+                      lowp=lowp)
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -410,11 +423,11 @@ def run_mixed(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": ("bf16+f32+f64" if args.lowp == "bf16" else "f32+f64"),
         "data": "synthetic",
-        "config": {"workload": "mixed fp32/fp64 Cholesky + iterative refinement of %d RHS to eta<=1e-12, "
+        "config": {"workload": "mixed %s/fp64 Cholesky + iterative refinement of %d RHS to eta<=1e-12, "
                                "n=%d, nb=%d, A=B*B^T/n+1e-4*I, B~U[-1,1] (seed %d)"
-                               % (args.nrhs, args.n, args.nb, seed),
+                               % (args.lowp, args.nrhs, args.n, args.nb, seed),
                    "n": args.n, "nb": args.nb, "nrhs": args.nrhs, "seed": seed, "shift": 1e-4},
         "roofline": r["factor_roofline"],
         "mixed": r,
@@ -559,6 +572,8 @@ def main():
                     help="factor workload: skip the mixed-precision comparison appended to the line")
     ap.add_argument("--count", type=int, default=4096, help="batched: number of systems")
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64", help="batched: storage precision")
+    ap.add_argument("--lowp", choices=["bf16", "fp32"], default="bf16",
+                    help="mixed: precision of the trailing GEMM updates")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -720,7 +735,9 @@ def main():
         del ws_s
         torch.cuda.empty_cache()
         out["mixed_refined"] = measure_mixed(torch, tc, dev, n, nb, nrhs, 2, 1e-4, 2, 1, policy,
-                                             fp64_ms=ms_per_step)
+                                             fp64_ms=ms_per_step, lowp=tc.LOWP_BF16)
+        out["mixed_refined_fp32"] = measure_mixed(torch, tc, dev, n, nb, nrhs, 2, 1e-4, 2, 1, policy,
+                                                  fp64_ms=ms_per_step, lowp=tc.LOWP_FP32)
         ws_s = None
 
     if not args.no_adjoint:

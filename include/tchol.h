@@ -71,6 +71,9 @@ extern "C" {
                                       tchol_factor_solve_noalloc's fixed array  */
 
 #define TCHOL_LOWP_FP32 1 /* mixed precision: FP32 working copy, FP32 matrix-core updates */
+#define TCHOL_LOWP_BF16 2 /* mixed precision: FP32 working copy, BF16 matrix-core updates
+                             (each panel value as three BF16 terms, six term products
+                             with FP32 accumulation: FP32-level update accuracy)   */
 
 #define TCHOL_NB_MIN 16
 #define TCHOL_NB_MAX 512
@@ -235,17 +238,21 @@ TCHOL_API int32_t tchol_factor_solve_batched_f32(float *A, const int64_t *a_off,
    factored on the same tile DAG and scheduler as tchol_factor (the paper's
    Cholesky DAG, section 4.1): SYRK / GEMM / TRSM on the copy with FP32
    matrix-core products, each diagonal tile promoted to FP64 for its POTRF
-   and kept in FP64.  Then x_0 = L~^{-T} L~^{-1} b, and while the normwise
+   and kept in FP64.  With lowp = TCHOL_LOWP_BF16 the GEMM updates run on
+   the BF16 matrix cores instead: each TRSM result is also stored as three
+   BF16 terms (hi + mid + lo), and the six term products whose orders add up
+   to at most two are accumulated in FP32, which keeps the updates at FP32
+   accuracy (the SYRK updates of the diagonal tiles stay FP32 products).  Then x_0 = L~^{-T} L~^{-1} b, and while the normwise
    backward error eta_j = ||r_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf)
    of some column exceeds tol: r = b - A x in FP64 against the original A,
    x += L~^{-T} L~^{-1} r (substitutions in FP64 arithmetic on the stored
    factor).  Each iteration reads the stopping test back to the host once.
    Arguments: 1 A, 2 n >= 0, 3 nb (as for tchol_factor), 4 B (n x nrhs, ld n,
    in: right-hand sides, out: solutions), 5 nrhs >= 0, 6 lowp
-   (TCHOL_LOWP_FP32), 7 tol > 0 (target eta, e.g. 1e-12), 8 maxit >= 0
+   (TCHOL_LOWP_FP32 or TCHOL_LOWP_BF16), 7 tol > 0 (target eta, e.g. 1e-12), 8 maxit >= 0
    (corrections at most), 9 berr_out (host, nrhs entries or NULL: final eta
    per column), 10 iters_out (host or NULL: corrections applied), 11 ws,
-   12 ws_bytes >= tchol_mixed_workspace_bytes(n, nb, nrhs), 13 stream,
+   12 ws_bytes >= tchol_mixed_workspace_bytes_ex(n, nb, nrhs, lowp), 13 stream,
    14 opts (NULL or as for tchol_factor_ex; kernel_ms and trace describe the
    factorization's launch).
    Returns 0 when every column met tol; k > 0 when the low-precision
@@ -255,6 +262,10 @@ TCHOL_API int32_t tchol_factor_solve_batched_f32(float *A, const int64_t *a_off,
    fall back to the FP64 path, tchol_factor + tchol_solve); other negative
    codes as for tchol_factor. */
 TCHOL_API int64_t tchol_mixed_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs);
+/* The same for a given lowp (TCHOL_LOWP_FP32 as above; TCHOL_LOWP_BF16 adds the
+   panels' BF16 terms, 6 bytes per element of the T nb x T nb grid); -4 for
+   another lowp. */
+TCHOL_API int64_t tchol_mixed_workspace_bytes_ex(int64_t n, int64_t nb, int64_t nrhs, int32_t lowp);
 TCHOL_API int32_t tchol_solve_mixed(const double *A, int64_t n, int64_t nb, double *B, int64_t nrhs, int32_t lowp,
                                     double tol, int32_t maxit, double *berr_out, int32_t *iters_out, void *ws,
                                     int64_t ws_bytes, void *stream, const tchol_opts *opts);

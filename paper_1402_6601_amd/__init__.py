@@ -26,7 +26,7 @@ OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD, OP_MIXED_FACTOR = 0, 1, 2, 3, 4
 POLICY_LIST, POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2, 3
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV, E_SCRATCH = -100, -101, -102, -103, -104, -105
 NOALLOC_SCRATCH_BYTES = 16 << 20
-LOWP_FP32 = 1
+LOWP_FP32, LOWP_BF16 = 1, 2
 KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV",
               "TRTRI", "DRED"]
 
@@ -72,6 +72,8 @@ def load() -> ctypes.CDLL:
     lib.tchol_backward_ex.argtypes = [vp, i64, i64, vp, vp, i64, vp, ctypes.POINTER(Opts)]
     lib.tchol_mixed_workspace_bytes.restype = i64
     lib.tchol_mixed_workspace_bytes.argtypes = [i64, i64, i64]
+    lib.tchol_mixed_workspace_bytes_ex.restype = i64
+    lib.tchol_mixed_workspace_bytes_ex.argtypes = [i64, i64, i64, i32]
     lib.tchol_solve_mixed.restype = i32
     lib.tchol_solve_mixed.argtypes = [vp, i64, i64, vp, i64, i32, ctypes.c_double, i32,
                                       ctypes.POINTER(ctypes.c_double), P32, vp, i64, vp, ctypes.POINTER(Opts)]
@@ -198,10 +200,10 @@ def batched_plan_query(n, nb, policy: int = POLICY_LIST, seed: int = 0) -> dict:
     return a
 
 
-def mixed_workspace_bytes(n: int, nb: int, nrhs: int) -> int:
-    r = load().tchol_mixed_workspace_bytes(n, nb, nrhs)
+def mixed_workspace_bytes(n: int, nb: int, nrhs: int, lowp: int = LOWP_FP32) -> int:
+    r = load().tchol_mixed_workspace_bytes_ex(n, nb, nrhs, lowp)
     if r < 0:
-        raise TcholError(int(r), "tchol_mixed_workspace_bytes")
+        raise TcholError(int(r), "tchol_mixed_workspace_bytes_ex")
     return int(r)
 
 
@@ -375,7 +377,7 @@ def solve_mixed_(A, Bc, nb: int, *, tol: float = 1e-12, maxit: int = 30, lowp: i
     berr = np.zeros(max(nrhs, 1), dtype=np.float64)
     iters = ctypes.c_int32(0)
     with torch.cuda.device(A.device):
-        need = mixed_workspace_bytes(n, nb, nrhs) if n else 256
+        need = mixed_workspace_bytes(n, nb, nrhs, lowp) if n else 256
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, A.device)
         o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)

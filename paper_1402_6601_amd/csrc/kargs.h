@@ -48,6 +48,10 @@ typedef struct KArgs {
   uint64_t *trace;      /* optional: 4 words per work item                        */
   int32_t *pool;        /* POOL_WORDS counters per diagonal tile of every system
                            (the split POTRF's sub-unit pool), zeroed per launch */
+  uint16_t *H;          /* BF16-update factorization: three BF16 terms of every panel
+                           tile, K-contiguous: column block k, row r, column c of
+                           term t at H[((t T + k) hrows + r) nb + c]             */
+  int64_t hrows;        /* rows per column block of H (T nb)                      */
 } KArgs;
 
 #define DESC_WORDS 8   /* kind, i, j, k, parts, succ_begin, succ_end, system */

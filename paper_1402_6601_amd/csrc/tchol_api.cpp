@@ -216,7 +216,7 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
                 void* ws, int64_t ws_bytes, void* stream_v, const tchol_opts& o, int32_t ws_arg,
                 int32_t* sinfo_out, double* D = nullptr, int mixed = 0, double* Qp = nullptr,
                 double* LTp = nullptr, int64_t ldq = 0, double* Dinv = nullptr, double* DinvT = nullptr,
-                double* Sx = nullptr) {
+                double* Sx = nullptr, uint16_t* H = nullptr, int64_t hrows = 0) {
   const Layout& L = img.lay;
   if (ws_bytes < L.end) return -(ws_arg + 1);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
@@ -260,6 +260,8 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.Dinv = Dinv;
   a.DinvT = DinvT;
   a.S = Sx;
+  a.H = H;
+  a.hrows = hrows;
   const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
   a.wait_limit = limit_us * di.clock_khz / 1000;
   a.trace = o.trace;
@@ -426,17 +428,21 @@ B32Layout b32_layout(std::vector<tchol::System>* sys, int64_t nrhs, const Plan& 
 // copy has ld = n + 3 rounded up to a multiple of 4 (its matrix-core loads
 // move four rows per 16-byte lane, so three rows past the order are read;
 // they hold zeros).
+// With BF16 updates the workspace also holds the panels' BF16 terms (H):
+// three terms, per column block T nb rows of nb K-contiguous values.
 struct MixedLayout {
-  int64_t ldw = 0, w = 0, d = 0, dinv = 0, dinvt = 0, b0 = 0, r = 0, sx = 0, part = 0, norms = 0, sched = 0,
-          end = 0;
+  int64_t ldw = 0, w = 0, h = 0, hrows = 0, d = 0, dinv = 0, dinvt = 0, b0 = 0, r = 0, sx = 0, part = 0, norms = 0,
+          sched = 0, end = 0;
 };
 
-MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, const Plan& sp) {
+MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, const Plan& sp, bool bf16 = false) {
   MixedLayout M;
   const int64_t T = (n + nb - 1) / nb;
   M.ldw = (n + 3 + 3) / 4 * 4;
   M.w = 0;
-  M.d = align_up(M.w + 4 * M.ldw * n);
+  M.h = align_up(M.w + 4 * M.ldw * n);
+  M.hrows = T * nb;
+  M.d = align_up(M.h + (bf16 ? 2 * 3 * T * M.hrows * nb : 0));
   M.dinv = align_up(M.d + 8 * T * nb * nb);        // L_kk^{-1} per diagonal tile (FP64)
   M.dinvt = align_up(M.dinv + 8 * T * nb * nb);    // L_kk^{-T}
   M.b0 = align_up(M.dinvt + 8 * T * nb * nb);
@@ -650,14 +656,19 @@ int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_
   return execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 11, info);
 }
 
-int64_t tchol_mixed_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs) {
+int64_t tchol_mixed_workspace_bytes_ex(int64_t n, int64_t nb, int64_t nrhs, int32_t lowp) {
   if (n < 0) return -1;
   if (!nb_ok(nb)) return -2;
   if (nrhs < 0) return -3;
+  if (lowp != TCHOL_LOWP_FP32 && lowp != TCHOL_LOWP_BF16) return -4;
   auto fp = tchol::get_plan(tchol::OP_FACTOR_INV, n, nb, TCHOL_POLICY_RANK, 0);
   auto sp = tchol::get_plan(tchol::OP_SOLVE_INV, n, nb, TCHOL_POLICY_RANK, 0);
   if (!fp || !sp) return TCHOL_E_UNSUPPORTED;
-  return mixed_layout(n, nb, nrhs, *fp, *sp).end;
+  return mixed_layout(n, nb, nrhs, *fp, *sp, lowp == TCHOL_LOWP_BF16).end;
+}
+
+int64_t tchol_mixed_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs) {
+  return tchol_mixed_workspace_bytes_ex(n, nb, nrhs, TCHOL_LOWP_FP32);
 }
 
 int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int64_t nrhs, int32_t lowp, double tol,
@@ -666,7 +677,7 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   if (n < 0) return -2;
   if (!nb_ok(nb)) return -3;
   if (nrhs < 0) return -5;
-  if (lowp != TCHOL_LOWP_FP32) return -6;
+  if (lowp != TCHOL_LOWP_FP32 && lowp != TCHOL_LOWP_BF16) return -6;
   if (!(tol > 0.0)) return -7;
   if (maxit < 0) return -8;
   if (iters_out) *iters_out = 0;
@@ -685,7 +696,8 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   auto fplan = tchol::get_plan(tchol::OP_FACTOR_INV, n, nb, o.policy, o.seed);
   auto splan = tchol::get_plan(tchol::OP_SOLVE_INV, n, nb, o.policy, o.seed);
   if (!fplan || !splan) return TCHOL_E_UNSUPPORTED;
-  const MixedLayout M = mixed_layout(n, nb, nrhs, *fplan, *splan);
+  const bool bf16 = lowp == TCHOL_LOWP_BF16;
+  const MixedLayout M = mixed_layout(n, nb, nrhs, *fplan, *splan, bf16);
   if (ws_bytes < M.end) return -12;
   auto fimg = image_of(fplan, M.ldw);
   auto simg = image_of(splan, M.ldw);
@@ -709,7 +721,8 @@ int32_t tchol_solve_mixed(const double* A, int64_t n, int64_t nb, double* B, int
   if (tchol_refine_diag(A, n, n, nb, D, s) != hipSuccess) return TCHOL_E_HIP;
   const tchol_opts& fo = o;  // kernel_ms and trace describe the factorization launch
   int32_t rc = execute(*fplan, *fimg, reinterpret_cast<double*>(W), nullptr, 0, true, false, sched, sched_bytes,
-                       stream_v, fo, 11, nullptr, D, 1, nullptr, nullptr, 0, Dinv, DinvT, nullptr);
+                       stream_v, fo, 11, nullptr, D, bf16 ? 5 : 1, nullptr, nullptr, 0, Dinv, DinvT, nullptr,
+                       bf16 ? reinterpret_cast<uint16_t*>(w + M.h) : nullptr, M.hrows);
   if (rc != 0) return rc;
   tchol_opts so = o;
   so.trace = nullptr;

@@ -107,6 +107,25 @@ __device__ __forceinline__ void st_dev(float* p, float v) {
 }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// BF16 (the upper half of an FP32 word) rounded to nearest even, and back.
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ double bf16_val(uint32_t h) { return (double)__uint_as_float(h << 16); }
+// x as hi + mid + lo, three BF16 terms of decreasing magnitude (each the
+// rounded remainder of the previous ones; the remainders are exact in FP64),
+// good to about 2^-24 relative, i.e. FP32 level.
+__device__ __forceinline__ void split3(double x, uint32_t& h, uint32_t& m, uint32_t& l) {
+  h = bf16_rne((float)x);
+  const double r1 = x - bf16_val(h);
+  m = bf16_rne((float)r1);
+  l = bf16_rne((float)(r1 - bf16_val(m)));
+}
 
 // s_waitcnt vmcnt(N) with the other counters left alone (gfx9 encoding).
 template <int N>
@@ -621,6 +640,118 @@ __device__ __forceinline__ void gemm_nt_f32_d(double* Cd, int64_t ldcd, const fl
 }
 
 // ---------------------------------------------------------------------------
+// BF16 GEMM item of the BF16-update factorization: C[M x N] (FP32, ld ldc)
+// -= A B^T with A (M x K) and B (N x K) each given as three BF16 terms
+// (hi + mid + lo, split3) in K-contiguous rows (row stride hld, terms hterm
+// apart); M <= 256, N <= 128, K % 32 == 0.  The six products of terms whose
+// orders add up to at most two (hh, hm, mh, mm, hl, lh) run on the BF16
+// matrix cores (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; the
+// terms left out are below 2^-24 of the product, so the update keeps FP32
+// accuracy.  2 x 2 wavefronts of 128 x 64.  A chunk of 32 k holds, per
+// term, 64-byte rows of A (256) and B (128) in LDS, filled by direct
+// 16-byte transfers (16 rows per wavefront instruction); the four 16-byte
+// quarters of a row are XOR-swizzled by bits 2-3 of the row, so the
+// fragment reads of 16 consecutive rows hit distinct banks.  Two stages;
+// the next chunk's 72 transfers go out at the start of the current chunk's
+// products.  The instruction has no operand negation: the accumulators
+// start from -C and -acc is stored.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+#define BW_SLOTS_A 1024                               // 16-byte slots per term of A: 256 rows x 4
+#define BW_SLOTS_B 512                                // of B: 128 rows x 4
+#define BW_STAGE_BYTES (3 * (BW_SLOTS_A + BW_SLOTS_B) * 16)
+
+__device__ __forceinline__ int bw_slot(int row, int q) { return row * 4 + (q ^ ((row >> 2) & 3)); }
+
+__device__ __forceinline__ void gemm_bf16x6_wide(float* __restrict__ C, int64_t ldc, const uint16_t* __restrict__ Ha,
+                                                 const uint16_t* __restrict__ Hb, int64_t hld, int64_t hterm, int M,
+                                                 int N, int K, double* lds_d) {
+  constexpr int KC = 32;
+  static_assert(2 * BW_STAGE_BYTES <= 8 * LDS_DOUBLES, "two stages must fit the workgroup LDS");
+  char* lds = reinterpret_cast<char*>(lds_d);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l16 = lane & 15, lg = lane >> 4;
+
+  f4 acc[8][4];
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 128 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+        acc[rb][cb][i] = -C[(int64_t)imin(col, N - 1) * ldc + imin(row, M - 1)];
+      }
+  // transfer j (0..71) of chunk ch: A term j / 16, rows 16 (j % 16) ..; then B term (j - 48) / 8
+  auto xfer = [&](int ch, int j) __attribute__((always_inline)) {
+    char* st = lds + (ch & 1) * BW_STAGE_BYTES;
+    const bool isa = j < 48;
+    const int term = isa ? j >> 4 : (j - 48) >> 3, grp = isa ? j & 15 : (j - 48) & 7;
+    const int row = grp * 16 + (lane >> 2);
+    const int q = (lane & 3) ^ ((row >> 2) & 3);
+    const uint16_t* g = (isa ? Ha : Hb) + term * hterm + (int64_t)imin(row, (isa ? M : N) - 1) * hld + ch * KC + 8 * q;
+    char* dst = st + (isa ? term * BW_SLOTS_A : 3 * BW_SLOTS_A + term * BW_SLOTS_B) * 16 + grp * 64 * 16;
+    dma16(g, reinterpret_cast<double*>(dst));
+  };
+  auto issue = [&](int ch) __attribute__((always_inline)) {
+#pragma unroll
+    for (int jj = 0; jj < 18; ++jj) xfer(ch, wave + 4 * jj);
+  };
+  auto compute = [&](int ch, int nx) __attribute__((always_inline)) {
+    const char* st = lds + (ch & 1) * BW_STAGE_BYTES;
+    if (nx >= 0) issue(nx);
+    bf16x8 fb[3][4];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        fb[t][cb] = *reinterpret_cast<const bf16x8*>(
+            st + (3 * BW_SLOTS_A + t * BW_SLOTS_B + bw_slot(wn * 64 + cb * 16 + l16, lg)) * 16);
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      bf16x8 fa[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        fa[t] = *reinterpret_cast<const bf16x8*>(st + (t * BW_SLOTS_A + bw_slot(wm * 128 + rb * 16 + l16, lg)) * 16);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        f4 c = acc[rb][cb];
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[2][cb], fa[0], c, 0, 0, 0);  // h l
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[0][cb], fa[2], c, 0, 0, 0);  // l h
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[1][cb], fa[1], c, 0, 0, 0);  // m m
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[1][cb], fa[0], c, 0, 0, 0);  // h m
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[0][cb], fa[1], c, 0, 0, 0);  // m h
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[0][cb], fa[0], c, 0, 0, 0);  // h h
+      }
+    }
+  };
+  const int nch = K / KC;
+  if (nch > 0) {
+    issue(0);
+    wait_vmcnt<0>();  // the loads of C and chunk 0
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      compute(ch, ch + 1 < nch ? ch + 1 : -1);
+      if (ch + 1 < nch) {
+        wait_vmcnt<0>();
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 128 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+        if (row < M && col < N) st_dev(C + (int64_t)col * ldc + row, -acc[rb][cb][i]);
+      }
+}
+
+// ---------------------------------------------------------------------------
 // POTRF work item: Akk (m x m, m <= 512) := chol(Akk), lower, in place.
 // Left-looking by panels of PW = 16 columns; a panel stays in LDS from its
 // update to its store:
@@ -957,10 +1088,14 @@ __device__ __forceinline__ int potrf_small(double* __restrict__ Akk, int64_t ld,
 // Qb := P^T (both at leading dimension ldq).
 #define TS 32
 
+// Hs (non-null): the solved strip is also stored as three BF16 terms
+// (split3) in K-contiguous rows: strip row r, column c of term t at
+// Hs[t * hterm + r * hld + c] (the BF16 panels of the BF16-update factorization).
 template <typename TX, int REV = 0>
 __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, const double* __restrict__ Lkk, int64_t ld,
                                            int S, int mk, double* lds, double* Qa = nullptr, double* Qb = nullptr,
-                                           int64_t ldq = 0) {
+                                           int64_t ldq = 0, uint16_t* Hs = nullptr, int64_t hld = 0,
+                                           int64_t hterm = 0) {
   double* Xs = lds;  // [2][512][16]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1085,6 +1220,23 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     const int r = tid & 31, c0 = tid >> 5;
     if (r < S)
       for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ldx + r, (TX)Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
+    if (Hs) {
+      // eight threads per row, each a run of mk / 8 columns (mk is a multiple of 16), two per 32-bit store
+      const int hr = tid >> 3, seg = mk >> 3, cs = (tid & 7) * seg;
+      if (hr < S) {
+        uint32_t* h0 = reinterpret_cast<uint32_t*>(Hs + (int64_t)hr * hld + cs);
+        uint32_t* h1 = reinterpret_cast<uint32_t*>(Hs + hterm + (int64_t)hr * hld + cs);
+        uint32_t* h2 = reinterpret_cast<uint32_t*>(Hs + 2 * hterm + (int64_t)hr * hld + cs);
+        for (int c = 0; c < seg; c += 2) {
+          uint32_t a0, a1, a2, b0, b1, b2;
+          split3(Xs[(hr >> 4) * 8192 + (cs + c) * 16 + (hr & 15)], a0, a1, a2);
+          split3(Xs[(hr >> 4) * 8192 + (cs + c + 1) * 16 + (hr & 15)], b0, b1, b2);
+          st_dev(h0 + c / 2, a0 | (b0 << 16));
+          st_dev(h1 + c / 2, a1 | (b1 << 16));
+          st_dev(h2 + c / 2, a2 | (b2 << 16));
+        }
+      }
+    }
     if constexpr (REV == 2) {
       for (int idx = tid; idx < S * mk; idx += NT) {
         const int rr = idx / mk, c = idx - rr * mk;
@@ -1850,18 +2002,22 @@ __device__ __forceinline__ bool pool_wait_unit(const KArgs& a, const int32_t* po
 // factorization / its solves: the matrix is the FP32 working copy (a.A points
 // to it), factored with FP32 MFMA updates and FP64 diagonal tiles kept in
 // a.D; solves run in FP64 reading L in FP32 off the diagonal and in FP64 on
-// it.  A mixed launch runs only its own task kinds (keeping each instance
-// small) and is always a 16-byte one.
+// it.  MODE 5: the mixed-precision factorization with BF16 updates: as
+// MODE 1, with the TRSM strips also storing their results as three BF16
+// terms (a.H) and the GEMM items running on the BF16 matrix cores over them.
+// A mixed launch runs only its own task kinds (keeping each instance small)
+// and is always a 16-byte one.
 template <int SEG, int MODE>
 __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
-  constexpr bool MIXED = MODE == 1 || MODE == 2 || MODE == 4;
-  constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1 || MODE == 4;
+  constexpr bool MIXED = MODE == 1 || MODE == 2 || MODE == 4 || MODE == 5;
+  constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1 || MODE == 4 || MODE == 5;
   constexpr bool SOLVE_KINDS = MODE == 0 || MODE == 2 || MODE == 4;
   constexpr bool ADJOINT_KINDS = MODE == 3;
-  // FP64 factorizations split large POTRF tasks over their work items (the
-  // tile's pool of sub-units); the mixed-precision instances factor each
-  // diagonal tile on one workgroup (only part 0 of a POTRF task works)
-  constexpr bool POOLED = MODE == 0;
+  // The FP64 and mixed-precision factorizations split large POTRF tasks
+  // over their work items (the tile's pool of sub-units; the mixed one on
+  // its FP64 diagonal tile); the batched FP32 instance factors each diagonal
+  // tile on one workgroup (only part 0 of a POTRF task works)
+  constexpr bool POOLED = MODE == 0 || MODE == 1 || MODE == 5;
   __shared__ double lds[LDS_DOUBLES];
   __shared__ int s_claim[4];
   __shared__ int32_t s_desc[DESC_WORDS];
@@ -2030,8 +2186,24 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         // work items (the plan's choice), else by the one-workgroup kernel
         int info;
         if constexpr (MIXED) {
-          if (part > 0) break;  // one workgroup factors the tile
-          info = uniform_i(potrf_tile_mixed(Dsys + (int64_t)tk * nb * nb, nb, tsz(tk), lds));
+          double* const Dk = Dsys + (int64_t)tk * nb * nb;
+          if (POOLED && unit >= 0) {
+            // P(b) on the FP64 diagonal tile; the last one pads a ragged tile
+            // to a multiple of 16 with the identity (for its inverse)
+            info = uniform_i(potrf_small(Dk + (int64_t)po_k * nb + po_k, nb, po_m, lds));
+            if (info != 0) {
+              info += po_k;
+            } else if (po_k + po_m == tsz(tk)) {
+              const int m = tsz(tk), mpad = (m + 15) & ~15;
+              for (int idx = tid; idx < mpad * mpad; idx += NT) {
+                const int c = idx / mpad, r = idx - c * mpad;
+                if (r >= c && (r >= m || c >= m)) st_dev(Dk + (int64_t)c * nb + r, r == c ? 1.0 : 0.0);
+              }
+            }
+          } else {
+            if (part > 0) break;  // one workgroup factors the tile
+            info = uniform_i(potrf_tile_mixed(Dk, nb, tsz(tk), lds));
+          }
         } else {
           const bool sub = unit >= 0;
           const int m = sub ? po_m : tsz(tk);
@@ -2059,9 +2231,21 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           break;
         }
         if constexpr (MIXED) {
-          const int r0 = part * a.trsm_rows;
-          const int S = imin(a.trsm_rows, tsz(ti) - r0);
-          trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dsys + (int64_t)tk * nb * nb, nb, S, tsz(tk), lds);
+          double* const Dk = Dsys + (int64_t)tk * nb * nb;
+          if (POOLED && unit >= 0) {
+            // strip of sub-block (r, b) of the FP64 diagonal tile
+            const int r0 = po_s * TS;
+            trsm_strip(Dk + (int64_t)po_k * nb + po_r + r0, nb, Dk + (int64_t)po_k * nb + po_k, nb,
+                       imin(TS, po_m - r0), po_kk, lds);
+          } else {
+            const int r0 = part * a.trsm_rows;
+            const int S = imin(a.trsm_rows, tsz(ti) - r0);
+            if constexpr (MODE == 5)  // the strip also as BF16 terms, for the BF16 updates
+              trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dk, nb, S, tsz(tk), lds, nullptr, nullptr, 0,
+                         a.H + ((int64_t)tk * a.hrows + (int64_t)ti * nb + r0) * nb, nb, (int64_t)a.T * a.hrows * nb);
+            else
+              trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dk, nb, S, tsz(tk), lds);
+          }
         } else {
           // a strip of A_ik, or of sub-block (r, b) of the diagonal tile for a pool unit
           const bool sub = unit >= 0;
@@ -2116,6 +2300,13 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         const E* Bp = Abase + kcol * ld + brow;
         const bool misaligned = ((reinterpret_cast<uintptr_t>(Ap) | reinterpret_cast<uintptr_t>(Bp)) & 15) != 0;
         if constexpr (MIXED) {
+          if (POOLED && unit >= 0) {
+            // sub-block (r, c) of the FP64 diagonal tile -= L_rb L_cb^T, in FP64
+            double* const Dk = Dsys + (int64_t)tk * nb * nb;
+            gemm_nt<128>(Dk + (int64_t)po_c * nb + po_r, Dk + (int64_t)po_k * nb + po_r,
+                         Dk + (int64_t)po_k * nb + po_c, nb, M, N, K, lower, lds);
+            break;
+          }
           // four rows per 16-byte lane: ld a multiple of 4 and three rows after the order
           if ((((int)ld & 3) != 0) || ld < sn + 3 || misaligned) {
             raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract
@@ -2125,6 +2316,9 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           if (kind == TK_SYRK)
             gemm_nt_f32_d(Dsys + (int64_t)ti * nb * nb + (int64_t)(sj * bn) * nb + si * bm, nb, Ap, Bp, ld, M, N,
                           tsz(tk), si == sj, lds);
+          else if (MODE == 5 && bm == 256 && bn == 128 && tsz(tk) % 32 == 0)
+            gemm_bf16x6_wide(C, ld, a.H + ((int64_t)tk * a.hrows + crow) * nb, a.H + ((int64_t)tk * a.hrows + brow) * nb,
+                             nb, (int64_t)a.T * a.hrows * nb, M, N, tsz(tk), lds);
           else if (bm == 256 && bn == 128 && tsz(tk) % 32 == 0)
             gemm_f32_wide<32, 3>(C, Ap, Bp, ld, M, N, tsz(tk), lds);
           else  // 128-row products (a 256-row item whose K is not a multiple of 32 takes two)
@@ -2191,7 +2385,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         break;
       }
       case TK_TRTRI: {
-        if constexpr (MODE != 1) {
+        if constexpr (MODE != 1 && MODE != 5) {
           ok = 0;
         } else {
           // L_kk^{-T} by 32-row strips: identity rows solved in place (into DinvT, ld nb),
@@ -2333,7 +2527,9 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
     e = hipEventRecord(ev0, stream);
     if (e != hipSuccess) return e;
   }
-  if (a->mixed == 4)
+  if (a->mixed == 5)
+    hipLaunchKernelGGL((tchol_persistent<128, 5>), dim3(grid), dim3(NT), 0, stream, *a);
+  else if (a->mixed == 4)
     hipLaunchKernelGGL((tchol_persistent<128, 4>), dim3(grid), dim3(NT), 0, stream, *a);
   else if (a->mixed == 3)
     hipLaunchKernelGGL((tchol_persistent<128, 3>), dim3(grid), dim3(NT), 0, stream, *a);
@@ -2380,6 +2576,10 @@ extern "C" hipError_t tchol_dev_max_grid(int device, int* grid) {
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occb, tchol_persistent<128, 4>, NT, 0);
   if (e != hipSuccess) return e;
+  int occf = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occf, tchol_persistent<128, 5>, NT, 0);
+  if (e != hipSuccess) return e;
+  occ = occ < occf ? occ : occf;
   occ = occ < occa ? occ : occa;
   occ = occ < occb ? occ : occb;
   occ = occ < occ32 ? occ : occ32;

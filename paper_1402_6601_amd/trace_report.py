@@ -78,6 +78,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--policy", choices=["rank", "list", "fifo", "random"], default="list")
+    ap.add_argument("--lowp", choices=["bf16", "fp32"], default="bf16", help="mixed: precision of the GEMM updates")
     args = ap.parse_args(argv)
     import torch
     import paper_1402_6601_amd as tc
@@ -110,9 +111,10 @@ def main(argv=None):
         if mixed:
             B = torch.from_numpy(spd_inputs.rhs(rng, n, 16)).to(dev).t().contiguous()
             X = B.clone()
-            tc.solve_mixed_(A, X, nb, maxit=0, policy=pol)
+            lowp = tc.LOWP_BF16 if args.lowp == "bf16" else tc.LOWP_FP32
+            tc.solve_mixed_(A, X, nb, maxit=0, policy=pol, lowp=lowp)
             X.copy_(B)
-            _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, policy=pol, want_kernel_ms=True, trace=trace)
+            _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, policy=pol, want_kernel_ms=True, trace=trace, lowp=lowp)
         elif args.op == "merged":
             # the benchmark's launch: factorization and 16-RHS solve as one DAG
             plan = tc.batched_plan_query([n], [nb], pol)

@@ -102,7 +102,14 @@ def test_mixed_validation_before_any_hip_call(lib):
     assert call(n_=-1) == -2
     assert call(nb_=40) == -3
     assert call(k_=-1) == -5
-    assert call(lowp=0) == -6 and call(lowp=2) == -6
+    assert call(lowp=0) == -6 and call(lowp=3) == -6
+    # BF16 updates need room for the panels' three BF16 terms as well
+    need_bf16 = lib.tchol_mixed_workspace_bytes_ex(n, nb, k, 2)
+    assert need_bf16 >= need + 2 * 3 * n * n
+    assert lib.tchol_mixed_workspace_bytes_ex(n, nb, k, 1) == need
+    assert lib.tchol_mixed_workspace_bytes_ex(n, nb, k, 3) == -4
+    assert call(lowp=2) == -12
+    assert call(lowp=2, wsb=need_bf16 - 256) == -12
     assert call(tol=0.0) == -7 and call(tol=float("nan")) == -7
     assert call(maxit=-1) == -8
     assert call(n_=0) == 0 and it.value == 0

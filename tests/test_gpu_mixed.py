@@ -14,6 +14,8 @@ Bar, per right-hand side:
     on the shift-1e-4 matrices, condition number about 1.3e4);
   - breakdown and non-convergence are reported as documented, and results
     do not depend on the claim order.
+Every check runs for both low precisions: FP32 trailing updates, and BF16
+updates (each panel value as three BF16 terms, FP32 accumulation).
 """
 import numpy as np
 import pytest
@@ -25,6 +27,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TARGET = 1e-12
+LOWPS = [1, 2]   # LOWP_FP32, LOWP_BF16
 
 
 @pytest.fixture(scope="module")
@@ -58,10 +61,11 @@ def _kappa_inf(A):
     (17, 16, 25, 1e-4, 4),
     (2048, 512, 26, 1e-4, 16),
 ])
-def test_mixed_reaches_target(tc, n, nb, seed, shift, nrhs):
-    print("case n=%d nb=%d seed=%d shift=%g nrhs=%d" % (n, nb, seed, shift, nrhs), flush=True)
+@pytest.mark.parametrize("lowp", LOWPS)
+def test_mixed_reaches_target(tc, n, nb, seed, shift, nrhs, lowp):
+    print("case n=%d nb=%d seed=%d shift=%g nrhs=%d lowp=%d" % (n, nb, seed, shift, nrhs, lowp), flush=True)
     A, b = spd_inputs.spd_matrix_and_rhs(n, seed, nrhs=nrhs, shift=shift)
-    rc, iters, berr, X = _mixed(tc, A, b, nb, tol=TARGET, maxit=30)
+    rc, iters, berr, X = _mixed(tc, A, b, nb, tol=TARGET, maxit=30, lowp=lowp)
     assert rc == 0, (rc, iters, berr)
     assert np.all(berr <= TARGET)
     eta = oracle.solve_backward_error(A, X, b)
@@ -76,11 +80,12 @@ def test_mixed_reaches_target(tc, n, nb, seed, shift, nrhs):
     print("  iters=%d max eta=%.3g max e_x=%.3g kappa_inf=%.3g" % (iters, eta.max(), ex.max(), kap), flush=True)
 
 
-def test_mixed_reported_error_matches_oracle_without_refinement(tc):
+@pytest.mark.parametrize("lowp", LOWPS)
+def test_mixed_reported_error_matches_oracle_without_refinement(tc, lowp):
     """maxit = 0: only the low-precision solve; the call reports
     non-convergence and the eta it measured, which the oracle confirms."""
     A, b = spd_inputs.spd_matrix_and_rhs(768, 27, nrhs=4, shift=1e-4)
-    rc, iters, berr, X = _mixed(tc, A, b, 128, tol=TARGET, maxit=0)
+    rc, iters, berr, X = _mixed(tc, A, b, 128, tol=TARGET, maxit=0, lowp=lowp)
     assert rc == tc.E_NOCONV and iters == 0
     eta = oracle.solve_backward_error(A, X, b)
     assert np.all(eta > TARGET)
@@ -91,23 +96,25 @@ def test_mixed_reported_error_matches_oracle_without_refinement(tc):
     assert np.all(ex <= 2.5 * _kappa_inf(A) * (eta + 1e-15))
 
 
-def test_mixed_bitwise_across_policies(tc):
+@pytest.mark.parametrize("lowp", LOWPS)
+def test_mixed_bitwise_across_policies(tc, lowp):
     A, b = spd_inputs.spd_matrix_and_rhs(900, 28, nrhs=3, shift=1e-4)
-    ref = _mixed(tc, A, b, 128)
+    ref = _mixed(tc, A, b, 128, lowp=lowp)
     for pol, seed in [(tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 9)]:
-        got = _mixed(tc, A, b, 128, policy=pol, seed=seed)
+        got = _mixed(tc, A, b, 128, policy=pol, seed=seed, lowp=lowp)
         assert got[0] == ref[0] and got[1] == ref[1]
         assert np.array_equal(got[3], ref[3])
 
 
-def test_mixed_breakdown_reports_the_minor(tc):
+@pytest.mark.parametrize("lowp", LOWPS)
+def test_mixed_breakdown_reports_the_minor(tc, lowp):
     A, L0 = spd_inputs.integer_spd(400, seed=29)
     j = 233
     A[j, j] -= 2.0 * L0[j, j] ** 2      # pivot j becomes -L0[j, j]^2: clearly negative
     _, info_o = oracle.potrf(A)
     assert info_o == j + 1
     b = np.ones((400, 2))
-    rc, iters, _, X = _mixed(tc, A, b, 64)
+    rc, iters, _, X = _mixed(tc, A, b, 64, lowp=lowp)
     assert rc == j + 1 and iters == 0
     assert np.array_equal(X, b)          # B untouched
 
@@ -136,3 +143,22 @@ def test_mixed_degenerate_sizes(tc):
     A1 = np.array([[4.0]])
     rc, iters, berr, X = _mixed(tc, A1, np.array([[2.0]]), 16)
     assert rc == 0 and abs(X[0, 0] - 0.5) <= 1e-15
+
+
+def test_bf16_updates_keep_fp32_accuracy(tc):
+    """The BF16 path's three-term products keep the updates at FP32 accuracy:
+    the backward error of the first low-precision solution (no refinement)
+    is of the same size as with FP32 updates (a one-term BF16 product would
+    leave it about 2^16 times larger), and the BF16 path needs at most one
+    correction more than the FP32 one to reach the target."""
+    A, b = spd_inputs.spd_matrix_and_rhs(2048, 34, nrhs=4, shift=1e-4)
+    _, _, _, X32 = _mixed(tc, A, b, 512, lowp=1, maxit=0)
+    _, _, _, X16 = _mixed(tc, A, b, 512, lowp=2, maxit=0)
+    e32 = oracle.solve_backward_error(A, X32, b)
+    e16 = oracle.solve_backward_error(A, X16, b)
+    print("first-solve eta: fp32 %.3g, bf16 %.3g" % (e32.max(), e16.max()), flush=True)
+    assert e16.max() <= 4.0 * e32.max(), (e16, e32)
+    _, it32, _, _ = _mixed(tc, A, b, 512, lowp=1)
+    rc, it16, _, X = _mixed(tc, A, b, 512, lowp=2)
+    assert rc == 0 and it16 <= it32 + 1, (it32, it16)
+    assert np.all(oracle.solve_backward_error(A, X, b) <= TARGET)
