@@ -110,6 +110,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void st_dev(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_dev(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // BF16 (the upper half of an FP32 word) rounded to nearest even, and back.
 __device__ __forceinline__ uint32_t bf16_rne(float f) {
@@ -1221,19 +1224,28 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     if (r < S)
       for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ldx + r, (TX)Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
     if (Hs) {
-      // eight threads per row, each a run of mk / 8 columns (mk is a multiple of 16), two per 32-bit store
-      const int hr = tid >> 3, seg = mk >> 3, cs = (tid & 7) * seg;
+      // runs of 4 columns (8 bytes per term): lane l of wavefront w takes row
+      // 16 (w & 1) + l % 16 (consecutive rows: conflict-free reads of Xs) and
+      // runs 4 u + l / 16 of its half of the columns (w / 2); a store
+      // instruction then writes 32-byte pieces of 16 rows
+      const int hr = 16 * (wave & 1) + l16, half = mk >> 3;  // runs of 4 per half of the columns
       if (hr < S) {
-        uint32_t* h0 = reinterpret_cast<uint32_t*>(Hs + (int64_t)hr * hld + cs);
-        uint32_t* h1 = reinterpret_cast<uint32_t*>(Hs + hterm + (int64_t)hr * hld + cs);
-        uint32_t* h2 = reinterpret_cast<uint32_t*>(Hs + 2 * hterm + (int64_t)hr * hld + cs);
-        for (int c = 0; c < seg; c += 2) {
-          uint32_t a0, a1, a2, b0, b1, b2;
-          split3(Xs[(hr >> 4) * 8192 + (cs + c) * 16 + (hr & 15)], a0, a1, a2);
-          split3(Xs[(hr >> 4) * 8192 + (cs + c + 1) * 16 + (hr & 15)], b0, b1, b2);
-          st_dev(h0 + c / 2, a0 | (b0 << 16));
-          st_dev(h1 + c / 2, a1 | (b1 << 16));
-          st_dev(h2 + c / 2, a2 | (b2 << 16));
+#pragma unroll 1
+        for (int u = 0; 4 * u + lg < half; ++u) {
+          const int c0 = (wave >> 1) * (mk >> 1) + 4 * (4 * u + lg);
+          uint64_t t0 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            uint32_t a0, a1, a2;
+            split3(Xs[(hr >> 4) * 8192 + (c0 + e) * 16 + (hr & 15)], a0, a1, a2);
+            t0 |= (uint64_t)a0 << (16 * e);
+            t1 |= (uint64_t)a1 << (16 * e);
+            t2 |= (uint64_t)a2 << (16 * e);
+          }
+          uint16_t* h = Hs + (int64_t)hr * hld + c0;
+          st_dev(reinterpret_cast<uint64_t*>(h), t0);
+          st_dev(reinterpret_cast<uint64_t*>(h + hterm), t1);
+          st_dev(reinterpret_cast<uint64_t*>(h + 2 * hterm), t2);
         }
       }
     }
