@@ -92,6 +92,7 @@ int64_t weight(int32_t kind, int32_t op) {
       case TK_TRSM: return 11;
       case TK_SYRK: return 4;
       case TK_GEMM: return 4;
+      case TK_GEMM2: return 8;
       case TK_TRTRI: return 11;
       default: break;
     }
@@ -101,6 +102,7 @@ int64_t weight(int32_t kind, int32_t op) {
     case TK_TRSM: return 10;
     case TK_SYRK: return 4;
     case TK_GEMM: return 6;
+    case TK_GEMM2: return 12;
     case TK_FTRSV: case TK_BTRSV: return 1;
     case TK_GREV: return 6;
     case TK_TREV: return 3;
@@ -134,6 +136,18 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
   std::vector<int32_t> id_gemm((size_t)T * T * T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
+  // The updates of tile (i, j), k = 0 .. j-1, are chained in k.  Every pair
+  // (k, k+1) with k even that does not contain the last update (k+1 <= j-2)
+  // is one GEMM2 task (K = 2 nb: half the loads and stores of the tile, and
+  // half the work items' fixed costs, for the same products in the same
+  // order); the last update before TRSM(i, j) stays a single GEMM, so the
+  // critical path does not wait for a double update.  id_gemm[(i, j, k)]
+  // holds the task that applies update k (a GEMM2 under both of its k).
+  auto pair_first = [](int32_t j, int32_t k) { return (k % 2 == 0) && (k + 1 <= j - 2); };
+  auto pair_second = [](int32_t j, int32_t k) { return (k % 2 == 1) && (k <= j - 2); };
+  auto gemm_parts = [&](int32_t i, int32_t j) {
+    return Builder::cdiv(b.tile_size(i), b.s.gemm_m) * Builder::cdiv(b.tile_size(j), b.s.gemm_n);
+  };
   for (int32_t k = 0; k < T; ++k) {
     // a single-tile system's POTRF is the whole factorization: in a batch of
     // many such systems the workgroups have independent work enough, so it
@@ -144,10 +158,14 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
     for (int32_t i = k + 1; i < T; ++i) {
       int32_t sb = Builder::cdiv(b.tile_size(i), b.s.syrk_b);
       id_syrk[ix2(i, k)] = b.add(TK_SYRK, i, i, k, sb * (sb + 1) / 2);
-      for (int32_t j = k + 1; j < i; ++j)
-        id_gemm[ix3(i, j, k)] = b.add(TK_GEMM, i, j, k,
-                                      Builder::cdiv(b.tile_size(i), b.s.gemm_m) *
-                                          Builder::cdiv(b.tile_size(j), b.s.gemm_n));
+      for (int32_t j = k + 1; j < i; ++j) {
+        if (pair_first(j, k)) continue;  // created with its second update, after TRSM(., k+1)
+        const bool second = pair_second(j, k);
+        const int32_t id = second ? b.add(TK_GEMM2, i, j, k - 1, gemm_parts(i, j))
+                                  : b.add(TK_GEMM, i, j, k, gemm_parts(i, j));
+        id_gemm[ix3(i, j, k)] = id;
+        if (second) id_gemm[ix3(i, j, k - 1)] = id;
+      }
     }
   }
   for (int32_t k = 0; k < T; ++k) {
@@ -158,8 +176,11 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
       for (int32_t j = k + 1; j < i; ++j) st.push_back(id_gemm[ix3(i, j, k)]);
       for (int32_t m = i + 1; m < T; ++m) st.push_back(id_gemm[ix3(m, i, k)]);
       succ[id_syrk[ix2(i, k)]].push_back(k + 1 < i ? id_syrk[ix2(i, k + 1)] : id_potrf[i]);
-      for (int32_t j = k + 1; j < i; ++j)
+      // each update task passes the tile on to the next one, the last to TRSM(i, j)
+      for (int32_t j = k + 1; j < i; ++j) {
+        if (pair_first(j, k)) continue;
         succ[id_gemm[ix3(i, j, k)]].push_back(k + 1 < j ? id_gemm[ix3(i, j, k + 1)] : id_trsm[ix2(i, j)]);
+      }
     }
   }
   if (trtri)
@@ -276,8 +297,13 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   int32_t kind = p.kind[t], step = p.tk[t];
   if (kind == TK_BTRSV || kind == TK_BGEMV) step = T + (T - 1 - p.tk[t]);
   if (p.op == TCHOL_OP_BATCHED && kind >= TK_FTRSV && kind <= TK_BGEMV) step += T;  // a system's solve after its factor
-  if (kind >= TK_GREV && kind != TK_TRTRI) step = T - 1 - p.tk[t];  // the adjoint runs its steps downwards
+  const bool adjoint = kind == TK_GREV || kind == TK_TREV || kind == TK_DPART || kind == TK_PREV || kind == TK_DRED;
+  if (adjoint) step = T - 1 - p.tk[t];  // the adjoint runs its steps downwards
   int32_t kord = kind;
+  if (kind == TK_GEMM2) {  // a double update belongs to the step of its second update
+    step = p.tk[t] + 1;
+    kord = TK_GEMM;
+  }
   if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV
   if (kind == TK_BGEMV) kord = 1;
   if (kind == TK_FTRSV) kord = 0;

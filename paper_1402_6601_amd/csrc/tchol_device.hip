@@ -646,7 +646,8 @@ __device__ __forceinline__ void gemm_nt_f32_d(double* Cd, int64_t ldcd, const fl
 // BF16 GEMM item of the BF16-update factorization: C[M x N] (FP32, ld ldc)
 // -= A B^T with A (M x K) and B (N x K) each given as three BF16 terms
 // (hi + mid + lo, split3) in K-contiguous rows (row stride hld, terms hterm
-// apart); M <= 256, N <= 128, K % 32 == 0.  The six products of terms whose
+// apart; K beyond one column block of kb columns continues in the next
+// block, hblk further); M <= 256, N <= 128, K % 32 == 0, kb % 32 == 0.  The six products of terms whose
 // orders add up to at most two (hh, hm, mh, mm, hl, lh) run on the BF16
 // matrix cores (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; the
 // terms left out are below 2^-24 of the product, so the update keeps FP32
@@ -666,8 +667,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ int bw_slot(int row, int q) { return row * 4 + (q ^ ((row >> 2) & 3)); }
 
 __device__ __forceinline__ void gemm_bf16x6_wide(float* __restrict__ C, int64_t ldc, const uint16_t* __restrict__ Ha,
-                                                 const uint16_t* __restrict__ Hb, int64_t hld, int64_t hterm, int M,
-                                                 int N, int K, double* lds_d) {
+                                                 const uint16_t* __restrict__ Hb, int64_t hld, int64_t hterm,
+                                                 int64_t hblk, int kb, int M, int N, int K, double* lds_d) {
   constexpr int KC = 32;
   static_assert(2 * BW_STAGE_BYTES <= 8 * LDS_DOUBLES, "two stages must fit the workgroup LDS");
   char* lds = reinterpret_cast<char*>(lds_d);
@@ -693,7 +694,9 @@ __device__ __forceinline__ void gemm_bf16x6_wide(float* __restrict__ C, int64_t 
     const int term = isa ? j >> 4 : (j - 48) >> 3, grp = isa ? j & 15 : (j - 48) & 7;
     const int row = grp * 16 + (lane >> 2);
     const int q = (lane & 3) ^ ((row >> 2) & 3);
-    const uint16_t* g = (isa ? Ha : Hb) + term * hterm + (int64_t)imin(row, (isa ? M : N) - 1) * hld + ch * KC + 8 * q;
+    const int kk = ch * KC;  // k of the chunk: column kk % kb of column block kk / kb
+    const uint16_t* g = (isa ? Ha : Hb) + term * hterm + (int64_t)(kk / kb) * hblk +
+                        (int64_t)imin(row, (isa ? M : N) - 1) * hld + kk % kb + 8 * q;
     char* dst = st + (isa ? term * BW_SLOTS_A : 3 * BW_SLOTS_A + term * BW_SLOTS_B) * 16 + grp * 64 * 16;
     dma16(g, reinterpret_cast<double*>(dst));
   };
@@ -711,22 +714,29 @@ __device__ __forceinline__ void gemm_bf16x6_wide(float* __restrict__ C, int64_t 
       for (int cb = 0; cb < 4; ++cb)
         fb[t][cb] = *reinterpret_cast<const bf16x8*>(
             st + (3 * BW_SLOTS_A + t * BW_SLOTS_B + bw_slot(wn * 64 + cb * 16 + l16, lg)) * 16);
+    // the A fragments of row block rb + 1 are read while the products of rb run
+    bf16x8 fan[2][3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      fan[0][t] = *reinterpret_cast<const bf16x8*>(st + (t * BW_SLOTS_A + bw_slot(wm * 128 + l16, lg)) * 16);
 #pragma unroll
     for (int rb = 0; rb < 8; ++rb) {
-      bf16x8 fa[3];
+      if (rb + 1 < 8) {
 #pragma unroll
-      for (int t = 0; t < 3; ++t)
-        fa[t] = *reinterpret_cast<const bf16x8*>(st + (t * BW_SLOTS_A + bw_slot(wm * 128 + rb * 16 + l16, lg)) * 16);
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        f4 c = acc[rb][cb];
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[2][cb], fa[0], c, 0, 0, 0);  // h l
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[0][cb], fa[2], c, 0, 0, 0);  // l h
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[1][cb], fa[1], c, 0, 0, 0);  // m m
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[1][cb], fa[0], c, 0, 0, 0);  // h m
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[0][cb], fa[1], c, 0, 0, 0);  // m h
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[0][cb], fa[0], c, 0, 0, 0);  // h h
+        for (int t = 0; t < 3; ++t)
+          fan[(rb + 1) & 1][t] = *reinterpret_cast<const bf16x8*>(
+              st + (t * BW_SLOTS_A + bw_slot(wm * 128 + (rb + 1) * 16 + l16, lg)) * 16);
       }
+      const bf16x8* fa = fan[rb & 1];
+      // term pairs (B term, A term) from the smallest: h l, l h, m m, h m, m h, h h;
+      // consecutive instructions go to the four independent accumulators
+      // of the row block, so none waits for the previous one's result
+      constexpr int PB[6] = {2, 0, 1, 1, 0, 0}, PA[6] = {0, 2, 1, 0, 1, 0};
+#pragma unroll
+      for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[PB[pr]][cb], fa[PA[pr]], acc[rb][cb], 0, 0, 0);
     }
   };
   const int nch = K / KC;
@@ -2271,7 +2281,8 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         break;
       }
       case TK_SYRK:
-      case TK_GEMM: {
+      case TK_GEMM:
+      case TK_GEMM2: {
         if constexpr (!FACTOR_KINDS) {
           ok = 0;
           break;
@@ -2292,7 +2303,9 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         }
         int M = imin(bm, tsz(ti) - si * bm);
         int N = imin(bn, tsz(tj) - sj * bn);
-        int K = tsz(tk);
+        // a double update streams the panel columns of steps k and k + 1,
+        // which are adjacent in the matrix: one product with K = 2 nb
+        int K = kind == TK_GEMM2 ? tsz(tk) + tsz(tk + 1) : tsz(tk);
         bool lower = kind == TK_SYRK && si == sj;
         int64_t crow = (int64_t)ti * nb + si * bm, ccol = (int64_t)tj * nb + sj * bn, kcol = (int64_t)tk * nb;
         int64_t brow = (int64_t)tj * nb + sj * bn;
@@ -2330,12 +2343,12 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
                           tsz(tk), si == sj, lds);
           else if (MODE == 5 && bm == 256 && bn == 128 && tsz(tk) % 32 == 0)
             gemm_bf16x6_wide(C, ld, a.H + ((int64_t)tk * a.hrows + crow) * nb, a.H + ((int64_t)tk * a.hrows + brow) * nb,
-                             nb, (int64_t)a.T * a.hrows * nb, M, N, tsz(tk), lds);
+                             nb, (int64_t)a.T * a.hrows * nb, a.hrows * nb, (int)nb, M, N, K, lds);
           else if (bm == 256 && bn == 128 && tsz(tk) % 32 == 0)
-            gemm_f32_wide<32, 3>(C, Ap, Bp, ld, M, N, tsz(tk), lds);
+            gemm_f32_wide<32, 3>(C, Ap, Bp, ld, M, N, K, lds);
           else  // 128-row products (a 256-row item whose K is not a multiple of 32 takes two)
             for (int r0 = 0; r0 < M; r0 += 128)
-              gemm_nt_f32(C + r0, Ap + r0, Bp, ld, imin(128, M - r0), N, tsz(tk), false, lds);
+              gemm_nt_f32(C + r0, Ap + r0, Bp, ld, imin(128, M - r0), N, K, false, lds);
         } else {
           if (SEG == 128 && (((int)ld & 1) != 0 || (((M | N) & 1) != 0 && ld <= sn) || misaligned)) {
             raise_error(a, DEV_ERR_LAYOUT);  // unreachable when the host honours the launch contract

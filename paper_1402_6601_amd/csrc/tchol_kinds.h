@@ -22,5 +22,7 @@
 #define TK_TRTRI 12  /* Dinv_k = L_kk^{-1}, DinvT_k = L_kk^{-T} (FP64)        */
 /* adjoint: the diagonal tile's partial products, summed by row strips */
 #define TK_DRED  13  /* Lbar_kk += sum_i S_ik (i ascending)                  */
-#define TK_NKINDS 14
+/* factorization: two consecutive updates of one tile in one task (K = 2 nb) */
+#define TK_GEMM2 14  /* A_ij <- A_ij - L_ik L_jk^T - L_i,k+1 L_j,k+1^T        */
+#define TK_NKINDS 15
 #endif

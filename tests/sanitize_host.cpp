@@ -106,7 +106,7 @@ int main() {
   int64_t counts[4] = {0, 0, 0, 0};
   CHECK(tchol_plan_query(TCHOL_OP_FACTOR, 1000, 128, TCHOL_POLICY_LIST, 0, counts, nullptr, nullptr, nullptr, nullptr,
                          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == 0);
-  CHECK(counts[0] == 8 + 28 + 28 + 56);
+  CHECK(counts[0] == 8 + 28 + 28 + 30 + 13);  // T = 8: 30 single GEMMs, 13 merged pairs
   std::vector<int32_t> kind(counts[0]), items(counts[2]);
   CHECK(tchol_plan_query(TCHOL_OP_FACTOR, 1000, 128, TCHOL_POLICY_RANDOM, 5, nullptr, kind.data(), nullptr, nullptr,
                          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, items.data(), nullptr) == 0);

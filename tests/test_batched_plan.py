@@ -15,10 +15,12 @@ import collections
 import numpy as np
 import pytest
 
+from tests import tiled_ref
+
 tc = pytest.importorskip("paper_1402_6601_amd")
 
 POTRF, TRSM, SYRK, GEMM, FTRSV, FGEMV, BTRSV, BGEMV = range(8)
-WEIGHT = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2}
+WEIGHT = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2, tiled_ref.GEMM2: 12}
 
 
 def bplan(n, nb, policy=0, seed=0):
@@ -63,14 +65,8 @@ def dataflow_edges_factor_solve(T):
         for d in writes:
             last_writer[d] = task
 
-    for k in range(T):
-        access((POTRF, k, k, k), [("L", k, k)], [("L", k, k)])
-        for i in range(k + 1, T):
-            access((TRSM, i, k, k), [("L", k, k), ("L", i, k)], [("L", i, k)])
-        for i in range(k + 1, T):
-            access((SYRK, i, i, k), [("L", i, k), ("L", i, i)], [("L", i, i)])
-            for j in range(k + 1, i):
-                access((GEMM, i, j, k), [("L", i, k), ("L", j, k), ("L", i, j)], [("L", i, j)])
+    for task, reads, writes in tiled_ref.factor_program(T):
+        access(task, [("L",) + r for r in reads], [("L",) + w for w in writes])
     for k in range(T):
         access((FTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)])
         for i in range(k + 1, T):
@@ -113,10 +109,11 @@ def test_batched_edges_equal_dataflow(n, nb):
         assert per.get(s, set()) == dataflow_edges_factor_solve(T), (s, ns, nbs)
         # every task of the system is present
         cnt = collections.Counter(int(k) for k, q in zip(p["kind"], p["sys"]) if q == s)
-        ng = T * (T - 1) * (T - 2) // 6
+        npair = sum((T - 1 - j) * ((j - 1) // 2) for j in range(1, T))
+        ng = T * (T - 1) * (T - 2) // 6 - 2 * npair
         assert cnt.get(POTRF, 0) == T == cnt.get(FTRSV, 0) == cnt.get(BTRSV, 0)
         assert cnt.get(TRSM, 0) == cnt.get(SYRK, 0) == T * (T - 1) // 2 == cnt.get(FGEMV, 0) == cnt.get(BGEMV, 0)
-        assert cnt.get(GEMM, 0) == ng
+        assert cnt.get(GEMM, 0) == ng and cnt.get(tiled_ref.GEMM2, 0) == npair
 
 
 @pytest.mark.parametrize("policy,seed", [(tc.POLICY_LIST, 0), (tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0),

@@ -20,7 +20,8 @@ from tests import tiled_ref
 tc = pytest.importorskip("paper_1402_6601_amd")
 
 POTRF, TRSM, SYRK, GEMM, FTRSV, FGEMV, BTRSV, BGEMV = range(8)
-WEIGHT = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2}
+GEMM2 = tiled_ref.GEMM2
+WEIGHT = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2, GEMM2: 12}
 
 
 def plan(op, n, nb, policy=0, seed=0):
@@ -55,14 +56,8 @@ def dataflow_edges_factor(T):
         for tile in writes:
             last_writer[tile] = task
 
-    for k in range(T):
-        access((POTRF, k, k, k), [(k, k)], [(k, k)])
-        for i in range(k + 1, T):
-            access((TRSM, i, k, k), [(k, k), (i, k)], [(i, k)])
-        for i in range(k + 1, T):
-            access((SYRK, i, i, k), [(i, k), (i, i)], [(i, i)])
-            for j in range(k + 1, i):
-                access((GEMM, i, j, k), [(i, k), (j, k), (i, j)], [(i, j)])
+    for task, reads, writes in tiled_ref.factor_program(T):
+        access(task, reads, writes)
     return out
 
 
@@ -113,16 +108,23 @@ def dataflow_edges_solve(T):
 def test_factor_counts_closed_forms(n, nb):
     p = plan(0, n, nb)
     T = -(-n // nb)
-    ngemm = T * (T - 1) * (T - 2) // 6
-    assert p["ntask"] == T + 2 * (T * (T - 1) // 2) + ngemm
-    assert p["nedge"] == 3 * T * (T - 1) // 2 + 3 * ngemm
+    # tile (i, j) takes j updates: floor((j - 1) / 2) merged pairs, the rest single
+    npair = sum((T - 1 - j) * ((j - 1) // 2) for j in range(1, T))
+    ngemm = T * (T - 1) * (T - 2) // 6 - 2 * npair
+    assert p["ntask"] == T + 2 * (T * (T - 1) // 2) + ngemm + npair
+    # in-degrees: POTRF 0 or 1, TRSM and SYRK 1 or 2 ((T - 1)^2 each), GEMM 2 and
+    # GEMM2 4 from the panels, plus one from the previous update of their tile
+    # for all but the tile's first update task
+    nchain = sum((T - 1 - j) * (j - (j - 1) // 2 - 1) for j in range(1, T))
+    assert p["nedge"] == (T - 1) * (2 * T - 1) + 2 * ngemm + 4 * npair + nchain
     assert int(np.sum(p["dep0"])) == p["nedge"]
     assert p["critical_path"] == 3 * T - 2
     kinds = collections.Counter(p["kind"].tolist())
-    assert kinds[POTRF] == T and kinds[TRSM] == T * (T - 1) // 2 == kinds[SYRK] and kinds[GEMM] == ngemm
+    assert kinds[POTRF] == T and kinds[TRSM] == T * (T - 1) // 2 == kinds[SYRK]
+    assert kinds[GEMM] == ngemm and kinds[GEMM2] == npair
 
 
-@pytest.mark.parametrize("T", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 8, 11])
 def test_factor_edges_equal_dataflow(T):
     p = plan(0, 16 * T, 16)
     assert edges(p) == dataflow_edges_factor(T)
@@ -181,7 +183,8 @@ def test_list_schedule_order(op, n, nb):
     assert int(p["kind"][p["item_task"][0]]) == POTRF and int(p["k"][p["item_task"][0]]) == 0
     # replay: 256 workers take the tickets in order; a ticket's item starts
     # when both its worker is free and its task's predecessors are done
-    w = {POTRF: 5, TRSM: 11, SYRK: 4, GEMM: 4, 12: 11} if op == tc.OP_MIXED_FACTOR else {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, 12: 3}
+    w = ({POTRF: 5, TRSM: 11, SYRK: 4, GEMM: 4, 12: 11, GEMM2: 8} if op == tc.OP_MIXED_FACTOR
+         else {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, 12: 3, GEMM2: 12})
     dur = np.array([w.get(int(k), 2) / max(1, int(q)) for k, q in zip(p["kind"], p["parts"])])
     import heapq
     free = [0.0] * 256
@@ -307,7 +310,7 @@ def test_mixed_factor_plan_split(n, nb):
     assert not any(e[0][0] == TRTRI for e in em)
     for t in range(pm["ntask"]):
         kind, i, j = int(pm["kind"][t]), int(pm["i"][t]), int(pm["j"][t])
-        if kind == GEMM:
+        if kind in (GEMM, GEMM2):
             want = -(-tsz(i) // 256) * -(-tsz(j) // 128)
         elif kind == SYRK:
             s = -(-tsz(i) // 128)

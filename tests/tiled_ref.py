@@ -12,6 +12,8 @@ PLASMA algorithm the paper schedules, section 4.1 "Benchmarks"):
     TRSM(i, k):    A_ik <- A_ik L_kk^{-T}                  (i > k)
     SYRK(i, k):    A_ii <- A_ii - L_ik L_ik^T  (lower)     (i > k)
     GEMM(i, j, k): A_ij <- A_ij - L_ik L_jk^T              (i > j > k)
+    GEMM2(i, j, k): GEMM(i, j, k), then GEMM(i, j, k + 1)  (two updates of
+                    one tile in one task, as the planner merges them)
 
 This module is independent of both the oracle and the GPU library.
 """
@@ -21,6 +23,7 @@ import math
 import numpy as np
 
 POTRF, TRSM, SYRK, GEMM = 0, 1, 2, 3
+GEMM2 = 14
 
 
 def tile_bounds(n: int, nb: int, t: int):
@@ -78,8 +81,43 @@ def run_task(A: np.ndarray, n: int, nb: int, kind: int, i: int, j: int, k: int):
         tile_syrk(A[ri0:ri1, ri0:ri1], A[ri0:ri1, rk0:rk1])
     elif kind == GEMM:
         tile_gemm(A[ri0:ri1, rj0:rj1], A[ri0:ri1, rk0:rk1], A[rj0:rj1, rk0:rk1])
+    elif kind == GEMM2:
+        rl0, rl1 = tile_bounds(n, nb, k + 1)
+        tile_gemm(A[ri0:ri1, rj0:rj1], A[ri0:ri1, rk0:rk1], A[rj0:rj1, rk0:rk1])
+        tile_gemm(A[ri0:ri1, rj0:rj1], A[ri0:ri1, rl0:rl1], A[rj0:rj1, rl0:rl1])
     else:
         raise ValueError(kind)
+
+
+def pair_first(j: int, k: int) -> bool:
+    """Update k of a tile in column j opens a merged pair (k, k + 1): k even,
+    and the pair does not hold the tile's last update j - 1."""
+    return k % 2 == 0 and k + 1 <= j - 2
+
+
+def pair_second(j: int, k: int) -> bool:
+    return k % 2 == 1 and k <= j - 2
+
+
+def factor_program(T: int):
+    """The factorization's tasks in program order (k outer), with each merged
+    pair of updates placed at its second step, and every task's tile reads and
+    writes: [(task, reads, writes)]."""
+    out = []
+    for k in range(T):
+        out.append(((POTRF, k, k, k), [(k, k)], [(k, k)]))
+        for i in range(k + 1, T):
+            out.append(((TRSM, i, k, k), [(k, k), (i, k)], [(i, k)]))
+        for i in range(k + 1, T):
+            out.append(((SYRK, i, i, k), [(i, k), (i, i)], [(i, i)]))
+            for j in range(k + 1, i):
+                if pair_first(j, k):
+                    continue
+                if pair_second(j, k):
+                    out.append(((GEMM2, i, j, k - 1), [(i, k - 1), (j, k - 1), (i, k), (j, k), (i, j)], [(i, j)]))
+                else:
+                    out.append(((GEMM, i, j, k), [(i, k), (j, k), (i, j)], [(i, j)]))
+    return out
 
 
 def tasks_k_major(n: int, nb: int):
