@@ -52,6 +52,7 @@ extern "C" {
 #define TCHOL_OP_BATCHED 2 /* factor + solve of many systems (plan introspection only) */
 #define TCHOL_OP_BACKWARD 3 /* adjoint of the factorization */
 #define TCHOL_OP_MIXED_FACTOR 4 /* the factorization launch of tchol_solve_mixed (plan introspection only) */
+#define TCHOL_OP_FACTOR_SOLVE 5 /* the merged launch of tchol_factor_solve (plan introspection only) */
 
 #define TCHOL_POLICY_LIST 0   /* HEFT's list schedule (section 3.1), the default
                                  (NULL options or a zeroed struct): ready items by
@@ -90,9 +91,24 @@ typedef struct tchol_opts {
                           persistent kernel measured with HIP events on `stream` */
   uint64_t *trace;     /* device buffer of 4 x uint64 per work item of the launch
                           (tchol_plan_query counts[2] for its op; for
-                          tchol_solve_mixed, TCHOL_OP_MIXED_FACTOR), or NULL:
+                          tchol_factor_solve, TCHOL_OP_FACTOR_SOLVE (opts.subst
+                          = 0); for tchol_solve_mixed, TCHOL_OP_MIXED_FACTOR), or NULL:
                           {claim, start} and {end} wall clock (100 MHz),
                           {task, part | wg<<32}                                  */
+  int64_t trace_words; /* length of trace in uint64 words; with trace set, a call
+                          whose launch has more than trace_words / 4 work items
+                          returns -i for its opts argument i and launches nothing */
+  int32_t subst;       /* FP64 solve (tchol_solve_ex, tchol_factor_solve): 0 (the
+                          default) applies explicit inverses of the diagonal
+                          tiles, L_kk^{-1} and L_kk^{-T}, computed in the same
+                          launch, by row strips over many workgroups (short
+                          dependency chain); its backward error grows with the
+                          condition of the diagonal tiles (at most sqrt(cond(A))
+                          for SPD A).  1: substitution against the tiles, one
+                          workgroup per diagonal step, backward stable (and
+                          exact on integer data whose intermediates are exact).
+                          A ragged last tile (order not a multiple of 16) always
+                          substitutes.                                          */
 } tchol_opts;
 
 /* Bytes of device workspace needed by `op` (TCHOL_OP_FACTOR, _SOLVE or
@@ -110,6 +126,9 @@ TCHOL_API int32_t tchol_factor_ex(double *A, int64_t n, int64_t nb, void *ws, in
 
 /* Solve (L L^T) X = B in place (B := X) given the factor from tchol_factor,
    by a forward then a backward tiled substitution on the same scheduler.
+   The diagonal steps apply the tiles' explicit inverses, computed by the same
+   launch (see tchol_opts.subst); the workspace holds them (n nb doubles) and
+   the intermediate Y (n nrhs doubles).
    Arguments: 1 L, 2 n, 3 nb, 4 B (n x nrhs, column-major, ld n), 5 nrhs >= 0,
    6 ws, 7 ws_bytes, 8 stream. */
 TCHOL_API int32_t tchol_solve(const double *L, int64_t n, int64_t nb, double *B, int64_t nrhs, void *ws,
@@ -147,7 +166,9 @@ TCHOL_API int32_t tchol_backward_ex(const double *L, int64_t n, int64_t nb, doub
    FGEMV(i, k)), so the forward substitution runs while the factorization
    still has work in flight; the claim order is decreasing upward rank over
    both (section 3.1).  Results are identical to tchol_factor followed by
-   tchol_solve.  Arguments: 1 A (in/out as for tchol_factor), 2 n, 3 nb,
+   tchol_solve (with the same opts.subst).  The solve's explicit inverses,
+   TRTRI(k) after POTRF(k), are computed while the factorization runs.
+   Arguments: 1 A (in/out as for tchol_factor), 2 n, 3 nb,
    4 B (n x nrhs, ld n, in/out as for tchol_solve), 5 nrhs >= 0, 6 ws,
    7 ws_bytes >= tchol_factor_solve_workspace_bytes(n, nb, nrhs), 8 stream,
    9 opts (NULL or as for tchol_factor_ex).  Returns 0, k > 0 (leading minor
@@ -159,8 +180,9 @@ TCHOL_API int32_t tchol_factor_solve(double *A, int64_t n, int64_t nb, double *B
 
 /* For callers that cannot allocate device memory (code under HIP graph
    capture, tight serving loops, harnesses that forbid hipMalloc): the same
-   merged factor + solve launch as tchol_factor_solve with the default options,
-   bitwise the same results, but with no workspace argument.  Its scheduler
+   merged factor + solve launch as tchol_factor_solve with opts.subst = 1 (the
+   diagonal tiles' inverses would not fit the fixed array), bitwise the same
+   results, but with no workspace argument.  Its scheduler
    scratch (header, dependency counters, task descriptors, successor lists,
    ticket list) lives in a fixed device array of the library,
    TCHOL_NOALLOC_SCRATCH_BYTES per GPU, held by every GPU the library runs on
@@ -172,9 +194,10 @@ TCHOL_API int32_t tchol_factor_solve(double *A, int64_t n, int64_t nb, double *B
    other streams) race on the array and must be serialised by the caller.
    Arguments: 1 A, 2 n, 3 nb, 4 B, 5 nrhs (as for tchol_factor_solve),
    6 stream.  Returns as tchol_factor_solve, or TCHOL_E_SCRATCH (checked
-   before any HIP call) when tchol_factor_solve_workspace_bytes(n, nb, nrhs)
-   exceeds TCHOL_NOALLOC_SCRATCH_BYTES (n = 32768 with nb = 512 needs
-   8.3 MiB; nb = 256 about 31 MiB). */
+   before any HIP call) when the launch's scheduler scratch, the same as
+   tchol_batched_workspace_bytes for the one system (n, nb), exceeds
+   TCHOL_NOALLOC_SCRATCH_BYTES (n = 32768 with nb = 512 needs 8.3 MiB;
+   nb = 256 about 31 MiB). */
 #define TCHOL_NOALLOC_SCRATCH_BYTES (16 << 20)
 TCHOL_API int32_t tchol_factor_solve_noalloc(double *A, int64_t n, int64_t nb, double *B, int64_t nrhs,
                                              void *stream);

@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtchol.so")
 
-OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD, OP_MIXED_FACTOR = 0, 1, 2, 3, 4
+OP_FACTOR, OP_SOLVE, OP_BATCHED, OP_BACKWARD, OP_MIXED_FACTOR, OP_FACTOR_SOLVE = 0, 1, 2, 3, 4, 5
 POLICY_LIST, POLICY_RANK, POLICY_FIFO, POLICY_RANDOM = 0, 1, 2, 3
 E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV, E_SCRATCH = -100, -101, -102, -103, -104, -105
 NOALLOC_SCRATCH_BYTES = 16 << 20
@@ -41,7 +41,8 @@ class TcholError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("seed", ctypes.c_uint32), ("wait_limit_us", ctypes.c_int64),
-                ("kernel_ms", ctypes.POINTER(ctypes.c_float)), ("trace", ctypes.c_void_p)]
+                ("kernel_ms", ctypes.POINTER(ctypes.c_float)), ("trace", ctypes.c_void_p),
+                ("trace_words", ctypes.c_int64), ("subst", ctypes.c_int32)]
 
 
 def load() -> ctypes.CDLL:
@@ -236,14 +237,22 @@ def _workspace(torch, nbytes: int, device):
     return ws
 
 
-def _opts(policy, seed, wait_limit_us, want_ms, trace):
+def _opts(policy, seed, wait_limit_us, want_ms, trace, subst=False):
     o = Opts()
     o.policy = policy
     o.seed = seed
     o.wait_limit_us = wait_limit_us
+    o.subst = 1 if subst else 0
     ms = ctypes.c_float(0.0)
     o.kernel_ms = ctypes.pointer(ms) if want_ms else ctypes.cast(None, ctypes.POINTER(ctypes.c_float))
-    o.trace = ctypes.c_void_p(trace.data_ptr()) if trace is not None else None
+    if trace is not None:
+        if trace.element_size() != 8 or not trace.is_contiguous():
+            raise ValueError("trace must be a contiguous tensor of 64-bit words")
+        o.trace = ctypes.c_void_p(trace.data_ptr())
+        o.trace_words = trace.numel()
+    else:
+        o.trace = None
+        o.trace_words = 0
     return o, ms
 
 
@@ -282,10 +291,12 @@ def factor(A, nb: int, **kw):
 
 
 def solve_(L, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
-           want_kernel_ms: bool = False, trace=None, check: bool = True):
+           want_kernel_ms: bool = False, trace=None, check: bool = True, subst: bool = False):
     """Solve in place.  L: the (n, n) buffer factored by factor_ (column-major
     lower = L).  Bc: CUDA float64 (nrhs, n) contiguous, i.e. B column-major.
-    trace: optional CUDA int64 tensor of 4 words per work item (see factor_)."""
+    trace: optional CUDA int64 tensor of 4 words per work item (see factor_).
+    subst: substitute against the diagonal tiles instead of applying their
+    explicit inverses (tchol_opts.subst)."""
     torch = _torch()
     n = L.shape[0]
     if Bc.dtype != torch.float64 or not Bc.is_contiguous() or Bc.dim() != 2 or Bc.shape[1] != n:
@@ -296,7 +307,7 @@ def solve_(L, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_lim
         need = workspace_bytes(OP_SOLVE, n, nb, nrhs) if n else 256
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, L.device)
-        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace, subst)
         rc = lib.tchol_solve_ex(ctypes.c_void_p(L.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()), nrhs,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(torch, L.device),
                                 ctypes.byref(o))
@@ -396,8 +407,8 @@ def solve_mixed(A, B, nb: int, *, fallback: bool = True, **kw):
 
     When the low-precision factorization breaks down or the refinement does
     not reach tol within maxit, and fallback is set, the system is solved by
-    the FP64 path (factor of a copy of A, then solve), as LAPACK's mixed
-    solvers do.  Returns (X, info) with info = {"rc", "iters", "berr",
+    the FP64 path (factor of a copy of A, then the backward-stable solve by
+    substitution), as LAPACK's mixed solvers do.  Returns (X, info) with info = {"rc", "iters", "berr",
     "fallback"}."""
     torch = _torch()
     vec = B.dim() == 1
@@ -411,7 +422,7 @@ def solve_mixed(A, B, nb: int, *, fallback: bool = True, **kw):
         if info != 0:
             raise TcholError(int(info), "tchol_factor (fallback)")
         Bc = B2.mT.contiguous().to(torch.float64)
-        solve_(Lbuf, Bc, nb)
+        solve_(Lbuf, Bc, nb, subst=True)
         used = True
     elif rc != 0:
         raise TcholError(int(rc), "tchol_solve_mixed")
@@ -537,11 +548,11 @@ def factor_solve_batched_f32_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, poli
 
 
 def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
-                  want_kernel_ms: bool = False, trace=None, check: bool = True):
+                  want_kernel_ms: bool = False, trace=None, check: bool = True, subst: bool = False):
     """Factor A in place and solve in place on Bc in one launch (merged DAG).
     A: CUDA float64 (n, n) contiguous symmetric; Bc: CUDA float64 (nrhs, n)
-    contiguous (B column-major).  Returns info (0, or the failing leading
-    minor), or (info, kernel_ms)."""
+    contiguous (B column-major).  subst: as for solve_.  Returns info (0, or
+    the failing leading minor), or (info, kernel_ms)."""
     torch = _torch()
     if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
         raise ValueError("A must be a contiguous square float64 tensor")
@@ -556,7 +567,7 @@ def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, w
             raise TcholError(int(need), "tchol_factor_solve_workspace_bytes")
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, A.device)
-        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace, subst)
         rc = lib.tchol_factor_solve(ctypes.c_void_p(A.data_ptr()), n, nb, ctypes.c_void_p(Bc.data_ptr()), nrhs,
                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(torch, A.device),
                                     ctypes.byref(o))
@@ -566,7 +577,7 @@ def factor_solve_(A, Bc, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, w
 
 
 def factor_solve_noalloc_(A, Bc, nb: int, *, check: bool = True):
-    """As factor_solve_ (default options) through tchol_factor_solve_noalloc:
+    """As factor_solve_ (default options, subst=True) through tchol_factor_solve_noalloc:
     the library's fixed per-GPU scratch array instead of a workspace, so
     nothing is allocated on the device by the call.  Returns info."""
     torch = _torch()

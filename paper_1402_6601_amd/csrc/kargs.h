@@ -38,9 +38,12 @@ typedef struct KArgs {
                            (A is the FP32 working copy); 3: the adjoint of the
                            factorization (A = L, B = Lbar, D = partial-product slots) */
   int32_t syrk_b;       /* SYRK output sub-tile (square)                          */
+  int32_t inv;          /* FP64 solve: 1 when the launch computes the diagonal tiles'
+                           explicit inverses (TRTRI tasks) and its diagonal steps
+                           apply them (y in S); 0: substitution in place in B    */
   double *Dinv;         /* mixed precision: L_kk^{-1}, nb x nb each (FP64)         */
-  double *DinvT;        /* mixed precision: L_kk^{-T}, nb x nb each (FP64)         */
-  double *S;            /* mixed precision: the solve's intermediate y, like B     */
+  double *DinvT;        /* mixed precision and inv: L_kk^{-T}, nb x nb each (FP64)  */
+  double *S;            /* mixed precision and inv: the solve's intermediate y, like B */
   double *Q;            /* adjoint: Q = twice the symmetric adjoint, ld ldq        */
   double *LT;           /* adjoint: L^T, ld ldq                                   */
   int64_t ldq;

@@ -18,6 +18,12 @@
 //   FGEMV(i, k)     B_i -= L_ik Y_k, i > k    after FTRSV(k), FGEMV(i, k-1)
 //   BTRSV(k)        X_k = L_kk^{-T} Y_k       after FTRSV(T-1) (k = T-1) or BGEMV(k, k+1)
 //   BGEMV(i, k)     Y_i -= L_ki^T X_k, i < k  after BTRSV(k), BGEMV(i, k+1)
+// The diagonal steps either substitute against L_kk (one work item, in
+// place) or apply the explicit inverses L_kk^{-1}, L_kk^{-T} by row strips
+// (as many work items as the updates), with Y kept in a scratch vector.
+// The FP64 solve computes those inverses itself:
+//   TRTRI(k)        L_kk^{-1}, L_kk^{-T}      after POTRF(k) (merged launch)
+// and FTRSV(k) then also waits for TRTRI(k).
 //
 // Batched plans hold several systems (each with its own order and tile
 // size); each system's solve follows its factorization through the edges
@@ -26,7 +32,8 @@
 // Priority: the upward rank of HEFT (section 3.1): rank(t) = w(t) + max over
 // successors s of rank(s), with w HEFT's computation cost of the task: the
 // time of its work items summed over its parts, in units of about 200 us at
-// nb = 512 on this part (POTRF 5, TRSM 10, SYRK 4, GEMM 6; TRSV 1, GEMV 2),
+// nb = 512 on this part (POTRF 5, TRSM 10, SYRK 4, GEMM 6; TRSV 1, GEMV 2,
+// and the solve's TRTRI as long as a TRSM, 10),
 // and no communication term (one device).  Flop counts (1, 3, 3, 6) would
 // undervalue POTRF and TRSM, whose tile kernels run far below the GEMM's
 // efficiency, and start the critical path late.  Every weight is positive, so
@@ -108,7 +115,7 @@ int64_t weight(int32_t kind, int32_t op) {
     case TK_TREV: return 3;
     case TK_DPART: return 3;
     case TK_PREV: return 4;
-    case TK_TRTRI: return 3;
+    case TK_TRTRI: return 10;
     case TK_DRED: return 1;
     default: return 2;
   }
@@ -196,15 +203,24 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
   }
 }
 
-// split_diag: the diagonal steps are split into row strips like the updates
-// (the mixed-precision solve applies explicit inverses there).
-void build_solve(Builder& b, const FactorIds* after = nullptr, bool split_diag = false) {
+// How the solve's diagonal steps run: substitution; explicit inverses that
+// another launch computed (the mixed-precision solve, which pads ragged
+// tiles); explicit inverses from this plan's own TRTRI tasks (the FP64 solve,
+// for the tiles whose order is a multiple of 16; a ragged last tile keeps
+// the substitution).
+enum class Diag { kSubst, kInvGiven, kInvHere };
+
+void build_solve(Builder& b, const FactorIds* after = nullptr, Diag diag = Diag::kSubst) {
   auto& succ = b.succ;
   const int32_t T = b.T;
-  std::vector<int32_t> id_ft(T), id_bt(T), id_fg((size_t)T * T, -1), id_bg((size_t)T * T, -1);
+  std::vector<int32_t> id_ft(T), id_bt(T), id_tri(T, -1), id_fg((size_t)T * T, -1), id_bg((size_t)T * T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
-  auto dparts = [&](int32_t k) { return split_diag ? Builder::cdiv(b.tile_size(k), b.s.gemv_rows) : 1; };
+  auto inv = [&](int32_t k) {
+    return diag == Diag::kInvGiven || (diag == Diag::kInvHere && b.tile_size(k) % 16 == 0);
+  };
+  auto dparts = [&](int32_t k) { return inv(k) ? Builder::cdiv(b.tile_size(k), b.s.gemv_rows) : 1; };
   for (int32_t k = 0; k < T; ++k) {
+    if (diag == Diag::kInvHere && inv(k)) id_tri[k] = b.add(TK_TRTRI, k, k, k, Builder::cdiv(b.tile_size(k), b.s.trsm_rows));
     id_ft[k] = b.add(TK_FTRSV, k, k, k, dparts(k));
     for (int32_t i = k + 1; i < T; ++i)
       id_fg[ix2(i, k)] = b.add(TK_FGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
@@ -214,10 +230,12 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, bool split_diag =
     for (int32_t i = 0; i < k; ++i)
       id_bg[ix2(i, k)] = b.add(TK_BGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
   }
+  for (int32_t k = 0; k < T; ++k)
+    if (id_tri[k] >= 0) succ[id_tri[k]].push_back(id_ft[k]);
   if (after) {
     // the solve of a system reads the final tiles of its factor
     for (int32_t k = 0; k < T; ++k) {
-      succ[after->potrf[k]].push_back(id_ft[k]);
+      succ[after->potrf[k]].push_back(id_tri[k] >= 0 ? id_tri[k] : id_ft[k]);
       for (int32_t i = k + 1; i < T; ++i) succ[after->trsm[ix2(i, k)]].push_back(id_fg[ix2(i, k)]);
     }
   }
@@ -303,6 +321,10 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   if (kind == TK_GEMM2) {  // a double update belongs to the step of its second update
     step = p.tk[t] + 1;
     kord = TK_GEMM;
+  }
+  if (kind == TK_TRTRI && p.op != OP_FACTOR_INV) {  // the FP64 solve's inverses: first in their step
+    if (p.op == TCHOL_OP_BATCHED) step += T;
+    kord = -1;
   }
   if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV
   if (kind == TK_BGEMV) kord = 1;
@@ -512,22 +534,26 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
   else if (op == OP_FACTOR_INV)
     build_factor(b, nullptr, true);
   else if (op == TCHOL_OP_SOLVE)
-    build_solve(b);
+    build_solve(b, nullptr, Diag::kInvHere);
   else if (op == OP_SOLVE_INV)
-    build_solve(b, nullptr, true);
+    build_solve(b, nullptr, Diag::kInvGiven);
+  else if (op == OP_SOLVE_SUBST)
+    build_solve(b);
   else if (op == TCHOL_OP_BACKWARD)
     build_backward(b);
   else
     return nullptr;
+  p.inv = op == TCHOL_OP_SOLVE;
   if (!finalize(p, succ, policy, seed)) return nullptr;
   return plan;
 }
 
 std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
-                                         const Split& split) {
+                                         const Split& split, bool inv) {
   auto plan = std::make_shared<Plan>();
   Plan& p = *plan;
   p.op = TCHOL_OP_BATCHED;
+  p.inv = inv && systems.size() == 1;
   p.policy = policy;
   p.seed = seed;
   p.systems = systems;
@@ -545,7 +571,7 @@ std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int
     Builder b(p, split, succ, s);
     FactorIds ids;
     build_factor(b, &ids);
-    build_solve(b, &ids);
+    build_solve(b, &ids, p.inv ? Diag::kInvHere : Diag::kSubst);
   }
   if (p.ntask() == 0) {
     p.succ_off.assign(1, 0);
@@ -572,11 +598,13 @@ std::shared_ptr<const Plan> get_plan(int32_t op, int64_t n, int64_t nb, int32_t 
   return p;
 }
 
-std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed) {
+std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
+                                             bool inv) {
   static std::mutex mu;
   static std::map<std::vector<int64_t>, std::shared_ptr<const Plan>> cache;
   std::vector<int64_t> key;
-  key.reserve(2 * systems.size() + 2);
+  key.reserve(2 * systems.size() + 3);
+  key.push_back(inv ? 1 : 0);
   key.push_back(policy);
   key.push_back(policy == TCHOL_POLICY_RANDOM ? seed : 0);
   for (const System& sy : systems) {
@@ -588,7 +616,7 @@ std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems,
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
   }
-  std::shared_ptr<const Plan> p = build_batched_plan(systems, policy, seed, default_split());
+  std::shared_ptr<const Plan> p = build_batched_plan(systems, policy, seed, default_split(), inv);
   if (!p) return nullptr;
   std::lock_guard<std::mutex> g(mu);
   if (cache.size() >= 8) cache.clear();

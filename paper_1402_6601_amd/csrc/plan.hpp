@@ -35,6 +35,8 @@ struct Plan {
   int32_t policy = 0;      // TCHOL_POLICY_*
   uint32_t seed = 0;       // for TCHOL_POLICY_RANDOM
   std::vector<System> systems;             // one for factor and solve plans
+  bool inv = false;        // the FP64 solve in it applies explicit inverses of the diagonal
+                           // tiles, computed by its TRTRI tasks (single-system plans)
   // per task
   std::vector<int32_t> kind, ti, tj, tk;   // kind and tile coordinates (i, j, k)
   std::vector<int32_t> sys;                // the system the task belongs to
@@ -57,13 +59,15 @@ struct Plan {
 // explicit inverses).
 constexpr int32_t OP_FACTOR_INV = 16;
 constexpr int32_t OP_SOLVE_INV = 17;
+// The FP64 solve by substitution against the diagonal tiles (tchol_opts.subst).
+constexpr int32_t OP_SOLVE_SUBST = 18;
 
 // Work-item granularity (rows x cols of one work item of each task kind).
 struct Split {
   int32_t gemm_m = 128, gemm_n = 128;   // GEMM output sub-tile (also the adjoint's products)
   int32_t syrk_b = 128;                 // SYRK output sub-tile (square; the lower ones of the tile)
   int32_t trsm_rows = 32;               // TRSM row strip
-  int32_t gemv_rows = 128;              // solve update row strip
+  int32_t gemv_rows = 32;               // solve update row strip
 };
 
 // Builds (or fetches from a process-wide cache) the plan.  Returns nullptr
@@ -76,15 +80,19 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
 
 // Factorization followed by the solve, for every system, as one DAG: each
 // system's factor tasks, then its solve tasks, joined by the data-flow
-// edges POTRF(k) -> FTRSV(k) and TRSM(i, k) -> FGEMV(i, k).  Uncached.
-// Returns nullptr if the task count exceeds what the kernel indexes.
+// edges POTRF(k) -> FTRSV(k) and TRSM(i, k) -> FGEMV(i, k).  With inv (one
+// system: the merged factor + solve launch) the solve applies explicit
+// inverses, POTRF(k) -> TRTRI(k) -> FTRSV(k) for the tiles whose order is a
+// multiple of 16.  Uncached.  Returns nullptr if the task count exceeds
+// what the kernel indexes.
 std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
-                                         const Split& split);
+                                         const Split& split, bool inv = false);
 
 // The batched plan for these systems' orders and tile sizes, from a small
 // process-wide cache keyed by them (offsets and leading dimensions are not
 // part of the plan's task structure; the caller supplies them per launch).
-std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed);
+std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
+                                             bool inv = false);
 
 const Split& default_split();
 // The split a single-system plan of this operation is built with: the

@@ -76,6 +76,25 @@ Layout layout_of(const Plan& p) {
   return L;
 }
 
+// The FP64 solve's explicit inverses and intermediate vector (plans with
+// inv), after the scheduler's regions: L_kk^{-T} of every diagonal tile
+// (nb x nb FP64 each) and y (n x nrhs FP64).
+struct InvLayout {
+  int64_t dinvt = 0, sx = 0, end = 0;
+};
+
+InvLayout inv_layout(const Plan& p, int64_t nrhs) {
+  InvLayout V;
+  V.end = layout_of(p).end;
+  if (!p.inv || p.systems.empty()) return V;
+  const tchol::System& sy = p.systems[0];
+  const int64_t T = sy.n == 0 ? 0 : (sy.n + sy.nb - 1) / sy.nb;
+  V.dinvt = align_up(V.end);
+  V.sx = align_up(V.dinvt + 8 * T * sy.nb * sy.nb);
+  V.end = align_up(V.sx + 8 * sy.n * std::max<int64_t>(nrhs, 1));
+  return V;
+}
+
 // The constant part of the workspace for one plan, in pinned host memory
 // when the runtime can provide it.
 struct Image {
@@ -205,7 +224,7 @@ bool policy_ok(int32_t p) { return p >= TCHOL_POLICY_LIST && p <= TCHOL_POLICY_R
 
 bool nb_ok(int64_t nb) { return nb >= TCHOL_NB_MIN && nb <= TCHOL_NB_MAX && nb % 16 == 0; }
 
-const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr};
+const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr, 0, 0};
 
 // Uploads the plan image, launches reset + persistent kernel on the stream,
 // reads the header back and synchronises.  sinfo_out (batched): per-system
@@ -220,6 +239,9 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   const Layout& L = img.lay;
   if (ws_bytes < L.end) return -(ws_arg + 1);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
+  // the trace buffer must hold 4 words per work item of this launch (the
+  // options follow the stream, which follows ws and ws_bytes)
+  if (o.trace && o.trace_words / 4 < plan.nitem()) return -(ws_arg + 3);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
   DeviceInfo di;
   if (device_info(&di) != hipSuccess) return TCHOL_E_HIP;
@@ -260,6 +282,7 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.Dinv = Dinv;
   a.DinvT = DinvT;
   a.S = Sx;
+  a.inv = plan.inv ? 1 : 0;
   a.H = H;
   a.hrows = hrows;
   const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
@@ -305,12 +328,19 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
             void* stream_v, const tchol_opts* opts, int32_t ws_arg) {
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
   if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
-  auto plan = tchol::get_plan(op, n, nb, o.policy, o.seed);
+  auto plan = tchol::get_plan(op == TCHOL_OP_SOLVE && o.subst ? tchol::OP_SOLVE_SUBST : op, n, nb, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
+  if (o.trace && o.trace_words / 4 < plan->nitem()) return -(ws_arg + 3);
   auto img = image_of(plan);
   // 16-byte panel transfers need an even leading dimension and an aligned matrix
   const bool wide = (n % 2 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
-  return execute(*plan, *img, A, B, nrhs, wide, false, ws, ws_bytes, stream_v, o, ws_arg, nullptr);
+  const InvLayout V = inv_layout(*plan, nrhs);
+  if (ws_bytes < V.end) return -(ws_arg + 1);
+  char* w = static_cast<char*>(ws);
+  double* DinvT = plan->inv ? reinterpret_cast<double*>(w + V.dinvt) : nullptr;
+  double* Sx = plan->inv ? reinterpret_cast<double*>(w + V.sx) : nullptr;
+  return execute(*plan, *img, A, B, nrhs, wide, false, ws, ws_bytes, stream_v, o, ws_arg, nullptr, nullptr, 0,
+                 nullptr, nullptr, 0, nullptr, DinvT, Sx);
 }
 
 void fill_query(const Plan& pl, int64_t* counts, int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* sys,
@@ -460,12 +490,25 @@ MixedLayout mixed_layout(int64_t n, int64_t nb, int64_t nrhs, const Plan& fp, co
 
 namespace tchol {
 
+// Workspace bytes of the merged factor + solve launch (inv as below).
+int64_t factor_solve_bytes(int64_t n, int64_t nb, int64_t nrhs, bool inv) {
+  std::vector<tchol::System> systems(1);
+  systems[0].n = n;
+  systems[0].nb = nb;
+  auto plan = tchol::get_batched_plan(systems, TCHOL_POLICY_RANK, 0, inv);
+  if (!plan) return TCHOL_E_UNSUPPORTED;
+  // every policy yields the same task, edge and item counts, hence the same layout
+  return inv_layout(*plan, nrhs).end;
+}
+
 // The merged factor + solve launch on validated arguments (n > 0).  pinned:
 // keep the plan's constant image in pinned host memory (allocated once per
 // plan); otherwise in pageable memory, so that the call allocates no device
-// or pinned memory once the plan is cached.
+// or pinned memory once the plan is cached.  inv: the solve applies the
+// diagonal tiles' explicit inverses (workspace for them included); else it
+// substitutes against the tiles.
 int32_t factor_solve_run(double* A, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
-                         void* stream, const tchol_opts* opts, bool pinned) {
+                         void* stream, const tchol_opts* opts, bool pinned, bool inv) {
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
   if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
   // one system of the merged factor + solve DAG: A at offset 0 with ld n, B at 0
@@ -473,8 +516,11 @@ int32_t factor_solve_run(double* A, int64_t n, int64_t nb, double* B, int64_t nr
   systems[0].n = n;
   systems[0].nb = nb;
   systems[0].ld = n;
-  auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
+  auto plan = tchol::get_batched_plan(systems, o.policy, o.seed, inv);
   if (!plan) return TCHOL_E_UNSUPPORTED;
+  const InvLayout V = inv_layout(*plan, nrhs);
+  if (ws_bytes < V.end) return -7;
+  if (o.trace && o.trace_words / 4 < plan->nitem()) return -9;
   std::shared_ptr<const Image> img;
   {
     // the image depends only on the plan here (fixed offsets), so it is cached
@@ -494,7 +540,11 @@ int32_t factor_solve_run(double* A, int64_t n, int64_t nb, double* B, int64_t nr
   }
   const bool wide = (n % 2 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
   int32_t info = 0;
-  const int32_t rc = execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 6, &info);
+  char* w = static_cast<char*>(ws);
+  double* DinvT = plan->inv ? reinterpret_cast<double*>(w + V.dinvt) : nullptr;
+  double* Sx = plan->inv ? reinterpret_cast<double*>(w + V.sx) : nullptr;
+  const int32_t rc = execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 6, &info, nullptr, 0,
+                             nullptr, nullptr, 0, nullptr, DinvT, Sx);
   if (rc != 0) return rc;
   return info;
 }
@@ -512,7 +562,7 @@ int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs) {
   if (!plan) return TCHOL_E_UNSUPPORTED;
   if (op == TCHOL_OP_BACKWARD) return back_layout(n, nb, *plan).end;
   // every policy yields the same task, edge and item counts, hence the same layout
-  return layout_of(*plan).end;
+  return inv_layout(*plan, nrhs).end;
 }
 
 int32_t tchol_factor_ex(double* A, int64_t n, int64_t nb, void* ws, int64_t ws_bytes, void* stream,
@@ -584,8 +634,7 @@ int64_t tchol_factor_solve_workspace_bytes(int64_t n, int64_t nb, int64_t nrhs) 
   if (n < 0 || n > INT32_MAX) return -1;
   if (!nb_ok(nb)) return -2;
   if (nrhs < 0) return -3;
-  const int32_t n32 = (int32_t)n, nb32 = (int32_t)nb;
-  return tchol_batched_workspace_bytes(&n32, &nb32, 1);
+  return tchol::factor_solve_bytes(n, nb, nrhs, true);
 }
 
 int32_t tchol_factor_solve(double* A, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
@@ -598,7 +647,7 @@ int32_t tchol_factor_solve(double* A, int64_t n, int64_t nb, double* B, int64_t 
   if (nrhs > 0 && !B) return -4;
   if (!ws) return -6;
   if (ws_bytes <= 0) return -7;
-  return tchol::factor_solve_run(A, n, nb, B, nrhs, ws, ws_bytes, stream, opts, true);
+  return tchol::factor_solve_run(A, n, nb, B, nrhs, ws, ws_bytes, stream, opts, true, !(opts && opts->subst));
 }
 
 int64_t tchol_batched_workspace_bytes(const int32_t* n, const int32_t* nb, int32_t batch) {
@@ -865,12 +914,21 @@ const char* tchol_version(void) { return "tchol 0.1 (gfx950)"; }
 int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint32_t seed, int64_t* counts,
                          int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* parts, int32_t* dep0,
                          int64_t* rank, int32_t* succ_off, int32_t* succ, int32_t* item_task, int32_t* item_part) {
-  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE && op != TCHOL_OP_BACKWARD && op != TCHOL_OP_MIXED_FACTOR)
+  if (op != TCHOL_OP_FACTOR && op != TCHOL_OP_SOLVE && op != TCHOL_OP_BACKWARD && op != TCHOL_OP_MIXED_FACTOR &&
+      op != TCHOL_OP_FACTOR_SOLVE)
     return -1;
-  if (n < 0) return -2;
+  if (n < 0 || n > INT32_MAX) return -2;
   if (!nb_ok(nb)) return -3;
   if (!policy_ok(policy)) return -4;
-  auto p = tchol::get_plan(op == TCHOL_OP_MIXED_FACTOR ? tchol::OP_FACTOR_INV : op, n, nb, policy, seed);
+  std::shared_ptr<const Plan> p;
+  if (op == TCHOL_OP_FACTOR_SOLVE) {
+    std::vector<tchol::System> systems(1);
+    systems[0].n = n;
+    systems[0].nb = nb;
+    p = tchol::get_batched_plan(systems, policy, seed, true);
+  } else {
+    p = tchol::get_plan(op == TCHOL_OP_MIXED_FACTOR ? tchol::OP_FACTOR_INV : op, n, nb, policy, seed);
+  }
   if (!p) return TCHOL_E_UNSUPPORTED;
   fill_query(*p, counts, kind, ti, tj, tk, nullptr, parts, dep0, rank, succ_off, succ, item_task, item_part);
   return 0;

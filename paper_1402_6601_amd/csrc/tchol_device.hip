@@ -1285,38 +1285,10 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
 
 // ---------------------------------------------------------------------------
 // Solve work items.  Right-hand sides are processed 16 columns at a time
-// (the N of an MFMA block), staged in LDS as Ys[j][r] (16 x YLD).
-// MFMA layout used here: A operand = L fragment (rows of L on lanes % 16),
-// B operand = Y fragment (right-hand sides on lanes % 16); a lane then holds
-// rows 4i + lane/16 of one right-hand side (lane % 16) of the 16x16 result.
-#define YLD 520
-
-// The loads of a thread are requested 16 at a time before any is stored,
-// so staging costs two memory latencies rather than one per element.
-__device__ __forceinline__ void stage_rhs(double* Ys, const double* Bk, int64_t ldb, int m, int j0, int jn) {
-  constexpr int PER = 16 * 512 / NT, BATCH = 16;
-#pragma unroll 1
-  for (int u0 = 0; u0 < PER; u0 += BATCH) {
-    double v[BATCH];
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int idx = threadIdx.x + (u0 + u) * NT, j = idx >> 9, r = idx & 511;
-      v[u] = Bk[(int64_t)(j0 + imin(j, jn - 1)) * ldb + imin(r, m - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int idx = threadIdx.x + (u0 + u) * NT, j = idx >> 9, r = idx & 511;
-      Ys[j * YLD + r] = (j < jn && r < m) ? v[u] : 0.0;
-    }
-  }
-}
-
-__device__ __forceinline__ void unstage_rhs(const double* Ys, double* Bk, int64_t ldb, int m, int j0, int jn) {
-  for (int idx = threadIdx.x; idx < 16 * 512; idx += NT) {
-    const int j = idx >> 9, r = idx & 511;
-    if (j < jn && r < m) st_dev(Bk + (int64_t)(j0 + j) * ldb + r, Ys[j * YLD + r]);
-  }
-}
+// (the N of an MFMA block).  MFMA layout used here: A operand = L fragment
+// (rows of L on lanes % 16), B operand = right-hand-side fragment
+// (right-hand sides on lanes % 16); a lane then holds rows 4i + lane/16 of
+// one right-hand side (lane % 16) of the 16x16 result.
 
 // Tile solves, register resident.  The tile's rows form blocks of 16
 // (nblk <= 32); wavefront w owns blocks w, w + 4, ..., and keeps their
@@ -1525,110 +1497,91 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
   }
 }
 
-// B_i[rows] -= L_ik[rows, :] Y_k  (forward update), rows = a strip of <= 128.
-// Each wavefront owns two 16-row blocks of the strip; the L fragments are
-// read straight from HBM (16 consecutive rows of a column per lane group).
-// ASSIGN: Bi := Lik Yk instead (no load of Bi, no negation): the diagonal
-// steps of the mixed-precision solve, with Lik an explicit inverse.
-template <typename TL, bool ASSIGN = false>
-__device__ __forceinline__ void fgemv(const TL* __restrict__ Lik, int64_t ld, double* Bi, const double* Yk,
-                                      int64_t ldb, int rows, int mk, int nrhs, double* lds) {
-  double* Ys = lds;
+// Solve update on one strip of at most 32 output rows:
+//     Y := Y - op(L) X     or, ASSIGN,     Y := op(L) X
+// with op(L) = L (output row r, K index c at L[c ld + r]: the forward
+// update, and the diagonal steps that apply an explicit inverse) or, TRANS,
+// L^T (output row r, K index c at L[r ld + c]: the backward update).  K runs
+// over [k0, k1) (row c of X at X[c]); right-hand side j at column j (ld ldb).
+// These items sit on the solve's dependency chain and move little data, so
+// their time is memory latency: the four wavefronts take a quarter of K each
+// and request all of their L fragments (two 16-row blocks, up to 32 k-steps
+// of 4) and right-hand-side fragments before the first product, one round
+// trip per item.  The quarters' partial products meet in LDS and are added
+// in wavefront order, so the result does not depend on timing.  L in FP64
+// or FP32 (the mixed-precision working copy); X and Y in FP64.
+template <typename TL, bool TRANS, bool ASSIGN>
+__device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld, double* Y, const double* X,
+                                           int64_t ldb, int rows, int k0, int k1, int nrhs, double* lds) {
+  double* Ps = lds;  // [wavefront][8][64]: the partial products
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
+  const int nsteps = (k1 - k0 + 3) >> 2;  // k-steps of 4
+  const int qs = (nsteps + 3) >> 2;       // per wavefront: at most 32 (K <= 512)
+  const int ns = imax(0, imin(qs, nsteps - wave * qs));
+  const int kw = k0 + 4 * wave * qs;
+  const int ra = imin(l16, rows - 1), rb = imin(16 + l16, rows - 1);
+  // fragments of k-steps past this wavefront's quarter are loaded (in
+  // bounds) but meet zeros in X, in groups of 8 k-steps
+  double fa[32], fb[32];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+    if (8 * g < ns) {
+#pragma unroll
+      for (int u = 8 * g; u < 8 * g + 8; ++u) {
+        const int c = imin(kw + 4 * u + lg, k1 - 1);
+        fa[u] = (double)(TRANS ? L[(int64_t)ra * ld + c] : L[(int64_t)c * ld + ra]);
+        fb[u] = (double)(TRANS ? L[(int64_t)rb * ld + c] : L[(int64_t)c * ld + rb]);
+      }
+    }
+  // this wavefront's two outputs of the strip's eight per lane: block wave / 2,
+  // rows 4 v + lg with v = 2 (wave % 2) + h
+  const int ob = wave >> 1;
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
-    stage_rhs(Ys, Yk, ldb, mk, j0, jn);
-    __syncthreads();
-    d4 acc[2];
-    const int jc = imin(l16, jn - 1);
+    const int jc = j0 + imin(l16, jn - 1);
+    double x[32];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      if (8 * g < ns) {
+#pragma unroll
+        for (int u = 8 * g; u < 8 * g + 8; ++u) {
+          const int c = kw + 4 * u + lg;
+          const double v = X[(int64_t)jc * ldb + imin(c, k1 - 1)];
+          x[u] = (u < ns && c < k1) ? v : 0.0;
+        }
+      }
+    double y[2] = {0.0, 0.0};
+    if (!ASSIGN)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = 16 * ob + 4 * (2 * (wave & 1) + h) + lg;
+        y[h] = Y[(int64_t)jc * ldb + imin(r, rows - 1)];
+      }
+    d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      if (8 * g < ns) {
+#pragma unroll
+        for (int u = 8 * g; u < 8 * g + 8; ++u) {
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], x[u], acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[u], x[u], acc[1], 0, 0, 0);
+        }
+      }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = (wave * 2 + t) * 16 + 4 * i + lg;
-        acc[t][i] = ASSIGN ? 0.0 : Bi[(int64_t)(j0 + jc) * ldb + imin(r, rows - 1)];
-      }
-    const int ra = imin((wave * 2) * 16 + l16, rows - 1), rbb = imin((wave * 2 + 1) * 16 + l16, rows - 1);
-    // K in batches of 32: the batch's 16 L fragments are requested together
-    // (this update streams L from HBM; it needs many loads in flight)
-    for (int kb = 0; kb < mk; kb += 32) {
-      double f0[8], f1[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = imin(kb + 4 * u + lg, mk - 1);
-        f0[u] = (double)Lik[(int64_t)q * ld + ra];
-        f1[u] = (double)Lik[(int64_t)q * ld + rbb];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = kb + 4 * u + lg;
-        const double fy = (k < mk) ? Ys[l16 * YLD + imin(k, 511)] : 0.0;
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[u], fy, acc[0], 0, 0, ASSIGN ? 0 : 2 /* neg B */);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[u], fy, acc[1], 0, 0, ASSIGN ? 0 : 2);
-      }
-    }
-    if (l16 < jn) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = (wave * 2 + t) * 16 + 4 * i + lg;
-          if (r < rows) st_dev(Bi + (int64_t)(j0 + l16) * ldb + r, acc[t][i]);
-        }
-    }
+      for (int v = 0; v < 4; ++v) Ps[(wave * 8 + 4 * t + v) * 64 + lane] = acc[t][v];
     __syncthreads();
-  }
-}
-
-// Y_i[cols] -= L_ki[:, cols]^T X_k  (backward update), cols = a strip of <= 128.
-template <typename TL>
-__device__ __forceinline__ void bgemv(const TL* __restrict__ Lki, int64_t ld, double* Yi, const double* Xk,
-                                      int64_t ldb, int cols, int mk, int nrhs, double* lds) {
-  double* Xs = lds;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int l16 = lane & 15, lg = lane >> 4;
-  for (int j0 = 0; j0 < nrhs; j0 += 16) {
-    const int jn = imin(16, nrhs - j0);
-    stage_rhs(Xs, Xk, ldb, mk, j0, jn);
-    __syncthreads();
-    d4 acc[2];
-    const int jc = imin(l16, jn - 1);
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int h = 0; h < 2; ++h) {
+      const int e = 4 * ob + 2 * (wave & 1) + h;
+      double s = ASSIGN ? Ps[e * 64 + lane] : y[h] - Ps[e * 64 + lane];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = (wave * 2 + t) * 16 + 4 * i + lg;
-        acc[t][i] = Yi[(int64_t)(j0 + jc) * ldb + imin(c, cols - 1)];
-      }
-    const TL* c0p = Lki + (int64_t)imin((wave * 2) * 16 + l16, cols - 1) * ld;
-    const TL* c1p = Lki + (int64_t)imin((wave * 2 + 1) * 16 + l16, cols - 1) * ld;
-    for (int kb = 0; kb < mk; kb += 32) {
-      double f0[8], f1[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = imin(kb + 4 * u + lg, mk - 1);
-        f0[u] = (double)c0p[q];
-        f1[u] = (double)c1p[q];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int k = kb + 4 * u + lg;
-        const double fx = (k < mk) ? Xs[l16 * YLD + imin(k, 511)] : 0.0;
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f0[u], fx, acc[0], 0, 0, 2 /* neg B */);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[u], fx, acc[1], 0, 0, 2);
-      }
-    }
-    if (l16 < jn) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int c = (wave * 2 + t) * 16 + 4 * i + lg;
-          if (c < cols) st_dev(Yi + (int64_t)(j0 + l16) * ldb + c, acc[t][i]);
-        }
+      for (int w = 1; w < 4; ++w) s = ASSIGN ? s + Ps[(w * 8 + e) * 64 + lane] : s - Ps[(w * 8 + e) * 64 + lane];
+      const int r = 16 * ob + 4 * (e & 3) + lg;
+      if (l16 < jn && r < rows) st_dev(Y + (int64_t)(j0 + l16) * ldb + r, s);
     }
     __syncthreads();
   }
@@ -2168,9 +2121,16 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     const int64_t sn = sr[2], nb = sr[3], ld = sr[4], ldb = sn;
     // mixed precision: the system's FP64 diagonal tiles and their inverses
     double* const Dsys = a.D + (MIXED ? sr[5] : 0);
-    double* const DinvSys = a.Dinv + (MIXED ? sr[5] : 0);
-    double* const DinvTSys = a.DinvT + (MIXED ? sr[5] : 0);
+    double* const DinvSys = a.Dinv + sr[5];
+    double* const DinvTSys = a.DinvT + sr[5];
     auto tsz = [&](int t) __attribute__((always_inline)) { return (int)tile_size(sn, nb, t); };
+    // the solve's diagonal step on tile t applies explicit inverses (and keeps
+    // y in the scratch vector): always in the mixed-precision solves; in the
+    // FP64 solve of a launch that computes them (their tiles' orders are
+    // multiples of 16), else substitution in place
+    auto inv_tile = [&](int t) __attribute__((always_inline)) {
+      return MODE == 2 || (MODE == 0 && a.inv != 0 && (tsz(t) & 15) == 0);
+    };
     // in a batched launch a system whose factorization failed only passes
     // its remaining tasks on, so that the DAG drains
     const bool skip = a.batched && uniform_i(ld_relaxed(&a.sinfo[sid])) != 0;
@@ -2367,21 +2327,30 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           // batched FP32 systems: substitution against the FP64 diagonal tile, in place
           tile_solve(Dsys + (int64_t)tk * nb * nb, nb, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs, kind == TK_BTRSV,
                      lds);
-        } else if constexpr (MIXED) {
-          // explicit FP64 inverses, 128-row strips: forward y_k := L_kk^{-1} b_k into
-          // the scratch vector, backward x_k := L_kk^{-T} y_k back into B
+        } else if (inv_tile(tk)) {
+          // explicit inverses, by row strips: forward y_k := L_kk^{-1} b_k into
+          // the scratch vector (its rows r0.. need columns up to r0 + rows), backward
+          // x_k := L_kk^{-T} y_k back into B (rows r0.. need columns from r0)
+          const int m = tsz(tk);
           const int r0 = part * a.gemv_rows;
-          const int rows = imin(a.gemv_rows, tsz(tk) - r0);
+          const int rows = imin(a.gemv_rows, m - r0);
           double* const Sbase = a.S + sr[1];
-          if (kind == TK_FTRSV)
-            fgemv<double, true>(DinvSys + (int64_t)tk * nb * nb + r0, nb, Sbase + tk * nb + r0, Bbase + tk * nb, ldb,
-                                rows, tsz(tk), (int)a.nrhs, lds);
+          if (kind == TK_FTRSV && MODE == 0)  // L_kk^{-1} = (L_kk^{-T})^T: rows of it are columns of DinvT
+            gemv_strip<double, true, true>(DinvTSys + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb,
+                                           Sbase + tk * nb + r0, Bbase + tk * nb, ldb, rows, 0, imin(m, r0 + rows),
+                                           (int)a.nrhs, lds);
+          else if (kind == TK_FTRSV)
+            gemv_strip<double, false, true>(DinvSys + (int64_t)tk * nb * nb + r0, nb, Sbase + tk * nb + r0,
+                                            Bbase + tk * nb, ldb, rows, 0, imin(m, r0 + rows), (int)a.nrhs, lds);
           else
-            fgemv<double, true>(DinvTSys + (int64_t)tk * nb * nb + r0, nb, Bbase + tk * nb + r0, Sbase + tk * nb, ldb,
-                                rows, tsz(tk), (int)a.nrhs, lds);
-        } else {
+            gemv_strip<double, false, true>(DinvTSys + (int64_t)tk * nb * nb + r0, nb, Bbase + tk * nb + r0,
+                                            Sbase + tk * nb, ldb, rows, r0, m, (int)a.nrhs, lds);
+        } else if constexpr (MODE == 0) {
+          // substitution against L_kk, in place (batched systems; an order not a multiple of 16)
           tile_solve(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
                      kind == TK_BTRSV, lds);
+        } else {
+          ok = 0;
         }
         break;
       case TK_FGEMV: {
@@ -2391,10 +2360,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         }
         const int r0 = part * a.gemv_rows;
         const int rows = imin(a.gemv_rows, tsz(ti) - r0);
-        // the mixed-precision solve keeps y in the scratch vector
-        const double* Yk = (MIXED && MODE != 4) ? a.S + sr[1] + tk * nb : Bbase + tk * nb;
-        fgemv(Abase + (tk * nb) * ld + ti * nb + r0, ld, Bbase + ti * nb + r0, Yk, ldb, rows, tsz(tk), (int)a.nrhs,
-              lds);
+        // y_k is in the scratch vector when the diagonal step applied an inverse
+        const double* Yk = inv_tile(tk) ? a.S + sr[1] + tk * nb : Bbase + tk * nb;
+        gemv_strip<E, false, false>(Abase + (tk * nb) * ld + ti * nb + r0, ld, Bbase + ti * nb + r0, Yk, ldb, rows,
+                                    0, tsz(tk), (int)a.nrhs, lds);
         break;
       }
       case TK_BGEMV: {
@@ -2404,17 +2373,20 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         }
         const int c0 = part * a.gemv_rows;
         const int cols = imin(a.gemv_rows, tsz(ti) - c0);
-        double* Yi = (MIXED && MODE != 4) ? a.S + sr[1] + ti * nb + c0 : Bbase + ti * nb + c0;
-        bgemv(Abase + (ti * nb + c0) * ld + tk * nb, ld, Yi, Bbase + tk * nb, ldb, cols, tsz(tk),
-              (int)a.nrhs, lds);
+        double* Yi = inv_tile(ti) ? a.S + sr[1] + ti * nb + c0 : Bbase + ti * nb + c0;
+        gemv_strip<E, true, false>(Abase + (ti * nb + c0) * ld + tk * nb, ld, Yi, Bbase + tk * nb, ldb, cols, 0,
+                                   tsz(tk), (int)a.nrhs, lds);
         break;
       }
       case TK_TRTRI: {
-        if constexpr (MODE != 1 && MODE != 5) {
+        if constexpr (MODE != 0 && MODE != 1 && MODE != 5) {
           ok = 0;
         } else {
-          // L_kk^{-T} by 32-row strips: identity rows solved in place (into DinvT, ld nb),
-          // their transposes stored as L_kk^{-1} (Dinv); ragged tiles are identity-padded
+          // L_kk^{-T} by 32-row strips: identity rows solved in place (into DinvT, ld nb).
+          // The mixed-precision factorization reads its FP64 diagonal tile,
+          // identity-padded when ragged, and also stores the transposes as
+          // L_kk^{-1} (Dinv); the FP64 solve reads L_kk in A (its order is then a
+          // multiple of 16) and keeps L_kk^{-T} only.
           const int mpad = (tsz(tk) + 15) & ~15;
           const int r0 = part * a.trsm_rows;
           const int S = imin(a.trsm_rows, mpad - r0);
@@ -2425,8 +2397,11 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           }
           wait_vmcnt<0>();
           __syncthreads();
-          trsm_strip<double, 2>(X, nb, Dsys + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,
-                                DinvSys + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
+          if constexpr (MODE == 0)
+            trsm_strip<double>(X, nb, Abase + (tk * nb) * ld + tk * nb, ld, S, mpad, lds);
+          else
+            trsm_strip<double, 2>(X, nb, Dsys + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,
+                                  DinvSys + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
         }
         break;
       }

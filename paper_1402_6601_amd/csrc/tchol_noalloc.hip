@@ -15,8 +15,9 @@
 #include "../../include/tchol.h"
 
 namespace tchol {
+int64_t factor_solve_bytes(int64_t n, int64_t nb, int64_t nrhs, bool inv);
 int32_t factor_solve_run(double* A, int64_t n, int64_t nb, double* B, int64_t nrhs, void* ws, int64_t ws_bytes,
-                         void* stream, const tchol_opts* opts, bool pinned);
+                         void* stream, const tchol_opts* opts, bool pinned, bool inv);
 }
 
 static __device__ __align__(256) char scratch[TCHOL_NOALLOC_SCRATCH_BYTES];
@@ -53,15 +54,17 @@ int32_t tchol_factor_solve_noalloc(double* A, int64_t n, int64_t nb, double* B, 
   if (n == 0) return 0;
   if (!A) return -1;
   if (nrhs > 0 && !B) return -4;
-  // the scheduler scratch this problem needs (host-side plan sizes only)
-  const int64_t need = tchol_factor_solve_workspace_bytes(n, nb, nrhs);
+  // the scheduler scratch this problem needs (host-side plan sizes only).  The
+  // solve substitutes against the diagonal tiles: their explicit inverses
+  // (n nb doubles) would not fit the fixed array at the orders it serves.
+  const int64_t need = tchol::factor_solve_bytes(n, nb, nrhs, false);
   if (need < 0) return (int32_t)need;
   if (need > TCHOL_NOALLOC_SCRATCH_BYTES) return TCHOL_E_SCRATCH;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return TCHOL_E_HIP;
   void* ws = scratch_ptr(dev);
   if (!ws) return TCHOL_E_HIP;
-  return tchol::factor_solve_run(A, n, nb, B, nrhs, ws, TCHOL_NOALLOC_SCRATCH_BYTES, stream, nullptr, false);
+  return tchol::factor_solve_run(A, n, nb, B, nrhs, ws, TCHOL_NOALLOC_SCRATCH_BYTES, stream, nullptr, false, false);
 }
 
 }  // extern "C"

@@ -117,7 +117,7 @@ def main(argv=None):
             _, _, _, ms = tc.solve_mixed_(A, X, nb, maxit=0, policy=pol, want_kernel_ms=True, trace=trace, lowp=lowp)
         elif args.op == "merged":
             # the benchmark's launch: factorization and 16-RHS solve as one DAG
-            plan = tc.batched_plan_query([n], [nb], pol)
+            plan = tc.plan_query(tc.OP_FACTOR_SOLVE, n, nb, pol)
             trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
             B = torch.from_numpy(spd_inputs.rhs(rng, n, 16)).to(dev).t().contiguous()
             W, X = A.clone(), B.clone()

@@ -156,7 +156,7 @@ def test_strerror_and_version(lib):
 
 def test_plan_query_validation(lib):
     with pytest.raises(tc.TcholError):
-        tc.plan_query(5, 100, 16)
+        tc.plan_query(6, 100, 16)
     with pytest.raises(tc.TcholError):
         tc.plan_query(0, 100, 20)
     with pytest.raises(tc.TcholError):
@@ -195,9 +195,29 @@ def test_noalloc_validation_and_scratch_limit(lib):
     assert f(None, 100, 128, FAKE, 1, None) == -1
     assert f(FAKE, 100, 128, None, 1, None) == -4
     # problems whose scheduler scratch exceeds the fixed array are refused
-    # before any HIP call; the bench configuration (n = 32768, nb = 512) fits
-    fs = lib.tchol_factor_solve_workspace_bytes
-    assert fs(32768, 512, 16) <= tc.NOALLOC_SCRATCH_BYTES
-    assert fs(32768, 256, 16) > tc.NOALLOC_SCRATCH_BYTES
+    # before any HIP call; the bench configuration (n = 32768, nb = 512) fits.
+    # Its solve substitutes against the diagonal tiles, so it needs what the
+    # batched launch of the one system needs (no inverses, no y vector)
+    fs = lambda n, nb: tc.batched_workspace_bytes([n], [nb])
+    assert fs(32768, 512) <= tc.NOALLOC_SCRATCH_BYTES
+    assert fs(32768, 256) > tc.NOALLOC_SCRATCH_BYTES
+    assert lib.tchol_factor_solve_workspace_bytes(32768, 512, 16) > fs(32768, 512)
     assert f(FAKE, 32768, 256, FAKE, 16, None) == tc.E_SCRATCH
     assert "scratch" in tc.strerror(tc.E_SCRATCH)
+
+
+def test_trace_buffer_too_small_is_refused(lib):
+    """A trace buffer shorter than 4 words per work item of the launch is an
+    invalid options argument, refused before anything is launched (the
+    buffer is never written)."""
+    n, nb, nrhs = 1024, 128, 2
+    items = tc.plan_query(tc.OP_FACTOR_SOLVE, n, nb)["nitem"]
+    o = tc.Opts()
+    o.trace = FAKE
+    o.trace_words = 4 * items - 1
+    big = 1 << 40
+    assert lib.tchol_factor_solve(FAKE, n, nb, FAKE, nrhs, FAKE, big, None, ctypes.byref(o)) == -9
+    o.trace_words = 4 * tc.plan_query(tc.OP_SOLVE, n, nb)["nitem"] - 4
+    assert lib.tchol_solve_ex(FAKE, n, nb, FAKE, nrhs, FAKE, big, None, ctypes.byref(o)) == -9
+    o.trace_words = 4 * tc.plan_query(tc.OP_FACTOR, n, nb)["nitem"] - 1
+    assert lib.tchol_factor_ex(FAKE, n, nb, FAKE, big, None, ctypes.byref(o)) == -7

@@ -30,7 +30,10 @@ def bplan(n, nb, policy=0, seed=0):
         pytest.skip(str(e))
 
 
-def reduce_transitively(out):
+def reduce_transitively(out, keep=lambda b: False):
+    """Drop the edges (a, b) a longer path implies, except into tasks b that
+    ``keep`` names (the factorization lists every panel a merged update
+    reads, even when its chain already orders the two)."""
     succ = collections.defaultdict(set)
     for a, b in out:
         succ[a].add(b)
@@ -48,13 +51,14 @@ def reduce_transitively(out):
             stack.extend(succ[x])
         return False
 
-    return {(a, b) for (a, b) in out if not reachable(a, b)}
+    return {(a, b) for (a, b) in out if keep(b) or not reachable(a, b)}
 
 
-def dataflow_edges_factor_solve(T):
+def dataflow_edges_factor_solve(T, inv=()):
     """Program-order replay of the tile factorization then the two tiled
     substitutions; edges join each access to the last writer of the datum
-    (tiles ("L", i, j), right-hand-side blocks ("B", i))."""
+    (tiles ("L", i, j), right-hand-side blocks ("B", i); for the diagonal
+    tiles in ``inv``, their inverses ("D", k) and the blocks ("S", k) of y)."""
     last_writer = {}
     out = set()
 
@@ -67,15 +71,9 @@ def dataflow_edges_factor_solve(T):
 
     for task, reads, writes in tiled_ref.factor_program(T):
         access(task, [("L",) + r for r in reads], [("L",) + w for w in writes])
-    for k in range(T):
-        access((FTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)])
-        for i in range(k + 1, T):
-            access((FGEMV, i, k, k), [("L", i, k), ("B", k), ("B", i)], [("B", i)])
-    for k in range(T - 1, -1, -1):
-        access((BTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)])
-        for i in range(k):
-            access((BGEMV, i, k, k), [("L", k, i), ("B", k), ("B", i)], [("B", i)])
-    return reduce_transitively(out)
+    for task, reads, writes in tiled_ref.solve_program(T, inv):
+        access(task, reads, writes)
+    return reduce_transitively(out, keep=lambda b: b[0] in (POTRF, TRSM, SYRK, GEMM, tiled_ref.GEMM2))
 
 
 def key(p, t):
@@ -114,6 +112,28 @@ def test_batched_edges_equal_dataflow(n, nb):
         assert cnt.get(POTRF, 0) == T == cnt.get(FTRSV, 0) == cnt.get(BTRSV, 0)
         assert cnt.get(TRSM, 0) == cnt.get(SYRK, 0) == T * (T - 1) // 2 == cnt.get(FGEMV, 0) == cnt.get(BGEMV, 0)
         assert cnt.get(GEMM, 0) == ng and cnt.get(tiled_ref.GEMM2, 0) == npair
+
+
+@pytest.mark.parametrize("n,nb", [(16, 16), (100, 16), (1024, 128), (1000, 128), (200, 64)])
+def test_factor_solve_plan_equals_dataflow(n, nb):
+    """The merged factor + solve launch of one system: its solve computes the
+    explicit inverse of every diagonal tile whose order is a multiple of 16
+    (TRTRI(k) after POTRF(k)) and applies it by row strips; a ragged last
+    tile substitutes in place."""
+    try:
+        p = tc.plan_query(tc.OP_FACTOR_SOLVE, n, nb)
+    except ImportError as e:  # library not built
+        pytest.skip(str(e))
+    T = -(-n // nb)
+    inv = [k for k in range(T) if min(nb, n - k * nb) % 16 == 0]
+    got = {(key(p, t), key(p, int(p["succ"][e])))
+           for t in range(p["ntask"]) for e in range(p["succ_off"][t], p["succ_off"][t + 1])}
+    assert got == dataflow_edges_factor_solve(T, inv)
+    w = dict(WEIGHT)
+    w[tiled_ref.TRTRI] = 10
+    for t in range(p["ntask"]):
+        succ = [p["rank"][p["succ"][e]] for e in range(p["succ_off"][t], p["succ_off"][t + 1])]
+        assert p["rank"][t] == w[int(p["kind"][t])] * (nb // 16) ** 3 + (max(succ) if succ else 0)
 
 
 @pytest.mark.parametrize("policy,seed", [(tc.POLICY_LIST, 0), (tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0),

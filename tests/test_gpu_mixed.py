@@ -126,7 +126,7 @@ def test_mixed_fallback_equals_fp64_path(tc):
     assert info["fallback"] and info["rc"] == tc.E_NOCONV
     W = A_d.clone()
     assert tc.factor_(W, 128) == 0
-    X64 = tc.solve(W, torch.from_numpy(b).cuda(), 128)
+    X64 = tc.solve(W, torch.from_numpy(b).cuda(), 128, subst=True)
     assert torch.equal(X, X64)
     assert np.all(oracle.solve_backward_error(A, X.cpu().numpy(), b) <= 1e-15)
 

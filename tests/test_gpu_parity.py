@@ -88,7 +88,10 @@ def test_exact_integer_recovery(tc, n, nb):
     b, x0 = spd_inputs.integer_rhs(A, 4, seed=n)
     W = _dev(A)
     assert tc.factor_(W, nb) == 0
-    x = tc.solve(W, _dev(b), nb).cpu().numpy()
+    # substitution keeps every intermediate an integer (the 4 x 4 inverses of
+    # its micro-steps are exact with power-of-two pivots); explicit inverses
+    # of whole tiles of such a factor are not representable
+    x = tc.solve(W, _dev(b), nb, subst=True).cpu().numpy()
     assert np.array_equal(x, x0)
 
 
@@ -161,21 +164,24 @@ def test_kernel_time_reported(tc):
     assert rc == 0 and ms > 0.0
 
 
+@pytest.mark.parametrize("subst", [False, True])
 @pytest.mark.parametrize("n,nb,nrhs,seed", [(1000, 128, 5, 40), (1024, 256, 16, 41), (999, 160, 3, 42),
                                             (513, 512, 1, 43), (17, 16, 2, 44), (300, 64, 0, 45)])
-def test_factor_solve_one_launch_equals_two(tc, n, nb, nrhs, seed):
+def test_factor_solve_one_launch_equals_two(tc, n, nb, nrhs, seed, subst):
     """The merged factor + solve launch gives bitwise the results of the two
-    separate launches (every tile sees the same updates in the same order)."""
-    print("case n=%d nb=%d nrhs=%d" % (n, nb, nrhs), flush=True)
+    separate launches (every tile sees the same updates in the same order),
+    with the diagonal tiles' inverses (computed in either launch by the same
+    tasks) and with substitution."""
+    print("case n=%d nb=%d nrhs=%d subst=%d" % (n, nb, nrhs, subst), flush=True)
     A, b = spd_inputs.spd_matrix_and_rhs(n, seed, nrhs=max(nrhs, 1))
     b = b[:, :nrhs]
     W1, W2 = _dev(A), _dev(A)
     B1 = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
     B2 = B1.clone()
-    assert tc.factor_solve_(W1, B1, nb) == 0
+    assert tc.factor_solve_(W1, B1, nb, subst=subst) == 0
     assert tc.factor_(W2, nb) == 0
     if nrhs:
-        assert tc.solve_(W2, B2, nb) == 0
+        assert tc.solve_(W2, B2, nb, subst=subst) == 0
     torch.cuda.synchronize()
     assert torch.equal(W1, W2) and torch.equal(B1, B2)
     L = np.tril(W1.cpu().numpy().T)
@@ -191,7 +197,7 @@ def test_factor_solve_one_launch_integer_and_breakdown(tc):
     b, x0 = spd_inputs.integer_rhs(A, 3, seed=46)
     W = _dev(A)
     Bc = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
-    assert tc.factor_solve_(W, Bc, 64) == 0
+    assert tc.factor_solve_(W, Bc, 64, subst=True) == 0
     assert np.array_equal(np.tril(W.cpu().numpy().T), L0)
     assert np.array_equal(Bc.cpu().numpy().T, x0)
     j = 150
@@ -199,3 +205,22 @@ def test_factor_solve_one_launch_integer_and_breakdown(tc):
     W = _dev(A)
     Bc = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
     assert tc.factor_solve_(W, Bc, 64) == j + 1
+
+
+@pytest.mark.parametrize("n,nb,shift,seed", [(1000, 128, 1e-6, 47), (1024, 512, 1e-8, 48), (777, 96, 1e-4, 49)])
+def test_inverse_solve_backward_error(tc, n, nb, shift, seed):
+    """The solve through the diagonal tiles' explicit inverses on ill-conditioned
+    SPD systems (cond(A) about 1.3 / shift): its normwise backward error stays
+    within 64 sqrt(cond(A)) eps (cond(L_kk)^2 <= cond(A) for the Cholesky
+    factor's diagonal tiles), and substitution's within 16 eps."""
+    print("case n=%d nb=%d shift=%g" % (n, nb, shift), flush=True)
+    A, b = spd_inputs.spd_matrix_and_rhs(n, seed, nrhs=4, shift=shift)
+    W = _dev(A)
+    assert tc.factor_(W, nb) == 0
+    eps = 2.0 ** -52
+    kappa = 1.4 / shift
+    for subst, bound in ((False, 64 * np.sqrt(kappa) * eps), (True, 16 * eps)):
+        x = tc.solve(W, _dev(b), nb, subst=subst).cpu().numpy()
+        berr = np.max(oracle.solve_backward_error(A, x, b))
+        print("  subst=%d backward error %.3g (bound %.3g)" % (subst, berr, bound), flush=True)
+        assert berr <= bound

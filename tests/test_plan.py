@@ -21,7 +21,8 @@ tc = pytest.importorskip("paper_1402_6601_amd")
 
 POTRF, TRSM, SYRK, GEMM, FTRSV, FGEMV, BTRSV, BGEMV = range(8)
 GEMM2 = tiled_ref.GEMM2
-WEIGHT = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2, GEMM2: 12}
+TRTRI = tiled_ref.TRTRI
+WEIGHT = {POTRF: 5, TRSM: 10, SYRK: 4, GEMM: 6, FTRSV: 1, FGEMV: 2, BTRSV: 1, BGEMV: 2, GEMM2: 12, TRTRI: 10}
 
 
 def plan(op, n, nb, policy=0, seed=0):
@@ -61,9 +62,10 @@ def dataflow_edges_factor(T):
     return out
 
 
-def dataflow_edges_solve(T):
+def dataflow_edges_solve(T, inv=()):
     """Same replay for the forward then backward block substitution; the
-    blocks of B and the final tiles of L are the data."""
+    blocks of B, the final tiles of L and, for the tiles in ``inv``, their
+    explicit inverses and the blocks of y are the data."""
     last_writer = {}
     out = set()
 
@@ -74,14 +76,8 @@ def dataflow_edges_solve(T):
         for blk in writes:
             last_writer[blk] = task
 
-    for k in range(T):
-        access((FTRSV, k, k, k), [k], [k])
-        for i in range(k + 1, T):
-            access((FGEMV, i, k, k), [k, i], [i])
-    for k in range(T - 1, -1, -1):
-        access((BTRSV, k, k, k), [k], [k])
-        for i in range(k):
-            access((BGEMV, i, k, k), [k, i], [i])
+    for task, reads, writes in tiled_ref.solve_program(T, inv):
+        access(task, reads, writes)
     # keep only edges that are not implied by a path (the planner lists
     # direct dependencies; the replay can also link a block to an older reader)
     succ = collections.defaultdict(set)
@@ -132,8 +128,26 @@ def test_factor_edges_equal_dataflow(T):
 
 @pytest.mark.parametrize("T", [1, 2, 3, 6])
 def test_solve_edges_equal_dataflow(T):
+    # the FP64 solve computes and applies every diagonal tile's inverse
     p = plan(1, 16 * T, 16)
-    assert edges(p) == dataflow_edges_solve(T)
+    assert edges(p) == dataflow_edges_solve(T, inv=range(T))
+
+
+@pytest.mark.parametrize("n,nb", [(100, 16), (40, 16), (1000, 128)])
+def test_solve_ragged_last_tile_substitutes(n, nb):
+    """A last tile whose order is not a multiple of 16 has no inverse: its
+    diagonal steps substitute in place (one work item each); the others are
+    split into row strips like the updates."""
+    p = plan(1, n, nb)
+    T = -(-n // nb)
+    assert edges(p) == dataflow_edges_solve(T, inv=range(T - 1))
+    for t in range(p["ntask"]):
+        kind, k = int(p["kind"][t]), int(p["k"][t])
+        m = min(nb, n - k * nb)
+        if kind in (FTRSV, BTRSV):
+            assert p["parts"][t] == (1 if k == T - 1 else -(-m // 32))
+        if kind == TRTRI:
+            assert k < T - 1 and p["parts"][t] == -(-m // 32)
 
 
 @pytest.mark.parametrize("op,n,nb", [(0, 1024, 128), (0, 1000, 128), (1, 1000, 128), (0, 4096, 512)])

@@ -3,7 +3,8 @@ scheduler scratch in the library's fixed per-GPU array, for callers that
 cannot allocate.  Through the C ABI, on two calls in a row (the second on a
 smaller problem, so it meets the first call's leftovers in the array), its
 factor and solution must be bitwise equal to those of tchol_factor_solve
-with a caller workspace, and within the oracle tolerance of the oracle."""
+with a caller workspace and substitution in the solve (the option it runs
+with), and within the oracle tolerance of the oracle."""
 import numpy as np
 import pytest
 
@@ -20,7 +21,7 @@ def _case(tc, n, nb, nrhs, seed):
     X1 = torch.from_numpy(np.ascontiguousarray(B.T)).cuda()
     W2, X2 = W1.clone(), X1.clone()
     print("noalloc case n=%d nb=%d nrhs=%d seed=%d" % (n, nb, nrhs, seed), flush=True)
-    assert tc.factor_solve_(W1, X1, nb) == 0
+    assert tc.factor_solve_(W1, X1, nb, subst=True) == 0
     assert tc.factor_solve_noalloc_(W2, X2, nb) == 0
     torch.cuda.synchronize()
     assert torch.equal(W1, W2)
@@ -55,7 +56,7 @@ def test_noalloc_breakdown_and_limit():
     W2 = W1.clone()
     X1 = torch.zeros(1, n, dtype=torch.float64, device="cuda")
     X2 = X1.clone()
-    assert tc.factor_solve_(W1, X1, nb) == j + 1
+    assert tc.factor_solve_(W1, X1, nb, subst=True) == j + 1
     assert tc.factor_solve_noalloc_(W2, X2, nb) == j + 1
     # beyond the fixed array: refused before any device work, nothing touched
     big = torch.zeros(4, dtype=torch.float64, device="cuda")

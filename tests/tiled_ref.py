@@ -120,6 +120,38 @@ def factor_program(T: int):
     return out
 
 
+FTRSV, FGEMV, BTRSV, BGEMV = 4, 5, 6, 7
+TRTRI = 12
+
+
+def solve_program(T: int, inv=()):
+    """The forward then backward tiled substitution's tasks in program order,
+    with the data each reads and writes: tiles ("L", i, j) of the factor,
+    blocks ("B", i) of the right-hand sides, and, for the diagonal tiles k in
+    ``inv`` (the FP64 solve's explicit inverses), the inverse ("D", k) made by
+    TRTRI(k) and the intermediate block ("S", k) that holds y_k.  A diagonal
+    step of a tile not in ``inv`` substitutes in place in B."""
+    inv = set(inv)
+    y = lambda k: ("S", k) if k in inv else ("B", k)  # where y_k lives
+    out = []
+    for k in range(T):
+        if k in inv:
+            out.append(((TRTRI, k, k, k), [("L", k, k)], [("D", k)]))
+            out.append(((FTRSV, k, k, k), [("D", k), ("B", k)], [("S", k)]))
+        else:
+            out.append(((FTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)]))
+        for i in range(k + 1, T):
+            out.append(((FGEMV, i, k, k), [("L", i, k), y(k), ("B", i)], [("B", i)]))
+    for k in range(T - 1, -1, -1):
+        if k in inv:
+            out.append(((BTRSV, k, k, k), [("D", k), ("S", k)], [("B", k)]))
+        else:
+            out.append(((BTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)]))
+        for i in range(k):
+            out.append(((BGEMV, i, k, k), [("L", k, i), ("B", k), y(i)], [y(i)]))
+    return out
+
+
 def tasks_k_major(n: int, nb: int):
     """Tile tasks in the textbook loop order (k outer)."""
     T = (n + nb - 1) // nb
