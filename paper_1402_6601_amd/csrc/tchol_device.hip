@@ -95,6 +95,18 @@ __device__ __forceinline__ void dma4s(const void* base, uint32_t off, double* l)
 
 constexpr int imin_c(int a, int b) { return a < b ? a : b; }
 
+// Makes every value of v available at this point (the compiler waits for
+// their loads here).  A value loaded only to be used under a condition would
+// otherwise have its load moved under that condition, one load and one wait
+// per value; issued unconditionally before this point, the loads overlap.
+template <int R, int C>
+__device__ __forceinline__ void materialize(double (&v)[R][C]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < C; ++c) asm volatile("" : : "v"(v[r][c]));
+}
+
 // Store with device (agent) scope: it is written through to the device's
 // point of coherence instead of staying dirty in this XCD's L2.  All results
 // a work item publishes to other workgroups are written this way.
@@ -498,22 +510,46 @@ __device__ __forceinline__ void gemm_f32_core(float* __restrict__ C, const float
     }
   }
   __syncthreads();
+  if constexpr (CD) {
+    // read-modify-write of the FP64 tile, two row blocks at a time: the 32
+    // old values are requested together (clamped into the tile, which is
+    // nb x nb in full) and all taken before the first store, one memory
+    // round trip per pair instead of one per value
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+    for (int rp = 0; rp < 4; rp += 2) {
+      double old[2][16];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = wm * 64 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
-        if (row < M && col < N && (!lower_only || row >= col)) {
-          if constexpr (CD) {
-            double* p = Cd + (int64_t)col * ldcd + row;
-            st_dev(p, *p + (double)acc[rb][cb][i]);
-          } else {
-            st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = wm * 64 + (rp + h) * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+            old[h][4 * cb + i] = Cd[(int64_t)imin(col, N - 1) * ldcd + imin(row, M - 1)];
           }
+      materialize(old);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = wm * 64 + (rp + h) * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+            if (row < M && col < N && (!lower_only || row >= col))
+              st_dev(Cd + (int64_t)col * ldcd + row, old[h][4 * cb + i] + (double)acc[rp + h][cb][i]);
+          }
+    }
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = wm * 64 + rb * 16 + l16, col = wn * 64 + cb * 16 + 4 * lg + i;
+          if (row < M && col < N && (!lower_only || row >= col)) st_dev(C + (int64_t)col * ld + row, acc[rb][cb][i]);
         }
-      }
+  }
 }
 
 __device__ __forceinline__ void gemm_nt_f32(float* C, const float* Ap, const float* Bp, int64_t ld, int M, int N,
@@ -1521,9 +1557,10 @@ __device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld,
   const int qs = (nsteps + 3) >> 2;       // per wavefront: at most 32 (K <= 512)
   const int ns = imax(0, imin(qs, nsteps - wave * qs));
   const int kw = k0 + 4 * wave * qs;
+  const int kend = imin(k1, kw + 4 * ns);  // end of this wavefront's K
   const int ra = imin(l16, rows - 1), rb = imin(16 + l16, rows - 1);
   // fragments of k-steps past this wavefront's quarter are loaded (in
-  // bounds) but meet zeros in X, in groups of 8 k-steps
+  // bounds) but meet zeros in place of X, in groups of 8 k-steps
   double fa[32], fb[32];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
@@ -1541,16 +1578,15 @@ __device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld,
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
     const int jc = j0 + imin(l16, jn - 1);
+    // loaded unconditionally (in bounds) and masked at their use: a select
+    // between a loaded value and zero would be turned into a branch around
+    // each load, with a wait for it at the join
     double x[32];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
       if (8 * g < ns) {
 #pragma unroll
-        for (int u = 8 * g; u < 8 * g + 8; ++u) {
-          const int c = kw + 4 * u + lg;
-          const double v = X[(int64_t)jc * ldb + imin(c, k1 - 1)];
-          x[u] = (u < ns && c < k1) ? v : 0.0;
-        }
+        for (int u = 8 * g; u < 8 * g + 8; ++u) x[u] = X[(int64_t)jc * ldb + imin(kw + 4 * u + lg, k1 - 1)];
       }
     double y[2] = {0.0, 0.0};
     if (!ASSIGN)
@@ -1565,8 +1601,9 @@ __device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld,
       if (8 * g < ns) {
 #pragma unroll
         for (int u = 8 * g; u < 8 * g + 8; ++u) {
-          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], x[u], acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[u], x[u], acc[1], 0, 0, 0);
+          const double xv = (kw + 4 * u + lg < kend) ? x[u] : 0.0;
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], xv, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[u], xv, acc[1], 0, 0, 0);
         }
       }
 #pragma unroll
