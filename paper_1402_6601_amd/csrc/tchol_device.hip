@@ -1533,6 +1533,103 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
   }
 }
 
+// The strip update of gemv_strip with 16-byte transfers (two FP64 values,
+// or two FP32 values in 8 bytes, per lane and load): half the load
+// instructions.  K is taken in pairs of k-steps: step u of a wavefront
+// covers K index kw + 8 (u / 2) + 2 (lane / 16) + u % 2, so that a lane's two
+// consecutive indices sit in steps 2j and 2j + 1.  Without TRANS a lane's
+// rows of L are paired instead: block t holds the strip's rows 2 m + t
+// (m = lane % 16), both loaded by one transfer.  Needs a full strip of 32
+// rows, a K range whose length is a multiple of 8 and starts even, even
+// leading dimensions and 16-byte aligned L and X; then every step of every
+// wavefront lies inside K and nothing is masked.
+template <typename TL, bool TRANS, bool ASSIGN>
+__device__ __forceinline__ void gemv_strip_wide(const TL* __restrict__ L, int64_t ld, double* Y, const double* X,
+                                                int64_t ldb, int k0, int k1, int nrhs, double* lds) {
+  typedef TL TL2 __attribute__((ext_vector_type(2)));
+  typedef const __attribute__((address_space(1))) char gchar;
+  typedef const __attribute__((address_space(1))) TL2 gTL2;
+  double* Ps = lds;  // [wavefront][8][64]: the partial products
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int nsteps = (k1 - k0) >> 2;                // even
+  const int qs = (((nsteps + 3) >> 2) + 1) & ~1;    // per wavefront, even, at most 32
+  const int ns = imax(0, imin(qs, nsteps - wave * qs));  // even
+  const int kw = k0 + 4 * wave * qs + 2 * lg;      // this lane's first K index
+  gchar* const Lu = (gchar*)uniform_ptr(L);
+  const uint32_t es = sizeof(TL), lds_b = (uint32_t)ld * es;
+  double fa[32], fb[32];
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (2 * j < ns) {
+      const uint32_t c = (uint32_t)(kw + 8 * j);
+      if (TRANS) {  // rows c, c + 1 of columns l16 and 16 + l16
+        const TL2 va = *(gTL2*)(Lu + ((uint32_t)l16 * lds_b + c * es));
+        const TL2 vb = *(gTL2*)(Lu + ((uint32_t)(16 + l16) * lds_b + c * es));
+        fa[2 * j] = (double)va[0];
+        fa[2 * j + 1] = (double)va[1];
+        fb[2 * j] = (double)vb[0];
+        fb[2 * j + 1] = (double)vb[1];
+      } else {      // rows 2 l16, 2 l16 + 1 of columns c and c + 1
+        const TL2 v0 = *(gTL2*)(Lu + (__umul24(c, lds_b) + (uint32_t)(2 * l16) * es));
+        const TL2 v1 = *(gTL2*)(Lu + (__umul24(c + 1, lds_b) + (uint32_t)(2 * l16) * es));
+        fa[2 * j] = (double)v0[0];
+        fb[2 * j] = (double)v0[1];
+        fa[2 * j + 1] = (double)v1[0];
+        fb[2 * j + 1] = (double)v1[1];
+      }
+    }
+  // output element (t, v) of a lane: strip row 2 (4 v + lg) + t (paired rows)
+  // or 16 t + 4 v + lg (TRANS); this wavefront adds up two of the eight
+  auto out_row = [&](int t, int v) __attribute__((always_inline)) {
+    return TRANS ? 16 * t + 4 * v + lg : 2 * (4 * v + lg) + t;
+  };
+  const int ob = wave >> 1;
+  for (int j0 = 0; j0 < nrhs; j0 += 16) {
+    const int jn = imin(16, nrhs - j0);
+    const int jc = j0 + imin(l16, jn - 1);
+    const double* const Xj = X + (int64_t)jc * ldb + kw;
+    double x[32];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (2 * j < ns) {
+        typedef double dd2 __attribute__((ext_vector_type(2)));
+        const dd2 v = *reinterpret_cast<const dd2*>(Xj + 8 * j);
+        x[2 * j] = v[0];
+        x[2 * j + 1] = v[1];
+      }
+    double y[2] = {0.0, 0.0};
+    if (!ASSIGN)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) y[h] = Y[(int64_t)jc * ldb + out_row(ob, 2 * (wave & 1) + h)];
+    d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (2 * j < ns) {
+#pragma unroll
+        for (int u = 2 * j; u < 2 * j + 2; ++u) {
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], x[u], acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[u], x[u], acc[1], 0, 0, 0);
+        }
+      }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ps[(wave * 8 + 4 * t + v) * 64 + lane] = acc[t][v];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = 4 * ob + 2 * (wave & 1) + h;
+      double s = ASSIGN ? Ps[e * 64 + lane] : y[h] - Ps[e * 64 + lane];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) s = ASSIGN ? s + Ps[(w * 8 + e) * 64 + lane] : s - Ps[(w * 8 + e) * 64 + lane];
+      if (l16 < jn) st_dev(Y + (int64_t)(j0 + l16) * ldb + out_row(ob, e & 3), s);
+    }
+    __syncthreads();
+  }
+}
+
 // Solve update on one strip of at most 32 output rows:
 //     Y := Y - op(L) X     or, ASSIGN,     Y := op(L) X
 // with op(L) = L (output row r, K index c at L[c ld + r]: the forward
@@ -1549,6 +1646,11 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
 template <typename TL, bool TRANS, bool ASSIGN>
 __device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld, double* Y, const double* X,
                                            int64_t ldb, int rows, int k0, int k1, int nrhs, double* lds) {
+  if (rows == 32 && ((k1 - k0) & 7) == 0 && (k0 & 1) == 0 && ((ld | ldb) & 1) == 0 &&
+      ((reinterpret_cast<uintptr_t>(L) | reinterpret_cast<uintptr_t>(X)) & 15) == 0) {
+    gemv_strip_wide<TL, TRANS, ASSIGN>(L, ld, Y, X, ldb, k0, k1, nrhs, lds);
+    return;
+  }
   double* Ps = lds;  // [wavefront][8][64]: the partial products
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1559,17 +1661,27 @@ __device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld,
   const int kw = k0 + 4 * wave * qs;
   const int kend = imin(k1, kw + 4 * ns);  // end of this wavefront's K
   const int ra = imin(l16, rows - 1), rb = imin(16 + l16, rows - 1);
-  // fragments of k-steps past this wavefront's quarter are loaded (in
-  // bounds) but meet zeros in place of X, in groups of 8 k-steps
+  // L fragments by 32-bit byte offsets from a wave-uniform base (the item
+  // spans less than 4 GB: at most 512 columns of at most 614400 rows), so
+  // that a fragment's address costs a multiply-add instead of 64-bit
+  // arithmetic.  Fragments of k-steps past this wavefront's quarter are
+  // loaded (in bounds) but meet zeros in place of X, in groups of 8 k-steps.
+  typedef const __attribute__((address_space(1))) char gchar;
+  typedef const __attribute__((address_space(1))) TL gTL;
+  gchar* const Lu = (gchar*)uniform_ptr(L);
+  const uint32_t es = sizeof(TL), lds_b = (uint32_t)ld * es;
+  const uint32_t offa = TRANS ? (uint32_t)ra * lds_b : (uint32_t)ra * es;
+  const uint32_t offb = TRANS ? (uint32_t)rb * lds_b : (uint32_t)rb * es;
   double fa[32], fb[32];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
     if (8 * g < ns) {
 #pragma unroll
       for (int u = 8 * g; u < 8 * g + 8; ++u) {
-        const int c = imin(kw + 4 * u + lg, k1 - 1);
-        fa[u] = (double)(TRANS ? L[(int64_t)ra * ld + c] : L[(int64_t)c * ld + ra]);
-        fb[u] = (double)(TRANS ? L[(int64_t)rb * ld + c] : L[(int64_t)c * ld + rb]);
+        const uint32_t c = (uint32_t)imin(kw + 4 * u + lg, k1 - 1);
+        const uint32_t oc = TRANS ? c * es : __umul24(c, lds_b);
+        fa[u] = (double)*(gTL*)(Lu + (offa + oc));
+        fb[u] = (double)*(gTL*)(Lu + (offb + oc));
       }
     }
   // this wavefront's two outputs of the strip's eight per lane: block wave / 2,
@@ -1578,6 +1690,7 @@ __device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld,
   for (int j0 = 0; j0 < nrhs; j0 += 16) {
     const int jn = imin(16, nrhs - j0);
     const int jc = j0 + imin(l16, jn - 1);
+    const double* const Xj = X + (int64_t)jc * ldb;
     // loaded unconditionally (in bounds) and masked at their use: a select
     // between a loaded value and zero would be turned into a branch around
     // each load, with a wait for it at the join
@@ -1586,7 +1699,7 @@ __device__ __forceinline__ void gemv_strip(const TL* __restrict__ L, int64_t ld,
     for (int g = 0; g < 4; ++g)
       if (8 * g < ns) {
 #pragma unroll
-        for (int u = 8 * g; u < 8 * g + 8; ++u) x[u] = X[(int64_t)jc * ldb + imin(kw + 4 * u + lg, k1 - 1)];
+        for (int u = 8 * g; u < 8 * g + 8; ++u) x[u] = Xj[imin(kw + 4 * u + lg, k1 - 1)];
       }
     double y[2] = {0.0, 0.0};
     if (!ASSIGN)
@@ -1888,8 +2001,10 @@ __device__ __forceinline__ bool wait_ready(const KArgs& a, int task, int lane) {
   const uint64_t t0 = wall_clock64();
   for (;;) {
     __builtin_amdgcn_s_sleep(2);
-    if (uniform_i(ld_relaxed(&a.dep[task])) == 0) break;
-    if (uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) != 0) return false;
+    // the counter and the abort flag in flight together: one round trip per poll
+    const int d = ld_relaxed(&a.dep[task]), ab = uniform_i(ld_relaxed(&a.hdr[HDR_ABORT]));
+    if (uniform_i(d) == 0) return ab == 0;
+    if (ab != 0) return false;
     if ((int64_t)(wall_clock64() - t0) > a.wait_limit) {
       if (lane == 0) {
         __hip_atomic_store(&a.hdr[HDR_ERROR], DEV_ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1898,7 +2013,6 @@ __device__ __forceinline__ bool wait_ready(const KArgs& a, int task, int lane) {
       return false;
     }
   }
-  return uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) == 0;
 }
 
 // Stops every worker with a runtime error code (the first one is kept).
@@ -1969,16 +2083,19 @@ __device__ __forceinline__ PoolUnit pool_unit(int m, int u) {
 // exceeds its bound (which then raises TCHOL_E_TIMEOUT like a task wait).
 __device__ __forceinline__ bool pool_wait(const KArgs& a, const int32_t* pool, int q0, int v0, int q1, int v1, int q2,
                                           int v2, int lane) {
+  // the three counters and the abort flag in flight together: one round trip per poll
+  int ab = 0;
   auto met = [&]() __attribute__((always_inline)) {
     const int x0 = ld_relaxed(pool + q0), x1 = ld_relaxed(pool + q1), x2 = ld_relaxed(pool + q2);
+    ab = uniform_i(ld_relaxed(&a.hdr[HDR_ABORT]));
     return uniform_i((x0 >= v0) & (x1 >= v1) & (x2 >= v2)) != 0;
   };
-  if (met()) return uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) == 0;
+  if (met()) return ab == 0;
   const uint64_t t0 = wall_clock64();
   for (;;) {
     __builtin_amdgcn_s_sleep(2);
-    if (met()) break;
-    if (uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) != 0) return false;
+    if (met()) return ab == 0;
+    if (ab != 0) return false;
     if ((int64_t)(wall_clock64() - t0) > a.wait_limit) {
       if (lane == 0) {
         __hip_atomic_store(&a.hdr[HDR_ERROR], DEV_ERR_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1987,7 +2104,6 @@ __device__ __forceinline__ bool pool_wait(const KArgs& a, const int32_t* pool, i
       return false;
     }
   }
-  return uniform_i(ld_relaxed(&a.hdr[HDR_ABORT])) == 0;
 }
 
 // Wavefront 0: waits for the predecessors of pool unit pu of a tile of order m.
