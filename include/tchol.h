@@ -147,12 +147,18 @@ TCHOL_API int32_t tchol_solve_ex(const double *L, int64_t n, int64_t nb, double 
    of each step reversed as GEMMs into the adjoints of its panel (chained
    per tile in a fixed order), its TRSMs as triangular solves with L_kk, its
    POTRF as the adjoint of the diagonal tile's factorization, on the same
-   persistent scheduler in upward-rank order.  Results do not depend on the
-   claim order.  L must have a positive diagonal (a factor tchol_factor
+   persistent scheduler in upward-rank order.  The diagonal tile's adjoint
+   is taken in closed form, S / 2 with S = L_kk^{-T} (M + M^T) L_kk^{-1} and
+   M = the lower triangle of L_kk^T Lbar_kk with its diagonal halved, by
+   products over 64 x 64 blocks (L_kk^{-T} computed in the same launch),
+   when the tile's order is a multiple of 16; a ragged last tile reverses its
+   factorization panel by panel.  Results do not depend on the claim order.
+   L must have a positive diagonal (a factor tchol_factor
    returned with info 0); only lower triangles are read or written.
    Workspace: tchol_workspace_bytes(TCHOL_OP_BACKWARD, n, nb, 0) bytes
-   (about 2 n^2 + n^2 / 2 doubles: the transposed factor, twice the
-   adjoint, and per-tile partial products).
+   (about 2 n^2 + n^2 / 2 + 3 n nb doubles: the transposed factor, twice
+   the adjoint, per-tile partial products, and per diagonal tile its
+   inverse and two scratch tiles).
    Arguments: 1 L, 2 n, 3 nb (as for tchol_factor; n / nb at most 160),
    4 Lbar (n x n, ld n), 5 ws, 6 ws_bytes, 7 stream, 8 opts (_ex). */
 TCHOL_API int32_t tchol_backward(const double *L, int64_t n, int64_t nb, double *Lbar, void *ws, int64_t ws_bytes,

@@ -41,8 +41,9 @@ typedef struct KArgs {
   int32_t inv;          /* FP64 solve: 1 when the launch computes the diagonal tiles'
                            explicit inverses (TRTRI tasks) and its diagonal steps
                            apply them (y in S); 0: substitution in place in B    */
-  double *Dinv;         /* mixed precision: L_kk^{-1}, nb x nb each (FP64)         */
-  double *DinvT;        /* mixed precision and inv: L_kk^{-T}, nb x nb each (FP64)  */
+  double *Dinv;         /* mixed precision: L_kk^{-1}, nb x nb each (FP64); adjoint:
+                           two scratch tiles per diagonal tile (Mn, Y^T)          */
+  double *DinvT;        /* mixed precision, inv and adjoint: L_kk^{-T}, nb x nb each */
   double *S;            /* mixed precision and inv: the solve's intermediate y, like B */
   double *Q;            /* adjoint: Q = twice the symmetric adjoint, ld ldq        */
   double *LT;           /* adjoint: L^T, ld ldq                                   */

@@ -115,8 +115,10 @@ int64_t weight(int32_t kind, int32_t op) {
     case TK_TREV: return 3;
     case TK_DPART: return 3;
     case TK_PREV: return 4;
-    case TK_TRTRI: return 10;
+    case TK_TRTRI: return op == TCHOL_OP_BACKWARD ? 40 : 10;
     case TK_DRED: return 1;
+    case TK_PADJM: case TK_PADJY: return 1;
+    case TK_PADJS: return 2;
     default: return 2;
   }
 }
@@ -271,11 +273,24 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, Diag diag = Diag:
 // The partial products S_ik give the diagonal tile's update one task per
 // term instead of a chain of T - k - 1 dependent ones on the critical path,
 // and their sum is spread over workgroups by row strips.
+//
+// A diagonal tile whose order is a multiple of 16 takes its adjoint in
+// closed form instead of PREV(k): DRED(k) (then also for k = T-1) leaves
+// Lbar_kk^T in the Q_kk tile, and
+//   TRTRI(k)       L_kk^{-T}, no predecessors (L is an input)
+//   PADJM(k)       M = Phi(L_kk^T Lbar_kk)         after DRED(k)
+//   PADJY(k)       Y^T = (M L_kk^{-1})^T           after PADJM(k), TRTRI(k)
+//   PADJS(k)       Q_kk = S, Lbar_kk = tril(S)/2   after PADJY(k)
+// each over TCHOL_PRB x TCHOL_PRB blocks of the tile's lower (Y^T: upper)
+// triangle, so that the chain of the diagonal tile runs on many workgroups.
+bool closed_form_tile(int64_t m) { return m % 16 == 0; }
+
 void build_backward(Builder& b) {
   auto& succ = b.succ;
   const int32_t T = b.T;
   std::vector<int32_t> id_prev(T), id_dred(T, -1), id_trev((size_t)T * T, -1), id_dpart((size_t)T * T, -1);
   std::vector<int32_t> id_grev((size_t)T * T * T, -1);
+  std::vector<int32_t> id_inv(T, -1), id_pm(T, -1), id_py(T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
   for (int32_t k = T - 1; k >= 0; --k) {
@@ -288,8 +303,18 @@ void build_backward(Builder& b) {
       id_trev[ix2(i, k)] = b.add(TK_TREV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
     const int32_t sb = Builder::cdiv(b.tile_size(k), b.s.gemm_m);
     for (int32_t i = k + 1; i < T; ++i) id_dpart[ix2(i, k)] = b.add(TK_DPART, i, k, k, sb * (sb + 1) / 2);
-    if (k + 1 < T) id_dred[k] = b.add(TK_DRED, k, k, k, Builder::cdiv(b.tile_size(k), 16));
-    id_prev[k] = b.add(TK_PREV, k, k, k, 1);
+    const int64_t m = b.tile_size(k);
+    if (closed_form_tile(m)) {
+      const int32_t nbk = Builder::cdiv(m, TCHOL_PRB), blocks = nbk * (nbk + 1) / 2;
+      id_inv[k] = b.add(TK_TRTRI, k, k, k, Builder::cdiv(m, b.s.trsm_rows));
+      id_dred[k] = b.add(TK_DRED, k, k, k, Builder::cdiv(m, 16));
+      id_pm[k] = b.add(TK_PADJM, k, k, k, blocks);
+      id_py[k] = b.add(TK_PADJY, k, k, k, blocks);
+      id_prev[k] = b.add(TK_PADJS, k, k, k, blocks);  // the task that produces Q_kk
+    } else {
+      if (k + 1 < T) id_dred[k] = b.add(TK_DRED, k, k, k, Builder::cdiv(m, 16));
+      id_prev[k] = b.add(TK_PREV, k, k, k, 1);
+    }
   }
   auto producer = [&](int32_t i, int32_t j) {
     return j < i ? id_trev[ix2(i, j)] : (j == i ? id_prev[i] : id_trev[ix2(j, i)]);
@@ -304,7 +329,14 @@ void build_backward(Builder& b) {
       succ[id_trev[ix2(i, k)]].push_back(id_dpart[ix2(i, k)]);
       succ[id_dpart[ix2(i, k)]].push_back(id_dred[k]);
     }
-    if (k + 1 < T) succ[id_dred[k]].push_back(id_prev[k]);
+    if (id_pm[k] >= 0) {
+      succ[id_dred[k]].push_back(id_pm[k]);
+      succ[id_pm[k]].push_back(id_py[k]);
+      succ[id_inv[k]].push_back(id_py[k]);
+      succ[id_py[k]].push_back(id_prev[k]);
+    } else if (id_dred[k] >= 0) {
+      succ[id_dred[k]].push_back(id_prev[k]);
+    }
   }
 }
 
@@ -315,14 +347,14 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   int32_t kind = p.kind[t], step = p.tk[t];
   if (kind == TK_BTRSV || kind == TK_BGEMV) step = T + (T - 1 - p.tk[t]);
   if (p.op == TCHOL_OP_BATCHED && kind >= TK_FTRSV && kind <= TK_BGEMV) step += T;  // a system's solve after its factor
-  const bool adjoint = kind == TK_GREV || kind == TK_TREV || kind == TK_DPART || kind == TK_PREV || kind == TK_DRED;
+  const bool adjoint = p.op == TCHOL_OP_BACKWARD;
   if (adjoint) step = T - 1 - p.tk[t];  // the adjoint runs its steps downwards
   int32_t kord = kind;
   if (kind == TK_GEMM2) {  // a double update belongs to the step of its second update
     step = p.tk[t] + 1;
     kord = TK_GEMM;
   }
-  if (kind == TK_TRTRI && p.op != OP_FACTOR_INV) {  // the FP64 solve's inverses: first in their step
+  if (kind == TK_TRTRI && p.op != OP_FACTOR_INV) {  // the FP64 solve's (the adjoint's) inverses: first in their step
     if (p.op == TCHOL_OP_BATCHED) step += T;
     kord = -1;
   }
@@ -335,7 +367,9 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   if (kind == TK_TREV) kord = 1;
   if (kind == TK_DPART) kord = 2;
   if (kind == TK_DRED) kord = 3;
-  if (kind == TK_PREV) kord = 4;
+  if (kind == TK_PREV || kind == TK_PADJM) kord = 4;
+  if (kind == TK_PADJY) kord = 5;
+  if (kind == TK_PADJS) kord = 6;
   // the chain of GREV(i, k, j) into Lbar_ik runs j downwards
   const int32_t tj = kind == TK_GREV ? T - 1 - p.tj[t] : p.tj[t];
   return std::make_tuple(p.sys[t], step, kord, p.ti[t], tj);

@@ -410,9 +410,10 @@ int32_t batched_systems(const int64_t* a_off, const int32_t* lda, const int64_t*
 // Adjoint: workspace regions (byte offsets).  LT (the transposed factor) and
 // Q (twice the symmetric adjoint) are np x np with np = n rounded up to 16
 // and ldq = np, zero past the order; the partial-product slots hold
-// T (T - 1) / 2 tiles of nb x nb.
+// T (T - 1) / 2 tiles of nb x nb; the diagonal tiles' inverses L_kk^{-T}
+// and the closed-form adjoint's two scratch tiles per diagonal tile follow.
 struct BackLayout {
-  int64_t np = 0, ldq = 0, lt = 0, q = 0, slots = 0, sched = 0, end = 0;
+  int64_t np = 0, ldq = 0, lt = 0, q = 0, slots = 0, inv = 0, scr = 0, sched = 0, end = 0;
 };
 
 BackLayout back_layout(int64_t n, int64_t nb, const Plan& p) {
@@ -423,7 +424,10 @@ BackLayout back_layout(int64_t n, int64_t nb, const Plan& p) {
   B.lt = 0;
   B.q = align_up(B.lt + 8 * B.ldq * B.np);
   B.slots = align_up(B.q + 8 * B.ldq * B.np);
-  B.sched = align_up(B.slots + 8 * (T * (T - 1) / 2) * nb * nb);
+  // the closed-form tile adjoints: L_kk^{-T}, then two scratch tiles, per diagonal tile
+  B.inv = align_up(B.slots + 8 * (T * (T - 1) / 2) * nb * nb);
+  B.scr = align_up(B.inv + 8 * T * nb * nb);
+  B.sched = align_up(B.scr + 8 * 2 * T * nb * nb);
   B.end = B.sched + layout_of(p).end;
   return B;
 }
@@ -622,7 +626,8 @@ int32_t tchol_backward_ex(const double* L, int64_t n, int64_t nb, double* Lbar, 
   if (tchol_dev_backward_prep(L, n, LT, Q, B.ldq, B.np, reinterpret_cast<hipStream_t>(stream_v)) != hipSuccess)
     return TCHOL_E_HIP;
   return execute(*plan, *img, const_cast<double*>(L), Lbar, 0, true, false, w + B.sched, ws_bytes - B.sched,
-                 stream_v, o, 5, nullptr, slots, 3, Q, LT, B.ldq);
+                 stream_v, o, 5, nullptr, slots, 3, Q, LT, B.ldq, reinterpret_cast<double*>(w + B.scr),
+                 reinterpret_cast<double*>(w + B.inv));
 }
 
 int32_t tchol_backward(const double* L, int64_t n, int64_t nb, double* Lbar, void* ws, int64_t ws_bytes,

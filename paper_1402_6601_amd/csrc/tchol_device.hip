@@ -1761,9 +1761,12 @@ __device__ __forceinline__ int potrf_tile_mixed(double* __restrict__ Dk, int64_t
 // the tile's partial products added, slot by slot in a fixed order (each slot
 // holds -tril(P_ik^T L_ik), nb x nb at stride slot_stride, ld ldslot; only
 // the lower triangle is read and written).  Eight entries per thread and
-// four slots per round keep 32 loads in flight.
+// four slots per round keep 32 loads in flight.  With LbT set, the strip's
+// rows also go transposed into columns [r0, r0 + 16) of LbT (ld ldt), zero
+// below the diagonal: Lbar_kk^T for the closed-form tile adjoint.
 __device__ __forceinline__ void dred_strip(double* __restrict__ Bkk, int64_t ld, const double* __restrict__ slots,
-                                           int64_t slot_stride, int nslots, int64_t ldslot, int m, int r0) {
+                                           int64_t slot_stride, int nslots, int64_t ldslot, int m, int r0,
+                                           double* __restrict__ LbT = nullptr, int64_t ldt = 0) {
   const int tid = threadIdx.x;
   const int ncol = imin(r0 + 16, m);          // columns that hold lower entries of these rows
   const int tot = 16 * ncol;                  // (row, column) pairs, rows fastest
@@ -1791,7 +1794,18 @@ __device__ __forceinline__ void dred_strip(double* __restrict__ Bkk, int64_t ld,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = base + u * NT + tid, c = idx >> 4, r = r0 + (idx & 15);
-      if (idx < tot && r < m && r >= c) st_dev(Bkk + (int64_t)c * ld + r, v[u]);
+      if (idx < tot && r < m && r >= c) {
+        st_dev(Bkk + (int64_t)c * ld + r, v[u]);
+        if (LbT) st_dev(LbT + (int64_t)r * ldt + c, v[u]);
+      }
+      if (LbT && idx < tot && r < m && r < c) st_dev(LbT + (int64_t)r * ldt + c, 0.0);
+    }
+  }
+  if (LbT) {  // the transposed rows below the strip's columns: zero
+    const int rows = imin(r0 + 16, m) - r0, below = m - ncol;
+    for (int idx = tid; idx < rows * below; idx += NT) {
+      const int rr = idx / below, c = ncol + idx - rr * below;
+      st_dev(LbT + (int64_t)(r0 + rr) * ldt + c, 0.0);
     }
   }
 }
@@ -1949,6 +1963,113 @@ __device__ __forceinline__ void prev_tile(const double* __restrict__ Lkk, const 
     }
     wait_vmcnt<0>();
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of a diagonal tile in closed form.  For the tile factorization
+// L_kk L_kk^T = A_kk and the adjoint Lbar_kk of its factor (after the
+// partial products of its column), the adjoint with respect to the tile is
+// the symmetric matrix S / 2 with
+//     S = L^{-T} (M + M^T) L^{-1} = L^{-T} Y + Y^T L^{-1},   Y = M L^{-1},
+// M = Phi(L^T Lbar) (Phi: the lower triangle with its diagonal halved); in
+// lower-parameter form P_kk = tril(S) - diag(S) / 2, so Q_kk = S, and the
+// output over Lbar_kk is tril(S) / 2.
+// This is the panel recursion of the tile's adjoint summed in closed form
+// (the same linear map; only the rounding differs), and it turns the long
+// chain of 16-column panels into three products over TCHOL_PRB-order blocks
+// that many workgroups share:
+//   PADJM: Mn = -M by lower blocks, from LT (L^T) and Lbar_kk^T (which
+//          DRED(k) leaves in the Q_kk tile)
+//   PADJY: Y^T = L^{-T} Mn^T negated, i.e. (M L^{-1})^T, by upper blocks
+//   PADJS: S by lower blocks, stored to Q_kk in both orientations and,
+//          halved, to the lower triangle of Lbar_kk
+// L^{-T} comes from TRTRI(k) (upper triangular, exact zeros below).  Every
+// product is C = -A B^T from a zero start (the matrix cores' primitive);
+// the negated M absorbs the first sign, the second cancels it, and the
+// third is undone at the store.  Zero regions: the products' K ranges
+// skip the blocks that vanish by triangularity, and inside the diagonal
+// blocks the stored zeros (of Mn above its diagonal, of L^{-T} below, of
+// Lbar^T below) make the rest exact.
+#define PRB TCHOL_PRB
+
+// C = -(A0 B0^T [+ A1 B1^T]) for one PRB x PRB block (M, N <= PRB, K a multiple
+// of 16, all four panels at ld); epi(row, col, value) stores each entry.
+template <class Epi>
+__device__ __forceinline__ void padj_block(const double* A0, const double* B0, const double* A1, const double* B1,
+                                           int64_t ld, int M, int N, int K, double* lds, Epi epi) {
+  using S = GemmShape<PRB, PRB, 16, 2, 4, 0>;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / S::WGN, wn = wave % S::WGN;
+  const int l16 = lane & 15, lg = lane >> 4;
+  d4 acc[S::RB][S::CB];
+#pragma unroll
+  for (int rb = 0; rb < S::RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < S::CB; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+  gemm_kloop<PRB, PRB, 16, 2, 4, 0, 128>(acc, A0, B0, ld, M, N, K, lds);
+  if (A1 != nullptr) {
+    __syncthreads();  // the stages are refilled only after every wavefront's last reads
+    gemm_kloop<PRB, PRB, 16, 2, 4, 0, 128>(acc, A1, B1, ld, M, N, K, lds);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < S::RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < S::CB; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
+        if (row < M && col < N) epi(row, col, acc[rb][cb][i]);
+      }
+}
+
+// Block (bi, bj), bi >= bj, of the lower triangle from a work item's part.
+__device__ __forceinline__ void lower_block(int part, int& bi, int& bj) {
+  bi = 0;
+  while ((bi + 1) * (bi + 2) / 2 <= part) ++bi;
+  bj = part - bi * (bi + 1) / 2;
+}
+
+// One work item of PADJM / PADJY / PADJS on tile k of order m (a multiple of
+// 16).  LTkk, Qkk: the tile of L^T and of Q (ld ldq); Bkk: Lbar_kk (ld);
+// IT: L_kk^{-T}, Mn and YT: the tile's scratch blocks (ld nb).
+__device__ __forceinline__ void padj_item(int kind, int part, int m, const double* __restrict__ LTkk,
+                                          double* __restrict__ Qkk, int64_t ldq, double* __restrict__ Bkk, int64_t ld,
+                                          const double* __restrict__ IT, double* __restrict__ Mn,
+                                          double* __restrict__ YT, int64_t nb, double* lds) {
+  int bi, bj;
+  lower_block(part, bi, bj);
+  const int i0 = bi * PRB, j0 = bj * PRB;
+  const int Mi = imin(PRB, m - i0), Nj = imin(PRB, m - j0);
+  if (kind == TK_PADJM) {
+    // Mn(i, j) = -sum_{t >= i} L^T(i, t) Lbar^T(j, t), diagonal halved, zero above it
+    padj_block(LTkk + (int64_t)i0 * ldq + i0, Qkk + (int64_t)i0 * ldq + j0, nullptr, nullptr, ldq, Mi, Nj, m - i0,
+               lds, [&](int r, int c, double v) __attribute__((always_inline)) {
+                 if (bi == bj) v = r > c ? v : (r == c ? 0.5 * v : 0.0);
+                 st_dev(Mn + (int64_t)(j0 + c) * nb + i0 + r, v);
+               });
+  } else if (kind == TK_PADJY) {
+    // Y^T(j, i) = -sum_{j <= t <= i} L^{-T}(j, t) Mn(i, t), the block of rows j0 and columns i0
+    const int kend = imin(i0 + PRB, m);
+    padj_block(IT + (int64_t)j0 * nb + j0, Mn + (int64_t)j0 * nb + i0, nullptr, nullptr, nb, Nj, Mi, kend - j0, lds,
+               [&](int r, int c, double v) __attribute__((always_inline)) {
+                 st_dev(YT + (int64_t)(i0 + c) * nb + j0 + r, v);
+               });
+  } else {
+    // S(i, j) = sum_{t >= i} L^{-T}(i, t) Y^T(j, t) + Y^T(i, t) L^{-T}(j, t), lower entries
+    padj_block(IT + (int64_t)i0 * nb + i0, YT + (int64_t)i0 * nb + j0, YT + (int64_t)i0 * nb + i0,
+               IT + (int64_t)i0 * nb + j0, nb, Mi, Nj, m - i0, lds,
+               [&](int r, int c, double v) __attribute__((always_inline)) {
+                 const int i = i0 + r, j = j0 + c;
+                 if (i >= j) {
+                   const double s = -v;
+                   st_dev(Qkk + (int64_t)j * ldq + i, s);
+                   st_dev(Qkk + (int64_t)i * ldq + j, s);
+                   st_dev(Bkk + (int64_t)j * ld + i, 0.5 * s);
+                 }
+               });
   }
 }
 
@@ -2532,14 +2653,14 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         break;
       }
       case TK_TRTRI: {
-        if constexpr (MODE != 0 && MODE != 1 && MODE != 5) {
+        if constexpr (MODE != 0 && MODE != 1 && MODE != 3 && MODE != 5) {
           ok = 0;
         } else {
           // L_kk^{-T} by 32-row strips: identity rows solved in place (into DinvT, ld nb).
           // The mixed-precision factorization reads its FP64 diagonal tile,
           // identity-padded when ragged, and also stores the transposes as
-          // L_kk^{-1} (Dinv); the FP64 solve reads L_kk in A (its order is then a
-          // multiple of 16) and keeps L_kk^{-T} only.
+          // L_kk^{-1} (Dinv); the FP64 solve and the adjoint read L_kk in A (its
+          // order is then a multiple of 16) and keep L_kk^{-T} only.
           const int mpad = (tsz(tk) + 15) & ~15;
           const int r0 = part * a.trsm_rows;
           const int S = imin(a.trsm_rows, mpad - r0);
@@ -2550,7 +2671,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           }
           wait_vmcnt<0>();
           __syncthreads();
-          if constexpr (MODE == 0)
+          if constexpr (MODE == 0 || MODE == 3)  // the adjoint: L (its A) is the factor
             trsm_strip<double>(X, nb, Abase + (tk * nb) * ld + tk * nb, ld, S, mpad, lds);
           else
             trsm_strip<double, 2>(X, nb, Dsys + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,
@@ -2562,7 +2683,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
       case TK_TREV:
       case TK_DPART:
       case TK_DRED:
-      case TK_PREV: {
+      case TK_PREV:
+      case TK_PADJM:
+      case TK_PADJY:
+      case TK_PADJS: {
         if constexpr (!ADJOINT_KINDS) {
           ok = 0;
         } else {
@@ -2606,8 +2730,18 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
                        a.Q + (ti * nb) * ldq + tk * nb + si * a.gemm_m, a.LT + (ti * nb) * ldq + tk * nb + sj * a.gemm_n,
                        ldq, M, N, K, si == sj, true, lds);
           } else if (kind == TK_DRED) {
+            // a tile whose order is a multiple of 16 takes the closed-form adjoint,
+            // which reads Lbar_kk^T from the Q_kk tile
+            const bool closed = (tsz(tk) & 15) == 0;
             dred_strip(Bbase + (tk * nb) * ld + tk * nb, ld, a.D + slot(tk + 1, tk) * nb * nb, nb * nb, T - 1 - tk, nb,
-                       tsz(tk), part * 16);
+                       tsz(tk), part * 16, closed ? a.Q + (tk * nb) * ldq + tk * nb : nullptr, ldq);
+          } else if (kind != TK_PREV) {
+            // the closed-form tile adjoint: L_kk^{-T} in DinvT, two scratch
+            // blocks (Mn, Y^T) per diagonal tile in Dinv
+            const int64_t nb2 = nb * nb;
+            padj_item(kind, part, tsz(tk), a.LT + (tk * nb) * ldq + tk * nb, a.Q + (tk * nb) * ldq + tk * nb, ldq,
+                      Bbase + (tk * nb) * ld + tk * nb, ld, DinvTSys + tk * nb2, DinvSys + 2 * tk * nb2,
+                      DinvSys + (2 * tk + 1) * nb2, nb, lds);
           } else {
             // the partial products were applied by DRED(k)
             prev_tile(Abase + (tk * nb) * ld + tk * nb, a.LT + (tk * nb) * ldq + tk * nb,

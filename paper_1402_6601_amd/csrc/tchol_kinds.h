@@ -24,5 +24,12 @@
 #define TK_DRED  13  /* Lbar_kk += sum_i S_ik (i ascending)                  */
 /* factorization: two consecutive updates of one tile in one task (K = 2 nb) */
 #define TK_GEMM2 14  /* A_ij <- A_ij - L_ik L_jk^T - L_i,k+1 L_j,k+1^T        */
-#define TK_NKINDS 15
+/* adjoint: the diagonal tile's adjoint in closed form (tiles whose order is a
+   multiple of 16; others take TK_PREV), three products over TCHOL_PRB x TCHOL_PRB
+   blocks, with L_kk^{-T} from TK_TRTRI and Lbar_kk^T (written by TK_DRED into Q_kk) */
+#define TK_PADJM 15  /* M_k = Phi(L_kk^T Lbar_kk), lower blocks, stored negated  */
+#define TK_PADJY 16  /* Y_k^T = L_kk^{-T} M_k^T, upper blocks                    */
+#define TK_PADJS 17  /* Q_kk = L_kk^{-T} Y_k + Y_k^T L_kk^{-1}, Lbar_kk = tril(Q_kk)/2 */
+#define TK_NKINDS 18
+#define TCHOL_PRB 64  /* block order of the TK_PADJ* products                      */
 #endif

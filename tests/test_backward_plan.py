@@ -6,6 +6,13 @@ The reverse program, per step k from T-1 down to 0,
     DPART(i, k)    S_ik = tril(P_ik^T L_ik)
     DRED(k)        Lbar_kk -= sum_i S_ik     (k < T-1)
     PREV(k)        P_kk (writes Q_kk)
+and, for a diagonal tile whose order is a multiple of 16, the closed form
+in place of PREV(k):
+    TRTRI(k)       L_kk^{-T}
+    DRED(k)        also for k = T-1; leaves Lbar_kk^T in the Q_kk tile
+    PADJM(k)       M = Phi(L_kk^T Lbar_kk)    (reads Lbar_kk^T)
+    PADJY(k)       Y^T = (M L_kk^{-1})^T
+    PADJS(k)       Q_kk = S, Lbar_kk = tril(S) / 2
 is replayed in program order with its data (Lbar tiles, the P tile behind
 each Q tile, the partial products S) and every read-after-write,
 write-after-read and write-after-write conflict becomes an edge (section 2,
@@ -21,8 +28,14 @@ import pytest
 
 tc = pytest.importorskip("paper_1402_6601_amd")
 
-GREV, TREV, DPART, PREV, DRED = 8, 9, 10, 11, 13
-WEIGHT = {GREV: 6, TREV: 3, DPART: 3, PREV: 4, DRED: 1}
+GREV, TREV, DPART, PREV, TRTRI, DRED, PADJM, PADJY, PADJS = 8, 9, 10, 11, 12, 13, 15, 16, 17
+WEIGHT = {GREV: 6, TREV: 3, DPART: 3, PREV: 4, TRTRI: 40, DRED: 1, PADJM: 1, PADJY: 1, PADJS: 2}
+PRB = 64
+
+
+def closed(m):
+    """The diagonal tile of order m takes the closed-form adjoint."""
+    return m % 16 == 0
 
 
 def bplan(n, nb, policy=0, seed=0):
@@ -53,7 +66,9 @@ def reduce_transitively(edges):
     return {(a, b) for (a, b) in edges if not reachable(a, b)}
 
 
-def dataflow_edges(T):
+def dataflow_edges(n, nb):
+    T = -(-n // nb)
+    tsz = lambda t: min(nb, n - nb * t)
     last_writer, readers = {}, collections.defaultdict(set)
     out = set()
 
@@ -84,9 +99,19 @@ def dataflow_edges(T):
             access((TREV, i, k, k), [("Lbar", i, k)], [("Lbar", i, k), ("P", i, k)])
         for i in range(k + 1, T):
             access((DPART, i, k, k), [("P", i, k)], [("S", i, k)])
-        if k + 1 < T:
-            access((DRED, k, k, k), [("S", i, k) for i in range(k + 1, T)] + [("Lbar", k, k)], [("Lbar", k, k)])
-        access((PREV, k, k, k), [("Lbar", k, k)], [("Lbar", k, k), ("P", k, k)])
+        if closed(tsz(k)):
+            access((TRTRI, k, k, k), [], [("IT", k)])
+            # Lbar_kk^T goes into the storage of the P tile behind Q_kk
+            access((DRED, k, k, k), [("S", i, k) for i in range(k + 1, T)] + [("Lbar", k, k)],
+                   [("Lbar", k, k), ("P", k, k)])
+            access((PADJM, k, k, k), [("P", k, k)], [("M", k)])
+            access((PADJY, k, k, k), [("M", k), ("IT", k)], [("Y", k)])
+            access((PADJS, k, k, k), [("Y", k), ("IT", k)], [("Lbar", k, k), ("P", k, k)])
+        else:
+            if k + 1 < T:
+                access((DRED, k, k, k), [("S", i, k) for i in range(k + 1, T)] + [("Lbar", k, k)],
+                       [("Lbar", k, k)])
+            access((PREV, k, k, k), [("Lbar", k, k)], [("Lbar", k, k), ("P", k, k)])
     return reduce_transitively(out)
 
 
@@ -94,7 +119,8 @@ def key(p, t):
     return (int(p["kind"][t]), int(p["i"][t]), int(p["j"][t]), int(p["k"][t]))
 
 
-@pytest.mark.parametrize("n,nb", [(16, 16), (40, 16), (100, 16), (130, 32), (512, 128), (1000, 256)])
+@pytest.mark.parametrize("n,nb", [(16, 16), (40, 16), (100, 16), (130, 32), (512, 128), (1000, 256), (200, 160),
+                                  (600, 256)])
 def test_backward_edges_equal_dataflow(n, nb):
     p = bplan(n, nb)
     T = -(-n // nb)
@@ -102,9 +128,11 @@ def test_backward_edges_equal_dataflow(n, nb):
     for t in range(p["ntask"]):
         for e in range(p["succ_off"][t], p["succ_off"][t + 1]):
             edges.add((key(p, t), key(p, int(p["succ"][e]))))
-    assert reduce_transitively(edges) == dataflow_edges(T)
+    assert reduce_transitively(edges) == dataflow_edges(n, nb)
     cnt = collections.Counter(int(x) for x in p["kind"])
-    assert cnt[PREV] == T and cnt[DRED] == T - 1
+    ragged = int(not closed(n - nb * (T - 1)))   # only the last tile can be ragged
+    assert cnt[PREV] == ragged and cnt[PADJM] == cnt[PADJY] == cnt[PADJS] == cnt[TRTRI] == T - ragged
+    assert cnt[DRED] == T - ragged
     assert cnt[TREV] == cnt[DPART] == T * (T - 1) // 2
     assert cnt[GREV] == sum((T - k - 1) ** 2 for k in range(T))
 
@@ -130,11 +158,15 @@ def test_backward_ranks_and_parts():
     tsz = lambda i: min(256, 600 - 256 * i)
     for t in range(p["ntask"]):
         kind, i, k = int(p["kind"][t]), int(p["i"][t]), int(p["k"][t])
+        tri = lambda s: s * (s + 1) // 2
         want = {GREV: -(-tsz(i) // 128) * -(-tsz(k) // 128), TREV: -(-tsz(i) // 32),
-                DPART: (lambda s: s * (s + 1) // 2)(-(-tsz(k) // 128)), PREV: 1, DRED: -(-tsz(k) // 16)}[kind]
+                DPART: tri(-(-tsz(k) // 128)), PREV: 1, DRED: -(-tsz(k) // 16), TRTRI: -(-tsz(k) // 32),
+                PADJM: tri(-(-tsz(k) // PRB)), PADJY: tri(-(-tsz(k) // PRB)), PADJS: tri(-(-tsz(k) // PRB))}[kind]
         assert p["parts"][t] == want
-    # the first task claimed is the adjoint of the last diagonal tile
-    assert int(p["kind"][p["item_task"][0]]) == PREV and int(p["k"][p["item_task"][0]]) == 2
+    # the inverses have no predecessors and a large weight: the first task
+    # claimed is the inverse of the last diagonal tile that takes the closed
+    # form (tile 1; the last tile, of order 88, is ragged)
+    assert int(p["kind"][p["item_task"][0]]) == TRTRI and int(p["k"][p["item_task"][0]]) == 1
 
 
 def test_backward_workspace_and_limits():
