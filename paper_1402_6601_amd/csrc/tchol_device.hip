@@ -99,6 +99,11 @@ constexpr int imin_c(int a, int b) { return a < b ? a : b; }
 // their loads here).  A value loaded only to be used under a condition would
 // otherwise have its load moved under that condition, one load and one wait
 // per value; issued unconditionally before this point, the loads overlap.
+template <int C>
+__device__ __forceinline__ void materialize(double (&v)[C]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) asm volatile("" : : "v"(v[c]));
+}
 template <int R, int C>
 __device__ __forceinline__ void materialize(double (&v)[R][C]) {
 #pragma unroll
@@ -801,211 +806,109 @@ __device__ __forceinline__ void gemm_bf16x6_wide(float* __restrict__ C, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// POTRF work item: Akk (m x m, m <= 512) := chol(Akk), lower, in place.
-// Left-looking by panels of PW = 16 columns; a panel stays in LDS from its
-// update to its store:
-//  1. the matrix cores apply every earlier column to the panel (gemm_core in
-//     slabs of 256 rows, result written to LDS);
-//  2. one wavefront factors the panel's 16 x 16 diagonal block in registers:
-//     lane r holds row r, the pivot and the column entries it needs are
-//     broadcast across lanes (readlane), so no barrier is needed;
-//  3. every thread solves one row below the block against it (forward
-//     substitution, the block and its reciprocal pivots in LDS);
-//  4. the finished panel is written to the tile once.
-// Returns 0, or the 1-based column (within the tile) whose pivot is not
-// positive (zero, negative or NaN).
+// Panel constants of the diagonal tile's adjoint (panels of PW columns).
 #define PW 16
 #define PPLD 516                              // LDS leading dimension of the panel
 #define P_STAGE_DOUBLES (272 * 8 * 4)         // stages of gemm_core<SEG, 256, 16, 8, 4, 4, 0>
-
-template <int SEG>
-__device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double* Ps = lds + P_STAGE_DOUBLES;              // [PW][PPLD] the panel
-  double* Ldd = Ps + PW * PPLD;                     // [PW][PW + 1] its diagonal block
-  double* Linv = Ldd + PW * (PW + 1);               // [PW] reciprocal pivots
-  __shared__ int s_info;
-  for (int c0 = 0; c0 < m; c0 += PW) {
-    const int w = imin(PW, m - c0);
-    const int R = m - c0;
-    double* P = Akk + (int64_t)c0 * ld + c0;
-    if (c0 > 0) {
-      // P - L[c0:, 0:c0] L[c0:c0+w, 0:c0]^T into LDS, in (at most two) slabs of 256 rows
-      for (int s0 = 0; s0 < R; s0 += 256) {
-        gemm_core<SEG, 256, PW, 8, 4, 4, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, imin(256, R - s0), w, c0, false, lds,
-                                    Ps + s0, PPLD);
-        __syncthreads();
-      }
-    } else {
-      for (int c = 0; c < w; ++c)
-        for (int r = tid; r < R; r += NT) Ps[c * PPLD + r] = P[(int64_t)c * ld + r];
-      __syncthreads();
-    }
-    if (wave == 0) {
-      // Lane r holds row r of the block.  Rows and columns past w are padded
-      // with the identity, so every loop below has a fixed trip count (the
-      // code is fully unrolled and x stays in registers).
-      double x[PW];
-      const int r = imin(lane, w - 1);
-      // every load is issued before any is used (kept out of the selects below)
-      double v[PW];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) {
-        v[c] = Ps[imin(c, w - 1) * PPLD + r];
-        asm volatile("" : "+v"(v[c]));
-      }
-#pragma unroll
-      for (int c = 0; c < PW; ++c)
-        x[c] = (lane < w) ? (((c <= lane) & (c < w)) ? v[c] : 0.0) : (c == lane ? 1.0 : 0.0);
-      int info = 0;
-      double pinv[PW];  // the pivots' reciprocals, also used for the rows below the block
-#pragma unroll
-      for (int cc = 0; cc < PW; ++cc) {
-        const double d = readlane_f64(x[cc], cc);
-        // the first column whose pivot is not positive; the arithmetic goes on
-        // (its results are discarded when info != 0)
-        info = (info == 0 && !(d > 0.0)) ? c0 + cc + 1 : info;
-        // l = sqrt(d) and 1/l from the hardware reciprocal square root and two
-        // Newton steps (y to about an ulp; then l = d y with one residual
-        // correction), a far shorter dependent chain than a correctly rounded
-        // square root and division; exact for powers of four.  Tiny (and
-        // non-positive) pivots take the correctly rounded path.
-        double l, inv;
-        if (d >= 0x1p-900) {
-          double y = __builtin_amdgcn_rsq(d);
-          y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
-          y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
-          l = d * y;
-          l = fma(fma(-l, l, d), 0.5 * y, l);
-          inv = y;
-        } else {
-          l = sqrt(d);
-          inv = 1.0 / l;
-        }
-        pinv[cc] = inv;
-        x[cc] = (lane == cc) ? l : ((lane > cc) ? x[cc] * inv : x[cc]);
-#pragma unroll
-        for (int c2 = cc + 1; c2 < PW; ++c2) {
-          const double v = readlane_f64(x[cc], c2);
-          x[c2] = (lane >= c2) ? x[c2] - x[cc] * v : x[c2];
-        }
-      }
-      if (lane == 0) s_info = info;
-      if (lane < w) {
-#pragma unroll
-        for (int c = 0; c < PW; ++c)
-          if (c <= lane) Ps[c * PPLD + lane] = x[c];
-      }
-      if (lane < PW) {
-#pragma unroll
-        for (int c = 0; c < PW; ++c) Ldd[lane * (PW + 1) + c] = (c <= lane) ? x[c] : 0.0;
-        double li = pinv[0];
-#pragma unroll
-        for (int c = 1; c < PW; ++c) li = (lane == c) ? pinv[c] : li;
-        Linv[lane] = li;
-      }
-    }
-    __syncthreads();
-    const int info = __builtin_amdgcn_readfirstlane(s_info);
-    if (info != 0) return info;
-    // rows below the diagonal block: y := y L_dd^{-T}, one row per thread
-    // and pass, column by column (right-looking); columns past w see the
-    // identity padding of Ldd
-#pragma unroll 1
-    for (int r = w + tid; r < R; r += NT) {
-      double y[PW];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) y[c] = Ps[c * PPLD + r];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) {
-        y[c] *= Linv[c];
-#pragma unroll
-        for (int c2 = c + 1; c2 < PW; ++c2) y[c2] -= y[c] * Ldd[c2 * (PW + 1) + c];
-      }
-#pragma unroll
-      for (int c = 0; c < PW; ++c) Ps[c * PPLD + r] = y[c];
-    }
-    __syncthreads();
-    // the finished panel (lower part) to the tile, then make it visible to
-    // every wavefront before the next panel's update reads it
-    for (int c = 0; c < w; ++c)
-      for (int r = c + tid; r < R; r += NT) st_dev(P + (int64_t)c * ld + r, Ps[c * PPLD + r]);
-    wait_vmcnt<0>();
-    __syncthreads();
-  }
-  return 0;
-}
 
 // ---------------------------------------------------------------------------
 // POTRF of a tile of order m <= 128 held in LDS for the whole factorization:
 // loaded once, factored right-looking by 16-column panels, stored once.  Per
 // panel: the 16 x 16 diagonal block is factored on wavefront 0 in registers
-// (as in potrf_tile), every thread solves one row below it, and the trailing
+// (diag16_x), every thread solves one row below it, and the trailing
 // lower blocks take the panel's update on the matrix cores (16 x 16 blocks,
 // K = 16); wavefront 0 updates and factors the next diagonal block first,
-// while the other wavefronts update the rest.  Each element receives the
-// same sequence of matrix-core updates in the same order as in potrf_tile,
-// so the two agree bit for bit.  Returns 0, or the 1-based column (within
-// the tile) whose pivot is not positive.
+// while the other wavefronts update the rest.  Returns 0, or the 1-based
+// column (within the tile) whose pivot is not positive.
 #define SLD 132   // LDS leading dimension of the resident tile
 
-// Factors the diagonal block at column c0 (width w) of the resident tile As
-// on one wavefront: lane r holds row r; pivots and column entries are
-// broadcast across lanes.  Writes L_dd back, a copy to Ldd[r][c] and the
-// reciprocal pivots to Linv.  Returns info (0 or the 1-based tile column).
-__device__ __forceinline__ int diag16_lds(double* As, int c0, int w, double* Ldd, double* Linv, int lane) {
+// Factors the 16 x 16 (w x w, rows and columns past w padded with the
+// identity) diagonal block at (off, off) of an LDS matrix X (leading
+// dimension LDX) on one wavefront: lane r holds row r in registers, the
+// pivot and the column entries are broadcast across lanes (readlane), so no
+// barrier is needed.  With extra > 0, lanes 16 .. 16 + extra - 1 hold the
+// rows off + 16 .. below the block, which the same steps solve against it
+// (X := X L_dd^{-T}) at no extra cost.  l = sqrt(d) and 1/l come from the
+// hardware reciprocal square root and two Newton steps (y to about an ulp;
+// then l = d y with one residual correction), a far shorter dependent chain
+// than a correctly rounded square root and division, and exact for powers
+// of four; pivots below 2^-900 are scaled by 2^1000 first (exactly), and
+// the results back.  No step branches, so the updates of one column overlap
+// the next pivot's chain.  Writes L_dd back (and the solved rows below), a
+// copy to Ldd[r * LDD + c] (r < 16 + extra) and the reciprocal pivots to
+// Linv.  Returns 0, or ibase + the 1-based column of the first pivot that
+// is not positive (zero, negative or NaN; the arithmetic goes on and its
+// results are discarded).
+template <int LDX, int LDD>
+__device__ __forceinline__ int diag16_x(double* X, int off, int w, double* Ldd, double* Linv, int lane, int ibase,
+                                        int extra = 0) {
+  double* As = X;
+  const int c0 = off;
+  const bool below = lane >= PW && lane < PW + extra;  // a row below the block
   double x[PW];
-  const int r = imin(lane, w - 1);
+  const int r = below ? lane : imin(lane, w - 1);
+  // every load is issued before any is used (and kept out of the selects below)
   double v[PW];
 #pragma unroll
-  for (int c = 0; c < PW; ++c) {
-    v[c] = As[(c0 + imin(c, w - 1)) * SLD + c0 + r];
-    asm volatile("" : "+v"(v[c]));
-  }
+  for (int c = 0; c < PW; ++c) v[c] = As[(c0 + imin(c, w - 1)) * LDX + c0 + r];
+  materialize(v);
 #pragma unroll
   for (int c = 0; c < PW; ++c)
-    x[c] = (lane < w) ? (((c <= lane) & (c < w)) ? v[c] : 0.0) : (c == lane ? 1.0 : 0.0);
+    x[c] = below ? ((c < w) ? v[c] : 0.0)
+                 : ((lane < w) ? (((c <= lane) & (c < w)) ? v[c] : 0.0) : (c == lane ? 1.0 : 0.0));
   int info = 0;
   double pinv[PW];
 #pragma unroll
   for (int cc = 0; cc < PW; ++cc) {
     const double d = readlane_f64(x[cc], cc);
-    info = (info == 0 && !(d > 0.0)) ? c0 + cc + 1 : info;
-    double l, inv;
-    if (d >= 0x1p-900) {
-      double y = __builtin_amdgcn_rsq(d);
-      y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
-      y = fma(0.5 * y, fma(-d, y * y, 1.0), y);
-      l = d * y;
-      l = fma(fma(-l, l, d), 0.5 * y, l);
-      inv = y;
-    } else {
-      l = sqrt(d);
-      inv = 1.0 / l;
-    }
+    info = (info == 0 && !(d > 0.0)) ? ibase + cc + 1 : info;
+    const bool tiny = d < 0x1p-900;
+    const double ds = tiny ? d * 0x1p+1000 : d;
+    double y = __builtin_amdgcn_rsq(ds);
+    y = fma(0.5 * y, fma(-ds, y * y, 1.0), y);
+    y = fma(0.5 * y, fma(-ds, y * y, 1.0), y);
+    double l = ds * y;
+    l = fma(fma(-l, l, ds), 0.5 * y, l);
+    l = tiny ? l * 0x1p-500 : l;
+    const double inv = tiny ? y * 0x1p+500 : y;
     pinv[cc] = inv;
-    x[cc] = (lane == cc) ? l : ((lane > cc) ? x[cc] * inv : x[cc]);
+    // the scaled column is broadcast before the pivot itself is set, which
+    // keeps l off the chain to the next pivot; entries above the diagonal
+    // (lane < column) are updated too, without a select: they are never
+    // read, and the identity padding stays exact
+    const double sc = x[cc] * inv;
 #pragma unroll
     for (int c2 = cc + 1; c2 < PW; ++c2) {
-      const double vv = readlane_f64(x[cc], c2);
-      x[c2] = (lane >= c2) ? x[c2] - x[cc] * vv : x[c2];
+      const double vv = readlane_f64(sc, c2);
+      x[c2] -= sc * vv;
     }
+    x[cc] = (lane == cc) ? l : sc;
   }
   if (lane < w) {
 #pragma unroll
     for (int c = 0; c < PW; ++c)
-      if (c <= lane) As[(c0 + c) * SLD + c0 + lane] = x[c];
+      if (c <= lane) As[(c0 + c) * LDX + c0 + lane] = x[c];
+  }
+  if (below) {
+#pragma unroll
+    for (int c = 0; c < PW; ++c) {
+      As[(c0 + c) * LDX + c0 + lane] = x[c];
+      Ldd[lane * LDD + c] = x[c];
+    }
   }
   if (lane < PW) {
 #pragma unroll
-    for (int c = 0; c < PW; ++c) Ldd[lane * (PW + 1) + c] = (c <= lane) ? x[c] : 0.0;
+    for (int c = 0; c < PW; ++c) Ldd[lane * LDD + c] = (c <= lane) ? x[c] : 0.0;
     double li = pinv[0];
 #pragma unroll
     for (int c = 1; c < PW; ++c) li = (lane == c) ? pinv[c] : li;
     Linv[lane] = li;
   }
   return info;
+}
+
+__device__ __forceinline__ int diag16_lds(double* As, int c0, int w, double* Ldd, double* Linv, int lane) {
+  return diag16_x<SLD, PW + 1>(As, c0, w, Ldd, Linv, lane, c0);
 }
 
 // Block (bi, bj) of the resident tile -= P(bi) P(bj)^T, P the 16 columns of
@@ -1107,6 +1010,145 @@ __device__ __forceinline__ int potrf_small(double* __restrict__ Akk, int64_t ld,
   for (int idx = tid; idx < m * 128; idx += NT) {
     const int c = idx >> 7, r = idx & 127;
     if (r < m && r >= c) st_dev(Akk + (int64_t)c * ld + r, As[c * SLD + r]);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// POTRF work item for a tile of order m <= 512 on one workgroup:
+// Akk := chol(Akk), lower, in place.  Left-looking by panels of PT_W = 32
+// columns, each taken in slabs of up to PT_SLAB = 256 rows that stay in LDS
+// from their update to their store:
+//  1. the matrix cores apply every earlier column to the slab (256 x 32
+//     outputs per K step, the result written to LDS);
+//  2. in the first slab, wavefront 0 factors the 32 x 32 diagonal block: its
+//     leading 16 x 16 block in registers (diag16_x, which also solves the 16
+//     rows below it), their product subtracted from the trailing 16 x 16
+//     block on the matrix cores, then that block factored;
+//  3. every thread solves one row of the slab below the block against L_dd;
+//  4. the slab goes to the tile (write-through stores), where the next
+//     panel's update reads it.
+// Panels of 32 columns halve the number of panels and the re-reads of the
+// factored columns relative to the 16 of the diagonal blocks, and give the
+// updates enough outputs per K step to keep the matrix cores busy.
+// Returns 0, or the 1-based column (within the tile) whose pivot is not
+// positive (zero, negative or NaN).
+#define PT_W 32
+#define PT_SLAB 256
+#define PT_LD 264                              // LDS leading dimension of a slab
+#define PT_STAGE (2 * 16 * (PT_SLAB + PT_W))   // stages of gemm_core<SEG, 256, 32, 16, 4, 2, 0>
+#define PT_LT 36                               // stride of the columns of L_dd
+
+template <int SEG>
+__device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds) {
+  static_assert(PT_STAGE + PT_W * PT_LD + PT_W * (PT_W + 1) + PT_W + PT_W * PT_LT <= LDS_DOUBLES, "LDS budget");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double* Ps = lds + PT_STAGE;               // [PT_W][PT_LD] the slab
+  double* Ldd = Ps + PT_W * PT_LD;           // [PT_W][PT_W + 1] the diagonal block (lower)
+  double* Linv = Ldd + PT_W * (PT_W + 1);    // [PT_W] reciprocal pivots
+  double* LT = Linv + PT_W;                  // [PT_W][PT_LT] L_dd by columns
+  __shared__ int s_info;
+  for (int c0 = 0; c0 < m; c0 += PT_W) {
+    const int w = imin(PT_W, m - c0);
+    const int R = m - c0;
+    double* P = Akk + (int64_t)c0 * ld + c0;
+    for (int s0 = 0; s0 < R; s0 += PT_SLAB) {
+      const int S = imin(PT_SLAB, R - s0);
+      if (c0 > 0) {
+        // the slab - L[c0 + s0 :, 0 : c0] L[c0 : c0 + w, 0 : c0]^T into LDS,
+        // on a product no taller than the slab needs
+        if (S > 128)
+          gemm_core<SEG, 256, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, PT_LD);
+        else if (S > 64)
+          gemm_core<SEG, 128, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, PT_LD);
+        else
+          gemm_core<SEG, 64, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, PT_LD);
+      } else if (tid < S) {
+        double v[PT_W];
+#pragma unroll
+        for (int c = 0; c < PT_W; ++c) v[c] = P[(int64_t)imin(c, w - 1) * ld + s0 + tid];
+#pragma unroll
+        for (int c = 0; c < PT_W; ++c) Ps[c * PT_LD + tid] = v[c];
+      }
+      __syncthreads();
+      if (s0 == 0) {
+        if (wave == 0) {
+          // the leading 16 x 16 block, the rows 16 .. w-1 below it solved in the same steps
+          int info = diag16_x<PT_LD, PT_W + 1>(Ps, 0, imin(16, w), Ldd, Linv, lane, c0, imax(w - 16, 0));
+          if (w > 16) {
+            const int wb = w - 16;
+            // trailing block -= (those rows)(those rows)^T: element v of lane
+            // l is row 16 + 4v + l/16, column 16 + l%16 (rows and columns past
+            // w only meet each other and are never read)
+            {
+              const int l16 = lane & 15, lg = lane >> 4;
+              d4 acc;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[v] = Ps[(16 + l16) * PT_LD + 16 + 4 * v + lg];
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const double f = Ps[(4 * s + lg) * PT_LD + 16 + l16];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(f, f, acc, 0, 0, 2 /* neg B */);
+              }
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Ps[(16 + l16) * PT_LD + 16 + 4 * v + lg] = acc[v];
+            }
+            const int info_b =
+                diag16_x<PT_LD, PT_W + 1>(Ps, 16, wb, Ldd + 16 * (PT_W + 1) + 16, Linv + 16, lane, c0 + 16);
+            info = info != 0 ? info : info_b;
+          }
+          if (lane == 0) s_info = info;
+        }
+        __syncthreads();
+        const int info = __builtin_amdgcn_readfirstlane(s_info);
+        if (info != 0) return info;
+        // L_dd by columns for the rows below: column c at LT[c * PT_LT + c2]
+        // (c2 > c), the reciprocal pivot at c2 = c
+        for (int idx = tid; idx < PT_W * PT_W; idx += NT) {
+          const int c = idx / PT_W, c2 = idx - c * PT_W;
+          LT[c * PT_LT + c2] = c2 == c ? Linv[c] : (c2 > c ? Ldd[c2 * (PT_W + 1) + c] : 0.0);
+        }
+        __syncthreads();
+      }
+      // rows below the diagonal block: y := y L_dd^{-T}, one row per thread
+      // (there are such rows only when the panel is 32 wide); each column's
+      // entries of L_dd are loaded together before they are used
+      {
+        const int r = (s0 == 0 ? w : 0) + tid;
+        if (r < S) {
+          double y[PT_W];
+#pragma unroll
+          for (int c = 0; c < PT_W; ++c) y[c] = Ps[c * PT_LD + r];
+#pragma unroll
+          for (int c = 0; c < PT_W; ++c) {
+            double l[PT_W];
+#pragma unroll
+            for (int c2 = c; c2 < PT_W; ++c2) l[c2] = LT[c * PT_LT + c2];
+#pragma unroll
+            for (int c2 = c; c2 < PT_W; ++c2) asm volatile("" : : "v"(l[c2]));
+            y[c] *= l[c];
+#pragma unroll
+            for (int c2 = c + 1; c2 < PT_W; ++c2) y[c2] -= y[c] * l[c2];
+          }
+#pragma unroll
+          for (int c = 0; c < PT_W; ++c) Ps[c * PT_LD + r] = y[c];
+        }
+      }
+      __syncthreads();
+      // the slab (lower part) to the tile, one row per thread; the next slab
+      // reuses the LDS
+      if (tid < S) {
+#pragma unroll
+        for (int c = 0; c < PT_W; ++c)
+          if (c < w && s0 + tid >= c) st_dev(P + (int64_t)c * ld + s0 + tid, Ps[c * PT_LD + tid]);
+      }
+      __syncthreads();
+    }
+    // the panel must be visible to every wavefront before the next panel's
+    // update reads it
+    wait_vmcnt<0>();
+    __syncthreads();
   }
   return 0;
 }

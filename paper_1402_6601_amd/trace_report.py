@@ -1,6 +1,7 @@
 """Per-kind work-item timing of one launch, from the kernel's trace buffer.
 
-    python -m paper_1402_6601_amd.trace_report [--op factor|merged|mixed|solve|adjoint] [--n N] [--nb NB] [--policy P]
+    python -m paper_1402_6601_amd.trace_report [--op factor|merged|mixed|solve|adjoint|batched] [--n N] [--nb NB]
+        [--policy P]
 
 The persistent kernel can record, per work item, the wall clock (100 MHz)
 when its ticket was claimed, when its wait ended, when it finished, and the
@@ -10,7 +11,8 @@ seed 1; merged: the same factorization and its 16-RHS solve as one
 launch; mixed: shift 1e-4, seed 2, the factorization launch of the
 mixed-precision solve; solve: the 16-RHS forward and backward solve launch
 on the factor of the seed-1 matrix; adjoint: shift 1, seed 3,
-Lbar = tril N(0, 1)), and
+Lbar = tril N(0, 1); batched: 4096 systems of orders uniform in [16, 512],
+seed 4, factor and 4-RHS solve in one launch, tiles from the tuned table), and
 prints the makespan, the fraction of worker time spent running and waiting,
 per task kind the item count and mean / median / max duration and mean wait,
 and the busy fraction over time in 20 buckets.
@@ -74,7 +76,8 @@ def report(tc, plan, trace, tag, out=print):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", choices=["factor", "merged", "mixed", "solve", "adjoint"], default="factor")
+    ap.add_argument("--op", choices=["factor", "merged", "mixed", "solve", "adjoint", "batched"], default="factor")
+    ap.add_argument("--count", type=int, default=4096, help="batched: number of systems")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--policy", choices=["rank", "list", "fifo", "random"], default="list")
@@ -89,6 +92,25 @@ def main(argv=None):
         return 1
     dev = torch.device("cuda:0")
     pol = {"rank": tc.POLICY_RANK, "list": tc.POLICY_LIST, "fifo": tc.POLICY_FIFO, "random": tc.POLICY_RANDOM}[args.policy]
+    if args.op == "batched":
+        # 4096 systems of orders uniform in [16, 512] (seed 4), 4 right-hand
+        # sides each, tile sizes from the tuned table: factor + solve in one launch
+        from paper_1402_6601_amd import autotune
+        ns, A0, a_off, lda, B0, b_off = spd_inputs.batched_systems_device(args.count, 4, 4)
+        # --nb: that tile size for every system larger than it instead of the table
+        nbs = (autotune.tile_sizes(ns) if not args.nb else
+               np.array([autotune.rule_nb(int(x), args.nb) for x in ns], dtype=np.int32))
+        plan = tc.batched_plan_query(ns, nbs, pol)
+        trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
+        A, B = A0.clone(), B0.clone()
+        tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nbs, 4, policy=pol)
+        A.copy_(A0)
+        B.copy_(B0)
+        _, ms = tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nbs, 4, policy=pol, want_kernel_ms=True,
+                                         trace=trace)
+        print("kernel %.3f ms (HIP events), %d systems, sum n = %d" % (ms, len(ns), int(ns.sum())), flush=True)
+        report(tc, plan, trace, args.op)
+        return 0
     if args.op == "adjoint":
         n, nb = args.n or 8192, args.nb or 256
         A, rng = spd_inputs.spd_matrix_device(n, 3, 1.0, device=dev)

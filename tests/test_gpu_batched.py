@@ -97,6 +97,32 @@ def test_batched_failure_stays_in_its_system(tc):
         assert np.max(np.abs(Xs[s] - Xo)) / np.max(np.abs(Xo)) <= TOL
 
 
+@pytest.mark.parametrize("align", [2, 1])
+def test_batched_single_tile_breakdown(tc, align):
+    """Breakdown inside one-tile systems above 128 (one workgroup, panels of
+    32 columns in slabs of 256 rows): in the leading and in the trailing 16
+    columns of a panel, in the first panel, and in a panel whose rows span
+    two slabs; the oracle's info for each, the other systems exact."""
+    sizes = [400, 400, 400, 300, 511, 200]
+    cols = [37, 50, 5, 290, 20, None]
+    As, bs = _systems(13, sizes)
+    for s, j in enumerate(cols):
+        if j is None:
+            continue
+        A1, L0 = spd_inputs.integer_spd(sizes[s], seed=20 + s)
+        A1[j, j] -= L0[j, j] ** 2
+        _, info_o = oracle.potrf(A1)
+        assert info_o == j + 1
+        As[s] = A1
+    nb = [_nb_single(n) for n in sizes]
+    info, Ls, Xs = _run(tc, As, bs, nb, align=align)
+    assert list(info) == [0 if j is None else j + 1 for j in cols]
+    Lo = oracle.cholesky(As[-1])
+    assert oracle.factor_error(Ls[-1], Lo) <= TOL
+    Xo = oracle.potrs(Lo, bs[-1])
+    assert np.max(np.abs(Xs[-1] - Xo)) / np.max(np.abs(Xo)) <= TOL
+
+
 def test_batched_integer_systems_exact(tc):
     sizes = [64, 300, 17, 512]
     As, bs, L0s, X0s = [], [], [], []
