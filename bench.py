@@ -188,6 +188,9 @@ def run_batched(args):
     run = tc.factor_solve_batched_f32_ if fp32 else tc.factor_solve_batched_
     table = autotune.load_table()
     nb = autotune.tile_sizes(ns, table)
+    # the FP32 launch factors each one-tile system on one workgroup
+    wgs = None if fp32 else autotune.potrf_wgs(ns, table)
+    extra = {} if fp32 else {"wgs": wgs}
     torch.cuda.synchronize()
     log("batched inputs ready in %.1f s (%d systems, sum n = %d)" % (time.time() - t0, len(ns), int(ns.sum())))
     wsb = tc.batched_f32_workspace_bytes(ns, nb, nrhs) if fp32 else tc.batched_workspace_bytes(ns, nb)
@@ -198,7 +201,7 @@ def run_batched(args):
     for w in range(Wm):
         Aw.copy_(A0)
         Bw.copy_(B0)
-        info = run(Aw, a_off, lda, Bw, b_off, ns, nb, nrhs, ws=ws)
+        info = run(Aw, a_off, lda, Bw, b_off, ns, nb, nrhs, ws=ws, **extra)
         if np.any(info != 0):
             raise RuntimeError("batched factorization failed")
         log("warmup %d done" % (w + 1))
@@ -210,7 +213,7 @@ def run_batched(args):
     failed = []
     t_start = time.perf_counter()
     for s_ in range(K):
-        info, ms = run(As[s_], a_off, lda, Bs[s_], b_off, ns, nb, nrhs, ws=ws, want_kernel_ms=True)
+        info, ms = run(As[s_], a_off, lda, Bs[s_], b_off, ns, nb, nrhs, ws=ws, want_kernel_ms=True, **extra)
         kernel_ms.append(ms)
         if np.any(info != 0):   # the info array is read back by the call itself (host memory)
             failed.append(s_)
@@ -276,7 +279,8 @@ def run_batched(args):
                                   len(ns), seed),
                    "count": int(len(ns)), "seed": seed, "nrhs": nrhs,
                    "tile_table": "tuned" if table else "one tile per system",
-                   "systems_split_into_tiles": int(np.sum(nb < ns))},
+                   "systems_split_into_tiles": int(np.sum(nb < ns)),
+                   "systems_on_several_workgroups": 0 if fp32 else int(np.sum(wgs > 1))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "tchol_persistent (batched factor + solve DAG)", "kernel_ms_mean": round(kmean, 3),

@@ -109,6 +109,14 @@ typedef struct tchol_opts {
                           exact on integer data whose intermediates are exact).
                           A ragged last tile (order not a multiple of 16) always
                           substitutes.                                          */
+  const int32_t *wgs;  /* tchol_factor_solve_batched only (host pointer, may be
+                          NULL): per system, the workgroups that share the
+                          factorization of a one-tile system whose order exceeds
+                          128 (the tile's sub-block DAG, section 2.1's workers
+                          taking its units), in [0, 8]; 0 or 1: one workgroup.
+                          A value outside [0, 8] returns -i for the opts
+                          argument i.  The tuned tables choose it per order
+                          bucket.                                               */
 } tchol_opts;
 
 /* Bytes of device workspace needed by `op` (TCHOL_OP_FACTOR, _SOLVE or
@@ -201,7 +209,7 @@ TCHOL_API int32_t tchol_factor_solve(double *A, int64_t n, int64_t nb, double *B
    Arguments: 1 A, 2 n, 3 nb, 4 B, 5 nrhs (as for tchol_factor_solve),
    6 stream.  Returns as tchol_factor_solve, or TCHOL_E_SCRATCH (checked
    before any HIP call) when the launch's scheduler scratch, the same as
-   tchol_batched_workspace_bytes for the one system (n, nb), exceeds
+   tchol_batched_workspace_bytes for the one system (n, nb) when nb < n, exceeds
    TCHOL_NOALLOC_SCRATCH_BYTES (n = 32768 with nb = 512 needs 8.3 MiB;
    nb = 256 about 31 MiB). */
 #define TCHOL_NOALLOC_SCRATCH_BYTES (16 << 20)
@@ -232,8 +240,10 @@ TCHOL_API int32_t tchol_factor_solve_noalloc(double *A, int64_t n, int64_t nb, d
    odd n[s] has lda[s] > n[s] (e.g. lda[s] = n[s] rounded up to even).
    Arguments: 1 A, 2 a_off, 3 lda, 4 B, 5 b_off, 6 n, 7 nb, 8 nrhs >= 0,
    9 batch >= 0, 10 info, 11 ws, 12 ws_bytes, 13 stream, 14 opts (NULL or as
-   for tchol_factor_ex).  Returns 0 when the launch ran (per-system failures
-   are reported in info only), or a negative code. */
+   for tchol_factor_ex; opts.wgs applies).  Returns 0 when the launch ran
+   (per-system failures are reported in info only), or a negative code.
+   tchol_batched_workspace_bytes: the workspace of that launch for any
+   opts.wgs. */
 TCHOL_API int64_t tchol_batched_workspace_bytes(const int32_t *n, const int32_t *nb, int32_t batch);
 TCHOL_API int32_t tchol_factor_solve_batched(double *A, const int64_t *a_off, const int32_t *lda, double *B,
                                              const int64_t *b_off, const int32_t *n, const int32_t *nb,
@@ -313,10 +323,12 @@ TCHOL_API int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t po
                          int32_t *item_task, int32_t *item_part);
 
 /* The same introspection for the merged DAG of tchol_factor_solve_batched
-   (systems given by n and nb, batch entries); sys (ntask) receives each
-   task's system.  Returns 0 or a negative code. */
+   (systems given by n and nb, batch entries, and wgs as tchol_opts.wgs, NULL
+   for the default); sys (ntask) receives each task's system.  Returns 0 or
+   a negative code (-6 for a wgs entry outside [0, 8]). */
 TCHOL_API int32_t tchol_batched_plan_query(const int32_t *n, const int32_t *nb, int32_t batch, int32_t policy,
-                                           uint32_t seed, int64_t *counts, int32_t *kind, int32_t *ti, int32_t *tj,
+                                           uint32_t seed, const int32_t *wgs, int64_t *counts, int32_t *kind,
+                                           int32_t *ti, int32_t *tj,
                                            int32_t *tk, int32_t *sys, int32_t *parts, int32_t *dep0, int64_t *rank,
                                            int32_t *succ_off, int32_t *succ, int32_t *item_task,
                                            int32_t *item_part);

@@ -42,7 +42,8 @@ class TcholError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("seed", ctypes.c_uint32), ("wait_limit_us", ctypes.c_int64),
                 ("kernel_ms", ctypes.POINTER(ctypes.c_float)), ("trace", ctypes.c_void_p),
-                ("trace_words", ctypes.c_int64), ("subst", ctypes.c_int32)]
+                ("trace_words", ctypes.c_int64), ("subst", ctypes.c_int32),
+                ("wgs", ctypes.POINTER(ctypes.c_int32))]
 
 
 def load() -> ctypes.CDLL:
@@ -86,7 +87,7 @@ def load() -> ctypes.CDLL:
     lib.tchol_plan_query.argtypes = [i32, i64, i64, i32, u32, P64, P32, P32, P32, P32, P32, P32, P64, P32, P32,
                                      P32, P32]
     lib.tchol_batched_plan_query.restype = i32
-    lib.tchol_batched_plan_query.argtypes = [P32, P32, i32, i32, u32, P64, P32, P32, P32, P32, P32, P32, P32, P64,
+    lib.tchol_batched_plan_query.argtypes = [P32, P32, i32, i32, u32, P32, P64, P32, P32, P32, P32, P32, P32, P32, P64,
                                              P32, P32, P32, P32]
     lib.tchol_batched_workspace_bytes.restype = i64
     lib.tchol_batched_workspace_bytes.argtypes = [P32, P32, i32]
@@ -164,19 +165,24 @@ def _i64(x):
     return np.ascontiguousarray(np.asarray(x, dtype=np.int64))
 
 
-def batched_plan_query(n, nb, policy: int = POLICY_LIST, seed: int = 0) -> dict:
+def batched_plan_query(n, nb, policy: int = POLICY_LIST, seed: int = 0, wgs=None) -> dict:
     """The merged factor + solve DAG of a batched launch (no GPU needed); as
-    plan_query, plus "sys", the system of every task."""
+    plan_query, plus "sys", the system of every task.  wgs as for
+    factor_solve_batched_."""
     lib = load()
     n32, nb32 = _i32(n), _i32(nb)
+    w32 = None if wgs is None else _i32(wgs)
+    if w32 is not None and len(w32) != len(n32):
+        raise ValueError("wgs must have one entry per system")
     P32 = ctypes.POINTER(ctypes.c_int32)
     P64 = ctypes.POINTER(ctypes.c_int64)
     null32, null64 = ctypes.cast(None, P32), ctypes.cast(None, P64)
     counts = np.zeros(4, dtype=np.int64)
     p = lambda x: x.ctypes.data_as(P32)
-    rc = lib.tchol_batched_plan_query(p(n32), p(nb32), len(n32), policy, seed, counts.ctypes.data_as(P64), null32,
-                                      null32, null32, null32, null32, null32, null32, null64, null32, null32,
-                                      null32, null32)
+    pw = null32 if w32 is None else p(w32)
+    rc = lib.tchol_batched_plan_query(p(n32), p(nb32), len(n32), policy, seed, pw, counts.ctypes.data_as(P64),
+                                      null32, null32, null32, null32, null32, null32, null32, null64, null32,
+                                      null32, null32, null32)
     if rc != 0:
         raise TcholError(rc, "tchol_batched_plan_query")
     nt, ne, ni = int(counts[0]), int(counts[1]), int(counts[2])
@@ -186,7 +192,7 @@ def batched_plan_query(n, nb, policy: int = POLICY_LIST, seed: int = 0) -> dict:
     a["succ"] = np.zeros(max(ne, 1), dtype=np.int32)
     a["item_task"] = np.zeros(max(ni, 1), dtype=np.int32)
     a["item_part"] = np.zeros(max(ni, 1), dtype=np.int32)
-    rc = lib.tchol_batched_plan_query(p(n32), p(nb32), len(n32), policy, seed, counts.ctypes.data_as(P64),
+    rc = lib.tchol_batched_plan_query(p(n32), p(nb32), len(n32), policy, seed, pw, counts.ctypes.data_as(P64),
                                       p(a["kind"]), p(a["i"]), p(a["j"]), p(a["k"]), p(a["sys"]), p(a["parts"]),
                                       p(a["dep0"]), a["rank"].ctypes.data_as(P64), p(a["succ_off"]), p(a["succ"]),
                                       p(a["item_task"]), p(a["item_part"]))
@@ -328,13 +334,14 @@ def solve(Lbuf, B, nb: int, **kw):
 
 def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: int = POLICY_LIST, seed: int = 0,
                           wait_limit_us: int = 0, ws=None, want_kernel_ms: bool = False, trace=None,
-                          check: bool = True):
+                          check: bool = True, wgs=None):
     """Factor and solve many systems in one launch, in place.
 
     A, B: CUDA float64 1-D tensors holding every system (see
     tchol_factor_solve_batched for the per-system layout given by the host
-    arrays a_off, lda, b_off, n and nb).  Returns the per-system info array
-    (numpy int32), or (info, kernel_ms)."""
+    arrays a_off, lda, b_off, n and nb).  wgs: optional per-system count of
+    workgroups sharing a one-tile system's factorization (tchol_opts.wgs).
+    Returns the per-system info array (numpy int32), or (info, kernel_ms)."""
     torch = _torch()
     if A.dtype != torch.float64 or B.dtype != torch.float64 or not A.is_contiguous() or not B.is_contiguous():
         raise ValueError("A and B must be contiguous float64 tensors")
@@ -354,6 +361,11 @@ def factor_solve_batched_(A, a_off, lda, B, b_off, n, nb, nrhs: int, *, policy: 
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, A.device)
         o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        if wgs is not None:
+            wgs = _i32(wgs)
+            if len(wgs) != batch:
+                raise ValueError("wgs must have one entry per system")
+            o.wgs = wgs.ctypes.data_as(P32)
         rc = lib.tchol_factor_solve_batched(ctypes.c_void_p(A.data_ptr()), a_off.ctypes.data_as(P64),
                                             lda.ctypes.data_as(P32), ctypes.c_void_p(B.data_ptr()),
                                             b_off.ctypes.data_as(P64), n.ctypes.data_as(P32),

@@ -1,19 +1,23 @@
-"""Autotuner of the batched launch's tile sizes.
+"""Autotuner of the batched launch: per order bucket, the tile size and the
+workgroups that share a system's factorization.
 
     python -m paper_1402_6601_amd.autotune [--count 4096] [--seed 4] [--out tune_batched.json]
 
 In a batched launch each system gets its own tile size nb.  One tile
-(nb >= n) keeps a system on a single workgroup; smaller tiles split its
-factorization and solve into a DAG whose tasks spread over many
-workgroups, which shortens that system's critical path at the price of more
-tasks.  Which is faster depends on the order and on the rest of the batch,
-so the tuner measures it: the systems are grouped into order buckets, and
-for every bucket each candidate tile size is timed on the GPU with a batch
-of that bucket's systems (kernel time from HIP events, best of a few runs).
-The fastest candidate per bucket goes into a JSON table, which
-:func:`tile_sizes` applies.  The table finally is validated on the whole
-batch against the one-tile-per-system default, and both times are recorded
-in it.
+(nb >= n) keeps a system's factorization on one workgroup, or, with wgs > 1
+(orders above 128), on wgs workgroups that share the tile's sub-block DAG
+(the split POTRF of the large factorizations); smaller tiles split its
+factorization and solve into a DAG whose tasks spread over many workgroups.
+Both shorten a system's critical path at the price of more, smaller work
+items.  Which is faster depends on the order and on the rest of the batch,
+so the tuner measures it, in the spirit of the history-based calibration of
+the paper's performance model (section 2.3): the systems are grouped into
+order buckets, and for every bucket each candidate (tile rule, wgs) is timed
+on the GPU with a batch of that bucket's systems (kernel time from HIP
+events, best of a few runs).  The fastest candidate per bucket goes into a
+JSON table, which :func:`tile_sizes` and :func:`potrf_wgs` apply.  The table
+finally is validated on the whole batch against the one-tile,
+one-workgroup default, and both times are recorded in it.
 """
 from __future__ import annotations
 
@@ -31,7 +35,9 @@ if ROOT not in sys.path:
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tune_batched.json")
 BUCKETS = [(1, 64), (65, 128), (129, 192), (193, 256), (257, 320), (321, 384), (385, 448), (449, 512)]
-CANDIDATES = [0, 256, 128, 64, 32]   # 0: one tile per system
+# (tile rule, wgs): rule 0 is one tile per system; wgs > 1 shares a one-tile
+# factorization above order 128 among that many workgroups
+CANDIDATES = [(0, 1), (0, 2), (0, 4), (0, 8), (256, 0), (128, 0), (64, 0), (32, 0)]
 
 
 def single_tile(n: int) -> int:
@@ -52,26 +58,39 @@ def load_table(path: str = DEFAULT_TABLE):
         return json.load(f)
 
 
+def _bucket_of(n, table):
+    """(rule, wgs) of the table's bucket holding order n; (0, 0) if none.
+    Entries are [lo, hi, rule] or [lo, hi, rule, wgs]."""
+    if table:
+        for e in table["buckets"]:
+            if int(e[0]) <= n <= int(e[1]):
+                return int(e[2]), (int(e[3]) if len(e) > 3 else 0)
+    return 0, 0
+
+
 def tile_sizes(ns, table=None):
     """Per-system tile sizes: the table's rule for each system's order bucket,
     one tile per system where no table (or bucket) applies."""
     if table is None:
         table = load_table()
-    rules = []
-    if table:
-        rules = [(int(lo), int(hi), int(r)) for lo, hi, r in table["buckets"]]
+    return np.asarray([rule_nb(int(n), _bucket_of(int(n), table)[0]) for n in ns], dtype=np.int32)
+
+
+def potrf_wgs(ns, table=None):
+    """Per-system workgroups sharing a one-tile factorization (tchol_opts.wgs):
+    the bucket's choice for a system kept in one tile above order 128, else 0
+    (one workgroup, or the default split of a tiled system)."""
+    if table is None:
+        table = load_table()
     out = []
     for n in ns:
-        r = 0
-        for lo, hi, rr in rules:
-            if lo <= n <= hi:
-                r = rr
-                break
-        out.append(rule_nb(int(n), r))
+        rule, w = _bucket_of(int(n), table)
+        one_tile = rule_nb(int(n), rule) >= n
+        out.append(w if (one_tile and n > 128 and w > 1) else 0)
     return np.asarray(out, dtype=np.int32)
 
 
-def _time_batch(tc, torch, ns, A0, a_off, lda, B0, b_off, nb, nrhs, reps, ws=None):
+def _time_batch(tc, torch, ns, A0, a_off, lda, B0, b_off, nb, nrhs, reps, ws=None, wgs=None):
     A = torch.empty_like(A0)
     B = torch.empty_like(B0)
     best = None
@@ -79,7 +98,8 @@ def _time_batch(tc, torch, ns, A0, a_off, lda, B0, b_off, nb, nrhs, reps, ws=Non
         A.copy_(A0)
         B.copy_(B0)
         torch.cuda.synchronize()
-        info, ms = tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nb, nrhs, ws=ws, want_kernel_ms=True)
+        info, ms = tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nb, nrhs, ws=ws, want_kernel_ms=True,
+                                            wgs=wgs)
         if np.any(info != 0):
             raise RuntimeError("a system failed during tuning")
         best = ms if best is None else min(best, ms)
@@ -113,29 +133,33 @@ def main(argv=None):
             continue
         sub = lambda arr: np.asarray(arr)[idx]
         times = {}
-        for cand in CANDIDATES:
-            if cand and cand >= hi:
+        for rule, w in CANDIDATES:
+            if rule and rule >= hi:
                 continue
-            nb = np.array([rule_nb(int(n), cand) for n in ns[idx]], dtype=np.int32)
-            times[cand] = _time_batch(tc, torch, sub(ns), A0, sub(a_off), sub(lda), B0, sub(b_off), nb, args.nrhs,
-                                      args.reps)
-            print("[tune] bucket %d-%d (%d systems) nb rule %s: %.3f ms" % (lo, hi, len(idx), cand or "one tile",
-                                                                          times[cand]), file=sys.stderr, flush=True)
+            if w > 1 and hi <= 128:
+                continue
+            cand = {"buckets": [[lo, hi, rule, w]]}
+            nb = tile_sizes(ns[idx], cand)
+            wg = potrf_wgs(ns[idx], cand)
+            times[(rule, w)] = _time_batch(tc, torch, sub(ns), A0, sub(a_off), sub(lda), B0, sub(b_off), nb,
+                                           args.nrhs, args.reps, wgs=wg)
+            print("[tune] bucket %d-%d (%d systems) nb rule %s, wgs %d: %.3f ms"
+                  % (lo, hi, len(idx), rule or "one tile", w, times[(rule, w)]), file=sys.stderr, flush=True)
         best = min(times, key=times.get)
-        rules.append([lo, hi, int(best)])
+        rules.append([lo, hi, int(best[0]), int(best[1])])
+        name = lambda c: ("one tile" if c[0] == 0 else "nb %d" % c[0]) + (", wgs %d" % c[1] if c[1] > 1 else "")
         report.append({"bucket": [lo, hi], "systems": int(len(idx)),
-                       "ms": {("one tile" if c == 0 else str(c)): round(t, 4) for c, t in times.items()},
-                       "chosen": "one tile" if best == 0 else int(best)})
+                       "ms": {name(c): round(t, 4) for c, t in times.items()}, "chosen": name(best)})
     table = {"device": torch.cuda.get_device_name(0), "count": args.count, "seed": args.seed, "nrhs": args.nrhs,
              "buckets": rules, "report": report}
-    nb_tuned = tile_sizes(ns, table)
+    nb_tuned, wgs_tuned = tile_sizes(ns, table), potrf_wgs(ns, table)
     nb_default = np.array([single_tile(n) for n in ns], dtype=np.int32)
-    t_tuned = _time_batch(tc, torch, ns, A0, a_off, lda, B0, b_off, nb_tuned, args.nrhs, args.reps)
+    t_tuned = _time_batch(tc, torch, ns, A0, a_off, lda, B0, b_off, nb_tuned, args.nrhs, args.reps, wgs=wgs_tuned)
     t_default = _time_batch(tc, torch, ns, A0, a_off, lda, B0, b_off, nb_default, args.nrhs, args.reps)
     table["validation_ms"] = {"tuned": round(t_tuned, 4), "one_tile_per_system": round(t_default, 4)}
     if t_default < t_tuned:
         # the per-bucket optimum did not carry over to the whole batch
-        table["buckets"] = [[lo, hi, 0] for lo, hi, _ in rules]
+        table["buckets"] = [[lo, hi, 0, 0] for lo, hi, _, _ in rules]
         table["validation_ms"]["kept"] = "one tile per system"
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)

@@ -160,8 +160,13 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
   for (int32_t k = 0; k < T; ++k) {
     // a single-tile system's POTRF is the whole factorization: in a batch of
     // many such systems the workgroups have independent work enough, so it
-    // takes one work item; the diagonal tiles of tiled systems are split
-    id_potrf[k] = b.add(TK_POTRF, k, k, k, T > 1 ? potrf_parts(b.tile_size(k)) : 1);
+    // takes one work item unless the system asks for several (wgs, a tuning
+    // choice: they share the tile's sub-block pool); the diagonal tiles of
+    // tiled systems are split
+    const int32_t wgs = b.p.systems[b.sys].wgs;
+    id_potrf[k] = b.add(TK_POTRF, k, k, k,
+                        T > 1 ? potrf_parts(b.tile_size(k))
+                              : (wgs > 1 && b.tile_size(k) > 128 ? std::min(wgs, potrf_parts(b.tile_size(k))) : 1));
     for (int32_t i = k + 1; i < T; ++i)
       id_trsm[ix2(i, k)] = b.add(TK_TRSM, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
     for (int32_t i = k + 1; i < T; ++i) {
@@ -637,13 +642,14 @@ std::shared_ptr<const Plan> get_batched_plan(const std::vector<System>& systems,
   static std::mutex mu;
   static std::map<std::vector<int64_t>, std::shared_ptr<const Plan>> cache;
   std::vector<int64_t> key;
-  key.reserve(2 * systems.size() + 3);
+  key.reserve(3 * systems.size() + 3);
   key.push_back(inv ? 1 : 0);
   key.push_back(policy);
   key.push_back(policy == TCHOL_POLICY_RANDOM ? seed : 0);
   for (const System& sy : systems) {
     key.push_back(sy.n);
     key.push_back(sy.nb);
+    key.push_back(sy.wgs);
   }
   {
     std::lock_guard<std::mutex> g(mu);

@@ -26,6 +26,8 @@ struct System {
   int64_t n = 0, nb = 0, ld = 0;
   int32_t T = 0;                 // tiles per side
   int64_t d_off = 0;             // mixed precision: offset (doubles) of its FP64 diagonal tiles
+  int32_t wgs = 0;               // work items of a one-tile system's POTRF above 128 (its
+                                 // sub-block pool); 0: the default (one)
 };
 
 struct Plan {

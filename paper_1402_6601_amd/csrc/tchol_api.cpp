@@ -224,7 +224,7 @@ bool policy_ok(int32_t p) { return p >= TCHOL_POLICY_LIST && p <= TCHOL_POLICY_R
 
 bool nb_ok(int64_t nb) { return nb >= TCHOL_NB_MIN && nb <= TCHOL_NB_MAX && nb % 16 == 0; }
 
-const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr, 0, 0};
+const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr, 0, 0, nullptr};
 
 // Uploads the plan image, launches reset + persistent kernel on the stream,
 // reads the header back and synchronises.  sinfo_out (batched): per-system
@@ -666,8 +666,13 @@ int64_t tchol_batched_workspace_bytes(const int32_t* n, const int32_t* nb, int32
   if (rc != 0) return rc;
   auto plan = tchol::get_batched_plan(systems, TCHOL_POLICY_RANK, 0);
   if (!plan) return TCHOL_E_UNSUPPORTED;
-  // every policy yields the same task, edge and item counts, hence the same layout
-  return layout_of(*plan).end;
+  // every policy yields the same task, edge and item counts, hence the same
+  // layout; up to 7 more work items (8 bytes each) for every one-tile system
+  // above 128 that opts.wgs may split
+  int64_t extra = 0;
+  for (const auto& sy : systems)
+    if (sy.n > 128 && sy.nb >= sy.n) extra += 7 * 8;
+  return layout_of(*plan).end + align_up(extra);
 }
 
 int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_t* lda, double* B,
@@ -701,6 +706,12 @@ int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_
   if (ws_bytes <= 0) return -12;
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
   if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
+  if (o.wgs) {
+    for (int32_t s = 0; s < batch; ++s) {
+      if (o.wgs[s] < 0 || o.wgs[s] > 8) return -14;
+      systems[s].wgs = o.wgs[s];
+    }
+  }
   if (nrhs == 0) {
     // nothing to solve: the plan still holds the solve tasks, which then have no columns
   }
@@ -940,7 +951,8 @@ int32_t tchol_plan_query(int32_t op, int64_t n, int64_t nb, int32_t policy, uint
 }
 
 int32_t tchol_batched_plan_query(const int32_t* n, const int32_t* nb, int32_t batch, int32_t policy, uint32_t seed,
-                                 int64_t* counts, int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* sys,
+                                 const int32_t* wgs, int64_t* counts, int32_t* kind, int32_t* ti, int32_t* tj,
+                                 int32_t* tk, int32_t* sys,
                                  int32_t* parts, int32_t* dep0, int64_t* rank, int32_t* succ_off, int32_t* succ,
                                  int32_t* item_task, int32_t* item_part) {
   if (batch < 0) return -3;
@@ -952,6 +964,12 @@ int32_t tchol_batched_plan_query(const int32_t* n, const int32_t* nb, int32_t ba
   if (rc == -6) return -1;
   if (rc == -7) return -2;
   if (rc != 0) return rc;
+  if (wgs) {
+    for (int32_t s = 0; s < batch; ++s) {
+      if (wgs[s] < 0 || wgs[s] > 8) return -6;
+      systems[s].wgs = wgs[s];
+    }
+  }
   auto p = tchol::build_batched_plan(systems, policy, seed, tchol::default_split());
   if (!p) return TCHOL_E_UNSUPPORTED;
   fill_query(*p, counts, kind, ti, tj, tk, sys, parts, dep0, rank, succ_off, succ, item_task, item_part);

@@ -100,14 +100,15 @@ def main(argv=None):
         # --nb: that tile size for every system larger than it instead of the table
         nbs = (autotune.tile_sizes(ns) if not args.nb else
                np.array([autotune.rule_nb(int(x), args.nb) for x in ns], dtype=np.int32))
-        plan = tc.batched_plan_query(ns, nbs, pol)
+        wgs = autotune.potrf_wgs(ns) if not args.nb else None
+        plan = tc.batched_plan_query(ns, nbs, pol, wgs=wgs)
         trace = torch.zeros(4 * plan["nitem"], dtype=torch.int64, device=dev)
         A, B = A0.clone(), B0.clone()
-        tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nbs, 4, policy=pol)
+        tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nbs, 4, policy=pol, wgs=wgs)
         A.copy_(A0)
         B.copy_(B0)
         _, ms = tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nbs, 4, policy=pol, want_kernel_ms=True,
-                                         trace=trace)
+                                         trace=trace, wgs=wgs)
         print("kernel %.3f ms (HIP events), %d systems, sum n = %d" % (ms, len(ns), int(ns.sum())), flush=True)
         report(tc, plan, trace, args.op)
         return 0

@@ -123,6 +123,29 @@ def test_batched_single_tile_breakdown(tc, align):
     assert np.max(np.abs(Xs[-1] - Xo)) / np.max(np.abs(Xo)) <= TOL
 
 
+@pytest.mark.parametrize("align", [2, 1])
+def test_batched_shared_factorization(tc, align):
+    """One-tile systems whose factorization several workgroups share
+    (tchol_opts.wgs, the tile's sub-block pool) match the oracle; a breakdown
+    inside a shared factorization gives the oracle's info and stays in its
+    system; wgs on systems of 128 or less changes nothing."""
+    sizes = [129, 200, 300, 512, 400, 100, 256]
+    wgs = [2, 4, 8, 8, 3, 4, 0]
+    As, bs = _systems(14, sizes)
+    A1, L0 = spd_inputs.integer_spd(400, seed=31)
+    j = 250
+    A1[j, j] -= L0[j, j] ** 2
+    As[4] = A1
+    nb = [_nb_single(n) for n in sizes]
+    info, Ls, Xs = _run(tc, As, bs, nb, align=align, wgs=wgs)
+    assert list(info) == [0, 0, 0, 0, j + 1, 0, 0]
+    for s in (0, 1, 2, 3, 5, 6):
+        Lo = oracle.cholesky(As[s])
+        assert oracle.factor_error(Ls[s], Lo) <= TOL
+        Xo = oracle.potrs(Lo, bs[s])
+        assert np.max(np.abs(Xs[s] - Xo)) / np.max(np.abs(Xo)) <= TOL
+
+
 def test_batched_integer_systems_exact(tc):
     sizes = [64, 300, 17, 512]
     As, bs, L0s, X0s = [], [], [], []
