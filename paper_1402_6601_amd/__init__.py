@@ -28,7 +28,8 @@ E_HIP, E_TIMEOUT, E_UNSUPPORTED, E_INTERNAL, E_NOCONV, E_SCRATCH = -100, -101, -
 NOALLOC_SCRATCH_BYTES = 16 << 20
 LOWP_FP32, LOWP_BF16 = 1, 2
 KIND_NAMES = ["POTRF", "TRSM", "SYRK", "GEMM", "FTRSV", "FGEMV", "BTRSV", "BGEMV", "GREV", "TREV", "DPART", "PREV",
-              "TRTRI", "DRED", "GEMM2", "PADJM", "PADJY", "PADJS"]
+              "TRTRI", "DRED", "GEMM2", "PADJM", "PADJY", "PADJS",
+              "GREV2"]
 
 _lib = None
 

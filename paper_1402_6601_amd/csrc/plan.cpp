@@ -117,6 +117,7 @@ int64_t weight(int32_t kind, int32_t op) {
     case TK_PREV: return 4;
     case TK_TRTRI: return op == TCHOL_OP_BACKWARD ? 40 : 10;
     case TK_DRED: return 1;
+    case TK_GREV2: return 11;
     case TK_PADJM: case TK_PADJY: return 1;
     case TK_PADJS: return 2;
     default: return 2;
@@ -290,6 +291,11 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, Diag diag = Diag:
 // triangle, so that the chain of the diagonal tile runs on many workgroups.
 bool closed_form_tile(int64_t m) { return m % 16 == 0; }
 
+// GREV(i, k, j) and GREV(i, k, j - 1) form one task (TK_GREV2 at j - 1)
+// when j is the upper link of a pair: the links j = T-1 .. k+2 are paired
+// from the top, k+1 stays alone (and so does k+2 when their count is odd).
+bool grev_paired(int32_t j, int32_t k, int32_t T) { return j - 1 >= k + 2 && (T - 1 - j) % 2 == 0; }
+
 void build_backward(Builder& b) {
   auto& succ = b.succ;
   const int32_t T = b.T;
@@ -299,11 +305,19 @@ void build_backward(Builder& b) {
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
   for (int32_t k = T - 1; k >= 0; --k) {
+    // the chain into Lbar_ik: its last link (j = k + 1, which waits for the
+    // most recent Q tile) alone, the links above it in pairs from the top
+    // (one task of K = 2 nb: half the loads and stores of Lbar_ik)
     for (int32_t i = k + 1; i < T; ++i)
-      for (int32_t j = T - 1; j > k; --j)
-        id_grev[ix3(i, j, k)] = b.add(TK_GREV, i, j, k,
-                                      Builder::cdiv(b.tile_size(i), b.s.gemm_m) *
-                                          Builder::cdiv(b.tile_size(k), b.s.gemm_n));
+      for (int32_t j = T - 1; j > k; --j) {
+        const int32_t parts = Builder::cdiv(b.tile_size(i), b.s.gemm_m) * Builder::cdiv(b.tile_size(k), b.s.gemm_n);
+        if (grev_paired(j, k, T)) {
+          id_grev[ix3(i, j, k)] = id_grev[ix3(i, j - 1, k)] = b.add(TK_GREV2, i, j - 1, k, parts);
+          --j;
+        } else {
+          id_grev[ix3(i, j, k)] = b.add(TK_GREV, i, j, k, parts);
+        }
+      }
     for (int32_t i = k + 1; i < T; ++i)
       id_trev[ix2(i, k)] = b.add(TK_TREV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
     const int32_t sb = Builder::cdiv(b.tile_size(k), b.s.gemm_m);
@@ -329,6 +343,7 @@ void build_backward(Builder& b) {
       for (int32_t j = T - 1; j > k; --j) {
         const int32_t g = id_grev[ix3(i, j, k)];
         succ[producer(i, j)].push_back(g);
+        if (j > k + 1 && id_grev[ix3(i, j - 1, k)] == g) continue;  // the pair's other link
         succ[g].push_back(j > k + 1 ? id_grev[ix3(i, j - 1, k)] : id_trev[ix2(i, k)]);
       }
       succ[id_trev[ix2(i, k)]].push_back(id_dpart[ix2(i, k)]);
@@ -368,7 +383,7 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   if (kind == TK_FTRSV) kord = 0;
   if (kind == TK_FGEMV) kord = 1;
   // within an adjoint step: the updates, the solves, the partial products, their sum, the tile
-  if (kind == TK_GREV) kord = 0;
+  if (kind == TK_GREV || kind == TK_GREV2) kord = 0;
   if (kind == TK_TREV) kord = 1;
   if (kind == TK_DPART) kord = 2;
   if (kind == TK_DRED) kord = 3;
@@ -376,7 +391,7 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   if (kind == TK_PADJY) kord = 5;
   if (kind == TK_PADJS) kord = 6;
   // the chain of GREV(i, k, j) into Lbar_ik runs j downwards
-  const int32_t tj = kind == TK_GREV ? T - 1 - p.tj[t] : p.tj[t];
+  const int32_t tj = (kind == TK_GREV || kind == TK_GREV2) ? T - 1 - p.tj[t] : p.tj[t];
   return std::make_tuple(p.sys[t], step, kord, p.ti[t], tj);
 }
 

@@ -2722,6 +2722,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
         break;
       }
       case TK_GREV:
+      case TK_GREV2:
       case TK_TREV:
       case TK_DPART:
       case TK_DRED:
@@ -2746,12 +2747,15 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           auto slot = [&](int i, int k) __attribute__((always_inline)) {
             return (int64_t)k * (T - 1) - (int64_t)k * (k - 1) / 2 + (i - k - 1);
           };
-          if (kind == TK_GREV) {
+          if (kind == TK_GREV || kind == TK_GREV2) {
+            // GREV2: the links j = tj and tj + 1 as one product over their
+            // consecutive columns of Q and L^T (K = 2 nb, less at the padded end)
             const int ncj = (tsz(tk) + a.gemm_n - 1) / a.gemm_n;
             const int si = part / ncj, sj = part % ncj;
             const int M = imin(a.gemm_m, tsz(ti) - si * a.gemm_m);
             const int N = imin(a.gemm_n, tsz(tk) - sj * a.gemm_n);
-            const int K = (int)(np - (int64_t)tj * nb < nb ? np - (int64_t)tj * nb : nb);
+            const int64_t kw = (kind == TK_GREV2 ? 2 : 1) * nb;
+            const int K = (int)(np - (int64_t)tj * nb < kw ? np - (int64_t)tj * nb : kw);
             gemm_nt_ex(Bbase + (tk * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m, ld,
                        a.Q + (tj * nb) * ldq + ti * nb + si * a.gemm_m, a.LT + (tj * nb) * ldq + tk * nb + sj * a.gemm_n,
                        ldq, M, N, K, false, false, lds);

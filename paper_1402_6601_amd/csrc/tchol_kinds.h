@@ -30,6 +30,8 @@
 #define TK_PADJM 15  /* M_k = Phi(L_kk^T Lbar_kk), lower blocks, stored negated  */
 #define TK_PADJY 16  /* Y_k^T = L_kk^{-T} M_k^T, upper blocks                    */
 #define TK_PADJS 17  /* Q_kk = L_kk^{-T} Y_k + Y_k^T L_kk^{-1}, Lbar_kk = tril(Q_kk)/2 */
-#define TK_NKINDS 18
+/* adjoint: two consecutive links of a GREV chain in one task (K = 2 nb) */
+#define TK_GREV2 18  /* Lbar_ik <- Lbar_ik - Q_ij L_jk - Q_i,j+1 L_j+1,k        */
+#define TK_NKINDS 19
 #define TCHOL_PRB 64  /* block order of the TK_PADJ* products                      */
 #endif

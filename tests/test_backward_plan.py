@@ -1,7 +1,8 @@
 """Host planner of the adjoint's reverse tile DAG (no GPU).
 
 The reverse program, per step k from T-1 down to 0,
-    GREV(i, k, j)  Lbar_ik -= Q_ij L_jk      i > k, j = T-1 .. k+1
+    GREV(i, k, j)  Lbar_ik -= Q_ij L_jk      i > k, j = T-1 .. k+1 (links above
+                   k+1 paired from the top into GREV2 tasks of two)
     TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}   (writes Q_ik and Q_ki)
     DPART(i, k)    S_ik = tril(P_ik^T L_ik)
     DRED(k)        Lbar_kk -= sum_i S_ik     (k < T-1)
@@ -28,8 +29,22 @@ import pytest
 
 tc = pytest.importorskip("paper_1402_6601_amd")
 
-GREV, TREV, DPART, PREV, TRTRI, DRED, PADJM, PADJY, PADJS = 8, 9, 10, 11, 12, 13, 15, 16, 17
-WEIGHT = {GREV: 6, TREV: 3, DPART: 3, PREV: 4, TRTRI: 40, DRED: 1, PADJM: 1, PADJY: 1, PADJS: 2}
+GREV, TREV, DPART, PREV, TRTRI, DRED, PADJM, PADJY, PADJS, GREV2 = 8, 9, 10, 11, 12, 13, 15, 16, 17, 18
+WEIGHT = {GREV: 6, TREV: 3, DPART: 3, PREV: 4, TRTRI: 40, DRED: 1, PADJM: 1, PADJY: 1, PADJS: 2, GREV2: 11}
+
+
+def grev_tasks(k, T):
+    """The chain into Lbar_ik as tasks (kind, js) in chain order: its last
+    link j = k + 1 alone, the links above it paired from the top."""
+    out, j = [], T - 1
+    while j > k:
+        if j - 1 >= k + 2 and (T - 1 - j) % 2 == 0:
+            out.append((GREV2, (j, j - 1)))
+            j -= 2
+        else:
+            out.append((GREV, (j,)))
+            j -= 1
+    return out
 PRB = 64
 
 
@@ -93,8 +108,8 @@ def dataflow_edges(n, nb):
 
     for k in range(T - 1, -1, -1):
         for i in range(k + 1, T):
-            for j in range(T - 1, k, -1):
-                access((GREV, i, j, k), [q(i, j), ("Lbar", i, k)], [("Lbar", i, k)])
+            for kind, js in grev_tasks(k, T):
+                access((kind, i, min(js), k), [q(i, j) for j in js] + [("Lbar", i, k)], [("Lbar", i, k)])
         for i in range(k + 1, T):
             access((TREV, i, k, k), [("Lbar", i, k)], [("Lbar", i, k), ("P", i, k)])
         for i in range(k + 1, T):
@@ -134,7 +149,8 @@ def test_backward_edges_equal_dataflow(n, nb):
     assert cnt[PREV] == ragged and cnt[PADJM] == cnt[PADJY] == cnt[PADJS] == cnt[TRTRI] == T - ragged
     assert cnt[DRED] == T - ragged
     assert cnt[TREV] == cnt[DPART] == T * (T - 1) // 2
-    assert cnt[GREV] == sum((T - k - 1) ** 2 for k in range(T))
+    assert cnt[GREV] + 2 * cnt[GREV2] == sum((T - k - 1) ** 2 for k in range(T))
+    assert cnt[GREV] == sum((T - k - 1) * (1 + (T - k - 2) % 2) for k in range(T - 1))
 
 
 @pytest.mark.parametrize("policy,seed", [(tc.POLICY_LIST, 0), (tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0),
@@ -159,7 +175,8 @@ def test_backward_ranks_and_parts():
     for t in range(p["ntask"]):
         kind, i, k = int(p["kind"][t]), int(p["i"][t]), int(p["k"][t])
         tri = lambda s: s * (s + 1) // 2
-        want = {GREV: -(-tsz(i) // 128) * -(-tsz(k) // 128), TREV: -(-tsz(i) // 32),
+        want = {GREV: -(-tsz(i) // 128) * -(-tsz(k) // 128), GREV2: -(-tsz(i) // 128) * -(-tsz(k) // 128),
+                TREV: -(-tsz(i) // 32),
                 DPART: tri(-(-tsz(k) // 128)), PREV: 1, DRED: -(-tsz(k) // 16), TRTRI: -(-tsz(k) // 32),
                 PADJM: tri(-(-tsz(k) // PRB)), PADJY: tri(-(-tsz(k) // PRB)), PADJS: tri(-(-tsz(k) // PRB))}[kind]
         assert p["parts"][t] == want
