@@ -271,7 +271,8 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, Diag diag = Diag:
 //                  chain per (i, k) in a fixed order; after the task that
 //                  produced Q_ij: TREV(i, j) (j < i), PREV(i) (j = i) or
 //                  TREV(j, i) (j > i)
-//   TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}  after GREV(i, k, k+1)
+//   TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}  after GREV(i, k, k+1) and TRTRI(k)
+//                  (the product with the explicit inverse)
 //   DPART(i, k)    S_ik = tril(P_ik^T L_ik)  after TREV(i, k)
 //   DRED(k)        Lbar_kk -= sum_i S_ik (i ascending), by 16-row strips,
 //                  after every DPART(i, k)   (k < T-1)
@@ -283,7 +284,7 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, Diag diag = Diag:
 // A diagonal tile whose order is a multiple of 16 takes its adjoint in
 // closed form instead of PREV(k): DRED(k) (then also for k = T-1) leaves
 // Lbar_kk^T in the Q_kk tile, and
-//   TRTRI(k)       L_kk^{-T}, no predecessors (L is an input)
+//   TRTRI(k)       L_kk^{-T}, no predecessors (L is an input); TREV(i, k) uses it too
 //   PADJM(k)       M = Phi(L_kk^T Lbar_kk)         after DRED(k)
 //   PADJY(k)       Y^T = (M L_kk^{-1})^T           after PADJM(k), TRTRI(k)
 //   PADJS(k)       Q_kk = S, Lbar_kk = tril(S)/2   after PADJY(k)
@@ -305,27 +306,36 @@ void build_backward(Builder& b) {
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
   for (int32_t k = T - 1; k >= 0; --k) {
+    const int64_t m = b.tile_size(k);
+    // tasks are numbered so that every edge runs forward: L_kk^{-T} first,
+    // as TREV(i, k) reads it
+    if (closed_form_tile(m)) id_inv[k] = b.add(TK_TRTRI, k, k, k, Builder::cdiv(m, b.s.trsm_rows));
     // the chain into Lbar_ik: its last link (j = k + 1, which waits for the
     // most recent Q tile) alone, the links above it in pairs from the top
     // (one task of K = 2 nb: half the loads and stores of Lbar_ik)
+    // the kinds on the critical path of a step (the last GREV link, TREV,
+    // DPART) work on TCHOL_PRB-order blocks, so that many workgroups share
+    // them; the paired links on 128 x 128 sub-tiles
     for (int32_t i = k + 1; i < T; ++i)
       for (int32_t j = T - 1; j > k; --j) {
-        const int32_t parts = Builder::cdiv(b.tile_size(i), b.s.gemm_m) * Builder::cdiv(b.tile_size(k), b.s.gemm_n);
         if (grev_paired(j, k, T)) {
+          const int32_t parts =
+              Builder::cdiv(b.tile_size(i), b.s.gemm_m) * Builder::cdiv(b.tile_size(k), b.s.gemm_n);
           id_grev[ix3(i, j, k)] = id_grev[ix3(i, j - 1, k)] = b.add(TK_GREV2, i, j - 1, k, parts);
           --j;
         } else {
+          const int32_t parts =
+              Builder::cdiv(b.tile_size(i), TCHOL_PRB) * Builder::cdiv(b.tile_size(k), TCHOL_PRB);
           id_grev[ix3(i, j, k)] = b.add(TK_GREV, i, j, k, parts);
         }
       }
+    // TREV by row blocks through L_kk^{-T} (TRTRI(k); tile k is never the ragged last one)
     for (int32_t i = k + 1; i < T; ++i)
-      id_trev[ix2(i, k)] = b.add(TK_TREV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
-    const int32_t sb = Builder::cdiv(b.tile_size(k), b.s.gemm_m);
+      id_trev[ix2(i, k)] = b.add(TK_TREV, i, k, k, Builder::cdiv(b.tile_size(i), TCHOL_PRB));
+    const int32_t sb = Builder::cdiv(b.tile_size(k), TCHOL_PRB);
     for (int32_t i = k + 1; i < T; ++i) id_dpart[ix2(i, k)] = b.add(TK_DPART, i, k, k, sb * (sb + 1) / 2);
-    const int64_t m = b.tile_size(k);
     if (closed_form_tile(m)) {
       const int32_t nbk = Builder::cdiv(m, TCHOL_PRB), blocks = nbk * (nbk + 1) / 2;
-      id_inv[k] = b.add(TK_TRTRI, k, k, k, Builder::cdiv(m, b.s.trsm_rows));
       id_dred[k] = b.add(TK_DRED, k, k, k, Builder::cdiv(m, 16));
       id_pm[k] = b.add(TK_PADJM, k, k, k, blocks);
       id_py[k] = b.add(TK_PADJY, k, k, k, blocks);
@@ -349,6 +359,8 @@ void build_backward(Builder& b) {
       succ[id_trev[ix2(i, k)]].push_back(id_dpart[ix2(i, k)]);
       succ[id_dpart[ix2(i, k)]].push_back(id_dred[k]);
     }
+    if (id_inv[k] >= 0)
+      for (int32_t i = k + 1; i < T; ++i) succ[id_inv[k]].push_back(id_trev[ix2(i, k)]);
     if (id_pm[k] >= 0) {
       succ[id_dred[k]].push_back(id_pm[k]);
       succ[id_pm[k]].push_back(id_py[k]);

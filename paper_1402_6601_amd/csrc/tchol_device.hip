@@ -192,7 +192,8 @@ struct GemmShape {
 template <int BM, int BN, int KC, int WGM, int NST, int PAD, int SEG, int RB, int CB>
 __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __restrict__ Ap,
                                            const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
-                                           double* lds) {
+                                           double* lds, int64_t ldb_ = -1) {
+  const int64_t ldB = ldb_ < 0 ? ld : ldb_;  // the B panel's leading dimension (default: A's)
   using S = GemmShape<BM, BN, KC, WGM, NST, PAD>;
   static_assert(RB == S::RB && CB == S::CB, "accumulator shape");
   constexpr int ALD = S::ALD, BLD = S::BLD, STAGE = S::STAGE;
@@ -221,7 +222,8 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
   // SEG, u = 0; lane element le falls in k row e0 / R + le / R).  Rows are
   // clamped to the last valid start row Vc; the base takes min(u, Vc), so
   // the lane offsets are never negative.
-  auto xfer = [&](const double* X, int R, int XLD, int V, int q, int k0, double* dst) __attribute__((always_inline)) {
+  auto xfer = [&](const double* X, int64_t ld, int R, int XLD, int V, int q, int k0, double* dst)
+                  __attribute__((always_inline)) {
     const int e0 = q * SEG;
     const int le = SEG == 128 ? 2 * lane : (lane >> 1);
     // a pair starts at an even row no later than V - 1; for odd V the pair
@@ -241,11 +243,11 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
   auto slot = [&](int j, int k0, double* As, double* Bs) __attribute__((always_inline)) {
     const int q = wave + 4 * j;
     if (UNIFORM) {
-      if (j < QA / 4) xfer(Ap, BM, ALD, M, q, k0, As);
-      else xfer(Bp, BN, BLD, N, q - QA, k0, Bs);
+      if (j < QA / 4) xfer(Ap, ld, BM, ALD, M, q, k0, As);
+      else xfer(Bp, ldB, BN, BLD, N, q - QA, k0, Bs);
     } else {
-      if (q < QA) xfer(Ap, BM, ALD, M, q, k0, As);
-      else if (q < QA + QB) xfer(Bp, BN, BLD, N, q - QA, k0, Bs);
+      if (q < QA) xfer(Ap, ld, BM, ALD, M, q, k0, As);
+      else if (q < QA + QB) xfer(Bp, ldB, BN, BLD, N, q - QA, k0, Bs);
     }
   };
   auto issue = [&](int ch) __attribute__((always_inline)) {
@@ -2036,10 +2038,14 @@ __device__ __forceinline__ void prev_tile(const double* __restrict__ Lkk, const 
 #define PRB TCHOL_PRB
 
 // C = -(A0 B0^T [+ A1 B1^T]) for one PRB x PRB block (M, N <= PRB, K a multiple
-// of 16, all four panels at ld); epi(row, col, value) stores each entry.
-template <class Epi>
+// of 16; the A panels at ld, the B panels at ldb, default ld); with Cinit the
+// products are subtracted from C (read at ldc) instead of from zero.
+// epi(row, col, value) stores each entry.  SEG as for gemm_core (128 needs
+// even leading dimensions and 16-byte aligned panels).
+template <int SEG = 128, class Epi>
 __device__ __forceinline__ void padj_block(const double* A0, const double* B0, const double* A1, const double* B1,
-                                           int64_t ld, int M, int N, int K, double* lds, Epi epi) {
+                                           int64_t ld, int M, int N, int K, double* lds, Epi epi, int64_t ldb = -1,
+                                           const double* Cinit = nullptr, int64_t ldc = 0) {
   using S = GemmShape<PRB, PRB, 16, 2, 4, 0>;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -2049,11 +2055,16 @@ __device__ __forceinline__ void padj_block(const double* A0, const double* B0, c
 #pragma unroll
   for (int rb = 0; rb < S::RB; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < S::CB; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
-  gemm_kloop<PRB, PRB, 16, 2, 4, 0, 128>(acc, A0, B0, ld, M, N, K, lds);
+    for (int cb = 0; cb < S::CB; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
+        acc[rb][cb][i] = Cinit ? Cinit[(int64_t)imin(col, N - 1) * ldc + imin(row, M - 1)] : 0.0;
+      }
+  gemm_kloop<PRB, PRB, 16, 2, 4, 0, SEG>(acc, A0, B0, ld, M, N, K, lds, ldb);
   if (A1 != nullptr) {
     __syncthreads();  // the stages are refilled only after every wavefront's last reads
-    gemm_kloop<PRB, PRB, 16, 2, 4, 0, 128>(acc, A1, B1, ld, M, N, K, lds);
+    gemm_kloop<PRB, PRB, 16, 2, 4, 0, SEG>(acc, A1, B1, ld, M, N, K, lds, ldb);
   }
   __syncthreads();
 #pragma unroll
@@ -2065,6 +2076,30 @@ __device__ __forceinline__ void padj_block(const double* A0, const double* B0, c
         const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
         if (row < M && col < N) epi(row, col, acc[rb][cb][i]);
       }
+}
+
+// TREV(i, k) work item through the tile's explicit inverse: rows r0 ..
+// r0 + M - 1 of P_ik = Lbar_ik L_kk^{-1}, with L_kk^{-T} (IT, ld nb, upper
+// triangular) from TRTRI(k).  Lb: those rows of Lbar_ik (ld); P(:, c) reads
+// the columns of Lbar from c on, so the column blocks go left to right and
+// each is written (P / 2 over Lbar, P into Q_ik at Qik and P^T into Q_ki at
+// Qki, both ld ldq) after its own product has read it.  SEG = 128 needs Lb
+// 16-byte aligned with an even ld; 32 serves the rest.
+template <int SEG>
+__device__ __forceinline__ void trev_rows(double* __restrict__ Lb, int64_t ld, const double* __restrict__ IT, int64_t nb,
+                                          int M, int m, double* __restrict__ Qik, double* __restrict__ Qki,
+                                          int64_t ldq, double* lds) {
+  for (int c0 = 0; c0 < m; c0 += PRB) {
+    padj_block<SEG>(Lb + (int64_t)c0 * ld, IT + (int64_t)c0 * nb + c0, nullptr, nullptr, ld, M, imin(PRB, m - c0),
+                    m - c0, lds,
+                    [&](int r, int c, double v) __attribute__((always_inline)) {
+                      const double p = -v;
+                      st_dev(Lb + (int64_t)(c0 + c) * ld + r, 0.5 * p);
+                      st_dev(Qik + (int64_t)(c0 + c) * ldq + r, p);
+                      st_dev(Qki + (int64_t)r * ldq + c0 + c, p);
+                    },
+                    nb);
+  }
 }
 
 // Block (bi, bj), bi >= bj, of the lower triangle from a work item's part.
@@ -2747,34 +2782,55 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           auto slot = [&](int i, int k) __attribute__((always_inline)) {
             return (int64_t)k * (T - 1) - (int64_t)k * (k - 1) / 2 + (i - k - 1);
           };
-          if (kind == TK_GREV || kind == TK_GREV2) {
-            // GREV2: the links j = tj and tj + 1 as one product over their
+          if (kind == TK_GREV) {
+            // a single link (the last of its chain, on the critical path): 64 x 64 blocks
+            const int ncj = (tsz(tk) + PRB - 1) / PRB;
+            const int si = part / ncj, sj = part % ncj;
+            const int M = imin(PRB, tsz(ti) - si * PRB), N = imin(PRB, tsz(tk) - sj * PRB);
+            const int K = (int)(np - (int64_t)tj * nb < nb ? np - (int64_t)tj * nb : nb);
+            double* C = Bbase + (tk * nb + sj * PRB) * ld + ti * nb + si * PRB;
+            padj_block(a.Q + (tj * nb) * ldq + ti * nb + si * PRB, a.LT + (tj * nb) * ldq + tk * nb + sj * PRB, nullptr,
+                       nullptr, ldq, M, N, K, lds,
+                       [&](int r, int c, double v) __attribute__((always_inline)) {
+                         st_dev(C + (int64_t)c * ld + r, v);
+                       },
+                       -1, C, ld);
+          } else if (kind == TK_GREV2) {
+            // the links j = tj and tj + 1 as one product over their
             // consecutive columns of Q and L^T (K = 2 nb, less at the padded end)
             const int ncj = (tsz(tk) + a.gemm_n - 1) / a.gemm_n;
             const int si = part / ncj, sj = part % ncj;
             const int M = imin(a.gemm_m, tsz(ti) - si * a.gemm_m);
             const int N = imin(a.gemm_n, tsz(tk) - sj * a.gemm_n);
-            const int64_t kw = (kind == TK_GREV2 ? 2 : 1) * nb;
+            const int64_t kw = 2 * nb;
             const int K = (int)(np - (int64_t)tj * nb < kw ? np - (int64_t)tj * nb : kw);
             gemm_nt_ex(Bbase + (tk * nb + sj * a.gemm_n) * ld + ti * nb + si * a.gemm_m, ld,
                        a.Q + (tj * nb) * ldq + ti * nb + si * a.gemm_m, a.LT + (tj * nb) * ldq + tk * nb + sj * a.gemm_n,
                        ldq, M, N, K, false, false, lds);
           } else if (kind == TK_TREV) {
-            const int r0 = part * a.trsm_rows;
-            const int S = imin(a.trsm_rows, tsz(ti) - r0);
-            trsm_strip<double, 1>(Bbase + (tk * nb) * ld + ti * nb + r0, ld, a.LT + (tk * nb) * ldq + tk * nb, ldq, S,
-                                  tsz(tk), lds, a.Q + (tk * nb) * ldq + ti * nb + r0,
-                                  a.Q + (ti * nb + r0) * ldq + tk * nb, ldq);
+            // 64-row blocks of P_ik through L_kk^{-T} from TRTRI(k) (tile k is
+            // never the ragged last one, so its order is a multiple of 16)
+            const int r0 = part * PRB;
+            double* Lb = Bbase + (tk * nb) * ld + ti * nb + r0;
+            const int M = imin(PRB, tsz(ti) - r0);
+            double* Qik = a.Q + (tk * nb) * ldq + ti * nb + r0;
+            double* Qki = a.Q + (ti * nb + r0) * ldq + tk * nb;
+            const double* IT = DinvTSys + (int64_t)tk * nb * nb;
+            if ((ld & 1) == 0 && (reinterpret_cast<uintptr_t>(Bbase) & 15) == 0)
+              trev_rows<128>(Lb, ld, IT, nb, M, tsz(tk), Qik, Qki, ldq, lds);
+            else
+              trev_rows<32>(Lb, ld, IT, nb, M, tsz(tk), Qik, Qki, ldq, lds);
           } else if (kind == TK_DPART) {
-            int si = 0;
-            while ((si + 1) * (si + 2) / 2 <= part) ++si;
-            const int sj = part - si * (si + 1) / 2;
-            const int M = imin(a.gemm_m, tsz(tk) - si * a.gemm_m);
-            const int N = imin(a.gemm_n, tsz(tk) - sj * a.gemm_n);
+            // 64 x 64 block (bi, bj) of the lower triangle of the slot, -(P_ik^T L_ik)
+            int bi, bj;
+            lower_block(part, bi, bj);
+            const int M = imin(PRB, tsz(tk) - bi * PRB), N = imin(PRB, tsz(tk) - bj * PRB);
             const int K = (int)(np - (int64_t)ti * nb < nb ? np - (int64_t)ti * nb : nb);
-            gemm_nt_ex(a.D + slot(ti, tk) * nb * nb + (sj * a.gemm_n) * nb + si * a.gemm_m, nb,
-                       a.Q + (ti * nb) * ldq + tk * nb + si * a.gemm_m, a.LT + (ti * nb) * ldq + tk * nb + sj * a.gemm_n,
-                       ldq, M, N, K, si == sj, true, lds);
+            double* Sk = a.D + slot(ti, tk) * nb * nb + (int64_t)(bj * PRB) * nb + bi * PRB;
+            padj_block(a.Q + (ti * nb) * ldq + tk * nb + bi * PRB, a.LT + (ti * nb) * ldq + tk * nb + bj * PRB, nullptr,
+                       nullptr, ldq, M, N, K, lds, [&](int r, int c, double v) __attribute__((always_inline)) {
+                         if (bi != bj || r >= c) st_dev(Sk + (int64_t)c * nb + r, v);
+                       });
           } else if (kind == TK_DRED) {
             // a tile whose order is a multiple of 16 takes the closed-form adjoint,
             // which reads Lbar_kk^T from the Q_kk tile

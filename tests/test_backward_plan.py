@@ -3,7 +3,8 @@
 The reverse program, per step k from T-1 down to 0,
     GREV(i, k, j)  Lbar_ik -= Q_ij L_jk      i > k, j = T-1 .. k+1 (links above
                    k+1 paired from the top into GREV2 tasks of two)
-    TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}   (writes Q_ik and Q_ki)
+    TREV(i, k)     P_ik = Lbar_ik L_kk^{-1}   (writes Q_ik and Q_ki; through
+                   L_kk^{-T} from TRTRI(k))
     DPART(i, k)    S_ik = tril(P_ik^T L_ik)
     DRED(k)        Lbar_kk -= sum_i S_ik     (k < T-1)
     PREV(k)        P_kk (writes Q_kk)
@@ -110,12 +111,13 @@ def dataflow_edges(n, nb):
         for i in range(k + 1, T):
             for kind, js in grev_tasks(k, T):
                 access((kind, i, min(js), k), [q(i, j) for j in js] + [("Lbar", i, k)], [("Lbar", i, k)])
+        if closed(tsz(k)):   # L_kk^{-T}, for TREV and the tile's adjoint
+            access((TRTRI, k, k, k), [], [("IT", k)])
         for i in range(k + 1, T):
-            access((TREV, i, k, k), [("Lbar", i, k)], [("Lbar", i, k), ("P", i, k)])
+            access((TREV, i, k, k), [("Lbar", i, k), ("IT", k)], [("Lbar", i, k), ("P", i, k)])
         for i in range(k + 1, T):
             access((DPART, i, k, k), [("P", i, k)], [("S", i, k)])
         if closed(tsz(k)):
-            access((TRTRI, k, k, k), [], [("IT", k)])
             # Lbar_kk^T goes into the storage of the P tile behind Q_kk
             access((DRED, k, k, k), [("S", i, k) for i in range(k + 1, T)] + [("Lbar", k, k)],
                    [("Lbar", k, k), ("P", k, k)])
@@ -175,9 +177,9 @@ def test_backward_ranks_and_parts():
     for t in range(p["ntask"]):
         kind, i, k = int(p["kind"][t]), int(p["i"][t]), int(p["k"][t])
         tri = lambda s: s * (s + 1) // 2
-        want = {GREV: -(-tsz(i) // 128) * -(-tsz(k) // 128), GREV2: -(-tsz(i) // 128) * -(-tsz(k) // 128),
-                TREV: -(-tsz(i) // 32),
-                DPART: tri(-(-tsz(k) // 128)), PREV: 1, DRED: -(-tsz(k) // 16), TRTRI: -(-tsz(k) // 32),
+        want = {GREV: -(-tsz(i) // PRB) * -(-tsz(k) // PRB), GREV2: -(-tsz(i) // 128) * -(-tsz(k) // 128),
+                TREV: -(-tsz(i) // PRB),
+                DPART: tri(-(-tsz(k) // PRB)), PREV: 1, DRED: -(-tsz(k) // 16), TRTRI: -(-tsz(k) // 32),
                 PADJM: tri(-(-tsz(k) // PRB)), PADJY: tri(-(-tsz(k) // PRB)), PADJS: tri(-(-tsz(k) // PRB))}[kind]
         assert p["parts"][t] == want
     # the inverses have no predecessors and a large weight: the first task
