@@ -681,7 +681,8 @@ def main():
     # for the record: the factorization and the solve as two launches
     Wt = work[0]
     Wt.copy_(A0)
-    _, factor_alone_ms = tc.factor_(Wt, nb, policy=policy, ws=ws_f, want_kernel_ms=True)
+    # the factorization alone, with the merged launch's TRSMs (through the inverses)
+    _, factor_alone_ms = tc.factor_(Wt, nb, policy=policy, ws=ws_f, want_kernel_ms=True, inv_trsm=True)
     Bt = rhs[0]
     Bt.copy_(B0c)
     torch.cuda.synchronize()

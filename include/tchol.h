@@ -117,6 +117,17 @@ typedef struct tchol_opts {
                           A value outside [0, 8] returns -i for the opts
                           argument i.  The tuned tables choose it per order
                           bucket.                                               */
+  int32_t inv_trsm;    /* tchol_factor_ex: 1 factors as tchol_factor_solve does:
+                          TRSM(i, k) applies L_kk^{-1} (from TRTRI(k) in the same
+                          launch, between POTRF(k) and the step's TRSMs) by
+                          128-row blocks on the matrix cores, so the factor is
+                          bitwise that of tchol_factor_solve; its backward error
+                          grows with the condition of the diagonal tiles (as for
+                          the solve with subst = 0).  0 (the default): TRSM by
+                          substitution (exact on integer data whose
+                          intermediates are exact).  tchol_factor_solve applies
+                          the inverses in its TRSMs whenever its solve does
+                          (subst = 0).                                          */
 } tchol_opts;
 
 /* Bytes of device workspace needed by `op` (TCHOL_OP_FACTOR, _SOLVE or

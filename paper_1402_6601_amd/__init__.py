@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("seed", ctypes.c_uint32), ("wait_limit_us", ctypes.c_int64),
                 ("kernel_ms", ctypes.POINTER(ctypes.c_float)), ("trace", ctypes.c_void_p),
                 ("trace_words", ctypes.c_int64), ("subst", ctypes.c_int32),
-                ("wgs", ctypes.POINTER(ctypes.c_int32))]
+                ("wgs", ctypes.POINTER(ctypes.c_int32)), ("inv_trsm", ctypes.c_int32)]
 
 
 def load() -> ctypes.CDLL:
@@ -264,10 +264,12 @@ def _opts(policy, seed, wait_limit_us, want_ms, trace, subst=False):
 
 
 def factor_(A, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_us: int = 0, ws=None,
-            want_kernel_ms: bool = False, trace=None, check: bool = True):
+            want_kernel_ms: bool = False, trace=None, check: bool = True, inv_trsm: bool = False):
     """Factor in place.  A: CUDA float64 (n, n) contiguous, symmetric (only the
     lower triangle of its column-major reading, i.e. the row-major upper
-    triangle, is read).  Returns info (0 = success), or (info, kernel_ms)."""
+    triangle, is read).  inv_trsm: TRSMs through the diagonal tiles' explicit
+    inverses, as in factor_solve_ (tchol_opts.inv_trsm).  Returns info
+    (0 = success), or (info, kernel_ms)."""
     torch = _torch()
     if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
         raise ValueError("A must be a contiguous square float64 tensor")
@@ -280,6 +282,7 @@ def factor_(A, nb: int, *, policy: int = POLICY_LIST, seed: int = 0, wait_limit_
         if ws is None or ws.numel() < need:
             ws = _workspace(torch, need, A.device)
         o, ms = _opts(policy, seed, wait_limit_us, want_kernel_ms, trace)
+        o.inv_trsm = 1 if inv_trsm else 0
         rc = lib.tchol_factor_ex(ctypes.c_void_p(A.data_ptr()), n, nb, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                  _stream_ptr(torch, A.device), ctypes.byref(o))
     if rc < 0 and check:

@@ -87,6 +87,7 @@ struct Builder {
 // ids of one system's tasks, for the edges between its factor and solve DAGs
 struct FactorIds {
   std::vector<int32_t> potrf, trsm;  // trsm[i * T + k]
+  std::vector<int32_t> trtri;        // inverse-TRSM factorizations: TRTRI(k) for k < T-1, else -1
 };
 
 // The mixed-precision factorization (OP_FACTOR_INV) has its own costs: its
@@ -139,10 +140,14 @@ int32_t potrf_parts(int64_t m) {
 
 // trtri: add TRTRI(k) after POTRF(k) (explicit inverses for the
 // mixed-precision solve; no task of the factorization waits for them).
-void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
+// inv_trsm: TRSM(i, k) applies L_kk^{-1} from TRTRI(k), which runs between
+// POTRF(k) and the step's TRSMs (k < T-1: every tile with a TRSM below it is
+// a full one), by 128-row blocks on the matrix cores.
+void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false, bool inv_trsm = false) {
   auto& succ = b.succ;
   const int32_t T = b.T;
   std::vector<int32_t> id_potrf(T, -1), id_trsm((size_t)T * T, -1), id_syrk((size_t)T * T, -1);
+  std::vector<int32_t> id_inv(T, -1);
   std::vector<int32_t> id_gemm((size_t)T * T * T, -1);
   auto ix2 = [T](int32_t i, int32_t k) { return (size_t)i * T + k; };
   auto ix3 = [T](int32_t i, int32_t j, int32_t k) { return ((size_t)k * T + i) * T + j; };
@@ -168,8 +173,10 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
     id_potrf[k] = b.add(TK_POTRF, k, k, k,
                         T > 1 ? potrf_parts(b.tile_size(k))
                               : (wgs > 1 && b.tile_size(k) > 128 ? std::min(wgs, potrf_parts(b.tile_size(k))) : 1));
+    if (inv_trsm && k + 1 < T) id_inv[k] = b.add(TK_TRTRI, k, k, k, Builder::cdiv(b.tile_size(k), b.s.trsm_rows));
     for (int32_t i = k + 1; i < T; ++i)
-      id_trsm[ix2(i, k)] = b.add(TK_TRSM, i, k, k, Builder::cdiv(b.tile_size(i), b.s.trsm_rows));
+      id_trsm[ix2(i, k)] =
+          b.add(TK_TRSM, i, k, k, Builder::cdiv(b.tile_size(i), inv_trsm ? b.s.gemm_m : b.s.trsm_rows));
     for (int32_t i = k + 1; i < T; ++i) {
       int32_t sb = Builder::cdiv(b.tile_size(i), b.s.syrk_b);
       id_syrk[ix2(i, k)] = b.add(TK_SYRK, i, i, k, sb * (sb + 1) / 2);
@@ -184,7 +191,12 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
     }
   }
   for (int32_t k = 0; k < T; ++k) {
-    for (int32_t i = k + 1; i < T; ++i) succ[id_potrf[k]].push_back(id_trsm[ix2(i, k)]);
+    if (id_inv[k] >= 0) {
+      succ[id_potrf[k]].push_back(id_inv[k]);
+      for (int32_t i = k + 1; i < T; ++i) succ[id_inv[k]].push_back(id_trsm[ix2(i, k)]);
+    } else {
+      for (int32_t i = k + 1; i < T; ++i) succ[id_potrf[k]].push_back(id_trsm[ix2(i, k)]);
+    }
     for (int32_t i = k + 1; i < T; ++i) {
       auto& st = succ[id_trsm[ix2(i, k)]];
       st.push_back(id_syrk[ix2(i, k)]);
@@ -208,6 +220,7 @@ void build_factor(Builder& b, FactorIds* ids = nullptr, bool trtri = false) {
   if (ids) {
     ids->potrf = id_potrf;
     ids->trsm = id_trsm;
+    ids->trtri = id_inv;
   }
 }
 
@@ -227,8 +240,11 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, Diag diag = Diag:
     return diag == Diag::kInvGiven || (diag == Diag::kInvHere && b.tile_size(k) % 16 == 0);
   };
   auto dparts = [&](int32_t k) { return inv(k) ? Builder::cdiv(b.tile_size(k), b.s.gemv_rows) : 1; };
+  // the factorization's own inverses (inverse-TRSM factorizations) serve the solve as well
+  auto given = [&](int32_t k) { return after && !after->trtri.empty() && after->trtri[k] >= 0; };
   for (int32_t k = 0; k < T; ++k) {
-    if (diag == Diag::kInvHere && inv(k)) id_tri[k] = b.add(TK_TRTRI, k, k, k, Builder::cdiv(b.tile_size(k), b.s.trsm_rows));
+    if (diag == Diag::kInvHere && inv(k) && !given(k))
+      id_tri[k] = b.add(TK_TRTRI, k, k, k, Builder::cdiv(b.tile_size(k), b.s.trsm_rows));
     id_ft[k] = b.add(TK_FTRSV, k, k, k, dparts(k));
     for (int32_t i = k + 1; i < T; ++i)
       id_fg[ix2(i, k)] = b.add(TK_FGEMV, i, k, k, Builder::cdiv(b.tile_size(i), b.s.gemv_rows));
@@ -243,7 +259,10 @@ void build_solve(Builder& b, const FactorIds* after = nullptr, Diag diag = Diag:
   if (after) {
     // the solve of a system reads the final tiles of its factor
     for (int32_t k = 0; k < T; ++k) {
-      succ[after->potrf[k]].push_back(id_tri[k] >= 0 ? id_tri[k] : id_ft[k]);
+      if (given(k) && diag == Diag::kInvHere)
+        succ[after->trtri[k]].push_back(id_ft[k]);
+      else
+        succ[after->potrf[k]].push_back(id_tri[k] >= 0 ? id_tri[k] : id_ft[k]);
       for (int32_t i = k + 1; i < T; ++i) succ[after->trsm[ix2(i, k)]].push_back(id_fg[ix2(i, k)]);
     }
   }
@@ -386,8 +405,11 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
     step = p.tk[t] + 1;
     kord = TK_GEMM;
   }
-  if (kind == TK_TRTRI && p.op != OP_FACTOR_INV) {  // the FP64 solve's (the adjoint's) inverses: first in their step
-    if (p.op == TCHOL_OP_BATCHED) step += T;
+  // the inverses that the factorization's TRSMs apply: right after POTRF(k)
+  const bool factor_inv = kind == TK_TRTRI && (p.op == OP_FACTOR_INVT || (p.op == TCHOL_OP_BATCHED && p.inv &&
+                                                                          p.tk[t] + 1 < T));
+  if (kind == TK_TRTRI && p.op != OP_FACTOR_INV && !factor_inv) {  // the FP64 solve's (the adjoint's) inverses:
+    if (p.op == TCHOL_OP_BATCHED) step += T;                        // first in their step
     kord = -1;
   }
   if (kind == TK_BTRSV) kord = 0;  // within a backward step: BTRSV before BGEMV
@@ -404,7 +426,9 @@ std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t> tie_key(const Plan& p, i
   if (kind == TK_PADJS) kord = 6;
   // the chain of GREV(i, k, j) into Lbar_ik runs j downwards
   const int32_t tj = (kind == TK_GREV || kind == TK_GREV2) ? T - 1 - p.tj[t] : p.tj[t];
-  return std::make_tuple(p.sys[t], step, kord, p.ti[t], tj);
+  // kinds in steps of two, so that a factorization's TRTRI(k) sits between
+  // POTRF(k) and the TRSMs of step k
+  return std::make_tuple(p.sys[t], step, factor_inv ? 2 * TK_POTRF + 1 : 2 * kord, p.ti[t], tj);
 }
 
 uint32_t xorshift32(uint32_t& x) {
@@ -554,6 +578,15 @@ bool finalize(Plan& p, std::vector<std::vector<int32_t>>& succ, int32_t policy, 
         if (--indeg[p.succ[e]] == 0) ready.push_back(p.succ[e]);
     }
   }
+  // every policy's order must be topological: the persistent kernel's
+  // freedom from deadlock rests on it (a plan that broke it is refused)
+  {
+    std::vector<int32_t> pos(nt);
+    for (int64_t q = 0; q < nt; ++q) pos[p.order[q]] = (int32_t)q;
+    for (int64_t t = 0; t < nt; ++t)
+      for (int32_t e = p.succ_off[t]; e < p.succ_off[t + 1]; ++e)
+        if (pos[p.succ[e]] < pos[t]) return false;
+  }
   int64_t ni = 0;
   for (int64_t t = 0; t < nt; ++t) ni += p.parts[t];
   if (ni > (int64_t)INT32_MAX / 2) return false;
@@ -597,6 +630,8 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
   Builder b(p, split, succ, 0);
   if (op == TCHOL_OP_FACTOR)
     build_factor(b);
+  else if (op == OP_FACTOR_INVT)
+    build_factor(b, nullptr, false, true);
   else if (op == OP_FACTOR_INV)
     build_factor(b, nullptr, true);
   else if (op == TCHOL_OP_SOLVE)
@@ -609,7 +644,7 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
     build_backward(b);
   else
     return nullptr;
-  p.inv = op == TCHOL_OP_SOLVE;
+  p.inv = op == TCHOL_OP_SOLVE || op == OP_FACTOR_INVT;
   if (!finalize(p, succ, policy, seed)) return nullptr;
   return plan;
 }
@@ -636,7 +671,7 @@ std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int
     if (p.systems[s].T == 0) continue;
     Builder b(p, split, succ, s);
     FactorIds ids;
-    build_factor(b, &ids);
+    build_factor(b, &ids, false, p.inv);
     build_solve(b, &ids, p.inv ? Diag::kInvHere : Diag::kSubst);
   }
   if (p.ntask() == 0) {

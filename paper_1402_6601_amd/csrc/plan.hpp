@@ -63,6 +63,10 @@ constexpr int32_t OP_FACTOR_INV = 16;
 constexpr int32_t OP_SOLVE_INV = 17;
 // The FP64 solve by substitution against the diagonal tiles (tchol_opts.subst).
 constexpr int32_t OP_SOLVE_SUBST = 18;
+// The FP64 factorization whose TRSM tasks apply the diagonal tiles' explicit
+// inverses (TRTRI(k) between POTRF(k) and TRSM(., k); tchol_opts.inv_trsm):
+// the factorization of the merged factor + solve launch, alone.
+constexpr int32_t OP_FACTOR_INVT = 19;
 
 // Work-item granularity (rows x cols of one work item of each task kind).
 struct Split {

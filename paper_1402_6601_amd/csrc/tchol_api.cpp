@@ -80,7 +80,7 @@ Layout layout_of(const Plan& p) {
 // inv), after the scheduler's regions: L_kk^{-T} of every diagonal tile
 // (nb x nb FP64 each) and y (n x nrhs FP64).
 struct InvLayout {
-  int64_t dinvt = 0, sx = 0, end = 0;
+  int64_t dinvt = 0, dinv = 0, sx = 0, end = 0;
 };
 
 InvLayout inv_layout(const Plan& p, int64_t nrhs) {
@@ -90,7 +90,8 @@ InvLayout inv_layout(const Plan& p, int64_t nrhs) {
   const tchol::System& sy = p.systems[0];
   const int64_t T = sy.n == 0 ? 0 : (sy.n + sy.nb - 1) / sy.nb;
   V.dinvt = align_up(V.end);
-  V.sx = align_up(V.dinvt + 8 * T * sy.nb * sy.nb);
+  V.dinv = align_up(V.dinvt + 8 * T * sy.nb * sy.nb);  // L_kk^{-1}, for the TRSM items
+  V.sx = align_up(V.dinv + 8 * T * sy.nb * sy.nb);
   V.end = align_up(V.sx + 8 * sy.n * std::max<int64_t>(nrhs, 1));
   return V;
 }
@@ -224,7 +225,7 @@ bool policy_ok(int32_t p) { return p >= TCHOL_POLICY_LIST && p <= TCHOL_POLICY_R
 
 bool nb_ok(int64_t nb) { return nb >= TCHOL_NB_MIN && nb <= TCHOL_NB_MAX && nb % 16 == 0; }
 
-const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr, 0, 0, nullptr};
+const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr, 0, 0, nullptr, 0};
 
 // Uploads the plan image, launches reset + persistent kernel on the stream,
 // reads the header back and synchronises.  sinfo_out (batched): per-system
@@ -328,7 +329,10 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
             void* stream_v, const tchol_opts* opts, int32_t ws_arg) {
   const tchol_opts& o = opts ? *opts : kDefaultOpts;
   if (!policy_ok(o.policy)) return TCHOL_E_UNSUPPORTED;
-  auto plan = tchol::get_plan(op == TCHOL_OP_SOLVE && o.subst ? tchol::OP_SOLVE_SUBST : op, n, nb, o.policy, o.seed);
+  const int32_t pop = op == TCHOL_OP_SOLVE && o.subst        ? tchol::OP_SOLVE_SUBST
+                     : op == TCHOL_OP_FACTOR && o.inv_trsm ? tchol::OP_FACTOR_INVT
+                                                           : op;
+  auto plan = tchol::get_plan(pop, n, nb, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
   if (o.trace && o.trace_words / 4 < plan->nitem()) return -(ws_arg + 3);
   auto img = image_of(plan);
@@ -338,9 +342,10 @@ int32_t run(int32_t op, double* A, double* B, int64_t n, int64_t nb, int64_t nrh
   if (ws_bytes < V.end) return -(ws_arg + 1);
   char* w = static_cast<char*>(ws);
   double* DinvT = plan->inv ? reinterpret_cast<double*>(w + V.dinvt) : nullptr;
+  double* Dinv = plan->inv ? reinterpret_cast<double*>(w + V.dinv) : nullptr;
   double* Sx = plan->inv ? reinterpret_cast<double*>(w + V.sx) : nullptr;
   return execute(*plan, *img, A, B, nrhs, wide, false, ws, ws_bytes, stream_v, o, ws_arg, nullptr, nullptr, 0,
-                 nullptr, nullptr, 0, nullptr, DinvT, Sx);
+                 nullptr, nullptr, 0, Dinv, DinvT, Sx);
 }
 
 void fill_query(const Plan& pl, int64_t* counts, int32_t* kind, int32_t* ti, int32_t* tj, int32_t* tk, int32_t* sys,
@@ -546,9 +551,10 @@ int32_t factor_solve_run(double* A, int64_t n, int64_t nb, double* B, int64_t nr
   int32_t info = 0;
   char* w = static_cast<char*>(ws);
   double* DinvT = plan->inv ? reinterpret_cast<double*>(w + V.dinvt) : nullptr;
+  double* Dinv = plan->inv ? reinterpret_cast<double*>(w + V.dinv) : nullptr;
   double* Sx = plan->inv ? reinterpret_cast<double*>(w + V.sx) : nullptr;
   const int32_t rc = execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 6, &info, nullptr, 0,
-                             nullptr, nullptr, 0, nullptr, DinvT, Sx);
+                             nullptr, nullptr, 0, Dinv, DinvT, Sx);
   if (rc != 0) return rc;
   return info;
 }
@@ -562,11 +568,18 @@ int64_t tchol_workspace_bytes(int32_t op, int64_t n, int64_t nb, int64_t nrhs) {
   if (n < 0) return -2;
   if (!nb_ok(nb)) return -3;
   if (op == TCHOL_OP_SOLVE && nrhs < 0) return -4;
-  auto plan = tchol::get_plan(op, n, nb, TCHOL_POLICY_RANK, 0);
+  // the factorization's workspace covers opts.inv_trsm (its DAG and inverses)
+  auto plan = tchol::get_plan(op == TCHOL_OP_FACTOR ? tchol::OP_FACTOR_INVT : op, n, nb, TCHOL_POLICY_RANK, 0);
   if (!plan) return TCHOL_E_UNSUPPORTED;
   if (op == TCHOL_OP_BACKWARD) return back_layout(n, nb, *plan).end;
   // every policy yields the same task, edge and item counts, hence the same layout
-  return inv_layout(*plan, nrhs).end;
+  int64_t end = inv_layout(*plan, nrhs).end;
+  if (op == TCHOL_OP_FACTOR) {
+    auto plain = tchol::get_plan(TCHOL_OP_FACTOR, n, nb, TCHOL_POLICY_RANK, 0);
+    if (!plain) return TCHOL_E_UNSUPPORTED;
+    end = std::max(end, inv_layout(*plain, nrhs).end);
+  }
+  return end;
 }
 
 int32_t tchol_factor_ex(double* A, int64_t n, int64_t nb, void* ws, int64_t ws_bytes, void* stream,

@@ -333,12 +333,14 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
 }
 
 // ldc: leading dimension of C when it differs from the panels' (< 0: ld);
-// zero_c: start from C = 0 instead of loading C.
+// zero_c: start from C = 0 instead of loading C; ldb: the B panel's leading
+// dimension when it differs from A's (< 0: ld); neg: store -C.
 template <int SEG, int BM, int BN, int KC, int WGM, int NST, int PAD = 8>
 __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* __restrict__ Ap,
                                           const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
                                           bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0,
-                                          int64_t ldc = -1, bool zero_c = false) {
+                                          int64_t ldc = -1, bool zero_c = false, int64_t ldb = -1,
+                                          bool neg = false) {
   const int64_t ldC = ldc < 0 ? ld : ldc;
   using S = GemmShape<BM, BN, KC, WGM, NST, PAD>;
   constexpr int RB = S::RB, CB = S::CB;
@@ -358,7 +360,7 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
         acc[rb][cb][i] = zero_c ? 0.0 : C[(int64_t)imin(col, N - 1) * ldC + imin(row, M - 1)];
       }
 
-  gemm_kloop<BM, BN, KC, WGM, NST, PAD, SEG>(acc, Ap, Bp, ld, M, N, K, lds);
+  gemm_kloop<BM, BN, KC, WGM, NST, PAD, SEG>(acc, Ap, Bp, ld, M, N, K, lds, ldb);
   __syncthreads();  // every wavefront is done with the stages before LDS is reused
 
 #pragma unroll
@@ -369,10 +371,11 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
       for (int i = 0; i < 4; ++i) {
         const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
         if (row < M && col < N && (!lower_only || row >= col)) {
+          const double v = neg ? -acc[rb][cb][i] : acc[rb][cb][i];
           if (Cl)
-            Cl[col * ldl + row] = acc[rb][cb][i];  // result kept in LDS (column-major, ld ldl)
+            Cl[col * ldl + row] = v;  // result kept in LDS (column-major, ld ldl)
           else
-            st_dev(C + (int64_t)col * ldC + row, acc[rb][cb][i]);
+            st_dev(C + (int64_t)col * ldC + row, v);
         }
       }
 }
@@ -1360,6 +1363,29 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
       const int r = idx / mk, c = idx - r * mk;
       st_dev(Qb + (int64_t)r * ldq + c, Xs[(r >> 4) * 8192 + (mk - 1 - c) * 16 + (r & 15)]);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// TRSM work item through the diagonal tile's explicit inverse (FP64 launches
+// that compute it, TRTRI(k) before TRSM(i, k)): rows of A_ik, X := X L_kk^{-T}
+// = X (L_kk^{-1})^T, one 128-row block per item, as products with L_kk^{-1}
+// (Linv, column-major, ld nb; entry (c, t) is zero for t > c) on the matrix
+// cores.  Column block c of the result reads the columns of X up to the
+// block's end, so the blocks go from the right to the left, each written
+// after its own product has read it; no other item touches these rows.
+template <int SEG>
+__device__ __forceinline__ void trsm_inv_rows(double* __restrict__ X, int64_t ld, const double* __restrict__ Linv,
+                                              int64_t nb, int M, int mk, double* lds) {
+  for (int c0 = ((mk - 1) / GB) * GB; c0 >= 0; c0 -= GB) {
+    const int N = imin(GB, mk - c0), K = c0 + N;
+    // C = 0 - X Linv^T over K, stored negated
+    if (K % 32 == 0)
+      gemm_core<SEG, GB, GB, 32, 2, 2>(X + (int64_t)c0 * ld, X, Linv + c0, ld, M, N, K, false, lds, nullptr, 0, -1,
+                                       true, nb, true);
+    else
+      gemm_core<SEG, GB, GB, 16, 2, 4>(X + (int64_t)c0 * ld, X, Linv + c0, ld, M, N, K, false, lds, nullptr, 0, -1,
+                                       true, nb, true);
   }
 }
 
@@ -2579,6 +2605,11 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
             else
               trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dk, nb, S, tsz(tk), lds);
           }
+        } else if (a.inv != 0 && unit < 0) {
+          // a 128-row block of A_ik through L_kk^{-1} (the launch's TRTRI(k))
+          const int r0 = part * GB;
+          trsm_inv_rows<SEG>(Abase + (tk * nb) * ld + ti * nb + r0, ld, DinvSys + (int64_t)tk * nb * nb, nb,
+                             imin(GB, tsz(ti) - r0), tsz(tk), lds);
         } else {
           // a strip of A_ik, or of sub-block (r, b) of the diagonal tile for a pool unit
           const bool sub = unit >= 0;
@@ -2736,8 +2767,9 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           // L_kk^{-T} by 32-row strips: identity rows solved in place (into DinvT, ld nb).
           // The mixed-precision factorization reads its FP64 diagonal tile,
           // identity-padded when ragged, and also stores the transposes as
-          // L_kk^{-1} (Dinv); the FP64 solve and the adjoint read L_kk in A (its
-          // order is then a multiple of 16) and keep L_kk^{-T} only.
+          // L_kk^{-1} (Dinv); the FP64 launches read L_kk in A (its order is
+          // then a multiple of 16) and keep L_kk^{-1} as well (for the TRSM
+          // items), the adjoint L_kk^{-T} only.
           const int mpad = (tsz(tk) + 15) & ~15;
           const int r0 = part * a.trsm_rows;
           const int S = imin(a.trsm_rows, mpad - r0);
@@ -2748,7 +2780,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           }
           wait_vmcnt<0>();
           __syncthreads();
-          if constexpr (MODE == 0 || MODE == 3)  // the adjoint: L (its A) is the factor
+          if constexpr (MODE == 0)  // with L_kk^{-1} too (Dinv), which the TRSM items apply
+            trsm_strip<double, 2>(X, nb, Abase + (tk * nb) * ld + tk * nb, ld, S, mpad, lds, nullptr,
+                                  DinvSys + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
+          else if constexpr (MODE == 3)  // the adjoint: L (its A) is the factor
             trsm_strip<double>(X, nb, Abase + (tk * nb) * ld + tk * nb, ld, S, mpad, lds);
           else
             trsm_strip<double, 2>(X, nb, Dsys + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,

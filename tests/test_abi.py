@@ -68,7 +68,11 @@ def test_factor_validation_before_any_hip_call(lib):
     assert lib.tchol_factor(None, 256, 64, FAKE, need, None) == -1
     assert lib.tchol_factor(FAKE, 256, 64, None, need, None) == -4
     assert lib.tchol_factor(FAKE, 256, 64, FAKE, 0, None) == -5
-    assert lib.tchol_factor(FAKE, 256, 64, FAKE, need - 256, None) == -5   # too small
+    assert lib.tchol_factor(FAKE, 256, 64, FAKE, 1024, None) == -5        # too small
+    # the query covers the inverse-applying TRSMs (opts.inv_trsm), which need all of it
+    o = tc.Opts()
+    o.inv_trsm = 1
+    assert lib.tchol_factor_ex(FAKE, 256, 64, FAKE, need - 256, None, ctypes.byref(o)) == -5
     assert lib.tchol_factor(FAKE, 256, 64, FAKE_MISALIGNED, need, None) == -4
 
 

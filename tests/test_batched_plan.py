@@ -54,11 +54,12 @@ def reduce_transitively(out, keep=lambda b: False):
     return {(a, b) for (a, b) in out if keep(b) or not reachable(a, b)}
 
 
-def dataflow_edges_factor_solve(T, inv=()):
+def dataflow_edges_factor_solve(T, inv=(), tri=False):
     """Program-order replay of the tile factorization then the two tiled
     substitutions; edges join each access to the last writer of the datum
     (tiles ("L", i, j), right-hand-side blocks ("B", i); for the diagonal
-    tiles in ``inv``, their inverses ("D", k) and the blocks ("S", k) of y)."""
+    tiles in ``inv``, their inverses ("D", k) and the blocks ("S", k) of y).
+    tri: the factorization's TRSMs apply the inverses of tiles 0 .. T-2."""
     last_writer = {}
     out = set()
 
@@ -69,9 +70,10 @@ def dataflow_edges_factor_solve(T, inv=()):
         for d in writes:
             last_writer[d] = task
 
-    for task, reads, writes in tiled_ref.factor_program(T):
-        access(task, [("L",) + r for r in reads], [("L",) + w for w in writes])
-    for task, reads, writes in tiled_ref.solve_program(T, inv):
+    tile = lambda d: d if isinstance(d[0], str) else ("L",) + d
+    for task, reads, writes in tiled_ref.factor_program(T, tri):
+        access(task, [tile(r) for r in reads], [tile(w) for w in writes])
+    for task, reads, writes in tiled_ref.solve_program(T, inv, given=range(T - 1) if tri else ()):
         access(task, reads, writes)
     return reduce_transitively(out, keep=lambda b: b[0] in (POTRF, TRSM, SYRK, GEMM, tiled_ref.GEMM2))
 
@@ -116,10 +118,10 @@ def test_batched_edges_equal_dataflow(n, nb):
 
 @pytest.mark.parametrize("n,nb", [(16, 16), (100, 16), (1024, 128), (1000, 128), (200, 64)])
 def test_factor_solve_plan_equals_dataflow(n, nb):
-    """The merged factor + solve launch of one system: its solve computes the
-    explicit inverse of every diagonal tile whose order is a multiple of 16
-    (TRTRI(k) after POTRF(k)) and applies it by row strips; a ragged last
-    tile substitutes in place."""
+    """The merged factor + solve launch of one system: the explicit inverse of
+    every diagonal tile whose order is a multiple of 16 (TRTRI(k) after
+    POTRF(k)), applied by the factorization's TRSM(., k) for k < T - 1 and
+    by the solve's row strips; a ragged last tile substitutes in place."""
     try:
         p = tc.plan_query(tc.OP_FACTOR_SOLVE, n, nb)
     except ImportError as e:  # library not built
@@ -128,7 +130,11 @@ def test_factor_solve_plan_equals_dataflow(n, nb):
     inv = [k for k in range(T) if min(nb, n - k * nb) % 16 == 0]
     got = {(key(p, t), key(p, int(p["succ"][e])))
            for t in range(p["ntask"]) for e in range(p["succ_off"][t], p["succ_off"][t + 1])}
-    assert got == dataflow_edges_factor_solve(T, inv)
+    assert got == dataflow_edges_factor_solve(T, inv, tri=True)
+    # TRSM items are 128-row blocks of the inverse's product
+    for t in range(p["ntask"]):
+        if int(p["kind"][t]) == TRSM:
+            assert p["parts"][t] == -(-min(nb, n - nb * int(p["i"][t])) // 128)
     w = dict(WEIGHT)
     w[tiled_ref.TRTRI] = 10
     for t in range(p["ntask"]):

@@ -4,7 +4,8 @@ factorization and the solve merged into one DAG in one launch, with the
 default claim order.  The oracle cannot factor the whole matrix in test time,
 so the checks are ones it can compute one by one or that hold at any size:
 - the merged launch's L and X are bitwise equal to those of the factorization
-  and the solve launched one after the other (the same DAG semantics);
+  (with the same inverse-applying TRSMs) and the solve launched one after the
+  other (the same DAG semantics);
 - the leading m x m block of L equals the oracle's factor of the leading
   principal m x m block of A (an exact sub-result of the Cholesky factor);
 - the whole factor's scaled backward error ||A - L L^T||_F / (n eps ||A||_F)
@@ -49,7 +50,7 @@ def test_merged_equals_two_launches_bitwise(merged):
     tc, A0, W, _, Bc0, Xc = merged
     W2 = A0.clone()
     print("factor, then solve, as two launches", flush=True)
-    assert tc.factor_(W2, NB) == 0
+    assert tc.factor_(W2, NB, inv_trsm=True) == 0
     X2 = Bc0.clone()
     tc.solve_(W2, X2, NB)
     torch.cuda.synchronize()

@@ -171,7 +171,8 @@ def test_factor_solve_one_launch_equals_two(tc, n, nb, nrhs, seed, subst):
     """The merged factor + solve launch gives bitwise the results of the two
     separate launches (every tile sees the same updates in the same order),
     with the diagonal tiles' inverses (computed in either launch by the same
-    tasks) and with substitution."""
+    tasks, and applied by the TRSMs too: the factor launch with inv_trsm) and
+    with substitution everywhere."""
     print("case n=%d nb=%d nrhs=%d subst=%d" % (n, nb, nrhs, subst), flush=True)
     A, b = spd_inputs.spd_matrix_and_rhs(n, seed, nrhs=max(nrhs, 1))
     b = b[:, :nrhs]
@@ -179,7 +180,7 @@ def test_factor_solve_one_launch_equals_two(tc, n, nb, nrhs, seed, subst):
     B1 = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
     B2 = B1.clone()
     assert tc.factor_solve_(W1, B1, nb, subst=subst) == 0
-    assert tc.factor_(W2, nb) == 0
+    assert tc.factor_(W2, nb, inv_trsm=not subst) == 0
     if nrhs:
         assert tc.solve_(W2, B2, nb, subst=subst) == 0
     torch.cuda.synchronize()

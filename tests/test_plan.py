@@ -178,7 +178,8 @@ def check_topological(p):
 
 @pytest.mark.parametrize("policy,seed", [(tc.POLICY_LIST, 0), (tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0),
                                          (tc.POLICY_RANDOM, 1), (tc.POLICY_RANDOM, 7)])
-@pytest.mark.parametrize("op,n,nb", [(0, 1024, 128), (0, 1000, 96), (1, 1000, 128)])
+@pytest.mark.parametrize("op,n,nb", [(0, 1024, 128), (0, 1000, 96), (1, 1000, 128), (5, 1024, 128), (5, 1000, 96),
+                                     (5, 4096, 512)])
 def test_claim_order_is_topological(policy, seed, op, n, nb):
     check_topological(plan(op, n, nb, policy, seed))
 

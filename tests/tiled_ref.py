@@ -89,6 +89,9 @@ def run_task(A: np.ndarray, n: int, nb: int, kind: int, i: int, j: int, k: int):
         raise ValueError(kind)
 
 
+TRTRI = 12
+
+
 def pair_first(j: int, k: int) -> bool:
     """Update k of a tile in column j opens a merged pair (k, k + 1): k even,
     and the pair does not hold the tile's last update j - 1."""
@@ -99,15 +102,19 @@ def pair_second(j: int, k: int) -> bool:
     return k % 2 == 1 and k <= j - 2
 
 
-def factor_program(T: int):
+def factor_program(T: int, tri: bool = False):
     """The factorization's tasks in program order (k outer), with each merged
     pair of updates placed at its second step, and every task's tile reads and
-    writes: [(task, reads, writes)]."""
+    writes: [(task, reads, writes)].  With ``tri`` (the merged factor + solve
+    launch), TRSM(i, k) applies the inverse ("D", k) that TRTRI(k) makes from
+    L_kk after POTRF(k), for k < T - 1."""
     out = []
     for k in range(T):
         out.append(((POTRF, k, k, k), [(k, k)], [(k, k)]))
+        if tri and k + 1 < T:
+            out.append(((TRTRI, k, k, k), [(k, k)], [("D", k)]))
         for i in range(k + 1, T):
-            out.append(((TRSM, i, k, k), [(k, k), (i, k)], [(i, k)]))
+            out.append(((TRSM, i, k, k), [("D", k) if tri else (k, k), (i, k)], [(i, k)]))
         for i in range(k + 1, T):
             out.append(((SYRK, i, i, k), [(i, k), (i, i)], [(i, i)]))
             for j in range(k + 1, i):
@@ -121,22 +128,24 @@ def factor_program(T: int):
 
 
 FTRSV, FGEMV, BTRSV, BGEMV = 4, 5, 6, 7
-TRTRI = 12
 
 
-def solve_program(T: int, inv=()):
+def solve_program(T: int, inv=(), given=()):
     """The forward then backward tiled substitution's tasks in program order,
     with the data each reads and writes: tiles ("L", i, j) of the factor,
     blocks ("B", i) of the right-hand sides, and, for the diagonal tiles k in
     ``inv`` (the FP64 solve's explicit inverses), the inverse ("D", k) made by
     TRTRI(k) and the intermediate block ("S", k) that holds y_k.  A diagonal
-    step of a tile not in ``inv`` substitutes in place in B."""
+    step of a tile not in ``inv`` substitutes in place in B.  The inverses of
+    the tiles in ``given`` were made by the factorization's own TRTRI tasks."""
     inv = set(inv)
+    given = set(given)
     y = lambda k: ("S", k) if k in inv else ("B", k)  # where y_k lives
     out = []
     for k in range(T):
         if k in inv:
-            out.append(((TRTRI, k, k, k), [("L", k, k)], [("D", k)]))
+            if k not in given:
+                out.append(((TRTRI, k, k, k), [("L", k, k)], [("D", k)]))
             out.append(((FTRSV, k, k, k), [("D", k), ("B", k)], [("S", k)]))
         else:
             out.append(((FTRSV, k, k, k), [("L", k, k), ("B", k)], [("B", k)]))
