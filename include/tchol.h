@@ -190,9 +190,13 @@ TCHOL_API int32_t tchol_backward_ex(const double *L, int64_t n, int64_t nb, doub
    soon as it is final: POTRF(k) before FTRSV(k), TRSM(i, k) before
    FGEMV(i, k)), so the forward substitution runs while the factorization
    still has work in flight; the claim order is decreasing upward rank over
-   both (section 3.1).  Results are identical to tchol_factor followed by
-   tchol_solve (with the same opts.subst).  The solve's explicit inverses,
-   TRTRI(k) after POTRF(k), are computed while the factorization runs.
+   both (section 3.1).  With opts.subst = 0 (the default) the diagonal
+   tiles' explicit inverses, TRTRI(k) between POTRF(k) and the step's TRSMs,
+   serve both the factorization's TRSMs (products with L_kk^{-1} on the
+   matrix cores) and the solve's diagonal steps; results are then identical
+   to tchol_factor_ex with opts.inv_trsm = 1 followed by tchol_solve.  With
+   opts.subst = 1 both substitute, identical to tchol_factor followed by
+   tchol_solve with opts.subst = 1.
    Arguments: 1 A (in/out as for tchol_factor), 2 n, 3 nb,
    4 B (n x nrhs, ld n, in/out as for tchol_solve), 5 nrhs >= 0, 6 ws,
    7 ws_bytes >= tchol_factor_solve_workspace_bytes(n, nb, nrhs), 8 stream,

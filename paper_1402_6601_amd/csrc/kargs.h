@@ -38,9 +38,10 @@ typedef struct KArgs {
                            (A is the FP32 working copy); 3: the adjoint of the
                            factorization (A = L, B = Lbar, D = partial-product slots) */
   int32_t syrk_b;       /* SYRK output sub-tile (square)                          */
-  int32_t inv;          /* FP64 solve: 1 when the launch computes the diagonal tiles'
-                           explicit inverses (TRTRI tasks) and its diagonal steps
-                           apply them (y in S); 0: substitution in place in B    */
+  int32_t inv;          /* FP64 launches: 1 when the launch computes the diagonal
+                           tiles' explicit inverses (TRTRI tasks) and applies them:
+                           the solve's diagonal steps (y in S) and the TRSMs (by
+                           128-row blocks); 0: substitution in place          */
   double *Dinv;         /* mixed precision: L_kk^{-1}, nb x nb each (FP64); adjoint:
                            two scratch tiles per diagonal tile (Mn, Y^T)          */
   double *DinvT;        /* mixed precision, inv and adjoint: L_kk^{-T}, nb x nb each */

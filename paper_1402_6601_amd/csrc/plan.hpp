@@ -87,9 +87,10 @@ std::shared_ptr<Plan> build_plan(int32_t op, int64_t n, int64_t nb, int32_t poli
 // Factorization followed by the solve, for every system, as one DAG: each
 // system's factor tasks, then its solve tasks, joined by the data-flow
 // edges POTRF(k) -> FTRSV(k) and TRSM(i, k) -> FGEMV(i, k).  With inv (one
-// system: the merged factor + solve launch) the solve applies explicit
-// inverses, POTRF(k) -> TRTRI(k) -> FTRSV(k) for the tiles whose order is a
-// multiple of 16.  Uncached.  Returns nullptr if the task count exceeds
+// system: the merged factor + solve launch) the diagonal tiles' explicit
+// inverses serve the TRSMs and the solve: POTRF(k) -> TRTRI(k) -> TRSM(., k)
+// and FTRSV(k) (the last tile's TRTRI only for the solve, when its order is
+// a multiple of 16).  Uncached.  Returns nullptr if the task count exceeds
 // what the kernel indexes.
 std::shared_ptr<Plan> build_batched_plan(const std::vector<System>& systems, int32_t policy, uint32_t seed,
                                          const Split& split, bool inv = false);
