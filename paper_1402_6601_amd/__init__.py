@@ -125,6 +125,14 @@ def workspace_bytes(op: int, n: int, nb: int, nrhs: int = 0) -> int:
     return int(r)
 
 
+def factor_solve_workspace_bytes(n: int, nb: int, nrhs: int) -> int:
+    """Bytes of workspace of the merged factor + solve launch (tchol_factor_solve)."""
+    r = load().tchol_factor_solve_workspace_bytes(n, nb, nrhs)
+    if r < 0:
+        raise TcholError(int(r), "tchol_factor_solve_workspace_bytes")
+    return int(r)
+
+
 # ---------------------------------------------------------------- plan introspection (host only)
 
 def plan_query(op: int, n: int, nb: int, policy: int = POLICY_LIST, seed: int = 0) -> dict:
