@@ -1175,13 +1175,6 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 //
 // REV = 2: the same solve, also storing P^T at Qb (ld ldq): the explicit
 // inverse of the mixed-precision solve, from identity strips.
-// REV = 1 (the adjoint's TRSM): X := X L^{-1} instead.  With J the order
-// reversal, X L^{-1} J = (X J) L'^{-T} for the lower-triangular
-// L' = J L^T J, so the same forward solve runs on the reversed columns of X
-// with L'(r, c) = L(mk-1-c, mk-1-r), read from the transposed copy LT of L
-// passed as Lkk (L'(r, c) sits at LT[(mk-1-c) ld + mk-1-r]).  The result P
-// is stored three times: X := P / 2 (the adjoint's output), Qa := P and
-// Qb := P^T (both at leading dimension ldq).
 #define TS 32
 
 // Hs (non-null): the solved strip is also stored as three BF16 terms
@@ -1189,7 +1182,7 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 // Hs[t * hterm + r * hld + c] (the BF16 panels of the BF16-update factorization).
 template <typename TX, int REV = 0>
 __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, const double* __restrict__ Lkk, int64_t ld,
-                                           int S, int mk, double* lds, double* Qa = nullptr, double* Qb = nullptr,
+                                           int S, int mk, double* lds, double* Qb = nullptr,
                                            int64_t ldq = 0, uint16_t* Hs = nullptr, int64_t hld = 0,
                                            int64_t hterm = 0) {
   double* Xs = lds;  // [2][512][16]
@@ -1198,10 +1191,7 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
   const int l16 = lane & 15, lg = lane >> 4;
   const int nblk = mk >> 4;
   // L(row, col) of the operator the forward solve applies
-  auto lat = [&](int row, int col) __attribute__((always_inline)) {
-    return REV == 1 ? Lkk[(int64_t)(mk - 1 - col) * ld + (mk - 1 - row)] : Lkk[(int64_t)col * ld + row];
-  };
-  auto xcol = [&](int c) __attribute__((always_inline)) { return REV == 1 ? mk - 1 - c : c; };
+  auto lat = [&](int row, int col) __attribute__((always_inline)) { return Lkk[(int64_t)col * ld + row]; };
   // the strip: thread (r, c0) moves rows r of columns c0 + 8u, 16 loads in flight
   {
     const int r = tid & 31, c0 = tid >> 5, rr = imin(r, S - 1);
@@ -1209,7 +1199,7 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     for (int part = 0; part < 4; ++part) {
       double v[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = (double)X[(int64_t)xcol(imin(c0 + 8 * (u + 16 * part), mk - 1)) * ldx + rr];
+      for (int u = 0; u < 16; ++u) v[u] = (double)X[(int64_t)imin(c0 + 8 * (u + 16 * part), mk - 1) * ldx + rr];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int c = c0 + 8 * (u + 16 * part);
@@ -1312,56 +1302,39 @@ __device__ __forceinline__ void trsm_strip(TX* __restrict__ X, int64_t ldx, cons
     if (rb + 1 < nblk) step(rb + 1, sb, sa);
   }
   __syncthreads();
-  if constexpr (REV != 1) {
-    const int r = tid & 31, c0 = tid >> 5;
-    if (r < S)
-      for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ldx + r, (TX)Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
-    if (Hs) {
-      // runs of 4 columns (8 bytes per term): lane l of wavefront w takes row
-      // 16 (w & 1) + l % 16 (consecutive rows: conflict-free reads of Xs) and
-      // runs 4 u + l / 16 of its half of the columns (w / 2); a store
-      // instruction then writes 32-byte pieces of 16 rows
-      const int hr = 16 * (wave & 1) + l16, half = mk >> 3;  // runs of 4 per half of the columns
-      if (hr < S) {
+  const int r = tid & 31, c0 = tid >> 5;
+  if (r < S)
+    for (int c = c0; c < mk; c += 8) st_dev(X + (int64_t)c * ldx + r, (TX)Xs[(r >> 4) * 8192 + c * 16 + (r & 15)]);
+  if (Hs) {
+    // runs of 4 columns (8 bytes per term): lane l of wavefront w takes row
+    // 16 (w & 1) + l % 16 (consecutive rows: conflict-free reads of Xs) and
+    // runs 4 u + l / 16 of its half of the columns (w / 2); a store
+    // instruction then writes 32-byte pieces of 16 rows
+    const int hr = 16 * (wave & 1) + l16, half = mk >> 3;  // runs of 4 per half of the columns
+    if (hr < S) {
 #pragma unroll 1
-        for (int u = 0; 4 * u + lg < half; ++u) {
-          const int c0 = (wave >> 1) * (mk >> 1) + 4 * (4 * u + lg);
-          uint64_t t0 = 0, t1 = 0, t2 = 0;
+      for (int u = 0; 4 * u + lg < half; ++u) {
+        const int c0 = (wave >> 1) * (mk >> 1) + 4 * (4 * u + lg);
+        uint64_t t0 = 0, t1 = 0, t2 = 0;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            uint32_t a0, a1, a2;
-            split3(Xs[(hr >> 4) * 8192 + (c0 + e) * 16 + (hr & 15)], a0, a1, a2);
-            t0 |= (uint64_t)a0 << (16 * e);
-            t1 |= (uint64_t)a1 << (16 * e);
-            t2 |= (uint64_t)a2 << (16 * e);
-          }
-          uint16_t* h = Hs + (int64_t)hr * hld + c0;
-          st_dev(reinterpret_cast<uint64_t*>(h), t0);
-          st_dev(reinterpret_cast<uint64_t*>(h + hterm), t1);
-          st_dev(reinterpret_cast<uint64_t*>(h + 2 * hterm), t2);
+        for (int e = 0; e < 4; ++e) {
+          uint32_t a0, a1, a2;
+          split3(Xs[(hr >> 4) * 8192 + (c0 + e) * 16 + (hr & 15)], a0, a1, a2);
+          t0 |= (uint64_t)a0 << (16 * e);
+          t1 |= (uint64_t)a1 << (16 * e);
+          t2 |= (uint64_t)a2 << (16 * e);
         }
+        uint16_t* h = Hs + (int64_t)hr * hld + c0;
+        st_dev(reinterpret_cast<uint64_t*>(h), t0);
+        st_dev(reinterpret_cast<uint64_t*>(h + hterm), t1);
+        st_dev(reinterpret_cast<uint64_t*>(h + 2 * hterm), t2);
       }
     }
-    if constexpr (REV == 2) {
-      for (int idx = tid; idx < S * mk; idx += NT) {
-        const int rr = idx / mk, c = idx - rr * mk;
-        st_dev(Qb + (int64_t)rr * ldq + c, Xs[(rr >> 4) * 8192 + c * 16 + (rr & 15)]);
-      }
-    }
-  } else {
-    {
-      const int r = tid & 31, c0 = tid >> 5;
-      if (r < S)
-        for (int c = c0; c < mk; c += 8) {
-          const double v = Xs[(r >> 4) * 8192 + c * 16 + (r & 15)];
-          st_dev(X + (int64_t)(mk - 1 - c) * ldx + r, (TX)(0.5 * v));
-          st_dev(Qa + (int64_t)(mk - 1 - c) * ldq + r, v);
-        }
-    }
-    // the transpose, consecutive threads along its columns
+  }
+  if constexpr (REV == 2) {
     for (int idx = tid; idx < S * mk; idx += NT) {
-      const int r = idx / mk, c = idx - r * mk;
-      st_dev(Qb + (int64_t)r * ldq + c, Xs[(r >> 4) * 8192 + (mk - 1 - c) * 16 + (r & 15)]);
+      const int rr = idx / mk, c = idx - rr * mk;
+      st_dev(Qb + (int64_t)rr * ldq + c, Xs[(rr >> 4) * 8192 + c * 16 + (rr & 15)]);
     }
   }
 }
@@ -2600,7 +2573,7 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
             const int r0 = part * a.trsm_rows;
             const int S = imin(a.trsm_rows, tsz(ti) - r0);
             if constexpr (MODE == 5)  // the strip also as BF16 terms, for the BF16 updates
-              trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dk, nb, S, tsz(tk), lds, nullptr, nullptr, 0,
+              trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dk, nb, S, tsz(tk), lds, nullptr, 0,
                          a.H + ((int64_t)tk * a.hrows + (int64_t)ti * nb + r0) * nb, nb, (int64_t)a.T * a.hrows * nb);
             else
               trsm_strip(Abase + (tk * nb) * ld + ti * nb + r0, ld, Dk, nb, S, tsz(tk), lds);
@@ -2781,12 +2754,12 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
           wait_vmcnt<0>();
           __syncthreads();
           if constexpr (MODE == 0)  // with L_kk^{-1} too (Dinv), which the TRSM items apply
-            trsm_strip<double, 2>(X, nb, Abase + (tk * nb) * ld + tk * nb, ld, S, mpad, lds, nullptr,
+            trsm_strip<double, 2>(X, nb, Abase + (tk * nb) * ld + tk * nb, ld, S, mpad, lds,
                                   DinvSys + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
           else if constexpr (MODE == 3)  // the adjoint: L (its A) is the factor
             trsm_strip<double>(X, nb, Abase + (tk * nb) * ld + tk * nb, ld, S, mpad, lds);
           else
-            trsm_strip<double, 2>(X, nb, Dsys + (int64_t)tk * nb * nb, nb, S, mpad, lds, nullptr,
+            trsm_strip<double, 2>(X, nb, Dsys + (int64_t)tk * nb * nb, nb, S, mpad, lds,
                                   DinvSys + (int64_t)tk * nb * nb + (int64_t)r0 * nb, nb);
         }
         break;
