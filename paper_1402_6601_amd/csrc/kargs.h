@@ -36,7 +36,9 @@ typedef struct KArgs {
   double *D;            /* mixed precision: FP64 diagonal tiles, nb x nb each, T of them */
   int32_t mixed;        /* 0: FP64; 1: mixed-precision factor, 2: its solves, 4: both
                            (A is the FP32 working copy); 3: the adjoint of the
-                           factorization (A = L, B = Lbar, D = partial-product slots) */
+                           factorization (A = L, B = Lbar, D = partial-product slots);
+                           5: the factorization with BF16 updates; 6: FP64 batched
+                           systems of one tile each (the compact instance)      */
   int32_t syrk_b;       /* SYRK output sub-tile (square)                          */
   int32_t inv;          /* FP64 launches: 1 when the launch computes the diagonal
                            tiles' explicit inverses (TRTRI tasks) and applies them:

@@ -17,6 +17,7 @@
 extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int32_t* dep0, int64_t npool, int grid,
                                        int wide, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 extern "C" hipError_t tchol_dev_max_grid(int device, int* grid);
+extern "C" hipError_t tchol_dev_compact_grid(int device, int* grid);
 extern "C" hipError_t tchol_dev_backward_prep(const double* L, int64_t n, double* LT, double* Q, int64_t ldq,
                                               int64_t np, hipStream_t stream);
 extern "C" hipError_t tchol_refine_convert(const double* A, int64_t lda, float* W, int64_t ldw, int64_t n,
@@ -194,6 +195,7 @@ std::shared_ptr<const Image> image_of(const std::shared_ptr<const Plan>& p, int6
 
 struct DeviceInfo {
   int grid = 0;
+  int grid_compact = 0;  // the compact instance (batched one-tile systems)
   int64_t clock_khz = 0;
 };
 
@@ -211,6 +213,8 @@ hipError_t device_info(DeviceInfo* out) {
   }
   DeviceInfo di;
   e = tchol_dev_max_grid(dev, &di.grid);
+  if (e != hipSuccess) return e;
+  e = tchol_dev_compact_grid(dev, &di.grid_compact);
   if (e != hipSuccess) return e;
   int khz = 0;
   e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
@@ -230,8 +234,9 @@ const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr, 0, 
 // Uploads the plan image, launches reset + persistent kernel on the stream,
 // reads the header back and synchronises.  sinfo_out (batched): per-system
 // failing columns.  mixed: 0 FP64; 1 / 2 the mixed-precision factor / solve
-// (A is then the FP32 working copy and D its FP64 diagonal tiles).  Returns
-// the library code.
+// (A is then the FP32 working copy and D its FP64 diagonal tiles); 6 the
+// compact FP64 instance for batched systems of one tile each.  Returns the
+// library code.
 int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_t nrhs, bool wide, bool batched,
                 void* ws, int64_t ws_bytes, void* stream_v, const tchol_opts& o, int32_t ws_arg,
                 int32_t* sinfo_out, double* D = nullptr, int mixed = 0, double* Qp = nullptr,
@@ -298,7 +303,7 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
     e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
   }
-  const int grid = (int)std::min<int64_t>(di.grid, std::max<int64_t>(1, plan.nitem()));
+  const int grid = (int)std::min<int64_t>(mixed == 6 ? di.grid_compact : di.grid, std::max<int64_t>(1, plan.nitem()));
   if (e == hipSuccess)
     e = tchol_dev_launch(&a, (int32_t)plan.ntask(), reinterpret_cast<const int32_t*>(w + L.dep0), L.npool, grid,
                          wide ? 1 : 0, stream, ev0, ev1);
@@ -731,7 +736,14 @@ int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_
   auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
   auto img = make_image(*plan, false, &systems);
-  return execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 11, info);
+  // systems of one tile each, factored by one workgroup (no pooled POTRF):
+  // the compact instance, two workgroups per compute unit
+  bool compact = wide;
+  for (int64_t t = 0; compact && t < plan->ntask(); ++t) {
+    const int32_t k = plan->kind[t];
+    if (!((k == TK_POTRF && plan->parts[t] == 1) || k == TK_FTRSV || k == TK_BTRSV)) compact = false;
+  }
+  return execute(*plan, *img, A, B, nrhs, wide, true, ws, ws_bytes, stream, o, 11, info, nullptr, compact ? 6 : 0);
 }
 
 int64_t tchol_mixed_workspace_bytes_ex(int64_t n, int64_t nb, int64_t nrhs, int32_t lowp) {

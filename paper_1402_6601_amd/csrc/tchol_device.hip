@@ -1036,51 +1036,65 @@ __device__ __forceinline__ int potrf_small(double* __restrict__ Akk, int64_t ld,
 // Panels of 32 columns halve the number of panels and the re-reads of the
 // factored columns relative to the 16 of the diagonal blocks, and give the
 // updates enough outputs per K step to keep the matrix cores busy.
+// SLAB = 128: slabs of 128 rows in a compact layout of 80000 bytes (two
+// workgroups per compute unit): L_dd and the reciprocal pivots live in the
+// update's staging area (free once the product is in the slab), the columns
+// of L_dd below the diagonal packed.
 // Returns 0, or the 1-based column (within the tile) whose pivot is not
 // positive (zero, negative or NaN).
 #define PT_W 32
 #define PT_SLAB 256
-#define PT_LD 264                              // LDS leading dimension of a slab
-#define PT_STAGE (2 * 16 * (PT_SLAB + PT_W))   // stages of gemm_core<SEG, 256, 32, 16, 4, 2, 0>
 #define PT_LT 36                               // stride of the columns of L_dd
+#define PT_LT_PACKED (PT_W * (PT_W + 1) / 2)   // the packed columns (c2 >= c)
+#define PT_LDS_COMPACT (2 * 16 * (128 + PT_W) + PT_W * 136 + PT_LT_PACKED)
+#define FRB_COMPACT_DOUBLES (32 * 4 * 64 + 2 * 4 * 64)  // tile_solve<true>
 
-template <int SEG>
+template <int SEG, int SLAB = PT_SLAB>
 __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds) {
-  static_assert(PT_STAGE + PT_W * PT_LD + PT_W * (PT_W + 1) + PT_W + PT_W * PT_LT <= LDS_DOUBLES, "LDS budget");
+  static_assert(SLAB == 256 || SLAB == 128, "slab height");
+  constexpr bool PACKED = SLAB < PT_SLAB;
+  constexpr int LDP = SLAB + 8;                        // LDS leading dimension of a slab
+  constexpr int STAGE = 2 * 16 * (SLAB + PT_W);        // stages of gemm_core<SEG, SLAB, 32, 16, 4, 2, 0>
+  static_assert(PACKED ? (STAGE + PT_W * LDP + PT_LT_PACKED == PT_LDS_COMPACT &&
+                          PT_W * (PT_W + 1) + PT_W <= STAGE)
+                       : STAGE + PT_W * LDP + PT_W * (PT_W + 1) + PT_W + PT_W * PT_LT <= LDS_DOUBLES,
+                "LDS budget");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double* Ps = lds + PT_STAGE;               // [PT_W][PT_LD] the slab
-  double* Ldd = Ps + PT_W * PT_LD;           // [PT_W][PT_W + 1] the diagonal block (lower)
-  double* Linv = Ldd + PT_W * (PT_W + 1);    // [PT_W] reciprocal pivots
-  double* LT = Linv + PT_W;                  // [PT_W][PT_LT] L_dd by columns
+  double* Ps = lds + STAGE;                                 // [PT_W][LDP] the slab
+  double* Ldd = PACKED ? lds : Ps + PT_W * LDP;             // [PT_W][PT_W + 1] the diagonal block (lower)
+  double* Linv = Ldd + PT_W * (PT_W + 1);                   // [PT_W] reciprocal pivots
+  double* LT = PACKED ? Ps + PT_W * LDP : Linv + PT_W;      // L_dd by columns
+  // column c of L_dd from its diagonal down (c2 >= c): LT[lt(c) + c2]
+  auto lt = [](int c) __attribute__((always_inline)) { return PACKED ? c * PT_W - c * (c + 1) / 2 : c * PT_LT; };
   __shared__ int s_info;
   for (int c0 = 0; c0 < m; c0 += PT_W) {
     const int w = imin(PT_W, m - c0);
     const int R = m - c0;
     double* P = Akk + (int64_t)c0 * ld + c0;
-    for (int s0 = 0; s0 < R; s0 += PT_SLAB) {
-      const int S = imin(PT_SLAB, R - s0);
+    for (int s0 = 0; s0 < R; s0 += SLAB) {
+      const int S = imin(SLAB, R - s0);
       if (c0 > 0) {
         // the slab - L[c0 + s0 :, 0 : c0] L[c0 : c0 + w, 0 : c0]^T into LDS,
         // on a product no taller than the slab needs
-        if (S > 128)
-          gemm_core<SEG, 256, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, PT_LD);
+        if (SLAB > 128 && S > 128)
+          gemm_core<SEG, SLAB, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, LDP);
         else if (S > 64)
-          gemm_core<SEG, 128, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, PT_LD);
+          gemm_core<SEG, 128, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, LDP);
         else
-          gemm_core<SEG, 64, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, PT_LD);
+          gemm_core<SEG, 64, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, LDP);
       } else if (tid < S) {
         double v[PT_W];
 #pragma unroll
         for (int c = 0; c < PT_W; ++c) v[c] = P[(int64_t)imin(c, w - 1) * ld + s0 + tid];
 #pragma unroll
-        for (int c = 0; c < PT_W; ++c) Ps[c * PT_LD + tid] = v[c];
+        for (int c = 0; c < PT_W; ++c) Ps[c * LDP + tid] = v[c];
       }
       __syncthreads();
       if (s0 == 0) {
         if (wave == 0) {
           // the leading 16 x 16 block, the rows 16 .. w-1 below it solved in the same steps
-          int info = diag16_x<PT_LD, PT_W + 1>(Ps, 0, imin(16, w), Ldd, Linv, lane, c0, imax(w - 16, 0));
+          int info = diag16_x<LDP, PT_W + 1>(Ps, 0, imin(16, w), Ldd, Linv, lane, c0, imax(w - 16, 0));
           if (w > 16) {
             const int wb = w - 16;
             // trailing block -= (those rows)(those rows)^T: element v of lane
@@ -1090,17 +1104,17 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
               const int l16 = lane & 15, lg = lane >> 4;
               d4 acc;
 #pragma unroll
-              for (int v = 0; v < 4; ++v) acc[v] = Ps[(16 + l16) * PT_LD + 16 + 4 * v + lg];
+              for (int v = 0; v < 4; ++v) acc[v] = Ps[(16 + l16) * LDP + 16 + 4 * v + lg];
 #pragma unroll
               for (int s = 0; s < 4; ++s) {
-                const double f = Ps[(4 * s + lg) * PT_LD + 16 + l16];
+                const double f = Ps[(4 * s + lg) * LDP + 16 + l16];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(f, f, acc, 0, 0, 2 /* neg B */);
               }
 #pragma unroll
-              for (int v = 0; v < 4; ++v) Ps[(16 + l16) * PT_LD + 16 + 4 * v + lg] = acc[v];
+              for (int v = 0; v < 4; ++v) Ps[(16 + l16) * LDP + 16 + 4 * v + lg] = acc[v];
             }
             const int info_b =
-                diag16_x<PT_LD, PT_W + 1>(Ps, 16, wb, Ldd + 16 * (PT_W + 1) + 16, Linv + 16, lane, c0 + 16);
+                diag16_x<LDP, PT_W + 1>(Ps, 16, wb, Ldd + 16 * (PT_W + 1) + 16, Linv + 16, lane, c0 + 16);
             info = info != 0 ? info : info_b;
           }
           if (lane == 0) s_info = info;
@@ -1112,7 +1126,7 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
         // (c2 > c), the reciprocal pivot at c2 = c
         for (int idx = tid; idx < PT_W * PT_W; idx += NT) {
           const int c = idx / PT_W, c2 = idx - c * PT_W;
-          LT[c * PT_LT + c2] = c2 == c ? Linv[c] : (c2 > c ? Ldd[c2 * (PT_W + 1) + c] : 0.0);
+          if (!PACKED || c2 >= c) LT[lt(c) + c2] = c2 == c ? Linv[c] : (c2 > c ? Ldd[c2 * (PT_W + 1) + c] : 0.0);
         }
         __syncthreads();
       }
@@ -1124,12 +1138,12 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
         if (r < S) {
           double y[PT_W];
 #pragma unroll
-          for (int c = 0; c < PT_W; ++c) y[c] = Ps[c * PT_LD + r];
+          for (int c = 0; c < PT_W; ++c) y[c] = Ps[c * LDP + r];
 #pragma unroll
           for (int c = 0; c < PT_W; ++c) {
             double l[PT_W];
 #pragma unroll
-            for (int c2 = c; c2 < PT_W; ++c2) l[c2] = LT[c * PT_LT + c2];
+            for (int c2 = c; c2 < PT_W; ++c2) l[c2] = LT[lt(c) + c2];
 #pragma unroll
             for (int c2 = c; c2 < PT_W; ++c2) asm volatile("" : : "v"(l[c2]));
             y[c] *= l[c];
@@ -1137,7 +1151,7 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
             for (int c2 = c + 1; c2 < PT_W; ++c2) y[c2] -= y[c] * l[c2];
           }
 #pragma unroll
-          for (int c = 0; c < PT_W; ++c) Ps[c * PT_LD + r] = y[c];
+          for (int c = 0; c < PT_W; ++c) Ps[c * LDP + r] = y[c];
         }
       }
       __syncthreads();
@@ -1146,7 +1160,7 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
       if (tid < S) {
 #pragma unroll
         for (int c = 0; c < PT_W; ++c)
-          if (c < w && s0 + tid >= c) st_dev(P + (int64_t)c * ld + s0 + tid, Ps[c * PT_LD + tid]);
+          if (c < w && s0 + tid >= c) st_dev(P + (int64_t)c * ld + s0 + tid, Ps[c * LDP + tid]);
       }
       __syncthreads();
     }
@@ -1391,20 +1405,28 @@ __device__ __forceinline__ void trsm_inv_rows(double* __restrict__ X, int64_t ld
 // LDS: Fr[blk][s][f][64] the A-operand fragments of the sub-steps (f = 0:
 // inverse, f = 1: update), then two 16 x 16 exchange buffers.
 #define FR_SLOT(blk, s, f) ((((blk) * 4 + (s)) * 2 + (f)) * 64)
+#define FR0_SLOT(blk, s) (((blk) * 4 + (s)) * 64)  // COMPACT: the inverses only
 
 // Builds Fr for the forward (trans = false) or backward (trans = true)
 // solve of the nblk diagonal 16-blocks of L_kk (m rows).  Rows and columns
-// past m behave as the identity.
+// past m behave as the identity.  COMPACT: only the inverse fragments (the
+// update fragments are read from L_kk by the solve).
+template <bool COMPACT = false>
 __device__ __forceinline__ void build_block_fragments(const double* __restrict__ Lkk, int64_t ld, int m,
                                                       bool trans, double* Fr) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int s = tid >> 6;  // wavefront w builds sub-step w of every block
   const int l16 = lane & 15, lg = lane >> 4;
   const int nblk = (m + 15) >> 4;
-  // update fragments (and zeros in the inverse slots): all 32 loads are
-  // requested before any is used.  Forward: A[i][k] = L[r0+i][r0+4s+k] for
-  // i >= 4s+4; backward: A[i][k] = L[r0+4s+k][r0+i] for i < 4s.
-  {
+  auto slot0 = [](int blk, int s4) __attribute__((always_inline)) {
+    return COMPACT ? FR0_SLOT(blk, s4) : FR_SLOT(blk, s4, 0);
+  };
+  if constexpr (COMPACT) {
+    for (int blk = 0; blk < nblk; ++blk) Fr[FR0_SLOT(blk, s) + lane] = 0.0;
+  } else {
+    // update fragments (and zeros in the inverse slots): all 32 loads are
+    // requested before any is used.  Forward: A[i][k] = L[r0+i][r0+4s+k] for
+    // i >= 4s+4; backward: A[i][k] = L[r0+4s+k][r0+i] for i < 4s.
     const int row = trans ? 4 * s + lg : l16, col = trans ? l16 : 4 * s + lg;
     const bool live = trans ? (l16 < 4 * s) : (l16 >= 4 * s + 4);
     double v[32];
@@ -1456,7 +1478,7 @@ __device__ __forceinline__ void build_block_fragments(const double* __restrict__
         // backward A[i'][k'] = W[k'][i'-4s] -> lane i*16 + 4s + c
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (i >= c) Fr[FR_SLOT(blk, s4, 0) + (trans ? i * 16 + 4 * s4 + c : c * 16 + 4 * s4 + i)] = w[i];
+          if (i >= c) Fr[slot0(blk, s4) + (trans ? i * 16 + 4 * s4 + c : c * 16 + 4 * s4 + i)] = w[i];
       }
     }
   }
@@ -1475,16 +1497,52 @@ __device__ __forceinline__ void solve_block(d4& acc, const double* Fr, int blk, 
   }
 }
 
+// The same with the inverse fragments of the compact layout and the update
+// fragments fu (sub-step order ss) read from L_kk: entry (row, col) of the
+// block's sub-step s = trans ? 3 - ss : ss, zero outside its live part.
+__device__ __forceinline__ void solve_block_c(d4& acc, const double* Fr, int blk, const double (&fu)[4], int m,
+                                              bool trans, int lane) {
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int bw = imin(16, m - blk * 16);
+#pragma unroll
+  for (int ss = 0; ss < 4; ++ss) {
+    const int s = trans ? 3 - ss : ss;
+    const int row = trans ? 4 * s + lg : l16, col = trans ? l16 : 4 * s + lg;
+    const bool live = (trans ? (l16 < 4 * s) : (l16 >= 4 * s + 4)) & (row < bw) & (col < bw);
+    const d4 z = __builtin_amdgcn_mfma_f64_16x16x4f64(Fr[FR0_SLOT(blk, s) + lane], acc[s], d4{0.0, 0.0, 0.0, 0.0},
+                                                     0, 0, 0);
+    acc[s] = z[s];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(live ? fu[ss] : 0.0, z[s], acc, 0, 0, 2 /* neg B */);
+  }
+}
+
 // trans = false: Y_k := L_kk^{-1} B_k; trans = true: X_k := L_kk^{-T} Y_k.
+// COMPACT (the compact instance, 69632 bytes of LDS, 256 registers): Fr
+// holds only the blocks' inverse fragments, the update fragments of the
+// block a step solves are loaded from L_kk one step ahead, and the step's
+// update fragments at its start (one buffer instead of two: the other
+// workgroup on the compute unit covers the wait).
+template <bool COMPACT = false>
 __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64_t ld, double* Bk, int64_t ldb,
                                            int m, int nrhs, bool trans, double* lds) {
-  double* Fr = lds;                  // [nblk][4][2][64]
-  double* Ex = lds + 32 * 4 * 2 * 64;  // [2][4][64]
+  double* Fr = lds;                                      // [nblk][4][2][64] (COMPACT: [nblk][4][64])
+  double* Ex = lds + 32 * 4 * (COMPACT ? 1 : 2) * 64;  // [2][4][64]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lg = lane >> 4;
   const int nblk = (m + 15) >> 4;
-  build_block_fragments(Lkk, ld, m, trans, Fr);
+  build_block_fragments<COMPACT>(Lkk, ld, m, trans, Fr);
+  // COMPACT: the raw entries behind block blk's update fragments (sub-step
+  // order), clamped into the tile; solve_block_c masks them
+  auto fetch_fu = [&](int blk, double (&fu)[4]) __attribute__((always_inline)) {
+    const int r0 = imin(imax(blk, 0), nblk - 1) * 16, bw = imin(16, m - r0);
+#pragma unroll
+    for (int ss = 0; ss < 4; ++ss) {
+      const int s = trans ? 3 - ss : ss;
+      const int row = trans ? 4 * s + lg : l16, col = trans ? l16 : 4 * s + lg;
+      fu[ss] = Lkk[(int64_t)(r0 + imin(col, bw - 1)) * ld + r0 + imin(row, bw - 1)];
+    }
+  };
   // fragments of the updates by solved block rb of the owned blocks ub = wave + 4t:
   // forward L[ub rows][rb cols], backward L[rb rows][ub cols]^T
   // Only the blocks the solved block rb still updates are fetched (forward:
@@ -1517,19 +1575,28 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
       }
     const int first = trans ? nblk - 1 : 0;
     double fla[8][4], flb[8][4];
-    fetch(first, fla);
+    double fua[4], fub[4];  // COMPACT: update fragments of the block a step solves
+    if constexpr (COMPACT)
+      fetch_fu(first, fub);
+    else
+      fetch(first, fla);
     // the first block: solved by its owner, published in buffer 0
 #pragma unroll
     for (int t = 0; t < 8; ++t)
       if (wave + 4 * t == first) {
-        solve_block(acc[t], Fr, first, trans, lane);
+        if constexpr (COMPACT)
+          solve_block_c(acc[t], Fr, first, fub, m, trans, lane);
+        else
+          solve_block(acc[t], Fr, first, trans, lane);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Ex[v * 64 + lane] = acc[t][v];
       }
+    if constexpr (COMPACT) fetch_fu(trans ? first - 1 : first + 1, fua);
     __syncthreads();
     // one step: block rb is solved and published in buffer (step & 1); its
     // contribution goes to every block still to be solved, the next block first
-    auto step = [&](int step_i, const double (&fl)[8][4], double (&fln)[8][4]) __attribute__((always_inline)) {
+    auto step = [&](int step_i, const double (&fl)[8][4], double (&fln)[8][4], const double (&fu)[4],
+                    double (&fun)[4]) __attribute__((always_inline)) {
       const int rb = trans ? nblk - 1 - step_i : step_i;
       const int nx = trans ? rb - 1 : rb + 1;
       const bool has_next = trans ? (rb > 0) : (rb + 1 < nblk);
@@ -1538,14 +1605,24 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
       d4 yb;
 #pragma unroll
       for (int v = 0; v < 4; ++v) yb[v] = ex[v * 64 + lane];
-      if (has_next) fetch(nx, fln);
+      if constexpr (COMPACT) {
+        // one buffer (fl and fln are the same array): this step's fragments
+        // now, the next solved block's update fragments one step ahead
+        fetch(rb, fln);
+        if (has_next) fetch_fu(trans ? nx - 1 : nx + 1, fun);
+      } else if (has_next) {
+        fetch(nx, fln);
+      }
 #pragma unroll
       for (int t = 0; t < 8; ++t)
         if (has_next && wave + 4 * t == nx) {
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk)
             acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fl[t][kk], yb[kk], acc[t], 0, 0, 2 /* neg B */);
-          solve_block(acc[t], Fr, nx, trans, lane);
+          if constexpr (COMPACT)
+            solve_block_c(acc[t], Fr, nx, fu, m, trans, lane);
+          else
+            solve_block(acc[t], Fr, nx, trans, lane);
 #pragma unroll
           for (int v = 0; v < 4; ++v) exn[v * 64 + lane] = acc[t][v];
         }
@@ -1561,8 +1638,13 @@ __device__ __forceinline__ void tile_solve(const double* __restrict__ Lkk, int64
       __syncthreads();
     };
     for (int si = 0; si < nblk; si += 2) {
-      step(si, fla, flb);
-      if (si + 1 < nblk) step(si + 1, flb, fla);
+      if constexpr (COMPACT) {
+        step(si, fla, fla, fua, fub);
+        if (si + 1 < nblk) step(si + 1, fla, fla, fub, fua);
+      } else {
+        step(si, fla, flb, fua, fub);
+        if (si + 1 < nblk) step(si + 1, flb, fla, fub, fua);
+      }
     }
     if (l16 < jn) {
 #pragma unroll
@@ -2333,7 +2415,7 @@ __device__ __forceinline__ bool pool_wait_unit(const KArgs& a, const int32_t* po
 // A mixed launch runs only its own task kinds (keeping each instance small)
 // and is always a 16-byte one.
 template <int SEG, int MODE>
-__global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
+__global__ void __launch_bounds__(NT, MODE == 6 ? 2 : 1) tchol_persistent(KArgs a) {
   constexpr bool MIXED = MODE == 1 || MODE == 2 || MODE == 4 || MODE == 5;
   constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1 || MODE == 4 || MODE == 5;
   constexpr bool SOLVE_KINDS = MODE == 0 || MODE == 2 || MODE == 4;
@@ -2343,7 +2425,10 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
   // its FP64 diagonal tile); the batched FP32 instance factors each diagonal
   // tile on one workgroup (only part 0 of a POTRF task works)
   constexpr bool POOLED = MODE == 0 || MODE == 1 || MODE == 5;
-  __shared__ double lds[LDS_DOUBLES];
+  // MODE 6 (batched systems of one tile each): the compact POTRF and tile
+  // solves only, in half the LDS, two workgroups per compute unit
+  static_assert(FRB_COMPACT_DOUBLES <= PT_LDS_COMPACT, "compact LDS budget");
+  __shared__ double lds[MODE == 6 ? PT_LDS_COMPACT : LDS_DOUBLES];
   __shared__ int s_claim[4];
   __shared__ int32_t s_desc[DESC_WORDS];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -2505,7 +2590,19 @@ __global__ void __launch_bounds__(NT, 1) tchol_persistent(KArgs a) {
     } else if (POOLED && unit == -2) {
       body = -1;
     }
-    switch (skip ? -1 : body) {
+    if constexpr (MODE == 6) {
+      if (skip) {
+      } else if (kind == TK_POTRF) {
+        const int info = uniform_i(potrf_tile<SEG, 128>(Abase + (tk * nb) * ld + tk * nb, ld, tsz(tk), lds));
+        if (info != 0 && tid == 0)
+          __hip_atomic_store(&a.sinfo[sid], (int)(tk * nb) + info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (kind == TK_FTRSV || kind == TK_BTRSV) {
+        tile_solve<true>(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
+                         kind == TK_BTRSV, lds);
+      } else {
+        ok = 0;
+      }
+    } else switch (skip ? -1 : body) {
       case -1:
         break;
       case TK_POTRF: {
@@ -2934,6 +3031,8 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
     hipLaunchKernelGGL((tchol_persistent<128, 1>), dim3(grid), dim3(NT), 0, stream, *a);
   else if (a->mixed == 2)
     hipLaunchKernelGGL((tchol_persistent<128, 2>), dim3(grid), dim3(NT), 0, stream, *a);
+  else if (a->mixed == 6)
+    hipLaunchKernelGGL((tchol_persistent<128, 6>), dim3(grid), dim3(NT), 0, stream, *a);
   else if (wide)
     hipLaunchKernelGGL((tchol_persistent<128, 0>), dim3(grid), dim3(NT), 0, stream, *a);
   else
@@ -2951,6 +3050,18 @@ extern "C" hipError_t tchol_dev_backward_prep(const double* L, int64_t n, double
   const unsigned g = (unsigned)((np + 31) / 32);
   hipLaunchKernelGGL(tchol_backward_prep, dim3(g, g), dim3(256), 0, stream, L, n, LT, Q, ldq, np);
   return hipGetLastError();
+}
+
+// Workgroups of the compact instance (batched systems of one tile each) that
+// the device holds at once.
+extern "C" hipError_t tchol_dev_compact_grid(int device, int* grid) {
+  int cus = 0, occ = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tchol_persistent<128, 6>, NT, 0);
+  if (e != hipSuccess) return e;
+  *grid = cus * (occ > 0 ? occ : 1);
+  return hipSuccess;
 }
 
 extern "C" hipError_t tchol_dev_max_grid(int device, int* grid) {
