@@ -19,6 +19,7 @@ extern "C" {
 struct KArgs;
 STUB(tchol_dev_launch, const KArgs*, int32_t, const int32_t*, int64_t, int, int, hipStream_t, hipEvent_t, hipEvent_t)
 STUB(tchol_dev_max_grid, int, int*)
+STUB(tchol_dev_compact_grid, int, int*)
 STUB(tchol_dev_backward_prep, const double*, int64_t, double*, double*, int64_t, int64_t, hipStream_t)
 STUB(tchol_refine_convert, const double*, int64_t, float*, int64_t, int64_t, hipStream_t)
 STUB(tchol_refine_residual, const double*, int64_t, int64_t, const double*, const double*, double*, int64_t, int, int,

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_internal_symbols_are_not_exported(lib):
-    for name in ["tchol_dev_launch", "tchol_dev_max_grid", "tchol_refine_convert", "tchol_refine_residual",
+    for name in ["tchol_dev_launch", "tchol_dev_max_grid", "tchol_dev_compact_grid", "tchol_refine_convert", "tchol_refine_residual",
                  "tchol_refine_colmax", "tchol_refine_axpy"]:
         with pytest.raises(AttributeError):
             getattr(lib, name)
