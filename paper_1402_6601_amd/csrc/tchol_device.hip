@@ -1036,26 +1036,35 @@ __device__ __forceinline__ int potrf_small(double* __restrict__ Akk, int64_t ld,
 // Panels of 32 columns halve the number of panels and the re-reads of the
 // factored columns relative to the 16 of the diagonal blocks, and give the
 // updates enough outputs per K step to keep the matrix cores busy.
-// SLAB = 128: slabs of 128 rows in a compact layout of 80000 bytes (two
+// SLAB = 128: slabs of 128 rows in a compact layout of 81024 bytes (two
 // workgroups per compute unit): L_dd and the reciprocal pivots live in the
 // update's staging area (free once the product is in the slab), the columns
-// of L_dd below the diagonal packed.
+// of L_dd below the diagonal packed.  With Bf (compact layout only) the
+// forward solve L y = b of nrhs <= 4 right-hand sides (column-major at Bf,
+// leading dimension ldbf) rides along, right-looking by panels: in the first
+// slab of a panel, thread 128 + j solves the panel's rows of column j
+// against L_dd (the same substitution as the rows below the block, on the
+// values the earlier panels left) and stores them, final, to Bf and to Yp;
+// when a slab is stored, each of its rows below the block takes
+// b -= L(row, panel) y_panel.  Bf then holds y.
 // Returns 0, or the 1-based column (within the tile) whose pivot is not
 // positive (zero, negative or NaN).
 #define PT_W 32
 #define PT_SLAB 256
 #define PT_LT 36                               // stride of the columns of L_dd
 #define PT_LT_PACKED (PT_W * (PT_W + 1) / 2)   // the packed columns (c2 >= c)
-#define PT_LDS_COMPACT (2 * 16 * (128 + PT_W) + PT_W * 136 + PT_LT_PACKED)
+#define PT_FWD 4                               // right-hand sides of the fused forward solve
+#define PT_LDS_COMPACT (2 * 16 * (128 + PT_W) + PT_W * 136 + PT_LT_PACKED + PT_W * PT_FWD)
 #define FRB_COMPACT_DOUBLES (32 * 4 * 64 + 2 * 4 * 64)  // tile_solve<true>
 
 template <int SEG, int SLAB = PT_SLAB>
-__device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds) {
+__device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds,
+                                          double* Bf = nullptr, int64_t ldbf = 0, int nrhs = 0) {
   static_assert(SLAB == 256 || SLAB == 128, "slab height");
   constexpr bool PACKED = SLAB < PT_SLAB;
   constexpr int LDP = SLAB + 8;                        // LDS leading dimension of a slab
   constexpr int STAGE = 2 * 16 * (SLAB + PT_W);        // stages of gemm_core<SEG, SLAB, 32, 16, 4, 2, 0>
-  static_assert(PACKED ? (STAGE + PT_W * LDP + PT_LT_PACKED == PT_LDS_COMPACT &&
+  static_assert(PACKED ? (STAGE + PT_W * LDP + PT_LT_PACKED + PT_W * PT_FWD == PT_LDS_COMPACT &&
                           PT_W * (PT_W + 1) + PT_W <= STAGE)
                        : STAGE + PT_W * LDP + PT_W * (PT_W + 1) + PT_W + PT_W * PT_LT <= LDS_DOUBLES,
                 "LDS budget");
@@ -1065,6 +1074,8 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
   double* Ldd = PACKED ? lds : Ps + PT_W * LDP;             // [PT_W][PT_W + 1] the diagonal block (lower)
   double* Linv = Ldd + PT_W * (PT_W + 1);                   // [PT_W] reciprocal pivots
   double* LT = PACKED ? Ps + PT_W * LDP : Linv + PT_W;      // L_dd by columns
+  double* Yp = LT + PT_LT_PACKED;                           // [PT_W][PT_FWD] the panel's rows of y (Bf)
+  const bool fwd = PACKED && Bf != nullptr;
   // column c of L_dd from its diagonal down (c2 >= c): LT[lt(c) + c2]
   auto lt = [](int c) __attribute__((always_inline)) { return PACKED ? c * PT_W - c * (c + 1) / 2 : c * PT_LT; };
   __shared__ int s_info;
@@ -1132,13 +1143,22 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
       }
       // rows below the diagonal block: y := y L_dd^{-T}, one row per thread
       // (there are such rows only when the panel is 32 wide); each column's
-      // entries of L_dd are loaded together before they are used
+      // entries of L_dd are loaded together before they are used.  With Bf,
+      // threads 128 + j of the first slab take the panel's rows of column j
+      // of b (rows of the compact slab never reach thread 128)
       {
         const int r = (s0 == 0 ? w : 0) + tid;
-        if (r < S) {
+        const int j = tid - 128;
+        const bool rhs = fwd && s0 == 0 && j >= 0 && j < nrhs;
+        if (r < S || rhs) {
           double y[PT_W];
+          if (rhs) {
 #pragma unroll
-          for (int c = 0; c < PT_W; ++c) y[c] = Ps[c * LDP + r];
+            for (int c = 0; c < PT_W; ++c) y[c] = c < w ? Bf[(int64_t)j * ldbf + c0 + c] : 0.0;
+          } else {
+#pragma unroll
+            for (int c = 0; c < PT_W; ++c) y[c] = Ps[c * LDP + r];
+          }
 #pragma unroll
           for (int c = 0; c < PT_W; ++c) {
             double l[PT_W];
@@ -1150,8 +1170,16 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 #pragma unroll
             for (int c2 = c + 1; c2 < PT_W; ++c2) y[c2] -= y[c] * l[c2];
           }
+          if (rhs) {
 #pragma unroll
-          for (int c = 0; c < PT_W; ++c) Ps[c * LDP + r] = y[c];
+            for (int c = 0; c < PT_W; ++c) {
+              Yp[c * PT_FWD + j] = y[c];
+              if (c < w) st_dev(Bf + (int64_t)j * ldbf + c0 + c, y[c]);
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < PT_W; ++c) Ps[c * LDP + r] = y[c];
+          }
         }
       }
       __syncthreads();
@@ -1161,6 +1189,24 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
 #pragma unroll
         for (int c = 0; c < PT_W; ++c)
           if (c < w && s0 + tid >= c) st_dev(P + (int64_t)c * ld + s0 + tid, Ps[c * LDP + tid]);
+        if (fwd && s0 + tid >= w) {
+          // b(row) -= L(row, panel) y_panel for the rows below the block
+          double* const bp = Bf + c0 + s0 + tid;
+          double bv[PT_FWD];
+#pragma unroll
+          for (int jj = 0; jj < PT_FWD; ++jj) bv[jj] = jj < nrhs ? bp[(int64_t)jj * ldbf] : 0.0;
+#pragma unroll
+          for (int c = 0; c < PT_W; ++c) {
+            if (c < w) {
+              const double lv = Ps[c * LDP + tid];
+#pragma unroll
+              for (int jj = 0; jj < PT_FWD; ++jj) bv[jj] -= lv * Yp[c * PT_FWD + jj];
+            }
+          }
+#pragma unroll
+          for (int jj = 0; jj < PT_FWD; ++jj)
+            if (jj < nrhs) st_dev(bp + (int64_t)jj * ldbf, bv[jj]);
+        }
       }
       __syncthreads();
     }
@@ -2591,15 +2637,18 @@ __global__ void __launch_bounds__(NT, MODE == 6 ? 2 : 1) tchol_persistent(KArgs 
       body = -1;
     }
     if constexpr (MODE == 6) {
+      const bool fuse_fwd = a.nrhs > 0 && a.nrhs <= PT_FWD;
       if (skip) {
       } else if (kind == TK_POTRF) {
-        const int info = uniform_i(potrf_tile<SEG, 128>(Abase + (tk * nb) * ld + tk * nb, ld, tsz(tk), lds));
+        // up to PT_FWD right-hand sides: the forward solve rides along (its FTRSV task only passes the completion on)
+        const int info = uniform_i(potrf_tile<SEG, 128>(Abase + (tk * nb) * ld + tk * nb, ld, tsz(tk), lds,
+                                                        fuse_fwd ? Bbase + tk * nb : nullptr, ldb, (int)a.nrhs));
         if (info != 0 && tid == 0)
           __hip_atomic_store(&a.sinfo[sid], (int)(tk * nb) + info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else if (kind == TK_FTRSV || kind == TK_BTRSV) {
+      } else if (kind == TK_BTRSV || (kind == TK_FTRSV && !fuse_fwd)) {
         tile_solve<true>(Abase + (tk * nb) * ld + tk * nb, ld, Bbase + tk * nb, ldb, tsz(tk), (int)a.nrhs,
                          kind == TK_BTRSV, lds);
-      } else {
+      } else if (kind != TK_FTRSV) {
         ok = 0;
       }
     } else switch (skip ? -1 : body) {

@@ -146,6 +146,41 @@ def test_batched_shared_factorization(tc, align):
         assert np.max(np.abs(Xs[s] - Xo)) / np.max(np.abs(Xo)) <= TOL
 
 
+@pytest.mark.parametrize("nrhs", [4, 1, 6])
+def test_batched_one_tile_compact(tc, nrhs):
+    """Every system one tile with even leading dimensions: the compact kernel
+    instance (128-row slabs, two workgroups per compute unit).  Up to four
+    right-hand sides ride along the factorization as its forward solve; six
+    take the separate forward-solve task."""
+    sizes = [1, 16, 17, 100, 128, 129, 200, 255, 256, 257, 300, 384, 385, 450, 511, 512]
+    As, bs = _systems(21, sizes, nrhs)
+    nb = [_nb_single(n) for n in sizes]
+    info, Ls, Xs = _run(tc, As, bs, nb)
+    assert np.all(info == 0)
+    for A, b, L, X in zip(As, bs, Ls, Xs):
+        Lo = oracle.cholesky(A)
+        assert oracle.factor_error(L, Lo) <= TOL
+        Xo = oracle.potrs(Lo, b)
+        assert np.max(np.abs(X - Xo)) / max(np.max(np.abs(Xo)), 1e-300) <= TOL
+        assert np.all(oracle.solve_backward_error(A, X, b) <= 1e-15)
+
+
+def test_batched_one_tile_compact_integer_exact(tc):
+    """Integer systems through the compact instance and its fused forward
+    solve: L and X exact."""
+    sizes = [64, 300, 17, 512, 129, 200, 1, 33]
+    As, bs, L0s, X0s = [], [], [], []
+    for i, n in enumerate(sizes):
+        A, L0 = spd_inputs.integer_spd(n, seed=60 + i)
+        b, x0 = spd_inputs.integer_rhs(A, 3, seed=60 + i)
+        As.append(A), bs.append(b), L0s.append(L0), X0s.append(x0)
+    info, Ls, Xs = _run(tc, As, bs, [_nb_single(n) for n in sizes])
+    assert np.all(info == 0)
+    for L, L0, X, X0 in zip(Ls, L0s, Xs, X0s):
+        assert np.array_equal(L, L0)
+        assert np.array_equal(X, X0)
+
+
 def test_batched_integer_systems_exact(tc):
     sizes = [64, 300, 17, 512]
     As, bs, L0s, X0s = [], [], [], []
