@@ -920,7 +920,24 @@ int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int
     desc[8 * s + 4] = systems[s].d_off;
     desc[8 * s + 6] = systems[s].b_off;
   }
-  auto img = make_image(*plan, false, &systems);
+  // Systems of one tile each (no pooled POTRF): the FP64 copy of every
+  // system is its whole matrix (D, leading dimension nb, even and 16-byte
+  // aligned), so the compact FP64 instance factors and solves the copies in
+  // place, addressed as systems of their own.
+  bool compact = true;
+  for (int64_t t = 0; compact && t < plan->ntask(); ++t) {
+    const int32_t k = plan->kind[t];
+    if (!((k == TK_POTRF && plan->parts[t] == 1) || k == TK_FTRSV || k == TK_BTRSV)) compact = false;
+  }
+  std::vector<tchol::System> dsys;
+  if (compact) {
+    dsys = systems;
+    for (auto& sy : dsys) {
+      sy.a_off = sy.d_off;
+      sy.ld = sy.nb;
+    }
+  }
+  auto img = make_image(*plan, false, compact ? &dsys : &systems);
   char* w = static_cast<char*>(ws);
   int64_t* ddesc = reinterpret_cast<int64_t*>(w + L.desc);
   double* D = reinterpret_cast<double*>(w + L.d);
@@ -928,8 +945,11 @@ int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int
   hipStream_t s = reinterpret_cast<hipStream_t>(stream_v);
   if (hipMemcpyAsync(ddesc, desc.data(), 8 * desc.size(), hipMemcpyHostToDevice, s) != hipSuccess) return TCHOL_E_HIP;
   if (tchol_b32_prepare(ddesc, batch, A, B, D, Bd, nrhs, s) != hipSuccess) return TCHOL_E_HIP;
-  const int32_t rc = execute(*plan, *img, reinterpret_cast<double*>(A), Bd, nrhs, true, true, w + L.sched,
-                             ws_bytes - L.sched, stream_v, o, 11, info, D, 4, nullptr, nullptr, 0, D, D, Bd);
+  const int32_t rc =
+      compact ? execute(*plan, *img, D, Bd, nrhs, true, true, w + L.sched, ws_bytes - L.sched, stream_v, o, 11, info,
+                        nullptr, 6)
+              : execute(*plan, *img, reinterpret_cast<double*>(A), Bd, nrhs, true, true, w + L.sched,
+                        ws_bytes - L.sched, stream_v, o, 11, info, D, 4, nullptr, nullptr, 0, D, D, Bd);
   if (rc != 0) return rc;
   if (tchol_b32_finish(ddesc, batch, A, B, D, Bd, nrhs, s) != hipSuccess) return TCHOL_E_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return TCHOL_E_HIP;

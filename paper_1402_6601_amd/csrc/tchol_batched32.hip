@@ -14,38 +14,45 @@
 
 #define BT 256
 
+// Columns of the diagonal tiles are dealt to the x blocks (one division per
+// column, not per entry); a column's rows go to consecutive threads.
 __global__ void b32_prepare(const int64_t* __restrict__ desc, int32_t batch, const float* __restrict__ A,
                             const float* __restrict__ B, double* __restrict__ D, double* __restrict__ Bd, int nrhs) {
   for (int32_t sy = blockIdx.y; sy < batch; sy += gridDim.y) {
-  const int64_t* d = desc + 8 * (int64_t)sy;
-  const int64_t a_off = d[0], lda = d[1], n = d[2], nb = d[3], d_off = d[4], b_off = d[5], bd_off = d[6];
-  const int64_t T = (n + nb - 1) / nb;
-  // diagonal tiles: T tiles of up to nb x nb
-  const int64_t per = nb * nb;
-  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < T * per; idx += (int64_t)gridDim.x * BT) {
-    const int64_t k = idx / per, e = idx - k * per, c = e / nb, r = e - c * nb;
-    const int64_t m = n - k * nb < nb ? n - k * nb : nb;
-    if (c < m && r < m && r >= c) D[d_off + k * per + c * nb + r] = (double)A[a_off + (k * nb + c) * lda + k * nb + r];
-  }
-  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < n * nrhs; idx += (int64_t)gridDim.x * BT)
-    Bd[bd_off + idx] = (double)B[b_off + idx];
+    const int64_t* d = desc + 8 * (int64_t)sy;
+    const int64_t a_off = d[0], lda = d[1], d_off = d[4], b_off = d[5], bd_off = d[6];
+    const int n = (int)d[2], nb = (int)d[3];
+    const int T = (n + nb - 1) / nb;
+    for (int col = blockIdx.x; col < T * nb; col += gridDim.x) {
+      const int k = col / nb, c = col - k * nb;
+      const int m = n - k * nb < nb ? n - k * nb : nb;
+      if (c >= m) continue;
+      const float* src = A + a_off + (int64_t)(k * nb + c) * lda + k * nb;
+      double* dst = D + d_off + (int64_t)k * nb * nb + (int64_t)c * nb;
+      for (int r = c + threadIdx.x; r < m; r += BT) dst[r] = (double)src[r];
+    }
+    for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < (int64_t)n * nrhs; idx += (int64_t)gridDim.x * BT)
+      Bd[bd_off + idx] = (double)B[b_off + idx];
   }
 }
 
 __global__ void b32_finish(const int64_t* __restrict__ desc, int32_t batch, float* __restrict__ A,
                            float* __restrict__ B, const double* __restrict__ D, const double* __restrict__ Bd, int nrhs) {
   for (int32_t sy = blockIdx.y; sy < batch; sy += gridDim.y) {
-  const int64_t* d = desc + 8 * (int64_t)sy;
-  const int64_t a_off = d[0], lda = d[1], n = d[2], nb = d[3], d_off = d[4], b_off = d[5], bd_off = d[6];
-  const int64_t T = (n + nb - 1) / nb;
-  const int64_t per = nb * nb;
-  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < T * per; idx += (int64_t)gridDim.x * BT) {
-    const int64_t k = idx / per, e = idx - k * per, c = e / nb, r = e - c * nb;
-    const int64_t m = n - k * nb < nb ? n - k * nb : nb;
-    if (c < m && r < m && r >= c) A[a_off + (k * nb + c) * lda + k * nb + r] = (float)D[d_off + k * per + c * nb + r];
-  }
-  for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < n * nrhs; idx += (int64_t)gridDim.x * BT)
-    B[b_off + idx] = (float)Bd[bd_off + idx];
+    const int64_t* d = desc + 8 * (int64_t)sy;
+    const int64_t a_off = d[0], lda = d[1], d_off = d[4], b_off = d[5], bd_off = d[6];
+    const int n = (int)d[2], nb = (int)d[3];
+    const int T = (n + nb - 1) / nb;
+    for (int col = blockIdx.x; col < T * nb; col += gridDim.x) {
+      const int k = col / nb, c = col - k * nb;
+      const int m = n - k * nb < nb ? n - k * nb : nb;
+      if (c >= m) continue;
+      float* dst = A + a_off + (int64_t)(k * nb + c) * lda + k * nb;
+      const double* src = D + d_off + (int64_t)k * nb * nb + (int64_t)c * nb;
+      for (int r = c + threadIdx.x; r < m; r += BT) dst[r] = (float)src[r];
+    }
+    for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < (int64_t)n * nrhs; idx += (int64_t)gridDim.x * BT)
+      B[b_off + idx] = (float)Bd[bd_off + idx];
   }
 }
 
@@ -53,7 +60,7 @@ extern "C" hipError_t tchol_b32_prepare(const int64_t* desc, int32_t batch, cons
                                         double* Bd, int nrhs, hipStream_t s) {
   if (batch == 0) return hipSuccess;
   const unsigned gy = (unsigned)(batch < 32768 ? batch : 32768);
-  hipLaunchKernelGGL(b32_prepare, dim3(16, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
+  hipLaunchKernelGGL(b32_prepare, dim3(64, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
   return hipGetLastError();
 }
 
@@ -61,6 +68,6 @@ extern "C" hipError_t tchol_b32_finish(const int64_t* desc, int32_t batch, float
                                        const double* Bd, int nrhs, hipStream_t s) {
   if (batch == 0) return hipSuccess;
   const unsigned gy = (unsigned)(batch < 32768 ? batch : 32768);
-  hipLaunchKernelGGL(b32_finish, dim3(16, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
+  hipLaunchKernelGGL(b32_finish, dim3(64, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
   return hipGetLastError();
 }

@@ -100,6 +100,24 @@ def test_batched_f32_failure_stays_in_its_system(tc):
         _check(A32s[s], b32s[s], Ls[s], Xs[s])
 
 
+def test_batched_f32_one_tile_compact(tc):
+    """Every system one tile: the FP64 copies are factored and solved by the
+    compact FP64 instance (two workgroups per compute unit, the forward solve
+    riding along the factorization); one system fails and stays alone."""
+    sizes = [1, 17, 100, 128, 129, 255, 300, 450, 511, 512, 200]
+    _, As, bs = spd_inputs.batched_systems(len(sizes), 35, 4, sizes=sizes)
+    A1, L0 = spd_inputs.integer_spd(200, seed=9)
+    j = 61
+    A1[j, j] -= 2.0 * L0[j, j] ** 2
+    _, info_o = oracle.potrf(A1.astype(np.float32).astype(np.float64))
+    assert info_o == j + 1
+    As[-1] = A1
+    info, A32s, b32s, Ls, Xs = _run(tc, As, bs, [_nb_single(n) for n in sizes])
+    assert list(info) == [0] * (len(sizes) - 1) + [j + 1]
+    for s in range(len(sizes) - 1):
+        _check(A32s[s], b32s[s], Ls[s], Xs[s])
+
+
 def test_batched_f32_bitwise_across_policies(tc):
     sizes = [400, 37, 600, 128, 250]
     _, As, bs = spd_inputs.batched_systems(len(sizes), 33, 3, sizes=sizes)
