@@ -193,6 +193,49 @@ std::shared_ptr<const Image> image_of(const std::shared_ptr<const Plan>& p, int6
   return img;
 }
 
+// The image of a batched launch: the plan with the systems' offsets and
+// leading dimensions of this call.  The last few are kept (pinned, so the
+// upload is one asynchronous copy), matched by plan and by every system's
+// record, so a caller that repeats a batch on the same buffers pays for the
+// image once.
+std::shared_ptr<const Image> batched_image_of(const std::shared_ptr<const Plan>& p,
+                                              const std::vector<tchol::System>& sys) {
+  struct Entry {
+    std::weak_ptr<const Plan> plan;
+    const Plan* key;
+    std::vector<tchol::System> sys;
+    std::shared_ptr<const Image> img;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;  // most recently used last
+  auto same = [&](const std::vector<tchol::System>& a) {
+    if (a.size() != sys.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i) {
+      const tchol::System &x = a[i], &y = sys[i];
+      if (x.a_off != y.a_off || x.b_off != y.b_off || x.n != y.n || x.nb != y.nb || x.ld != y.ld ||
+          x.d_off != y.d_off)
+        return false;
+    }
+    return true;
+  };
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (size_t i = 0; i < cache.size(); ++i) {
+      if (cache[i].key == p.get() && !cache[i].plan.expired() && same(cache[i].sys)) {
+        Entry e = cache[i];
+        cache.erase(cache.begin() + (std::ptrdiff_t)i);
+        cache.push_back(e);
+        return e.img;
+      }
+    }
+  }
+  std::shared_ptr<const Image> img = make_image(*p, true, &sys);
+  std::lock_guard<std::mutex> g(mu);
+  if (cache.size() >= 8) cache.erase(cache.begin());
+  cache.push_back(Entry{std::weak_ptr<const Plan>(p), p.get(), sys, img});
+  return img;
+}
+
 struct DeviceInfo {
   int grid = 0;
   int grid_compact = 0;  // the compact instance (batched one-tile systems)
@@ -735,7 +778,7 @@ int32_t tchol_factor_solve_batched(double* A, const int64_t* a_off, const int32_
   }
   auto plan = tchol::get_batched_plan(systems, o.policy, o.seed);
   if (!plan) return TCHOL_E_UNSUPPORTED;
-  auto img = make_image(*plan, false, &systems);
+  auto img = batched_image_of(plan, systems);
   // systems of one tile each, factored by one workgroup (no pooled POTRF):
   // the compact instance, two workgroups per compute unit
   bool compact = wide;
@@ -937,7 +980,7 @@ int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int
       sy.ld = sy.nb;
     }
   }
-  auto img = make_image(*plan, false, compact ? &dsys : &systems);
+  auto img = batched_image_of(plan, compact ? dsys : systems);
   char* w = static_cast<char*>(ws);
   int64_t* ddesc = reinterpret_cast<int64_t*>(w + L.desc);
   double* D = reinterpret_cast<double*>(w + L.d);
