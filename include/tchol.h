@@ -253,6 +253,11 @@ TCHOL_API int32_t tchol_factor_solve_noalloc(double *A, int64_t n, int64_t nb, d
    Systems must not overlap in memory.  The faster 16-byte transfer path is
    used when every lda[s] is even, every A_s is 16-byte aligned, and every
    odd n[s] has lda[s] > n[s] (e.g. lda[s] = n[s] rounded up to even).
+   When, in addition, every system is one tile (nb[s] >= n[s]) factored by
+   one workgroup (opts.wgs absent or at most 1), the launch runs a compact
+   kernel instance (two workgroups per compute unit) and, for nrhs <= 4,
+   solves forward inside each factorization; the results and their
+   contract are the same.
    Arguments: 1 A, 2 a_off, 3 lda, 4 B, 5 b_off, 6 n, 7 nb, 8 nrhs >= 0,
    9 batch >= 0, 10 info, 11 ws, 12 ws_bytes, 13 stream, 14 opts (NULL or as
    for tchol_factor_ex; opts.wgs applies).  Returns 0 when the launch ran
@@ -272,7 +277,9 @@ TCHOL_API int32_t tchol_factor_solve_batched(double *A, const int64_t *a_off, co
    are kept in FP64 in the workspace (their SYRK updates added in FP64, POTRF
    in FP64); TRSM and the solves compute in FP64 against them (the
    right-hand sides are staged in FP64); results are rounded to FP32 when
-   written back.  No refinement.
+   written back.  No refinement.  When every system is one tile, its FP64
+   copy is the whole system, and the copies are factored and solved by the
+   compact kernel instance of tchol_factor_solve_batched.
    Arguments as for tchol_factor_solve_batched with FP32 A and B (offsets in
    floats), except: every non-empty system needs lda[s] a multiple of 4 and
    lda[s] >= n[s] + 3 (the FP32 tile loads move four rows per 16-byte lane and

@@ -165,6 +165,22 @@ def test_batched_one_tile_compact(tc, nrhs):
         assert np.all(oracle.solve_backward_error(A, X, b) <= 1e-15)
 
 
+def test_batched_one_tile_compact_bitwise_across_policies(tc):
+    """The compact instance gives the same bits under every claim order, with
+    the fused forward solve (four right-hand sides) and without (five)."""
+    sizes = [400, 37, 512, 128, 250, 300, 16, 511]
+    nb = [_nb_single(n) for n in sizes]
+    for nrhs in (4, 5):
+        As, bs = _systems(23, sizes, nrhs)
+        ref = _run(tc, As, bs, nb)
+        assert np.all(ref[0] == 0)
+        for pol, seed in [(tc.POLICY_RANK, 0), (tc.POLICY_FIFO, 0), (tc.POLICY_RANDOM, 9)]:
+            got = _run(tc, As, bs, nb, policy=pol, seed=seed)
+            assert np.array_equal(got[0], ref[0])
+            assert all(np.array_equal(a, b) for a, b in zip(got[1], ref[1]))
+            assert all(np.array_equal(a, b) for a, b in zip(got[2], ref[2]))
+
+
 def test_batched_one_tile_compact_integer_exact(tc):
     """Integer systems through the compact instance and its fused forward
     solve: L and X exact."""
