@@ -234,3 +234,54 @@ def test_batched_factor_only_and_empty(tc):
             assert oracle.factor_error(L, oracle.cholesky(A)) <= TOL
     e = torch.zeros(1, dtype=torch.float64, device="cuda")
     assert len(tc.factor_solve_batched_(e, [], [], e, [], [], [], 4)) == 0
+
+
+def test_batched_config5_full_size(tc):
+    """The timed batched launch at its full size: 4096 systems of orders
+    uniform in [16, 512] (seed 4), 4 right-hand sides, tile sizes from the
+    tuned table (the compact instance), one launch.  Every system: info 0,
+    the scaled backward error of its factor ||A - L L^T||_F / (n eps ||A||_F)
+    at most 10 and the normwise backward error of its solutions at most
+    1e-13, both computed on the device in FP64 as checkers; 32 sampled
+    systems (the smallest and largest among them) against the oracle to
+    1e-10, with the oracle's long-double backward error at most 1e-15."""
+    from paper_1402_6601_amd import autotune
+    print("case: 4096 systems, seed 4, 4 RHS, tuned table", flush=True)
+    ns, A0, a_off, lda, B0, b_off = spd_inputs.batched_systems_device(4096, 4, 4)
+    nb = autotune.tile_sizes(ns)
+    wgs = autotune.potrf_wgs(ns)
+    A, B = A0.clone(), B0.clone()
+    info = tc.factor_solve_batched_(A, a_off, lda, B, b_off, ns, nb, 4, wgs=wgs)
+    torch.cuda.synchronize()
+    assert np.all(info == 0)
+    eps = np.finfo(np.float64).eps
+    worst_beta, worst_eta = 0.0, 0.0
+    for s_, (n, o, l, ob) in enumerate(zip(ns, a_off, lda, b_off)):
+        n, o, l, ob = int(n), int(o), int(l), int(ob)
+        S = A0[o:o + n * l].view(n, l)[:, :n]            # symmetric: row c = column c
+        L = torch.tril(A[o:o + n * l].view(n, l)[:, :n].t())
+        beta = float(torch.linalg.norm(S - L @ L.t().contiguous()) / (n * eps * torch.linalg.norm(S)))
+        b = B0[ob:ob + n * 4].view(4, n).t()
+        x = B[ob:ob + n * 4].view(4, n).t()
+        r = b - S @ x.contiguous()
+        an = float(torch.max(torch.sum(torch.abs(S), dim=1)))
+        eta = torch.max(torch.abs(r), dim=0).values / (an * torch.max(torch.abs(x), dim=0).values +
+                                                      torch.max(torch.abs(b), dim=0).values)
+        worst_beta = max(worst_beta, beta)
+        worst_eta = max(worst_eta, float(torch.max(eta)))
+    print("worst beta %.3f, worst eta %.3e" % (worst_beta, worst_eta), flush=True)
+    assert worst_beta <= 10.0
+    assert worst_eta <= 1e-13
+    rng = np.random.default_rng(5)
+    sample = set(rng.choice(len(ns), size=30, replace=False).tolist()) | {int(np.argmin(ns)), int(np.argmax(ns))}
+    for s_ in sorted(sample):
+        n, o, l, ob = int(ns[s_]), int(a_off[s_]), int(lda[s_]), int(b_off[s_])
+        Ah = A0[o:o + n * l].view(n, l)[:, :n].cpu().numpy()
+        bh = B0[ob:ob + n * 4].view(4, n).t().cpu().numpy()
+        Lh = np.tril(A[o:o + n * l].view(n, l)[:, :n].cpu().numpy().T)
+        Xh = B[ob:ob + n * 4].view(4, n).t().cpu().numpy()
+        Lo = oracle.cholesky(Ah)
+        assert oracle.factor_error(Lh, Lo) <= TOL
+        Xo = oracle.potrs(Lo, bh)
+        assert np.max(np.abs(Xh - Xo)) / np.max(np.abs(Xo)) <= TOL
+        assert np.all(oracle.solve_backward_error(Ah, Xh, bh) <= 1e-15)

@@ -144,3 +144,36 @@ def test_batched_f32_factor_only_empty_and_layout(tc):
     A = torch.zeros(64 * 64, dtype=torch.float32, device="cuda")
     with pytest.raises(tc.TcholError):
         tc.factor_solve_batched_f32_(A, [0], [64], A, [0], [64], [64], 1)
+
+
+def test_batched_f32_config5_full_size(tc):
+    """The FP32 batch at its full size (4096 systems of orders uniform in
+    [16, 512], seed 4, 4 right-hand sides, tuned table, one launch): every
+    system's factor within 10 n eps32 ||A||_F of its FP32 matrix and every
+    solution's normwise backward error at most 1e-6, both computed on the
+    device in FP64 as checkers."""
+    from paper_1402_6601_amd import autotune
+    print("case: 4096 FP32 systems, seed 4, 4 RHS, tuned table", flush=True)
+    ns, A0, a_off, lda, B0, b_off = spd_inputs.batched_systems_device(4096, 4, 4, align=4, pad=3, fp32=True)
+    nb = autotune.tile_sizes(ns)
+    A, B = A0.clone(), B0.clone()
+    info = tc.factor_solve_batched_f32_(A, a_off, lda, B, b_off, ns, nb, 4)
+    torch.cuda.synchronize()
+    assert np.all(info == 0)
+    worst_beta, worst_eta = 0.0, 0.0
+    for n, o, l, ob in zip(ns, a_off, lda, b_off):
+        n, o, l, ob = int(n), int(o), int(l), int(ob)
+        S = A0[o:o + n * l].view(n, l)[:, :n].double()
+        L = torch.tril(A[o:o + n * l].view(n, l)[:, :n].t().double())
+        beta = float(torch.linalg.norm(S - L @ L.t().contiguous()) / (n * EPS32 * torch.linalg.norm(S)))
+        b = B0[ob:ob + n * 4].view(4, n).t().double()
+        x = B[ob:ob + n * 4].view(4, n).t().double()
+        r = b - S @ x.contiguous()
+        an = float(torch.max(torch.sum(torch.abs(S), dim=1)))
+        eta = torch.max(torch.abs(r), dim=0).values / (an * torch.max(torch.abs(x), dim=0).values +
+                                                      torch.max(torch.abs(b), dim=0).values)
+        worst_beta = max(worst_beta, beta)
+        worst_eta = max(worst_eta, float(torch.max(eta)))
+    print("worst beta32 %.3f, worst eta %.3e" % (worst_beta, worst_eta), flush=True)
+    assert worst_beta <= 10.0
+    assert worst_eta <= 1e-6
