@@ -14,8 +14,9 @@
 
 #define BT 256
 
-// Columns of the diagonal tiles are dealt to the x blocks (one division per
-// column, not per entry); a column's rows go to consecutive threads.
+// Columns of the diagonal tiles are dealt to the wavefronts of the x blocks
+// (one division per column, not per entry); a wavefront moves its column's
+// rows four 64-row runs at a time, their loads issued before their stores.
 __global__ void b32_prepare(const int64_t* __restrict__ desc, int32_t batch, const float* __restrict__ A,
                             const float* __restrict__ B, double* __restrict__ D, double* __restrict__ Bd, int nrhs) {
   for (int32_t sy = blockIdx.y; sy < batch; sy += gridDim.y) {
@@ -23,13 +24,26 @@ __global__ void b32_prepare(const int64_t* __restrict__ desc, int32_t batch, con
     const int64_t a_off = d[0], lda = d[1], d_off = d[4], b_off = d[5], bd_off = d[6];
     const int n = (int)d[2], nb = (int)d[3];
     const int T = (n + nb - 1) / nb;
-    for (int col = blockIdx.x; col < T * nb; col += gridDim.x) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int col = blockIdx.x * (BT / 64) + wave; col < T * nb; col += gridDim.x * (BT / 64)) {
       const int k = col / nb, c = col - k * nb;
       const int m = n - k * nb < nb ? n - k * nb : nb;
       if (c >= m) continue;
       const float* src = A + a_off + (int64_t)(k * nb + c) * lda + k * nb;
       double* dst = D + d_off + (int64_t)k * nb * nb + (int64_t)c * nb;
-      for (int r = c + threadIdx.x; r < m; r += BT) dst[r] = (double)src[r];
+      for (int r0 = c; r0 < m; r0 += 4 * 64) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + lane + 64 * u;
+          v[u] = r < m ? src[r] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + lane + 64 * u;
+          if (r < m) dst[r] = (double)v[u];
+        }
+      }
     }
     for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < (int64_t)n * nrhs; idx += (int64_t)gridDim.x * BT)
       Bd[bd_off + idx] = (double)B[b_off + idx];
@@ -43,13 +57,26 @@ __global__ void b32_finish(const int64_t* __restrict__ desc, int32_t batch, floa
     const int64_t a_off = d[0], lda = d[1], d_off = d[4], b_off = d[5], bd_off = d[6];
     const int n = (int)d[2], nb = (int)d[3];
     const int T = (n + nb - 1) / nb;
-    for (int col = blockIdx.x; col < T * nb; col += gridDim.x) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int col = blockIdx.x * (BT / 64) + wave; col < T * nb; col += gridDim.x * (BT / 64)) {
       const int k = col / nb, c = col - k * nb;
       const int m = n - k * nb < nb ? n - k * nb : nb;
       if (c >= m) continue;
       float* dst = A + a_off + (int64_t)(k * nb + c) * lda + k * nb;
       const double* src = D + d_off + (int64_t)k * nb * nb + (int64_t)c * nb;
-      for (int r = c + threadIdx.x; r < m; r += BT) dst[r] = (float)src[r];
+      for (int r0 = c; r0 < m; r0 += 4 * 64) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + lane + 64 * u;
+          v[u] = r < m ? src[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + lane + 64 * u;
+          if (r < m) dst[r] = (float)v[u];
+        }
+      }
     }
     for (int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x; idx < (int64_t)n * nrhs; idx += (int64_t)gridDim.x * BT)
       B[b_off + idx] = (float)Bd[bd_off + idx];
@@ -60,7 +87,7 @@ extern "C" hipError_t tchol_b32_prepare(const int64_t* desc, int32_t batch, cons
                                         double* Bd, int nrhs, hipStream_t s) {
   if (batch == 0) return hipSuccess;
   const unsigned gy = (unsigned)(batch < 32768 ? batch : 32768);
-  hipLaunchKernelGGL(b32_prepare, dim3(64, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
+  hipLaunchKernelGGL(b32_prepare, dim3(16, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
   return hipGetLastError();
 }
 
@@ -68,6 +95,6 @@ extern "C" hipError_t tchol_b32_finish(const int64_t* desc, int32_t batch, float
                                        const double* Bd, int nrhs, hipStream_t s) {
   if (batch == 0) return hipSuccess;
   const unsigned gy = (unsigned)(batch < 32768 ? batch : 32768);
-  hipLaunchKernelGGL(b32_finish, dim3(64, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
+  hipLaunchKernelGGL(b32_finish, dim3(16, gy), dim3(BT), 0, s, desc, batch, A, B, D, Bd, nrhs);
   return hipGetLastError();
 }
