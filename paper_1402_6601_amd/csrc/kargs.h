@@ -38,7 +38,8 @@ typedef struct KArgs {
                            (A is the FP32 working copy); 3: the adjoint of the
                            factorization (A = L, B = Lbar, D = partial-product slots);
                            5: the factorization with BF16 updates; 6: FP64 batched
-                           systems of one tile each (the compact instance)      */
+                           systems of one tile each (the compact instance); 7: the
+                           same for FP32 batched systems (their FP64 copies in A) */
   int32_t syrk_b;       /* SYRK output sub-tile (square)                          */
   int32_t inv;          /* FP64 launches: 1 when the launch computes the diagonal
                            tiles' explicit inverses (TRTRI tasks) and applies them:
@@ -59,13 +60,18 @@ typedef struct KArgs {
                            tile, K-contiguous: column block k, row r, column c of
                            term t at H[((t T + k) hrows + r) nb + c]             */
   int64_t hrows;        /* rows per column block of H (T nb)                      */
+  float *A32;           /* mode 7: the systems' FP32 matrices (system s at A32 +
+                           sys word 5, leading dimension sys word 7), read for the
+                           factorization and overwritten by L rounded to FP32   */
 } KArgs;
 
 #define DESC_WORDS 8   /* kind, i, j, k, parts, succ_begin, succ_end, system */
 #define SYS_WORDS 8    /* a_off, b_off, n, nb, ld, d_off (mixed precision: offset of the
-                          system's FP64 diagonal tiles and inverses), pool_off
-                          (index of the system's first diagonal tile among all
-                          systems' diagonal tiles, for the POTRF pools), 0     */
+                          system's FP64 diagonal tiles and inverses; mode 7: of
+                          its FP32 matrix in A32), pool_off (index of the
+                          system's first diagonal tile among all systems'
+                          diagonal tiles, for the POTRF pools), ld2 (mode 7:
+                          the FP32 matrix's leading dimension; else 0)        */
 #define POOL_WORDS 64  /* counters of one diagonal tile's POTRF pool          */
 
 #endif

@@ -28,6 +28,8 @@ struct System {
   int64_t d_off = 0;             // mixed precision: offset (doubles) of its FP64 diagonal tiles
   int32_t wgs = 0;               // work items of a one-tile system's POTRF above 128 (its
                                  // sub-block pool); 0: the default (one)
+  int64_t ld2 = 0;               // FP32 batched systems on the compact instance: the
+                                 // leading dimension of the FP32 matrix (d_off its offset)
 };
 
 struct Plan {

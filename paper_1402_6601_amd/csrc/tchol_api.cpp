@@ -161,6 +161,7 @@ std::shared_ptr<Image> make_image(const Plan& p, bool pin, const std::vector<tch
     r[4] = sy.ld;
     r[5] = sy.d_off;
     r[6] = pool_off;
+    r[7] = sy.ld2;
     pool_off += p.systems[s].n == 0 ? 0 : (p.systems[s].n + p.systems[s].nb - 1) / p.systems[s].nb;
   }
   return img;
@@ -213,7 +214,7 @@ std::shared_ptr<const Image> batched_image_of(const std::shared_ptr<const Plan>&
     for (size_t i = 0; i < a.size(); ++i) {
       const tchol::System &x = a[i], &y = sys[i];
       if (x.a_off != y.a_off || x.b_off != y.b_off || x.n != y.n || x.nb != y.nb || x.ld != y.ld ||
-          x.d_off != y.d_off)
+          x.d_off != y.d_off || x.ld2 != y.ld2)
         return false;
     }
     return true;
@@ -278,13 +279,13 @@ const tchol_opts kDefaultOpts = {TCHOL_POLICY_LIST, 0u, 0, nullptr, nullptr, 0, 
 // reads the header back and synchronises.  sinfo_out (batched): per-system
 // failing columns.  mixed: 0 FP64; 1 / 2 the mixed-precision factor / solve
 // (A is then the FP32 working copy and D its FP64 diagonal tiles); 6 the
-// compact FP64 instance for batched systems of one tile each.  Returns the
-// library code.
+// compact FP64 instance for batched systems of one tile each, 7 the same
+// reading and writing FP32 matrices at A32.  Returns the library code.
 int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_t nrhs, bool wide, bool batched,
                 void* ws, int64_t ws_bytes, void* stream_v, const tchol_opts& o, int32_t ws_arg,
                 int32_t* sinfo_out, double* D = nullptr, int mixed = 0, double* Qp = nullptr,
                 double* LTp = nullptr, int64_t ldq = 0, double* Dinv = nullptr, double* DinvT = nullptr,
-                double* Sx = nullptr, uint16_t* H = nullptr, int64_t hrows = 0) {
+                double* Sx = nullptr, uint16_t* H = nullptr, int64_t hrows = 0, float* A32 = nullptr) {
   const Layout& L = img.lay;
   if (ws_bytes < L.end) return -(ws_arg + 1);
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return -ws_arg;
@@ -334,6 +335,7 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
   a.inv = plan.inv ? 1 : 0;
   a.H = H;
   a.hrows = hrows;
+  a.A32 = A32;
   const int64_t limit_us = o.wait_limit_us > 0 ? o.wait_limit_us : 30000000;
   a.wait_limit = limit_us * di.clock_khz / 1000;
   a.trace = o.trace;
@@ -346,7 +348,8 @@ int32_t execute(const Plan& plan, const Image& img, double* A, double* B, int64_
     e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
   }
-  const int grid = (int)std::min<int64_t>(mixed == 6 ? di.grid_compact : di.grid, std::max<int64_t>(1, plan.nitem()));
+  const int grid =
+      (int)std::min<int64_t>(mixed >= 6 ? di.grid_compact : di.grid, std::max<int64_t>(1, plan.nitem()));
   if (e == hipSuccess)
     e = tchol_dev_launch(&a, (int32_t)plan.ntask(), reinterpret_cast<const int32_t*>(w + L.dep0), L.npool, grid,
                          wide ? 1 : 0, stream, ev0, ev1);
@@ -963,10 +966,11 @@ int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int
     desc[8 * s + 4] = systems[s].d_off;
     desc[8 * s + 6] = systems[s].b_off;
   }
-  // Systems of one tile each (no pooled POTRF): the FP64 copy of every
-  // system is its whole matrix (D, leading dimension nb, even and 16-byte
-  // aligned), so the compact FP64 instance factors and solves the copies in
-  // place, addressed as systems of their own.
+  // Systems of one tile each (no pooled POTRF): the compact instance for
+  // FP32 storage factors each system reading its FP32 matrix, keeps L in
+  // FP64 in the system's tile of D (leading dimension nb, even and 16-byte
+  // aligned) for its products and solves, and writes L rounded to FP32 back;
+  // only the right-hand sides are staged.
   bool compact = true;
   for (int64_t t = 0; compact && t < plan->ntask(); ++t) {
     const int32_t k = plan->kind[t];
@@ -975,9 +979,13 @@ int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int
   std::vector<tchol::System> dsys;
   if (compact) {
     dsys = systems;
-    for (auto& sy : dsys) {
-      sy.a_off = sy.d_off;
+    for (size_t i = 0; i < dsys.size(); ++i) {
+      auto& sy = dsys[i];
+      sy.ld2 = sy.ld;
+      sy.d_off = sy.a_off;
+      sy.a_off = systems[i].d_off;
       sy.ld = sy.nb;
+      desc[8 * i + 7] = 1;
     }
   }
   auto img = batched_image_of(plan, compact ? dsys : systems);
@@ -990,7 +998,7 @@ int32_t tchol_factor_solve_batched_f32(float* A, const int64_t* a_off, const int
   if (tchol_b32_prepare(ddesc, batch, A, B, D, Bd, nrhs, s) != hipSuccess) return TCHOL_E_HIP;
   const int32_t rc =
       compact ? execute(*plan, *img, D, Bd, nrhs, true, true, w + L.sched, ws_bytes - L.sched, stream_v, o, 11, info,
-                        nullptr, 6)
+                        nullptr, 7, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, A)
               : execute(*plan, *img, reinterpret_cast<double*>(A), Bd, nrhs, true, true, w + L.sched,
                         ws_bytes - L.sched, stream_v, o, 11, info, D, 4, nullptr, nullptr, 0, D, D, Bd);
   if (rc != 0) return rc;

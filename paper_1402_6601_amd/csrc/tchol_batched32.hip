@@ -6,9 +6,10 @@
 // A_s,kk -> D (lower triangles) and B -> Bd.  After it: the factored
 // diagonal tiles D -> A (lower, rounded) and the solutions Bd -> B.
 //
-// desc: per system, 8 words: a_off, lda, n, nb, d_off, b_off, bd_off, 0
+// desc: per system, 8 words: a_off, lda, n, nb, d_off, b_off, bd_off, own
 // (a_off and b_off in floats from A and B, d_off and bd_off in doubles
-// from D and Bd; D holds T_s tiles of nb_s x nb_s per system).
+// from D and Bd; D holds T_s tiles of nb_s x nb_s per system; own != 0: the
+// launch itself reads A_s and writes L_s back, only B is staged).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -23,7 +24,7 @@ __global__ void b32_prepare(const int64_t* __restrict__ desc, int32_t batch, con
     const int64_t* d = desc + 8 * (int64_t)sy;
     const int64_t a_off = d[0], lda = d[1], d_off = d[4], b_off = d[5], bd_off = d[6];
     const int n = (int)d[2], nb = (int)d[3];
-    const int T = (n + nb - 1) / nb;
+    const int T = d[7] != 0 ? 0 : (n + nb - 1) / nb;  // own: no diagonal tiles to move
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int col = blockIdx.x * (BT / 64) + wave; col < T * nb; col += gridDim.x * (BT / 64)) {
       const int k = col / nb, c = col - k * nb;
@@ -56,7 +57,7 @@ __global__ void b32_finish(const int64_t* __restrict__ desc, int32_t batch, floa
     const int64_t* d = desc + 8 * (int64_t)sy;
     const int64_t a_off = d[0], lda = d[1], d_off = d[4], b_off = d[5], bd_off = d[6];
     const int n = (int)d[2], nb = (int)d[3];
-    const int T = (n + nb - 1) / nb;
+    const int T = d[7] != 0 ? 0 : (n + nb - 1) / nb;  // own: no diagonal tiles to move
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int col = blockIdx.x * (BT / 64) + wave; col < T * nb; col += gridDim.x * (BT / 64)) {
       const int k = col / nb, c = col - k * nb;

@@ -334,13 +334,15 @@ __device__ __forceinline__ void gemm_kloop(d4 (&acc)[RB][CB], const double* __re
 
 // ldc: leading dimension of C when it differs from the panels' (< 0: ld);
 // zero_c: start from C = 0 instead of loading C; ldb: the B panel's leading
-// dimension when it differs from A's (< 0: ld); neg: store -C.
-template <int SEG, int BM, int BN, int KC, int WGM, int NST, int PAD = 8>
+// dimension when it differs from A's (< 0: ld); neg: store -C.  CF32: the
+// initial C is read from the FP32 matrix Cf (leading dimension ldcf) instead.
+template <int SEG, int BM, int BN, int KC, int WGM, int NST, int PAD = 8, bool CF32 = false>
 __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* __restrict__ Ap,
                                           const double* __restrict__ Bp, int64_t ld, int M, int N, int K,
                                           bool lower_only, double* lds, double* Cl = nullptr, int ldl = 0,
                                           int64_t ldc = -1, bool zero_c = false, int64_t ldb = -1,
-                                          bool neg = false) {
+                                          bool neg = false, const float* __restrict__ Cf = nullptr,
+                                          int64_t ldcf = 0) {
   const int64_t ldC = ldc < 0 ? ld : ldc;
   using S = GemmShape<BM, BN, KC, WGM, NST, PAD>;
   constexpr int RB = S::RB, CB = S::CB;
@@ -357,7 +359,10 @@ __device__ __forceinline__ void gemm_core(double* __restrict__ C, const double* 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = wm * S::WTM + rb * 16 + l16, col = wn * S::WTN + cb * 16 + 4 * i + lg;
-        acc[rb][cb][i] = zero_c ? 0.0 : C[(int64_t)imin(col, N - 1) * ldC + imin(row, M - 1)];
+        if constexpr (CF32)
+          acc[rb][cb][i] = (double)Cf[(int64_t)imin(col, N - 1) * ldcf + imin(row, M - 1)];
+        else
+          acc[rb][cb][i] = zero_c ? 0.0 : C[(int64_t)imin(col, N - 1) * ldC + imin(row, M - 1)];
       }
 
   gemm_kloop<BM, BN, KC, WGM, NST, PAD, SEG>(acc, Ap, Bp, ld, M, N, K, lds, ldb);
@@ -1057,9 +1062,14 @@ __device__ __forceinline__ int potrf_small(double* __restrict__ Akk, int64_t ld,
 #define PT_LDS_COMPACT (2 * 16 * (128 + PT_W) + PT_W * 136 + PT_LT_PACKED + PT_W * PT_FWD)
 #define FRB_COMPACT_DOUBLES (32 * 4 * 64 + 2 * 4 * 64)  // tile_solve<true>
 
-template <int SEG, int SLAB = PT_SLAB>
+// IN32 (compact layout): the tile's values are read from the FP32 matrix A32
+// (leading dimension ld32) instead of Akk, and L is written to both (Akk in
+// FP64 for the later panels' products, A32 rounded to FP32).
+template <int SEG, int SLAB = PT_SLAB, bool IN32 = false>
 __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, int m, double* lds,
-                                          double* Bf = nullptr, int64_t ldbf = 0, int nrhs = 0) {
+                                          double* Bf = nullptr, int64_t ldbf = 0, int nrhs = 0,
+                                          float* __restrict__ A32 = nullptr, int64_t ld32 = 0) {
+  static_assert(!IN32 || SLAB == 128, "FP32 input in the compact layout only");
   static_assert(SLAB == 256 || SLAB == 128, "slab height");
   constexpr bool PACKED = SLAB < PT_SLAB;
   constexpr int LDP = SLAB + 8;                        // LDS leading dimension of a slab
@@ -1083,21 +1093,26 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
     const int w = imin(PT_W, m - c0);
     const int R = m - c0;
     double* P = Akk + (int64_t)c0 * ld + c0;
+    float* const P32 = IN32 ? A32 + (int64_t)c0 * ld32 + c0 : nullptr;
     for (int s0 = 0; s0 < R; s0 += SLAB) {
       const int S = imin(SLAB, R - s0);
       if (c0 > 0) {
         // the slab - L[c0 + s0 :, 0 : c0] L[c0 : c0 + w, 0 : c0]^T into LDS,
         // on a product no taller than the slab needs
         if (SLAB > 128 && S > 128)
-          gemm_core<SEG, SLAB, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, LDP);
+          gemm_core<SEG, SLAB, PT_W, 16, 4, 2, 0, IN32>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps,
+                                                        LDP, -1, false, -1, false, IN32 ? P32 + s0 : nullptr, ld32);
         else if (S > 64)
-          gemm_core<SEG, 128, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, LDP);
+          gemm_core<SEG, 128, PT_W, 16, 4, 2, 0, IN32>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps,
+                                                       LDP, -1, false, -1, false, IN32 ? P32 + s0 : nullptr, ld32);
         else
-          gemm_core<SEG, 64, PT_W, 16, 4, 2, 0>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps, LDP);
+          gemm_core<SEG, 64, PT_W, 16, 4, 2, 0, IN32>(P + s0, Akk + c0 + s0, Akk + c0, ld, S, w, c0, false, lds, Ps,
+                                                      LDP, -1, false, -1, false, IN32 ? P32 + s0 : nullptr, ld32);
       } else if (tid < S) {
         double v[PT_W];
 #pragma unroll
-        for (int c = 0; c < PT_W; ++c) v[c] = P[(int64_t)imin(c, w - 1) * ld + s0 + tid];
+        for (int c = 0; c < PT_W; ++c)
+          v[c] = IN32 ? (double)P32[(int64_t)imin(c, w - 1) * ld32 + s0 + tid] : P[(int64_t)imin(c, w - 1) * ld + s0 + tid];
 #pragma unroll
         for (int c = 0; c < PT_W; ++c) Ps[c * LDP + tid] = v[c];
       }
@@ -1188,7 +1203,10 @@ __device__ __forceinline__ int potrf_tile(double* __restrict__ Akk, int64_t ld, 
       if (tid < S) {
 #pragma unroll
         for (int c = 0; c < PT_W; ++c)
-          if (c < w && s0 + tid >= c) st_dev(P + (int64_t)c * ld + s0 + tid, Ps[c * LDP + tid]);
+          if (c < w && s0 + tid >= c) {
+            st_dev(P + (int64_t)c * ld + s0 + tid, Ps[c * LDP + tid]);
+            if constexpr (IN32) st_dev(P32 + (int64_t)c * ld32 + s0 + tid, (float)Ps[c * LDP + tid]);
+          }
         if (fwd && s0 + tid >= w) {
           // b(row) -= L(row, panel) y_panel for the rows below the block
           double* const bp = Bf + c0 + s0 + tid;
@@ -2461,7 +2479,7 @@ __device__ __forceinline__ bool pool_wait_unit(const KArgs& a, const int32_t* po
 // A mixed launch runs only its own task kinds (keeping each instance small)
 // and is always a 16-byte one.
 template <int SEG, int MODE>
-__global__ void __launch_bounds__(NT, MODE == 6 ? 2 : 1) tchol_persistent(KArgs a) {
+__global__ void __launch_bounds__(NT, MODE >= 6 ? 2 : 1) tchol_persistent(KArgs a) {
   constexpr bool MIXED = MODE == 1 || MODE == 2 || MODE == 4 || MODE == 5;
   constexpr bool FACTOR_KINDS = MODE == 0 || MODE == 1 || MODE == 4 || MODE == 5;
   constexpr bool SOLVE_KINDS = MODE == 0 || MODE == 2 || MODE == 4;
@@ -2472,9 +2490,12 @@ __global__ void __launch_bounds__(NT, MODE == 6 ? 2 : 1) tchol_persistent(KArgs 
   // tile on one workgroup (only part 0 of a POTRF task works)
   constexpr bool POOLED = MODE == 0 || MODE == 1 || MODE == 5;
   // MODE 6 (batched systems of one tile each): the compact POTRF and tile
-  // solves only, in half the LDS, two workgroups per compute unit
+  // solves only, in half the LDS, two workgroups per compute unit; MODE 7 the
+  // same with each system's matrix read from and L written to FP32 storage
+  // (A32, the FP64 tile in A for the products and the solves)
   static_assert(FRB_COMPACT_DOUBLES <= PT_LDS_COMPACT, "compact LDS budget");
-  __shared__ double lds[MODE == 6 ? PT_LDS_COMPACT : LDS_DOUBLES];
+  constexpr bool COMPACT = MODE == 6 || MODE == 7;
+  __shared__ double lds[COMPACT ? PT_LDS_COMPACT : LDS_DOUBLES];
   __shared__ int s_claim[4];
   __shared__ int32_t s_desc[DESC_WORDS];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -2636,13 +2657,15 @@ __global__ void __launch_bounds__(NT, MODE == 6 ? 2 : 1) tchol_persistent(KArgs 
     } else if (POOLED && unit == -2) {
       body = -1;
     }
-    if constexpr (MODE == 6) {
+    if constexpr (COMPACT) {
       const bool fuse_fwd = a.nrhs > 0 && a.nrhs <= PT_FWD;
       if (skip) {
       } else if (kind == TK_POTRF) {
         // up to PT_FWD right-hand sides: the forward solve rides along (its FTRSV task only passes the completion on)
-        const int info = uniform_i(potrf_tile<SEG, 128>(Abase + (tk * nb) * ld + tk * nb, ld, tsz(tk), lds,
-                                                        fuse_fwd ? Bbase + tk * nb : nullptr, ldb, (int)a.nrhs));
+        // MODE 7: the system's FP32 matrix at A32 + sr[5], leading dimension sr[7]
+        const int info = uniform_i(potrf_tile<SEG, 128, MODE == 7>(
+            Abase + (tk * nb) * ld + tk * nb, ld, tsz(tk), lds, fuse_fwd ? Bbase + tk * nb : nullptr, ldb,
+            (int)a.nrhs, MODE == 7 ? a.A32 + sr[5] + (tk * nb) * sr[7] + tk * nb : nullptr, sr[7]));
         if (info != 0 && tid == 0)
           __hip_atomic_store(&a.sinfo[sid], (int)(tk * nb) + info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if (kind == TK_BTRSV || (kind == TK_FTRSV && !fuse_fwd)) {
@@ -3082,6 +3105,8 @@ extern "C" hipError_t tchol_dev_launch(const KArgs* a, int32_t ntask, const int3
     hipLaunchKernelGGL((tchol_persistent<128, 2>), dim3(grid), dim3(NT), 0, stream, *a);
   else if (a->mixed == 6)
     hipLaunchKernelGGL((tchol_persistent<128, 6>), dim3(grid), dim3(NT), 0, stream, *a);
+  else if (a->mixed == 7)
+    hipLaunchKernelGGL((tchol_persistent<128, 7>), dim3(grid), dim3(NT), 0, stream, *a);
   else if (wide)
     hipLaunchKernelGGL((tchol_persistent<128, 0>), dim3(grid), dim3(NT), 0, stream, *a);
   else
@@ -3109,6 +3134,10 @@ extern "C" hipError_t tchol_dev_compact_grid(int device, int* grid) {
   if (e != hipSuccess) return e;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, tchol_persistent<128, 6>, NT, 0);
   if (e != hipSuccess) return e;
+  int occ7 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ7, tchol_persistent<128, 7>, NT, 0);
+  if (e != hipSuccess) return e;
+  occ = occ < occ7 ? occ : occ7;
   *grid = cus * (occ > 0 ? occ : 1);
   return hipSuccess;
 }
