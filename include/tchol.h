@@ -277,9 +277,10 @@ TCHOL_API int32_t tchol_factor_solve_batched(double *A, const int64_t *a_off, co
    are kept in FP64 in the workspace (their SYRK updates added in FP64, POTRF
    in FP64); TRSM and the solves compute in FP64 against them (the
    right-hand sides are staged in FP64); results are rounded to FP32 when
-   written back.  No refinement.  When every system is one tile, its FP64
-   copy is the whole system, and the copies are factored and solved by the
-   compact kernel instance of tchol_factor_solve_batched.
+   written back.  No refinement.  When every system is one tile, a compact
+   kernel instance (two workgroups per compute unit) reads each FP32 matrix
+   itself, keeps L in FP64 in the workspace for its products and solves, and
+   writes L rounded to FP32 back; only the right-hand sides are staged.
    Arguments as for tchol_factor_solve_batched with FP32 A and B (offsets in
    floats), except: every non-empty system needs lda[s] a multiple of 4 and
    lda[s] >= n[s] + 3 (the FP32 tile loads move four rows per 16-byte lane and
